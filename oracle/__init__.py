@@ -1,0 +1,14 @@
+"""CPU oracle of the factorized shading bake and the factored re-render loss.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, by the smoke check and
+by the benchmark's CPU-baseline leg, never by the GPU library or its Python
+binding.  It shares no code with the GPU path; the two meet only on the
+seeded inputs from ``synth``.
+
+* ``oracle.bake``    shading points and the Monte Carlo bake (Eq. 6, 7, 9),
+                     brute-force ray casting in double precision (C, built by
+                     ``oracle.build``);
+* ``oracle.render``  factored re-render, photometric loss and its gradient
+                     (Eq. 5, 8, 2/15), trilinear material grid and its
+                     adjoint, in numpy float64.
+"""
