@@ -1,0 +1,330 @@
+"""Benchmark of the factorized-shading hot path on one MI355X.
+
+One step = the whole hot path over the synthetic room (189,440 triangles,
+24 cameras x 320 x 240 = 1,843,200 shading points, 128 samples per lobe,
+6 roughness levels):
+  shading points from the cameras -> bake of Ld, Ls0[6], Ls1[6]
+  (1,651,507,200 lobe samples) -> material gather from a 128^3 grid ->
+  factored re-render + loss + gradient -> gradient scatter to the grid.
+
+Prints one JSON line.  `value` is lobe samples baked per second over whole
+steps (inputs resident in HBM).  Per-kernel times come from HIP events on
+the stream the kernels run on.  The serving leg replays a Poisson trace of
+bake requests against the continuous-batching server and against
+one-request-at-a-time baking and reports p50/p99 latency.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_2304_05669_amd import fipt  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+SHADING_PLANES = 39
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on torch's current stream (where the library launches)."""
+
+    def __init__(self):
+        self.ev = {}
+
+    def mark(self, name):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.ev.setdefault(name, []).append(e)
+
+    def spans(self, a, b):
+        return [x.elapsed_time(y) for x, y in zip(self.ev[a], self.ev[b])]
+
+
+def setup_room(sc, dev):
+    scene = fipt.Scene(sc.verts, sc.tris, device=0)
+    kind = fipt.CACHE_VERTEX if sc.cache_kind == "vertex" else fipt.CACHE_TRIANGLE
+    scene.set_radiance(torch.from_numpy(sc.cache).to(dev), kind,
+                       torch.from_numpy(sc.emission).to(dev))
+    return scene
+
+
+def traversal_bytes(scene, planes, tri, sc, out):
+    """Algorithmic bytes of one bake launch, from the instrumented kernel:
+    64 B per BVH node fetched, 48 B per triangle tested, 48 B radiance
+    record per hit, 40 B per point read and 156 B per point written."""
+    stats = torch.zeros(4, dtype=torch.int64, device=planes.device)
+    fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out, stats=stats)
+    torch.cuda.synchronize()
+    rays, nodes, tris, hits = [int(v) for v in stats.cpu()]
+    n = planes.shape[1]
+    P = 3 + 6 * len(sc.sigma)
+    total = nodes * 64 + tris * 48 + hits * 48 + n * 40 + n * P * 4
+    return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, bytes=total,
+                nodes_per_ray=nodes / max(rays, 1), tris_per_ray=tris / max(rays, 1))
+
+
+def cpu_baseline(sc, planes, tri, budget_s):
+    """The oracle (double precision, brute force) on a bounded sample of the
+    same workload, with every host thread."""
+    from oracle import bake as ob
+    osc = ob.OracleScene(sc)
+    threads = ob.max_threads()
+    n_pts = planes.shape[1]
+    S = sc.spp * (1 + len(sc.sigma))
+    pts = planes.cpu().numpy()
+    tr = tri.cpu().numpy()
+    rng = np.random.default_rng(0)
+    # calibrate on one point per thread, then size the sample to the budget
+    idx = np.sort(rng.choice(n_pts, threads, replace=False))
+    t0 = time.perf_counter()
+    ob.bake(osc, pts, tr, idx=idx, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed, threads=threads)
+    dt = time.perf_counter() - t0
+    k = max(1, int(budget_s / max(dt, 1e-3)))
+    idx = np.sort(rng.choice(n_pts, min(n_pts, k * threads), replace=False))
+    t0 = time.perf_counter()
+    ob.bake(osc, pts, tr, idx=idx, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed, threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=len(idx) * S / dt / 1e9, unit="Gsamples/s", cores=threads, kind="oracle",
+                sample=f"{len(idx)} random points of the room x {S} lobe samples, "
+                       f"brute-force float64 over all {sc.n_tris} triangles, {dt:.1f} s")
+
+
+def run_serving(dev, n_requests, rate, log_every=20):
+    """Replay a Poisson trace of bake requests over eight resident rooms,
+    through the server and one request at a time; latency = completion -
+    arrival."""
+    rooms = synth.serving_rooms()
+    scenes, pts = [], []
+    for r in rooms:
+        s = setup_room(r, dev)
+        planes, tri = fipt.fipt_gen_points(s, r.cameras)
+        scenes.append(s)
+        pts.append((planes, tri))
+    torch.cuda.synchronize()
+    trace = synth.serving_trace(n_requests, rate, [p[0].shape[1] for p in pts])
+    sig = synth.SIGMA_GRID
+    samples = sum(q["count"] * q["spp"] * (1 + len(sig)) for q in trace)
+
+    # continuous batching
+    srv = fipt.Server(device=0, pool_bytes=8 << 30, max_inflight=64, samples_per_launch=1 << 26)
+    t0 = time.perf_counter()
+    tickets = [None] * len(trace)
+
+    def feeder():
+        for i, q in enumerate(trace):
+            d = t0 + q["arrival"] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            planes, tri = pts[q["room"]]
+            tickets[i] = (srv.submit(scenes[q["room"]], planes, tri, q["spp"], q["spp"], sig,
+                                     q["seed"], offset=q["offset"], count=q["count"]),
+                          time.perf_counter())
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    lat = []
+    for i in range(len(trace)):
+        while tickets[i] is None:
+            time.sleep(1e-4)
+        t, _ = tickets[i]
+        srv.wait(t)
+        res = srv.result(t, copy=False)
+        lat.append((res.t_done_us - res.t_submit_us) / 1e3)
+        srv.release(t)
+        if (i + 1) % log_every == 0:
+            log(f"serving: {i + 1}/{len(trace)} requests done")
+    th.join()
+    t_batched = time.perf_counter() - t0
+    st = srv.stats()
+    srv.destroy()
+
+    # one at a time, FIFO, same arrivals
+    out = torch.empty((SHADING_PLANES, 2_000_000), dtype=torch.float32, device=dev)
+    lat1 = []
+    t0 = time.perf_counter()
+    for i, q in enumerate(trace):
+        d = t0 + q["arrival"] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        planes, tri = pts[q["room"]]
+        o, c = q["offset"], q["count"]
+        fipt.fipt_bake(scenes[q["room"]], planes[:, o:o + c].contiguous(), tri[o:o + c].contiguous(),
+                       q["spp"], q["spp"], sig, q["seed"], out=out)
+        torch.cuda.synchronize()
+        lat1.append((time.perf_counter() - (t0 + q["arrival"])) * 1e3)
+        if (i + 1) % log_every == 0:
+            log(f"one-at-a-time: {i + 1}/{len(trace)} requests done")
+    t_single = time.perf_counter() - t0
+    for s in scenes:
+        s.destroy()
+    return dict(
+        requests=len(trace), rate_per_s=rate, rooms=[r.n_tris for r in rooms],
+        lobe_samples=samples,
+        batched=dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                     makespan_s=t_batched, gsamples_per_s=samples / t_batched / 1e9,
+                     launches=int(st.launches), tiles=int(st.tiles)),
+        one_at_a_time=dict(p50_ms=float(np.percentile(lat1, 50)),
+                           p99_ms=float(np.percentile(lat1, 99)), makespan_s=t_single,
+                           gsamples_per_s=samples / t_single / 1e9))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=0)
+    ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--no-counters", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on one GPU only (the hot path has no multi-GPU leg); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(0)
+
+    t_setup = time.perf_counter()
+    sc = synth.room()
+    scene = setup_room(sc, dev)
+    N = sc.n_points
+    K = len(sc.sigma)
+    P = 3 + 6 * K
+    S = sc.spp * (1 + K)
+    planes, tri = fipt.fipt_gen_points(scene, sc.cameras)
+    shading = torch.empty((P, N), dtype=torch.float32, device=dev)
+    R = 128
+    bmin, bmax = sc.bmin.tolist(), sc.bmax.tolist()
+    grid_gt = torch.from_numpy(synth.material_grid(R, seed=1003)).to(dev)
+    grid = torch.from_numpy(synth.material_grid(R, seed=1006)).to(dev)
+    plan = fipt.GridPlan(planes[0:3].cpu().numpy(), R, bmin, bmax)
+    # observations: factored render of the hidden material x (1 + 1% noise)
+    fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=shading)
+    mat_gt = fipt.fipt_grid_gather(grid_gt, bmin, bmax, planes[0:3].contiguous())
+    zeros = torch.zeros((3, N), dtype=torch.float32, device=dev)
+    _, _, lr_gt = fipt.fipt_render_loss(shading, mat_gt, zeros, sc.sigma, want_grad=False,
+                                        want_lr=True)
+    noise = torch.from_numpy(synth.observation_noise(N)).to(dev)
+    obs = (lr_gt * (1.0 + 0.01 * noise)).contiguous()
+    pos = planes[0:3].contiguous()
+    mat = torch.empty((5, N), dtype=torch.float32, device=dev)
+    grad_pts = torch.empty((5, N), dtype=torch.float32, device=dev)
+    grad_grid = torch.empty_like(grid)
+    loss_buf = torch.empty((fipt.LOSS_SLOTS,), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t_setup:.1f} s: {sc.n_tris} triangles, {N} points")
+
+    tm = Timer()
+
+    def step(timed):
+        if timed:
+            tm.mark("a")
+        fipt.fipt_gen_points(scene, sc.cameras, planes=planes, tri=tri)
+        if timed:
+            tm.mark("b")
+        fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=shading)
+        if timed:
+            tm.mark("c")
+        fipt.fipt_grid_gather(grid, bmin, bmax, pos, out=mat)
+        if timed:
+            tm.mark("d")
+        fipt.fipt_render_loss(shading, mat, obs, sc.sigma, loss_buf=loss_buf, grad=grad_pts)
+        if timed:
+            tm.mark("e")
+        plan.scatter(grad_pts, out=grad_grid)
+        if timed:
+            tm.mark("f")
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done")
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    t_pts = float(np.mean(tm.spans("a", "b")))
+    t_bake = float(np.mean(tm.spans("b", "c")))
+    t_gather = float(np.mean(tm.spans("c", "d")))
+    t_loss = float(np.mean(tm.spans("d", "e")))
+    t_scatter = float(np.mean(tm.spans("e", "f")))
+    loss_value = float(loss_buf[0].item())
+
+    trav = None
+    if not args.no_counters:
+        trav = traversal_bytes(scene, planes, tri, sc, shading)
+        log(f"traversal: {trav}")
+    bake_bytes = trav["bytes"] if trav else None
+    achieved = bake_bytes / (t_bake * 1e-3) / 1e9 if trav else None
+    # render-loss: Ld + all 12 level planes x 3 channels (a per-point
+    # roughness touches every level's cache lines) + material + Lgt + grad
+    loss_bytes_pt = 4 * (P + 5 + 3 + 5)
+    loss_gbs = N * loss_bytes_pt / (t_loss * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline: timing the oracle on a bounded sample ...")
+        cpu = cpu_baseline(sc, planes, tri, args.cpu_budget_s)
+        log(f"cpu baseline: {cpu}")
+
+    serving = None
+    if args.serving_requests > 0:
+        serving = run_serving(dev, args.serving_requests, args.serving_rate)
+
+    out = {
+        "metric": "Gsamples/s shading bake; factored loss+grad points/s; p50/p99 bake latency",
+        "value": N * S / (ms_step * 1e-3) / 1e9,
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "room: 189,440 triangles, 24 cameras x 320x240 = 1,843,200 points, "
+                               "128 spp per lobe, 6 roughness levels; 128^3 material grid",
+                   "points": N, "lobe_samples_per_point": S, "triangles": sc.n_tris,
+                   "parallelism": "single GPU"},
+        "breakdown_ms": {"points": t_pts, "bake": t_bake, "grid_gather": t_gather,
+                         "render_loss_fwd_bwd": t_loss, "grid_scatter": t_scatter},
+        "bake_gsamples_per_s": N * S / (t_bake * 1e-3) / 1e9,
+        "loss_grad_points_per_s": N / ((t_loss + t_gather + t_scatter) * 1e-3),
+        "render_loss_points_per_s": N / (t_loss * 1e-3),
+        "render_loss_gbs": loss_gbs,
+        "loss": loss_value,
+        "traversal": trav,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                     "kernel": "k_bake", "algorithmic_bytes_per_launch": bake_bytes},
+        "roofline_render_loss": {"bound": "hbm", "achieved": loss_gbs, "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": loss_gbs / PEAK_HBM_GBS,
+                                 "bytes_per_point": loss_bytes_pt},
+        "cpu_baseline": cpu,
+        "serving": serving,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

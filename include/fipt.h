@@ -1,0 +1,328 @@
+/*
+ * fipt.h -- C ABI of the MI355X (gfx950) hot path of Factorized Inverse Path
+ * Tracing (Wu, Zhu et al., "Factorized Inverse Path Tracing for Efficient and
+ * Accurate Material-Lighting Estimation", ICCV 2023).
+ *
+ * The library bakes the factorized shading terms of Eq. 6 (diffuse shading
+ * Ld and the two specular shadings Ls0, Ls1 of the Fresnel split, Eq. 7, at
+ * each roughness level of the lerp table, Eq. 8) for a set of surface
+ * points, with the stage-1 radiance query of Eq. 9 (incident radiance =
+ * radiance cache + per-triangle emission at the first hit along each
+ * sampled direction), and evaluates the factored re-render of Eq. 5 with the
+ * photometric loss of Eq. 2 / Eq. 15 and its gradient with respect to the
+ * per-point material (albedo a, roughness sigma, metallic m).
+ *
+ * Conventions shared by every call:
+ *   - Status: every call returns FIPT_OK (0) or a negative FIPT_E* code; the
+ *     text of the last error on the calling thread is fipt_last_error().
+ *     All arguments are validated before any work is enqueued.
+ *   - Memory: pointers documented "device" must point to memory of the
+ *     current HIP device (e.g. a torch CUDA tensor's data_ptr()); "host"
+ *     pointers are read during the call only.  Device buffers are borrowed:
+ *     the caller keeps them alive until the stream work has completed.
+ *   - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *     Every compute call is asynchronous on that stream.
+ *   - Layout: per-point data are structure-of-arrays float planes; plane k of
+ *     a buffer starts at base + k * stride elements.
+ *   - No call allocates device memory except fipt_scene_create,
+ *     fipt_grid_plan_create and fipt_server_create (and their set-up calls).
+ */
+#ifndef FIPT_H
+#define FIPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FIPT_OK 0
+#define FIPT_EINVAL (-1)     /* invalid argument                              */
+#define FIPT_ENOMEM (-2)     /* device or host allocation failed              */
+#define FIPT_EHIP (-3)       /* a HIP runtime call failed                      */
+#define FIPT_EBUSY (-4)      /* object still referenced by work in flight     */
+#define FIPT_EAGAIN (-5)     /* not ready yet (serving poll)                  */
+#define FIPT_ECANCELED (-6)  /* request cancelled or timed out                */
+
+#define FIPT_MAX_LEVELS 16   /* maximum number of roughness levels K          */
+#define FIPT_LOSS_SLOTS 2049 /* doubles in a render-loss result buffer        */
+
+/* Radiance cache kinds (fipt_scene_set_radiance). */
+#define FIPT_CACHE_TRIANGLE 0   /* one RGB value per triangle, [3][T]          */
+#define FIPT_CACHE_VERTEX 1     /* one RGB value per vertex, [3][V], linear
+                                   (barycentric) interpolation over triangles */
+
+/* Tone maps of the loss (fipt_render_loss). */
+#define FIPT_TONEMAP_NONE 0     /* Gamma(x) = x                                */
+#define FIPT_TONEMAP_LOG_SRGB 1 /* Gamma(x) = sRGB-OETF(log(1 + max(x, 0)))    */
+
+typedef struct fipt_scene_s* fipt_scene;
+typedef struct fipt_grid_plan_s* fipt_grid_plan;
+typedef struct fipt_server_s* fipt_server;
+
+/* Pinhole camera: rays leave `pos` through pixel centres; `fwd` is the view
+ * direction, `up` fixes the roll, `vfov_deg` the vertical field of view;
+ * square pixels; pixel (i, j) (j = 0 the top row) of camera c is point
+ * offset(c) + j * width + i, offsets accumulating width * height per camera. */
+typedef struct fipt_camera {
+    float pos[3];
+    float fwd[3];
+    float up[3];
+    float vfov_deg;
+    int32_t width;
+    int32_t height;
+} fipt_camera;
+
+/* Shading points (the (x, wo) pairs of Eq. 2), device SoA:
+ *   planes: 9 float planes px py pz nx ny nz ox oy oz -- position x, unit
+ *           geometric normal n facing the viewer, unit direction wo toward
+ *           the viewer;
+ *   tri:    index of the triangle x lies on, or -1 for "no surface" (the
+ *           bake writes zeros for such points);
+ *   n:      number of points; stride: elements between planes (>= n). */
+typedef struct fipt_points {
+    float* planes;
+    int32_t* tri;
+    int64_t n;
+    int64_t stride;
+} fipt_points;
+
+/* Baked shading terms, device SoA, 3 + 6K float planes:
+ *   plane 0..2                 Ld (r, g, b)
+ *   plane 3 + 3k + c           Ls0 at roughness level k, channel c
+ *   plane 3 + 3K + 3k + c      Ls1 at roughness level k, channel c */
+typedef struct fipt_shading {
+    float* planes;
+    int64_t stride;
+} fipt_shading;
+
+/* Bake parameters (Eq. 6 estimated by importance-sampled Monte Carlo):
+ *   spp_d     samples of the cosine lobe per point, 1..65536;
+ *   spp_s     samples of each GGX level per point, 1..65536;
+ *   n_levels  K, 1..FIPT_MAX_LEVELS; sigma[0..K-1] strictly increasing in
+ *             (0, 1]; the GGX width is alpha = sigma^2;
+ *   seed      Philox4x32-10 key; sample s of lobe l (0 = diffuse, 1 + k =
+ *             level k) of point p uses counter (p lo, p hi, l, s);
+ *   ray_eps   offset of ray origins along n, > 0, scene units;
+ *   flags     0. */
+typedef struct fipt_bake_params {
+    int32_t spp_d;
+    int32_t spp_s;
+    int32_t n_levels;
+    float sigma[FIPT_MAX_LEVELS];
+    uint64_t seed;
+    float ray_eps;
+    int32_t flags;
+} fipt_bake_params;
+
+/* Scene summary (fipt_scene_info). */
+typedef struct fipt_scene_info {
+    int64_t n_tris;
+    int64_t n_verts;
+    int64_t n_nodes;        /* BVH nodes                                     */
+    int64_t device_bytes;   /* resident device memory of the scene           */
+    int32_t max_depth;      /* deepest BVH node                              */
+    int32_t cache_kind;     /* FIPT_CACHE_* last set, -1 if none             */
+    float bmin[3];
+    float bmax[3];
+} fipt_scene_info;
+
+/* Per-launch traversal counters (fipt_bake_traversal_stats). */
+typedef struct fipt_traversal_stats {
+    uint64_t rays;          /* rays cast                                     */
+    uint64_t nodes;         /* BVH nodes fetched                             */
+    uint64_t tris;          /* triangles tested                              */
+    uint64_t hits;          /* rays that hit a surface                       */
+} fipt_traversal_stats;
+
+/* ---- library ----------------------------------------------------------- */
+
+/* Text of the last error on the calling thread (empty if none); valid until
+ * the next fipt_* call on that thread. */
+const char* fipt_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int32_t fipt_version(void);
+
+/* ---- scene (triangle mesh, BVH, radiance cache, emission) -------------- */
+
+/* Copy a triangle mesh (the scene geometry assumed given, Sec. 3), build a
+ * bounding-volume hierarchy on the host and upload it to `device`.
+ *   verts: host float [n_verts][3]; tris: host int32 [n_tris][3] vertex
+ *   indices (each in [0, n_verts)); 1 <= n_tris < 2^28.
+ * The scene owns its device memory until fipt_scene_destroy.  The radiance
+ * starts at zero (no cache, no emission).  FIPT_EINVAL on bad sizes or
+ * indices, FIPT_ENOMEM on allocation failure, FIPT_EHIP on HIP errors. */
+int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris,
+                      int64_t n_tris, int32_t device, void* stream, fipt_scene* out);
+
+/* Set the radiance the bake returns at a hit: radiance cache L' (Eq. 9) of
+ * kind FIPT_CACHE_TRIANGLE ([3][n_tris]) or FIPT_CACHE_VERTEX ([3][n_verts]),
+ * plus per-triangle emission Le ([3][n_tris], NULL = zero).  Both device
+ * float planes; read on `stream`, not retained. */
+int fipt_scene_set_radiance(fipt_scene s, int32_t cache_kind, const float* cache,
+                            int64_t n_cache, const float* emission, void* stream);
+
+/* Replace the per-triangle emission only (device [3][n_tris]); the cache set
+ * last is kept.  Used between re-bakes when emitters are re-estimated. */
+int fipt_scene_set_emission(fipt_scene s, const float* emission, void* stream);
+
+int fipt_scene_info_get(fipt_scene s, fipt_scene_info* out);
+
+/* Host-only diagnostic: build the BVH of a mesh exactly as
+ * fipt_scene_create does, without touching any GPU, and verify it: every
+ * triangle appears in exactly one leaf, every child box encloses the
+ * triangles below it, and no internal node is deeper than the traversal
+ * stack allows.  Writes the node count and the deepest internal node.
+ * FIPT_EINVAL (with the violated property in the error text) otherwise. */
+int fipt_bvh_validate(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                      int64_t* n_nodes, int32_t* max_depth);
+
+/* Release the scene's device memory.  FIPT_EBUSY while a serving request
+ * references it. */
+int fipt_scene_destroy(fipt_scene s);
+
+/* ---- shading points ---------------------------------------------------- */
+
+/* For every pixel centre of every camera (host array of n_cams, at most 48
+ * per call; offset out->planes / out->tri for more), cast the
+ * camera ray and write the closest hit as a shading point: position, face
+ * normal flipped toward the camera, wo = -direction, triangle index (-1 on a
+ * miss).  out->n must equal the total pixel count. */
+int fipt_gen_points(fipt_scene s, const fipt_camera* cams, int32_t n_cams,
+                    const fipt_points* out, void* stream);
+
+/* ---- the bake (Eq. 6, 7, 9) --------------------------------------------- */
+
+/* Bake Ld, Ls0[k], Ls1[k] for all points:
+ *   Ld    = mean over cosine-distributed directions of R,
+ *   Ls0_k = mean over GGX(alpha_k) half vectors m of R F0 w,
+ *   Ls1_k = mean over the same of R F1 w,
+ * where R = cache + emission at the first hit (0 on a miss),
+ * w = G(wi, wo) (wo.m) / ((n.wo)(n.m)) with separable Smith G, F1 =
+ * (1 - wi.m)^5, F0 = 1 - F1, and samples with wo.m <= 0 or n.wi <= 0 count
+ * as zero.  Points with tri < 0 or n.wo = 0 get zeros.  `out` must hold
+ * 3 + 6K planes of at least pts->n elements.  Asynchronous on `stream`. */
+int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
+              const fipt_shading* out, void* stream);
+
+/* Same bake, instrumented: also accumulates traversal counters into
+ * `stats_dev` (device, 4 uint64 in fipt_traversal_stats order, added to).
+ * Slower than fipt_bake; meant for measuring algorithmic bytes per ray. */
+int fipt_bake_traversal_stats(fipt_scene s, const fipt_points* pts,
+                              const fipt_bake_params* p, const fipt_shading* out,
+                              uint64_t* stats_dev, void* stream);
+
+/* ---- factored re-render and loss (Eq. 5, 8, 2 / 15) -------------------- */
+
+/* For n points, with material[5][mat_stride] = (a_r, a_g, a_b, sigma, m) and
+ * observed radiance Lgt[3][obs_stride] (device float planes):
+ *   kd = a (1 - m), ks = 0.04 (1 - m) + a m,
+ *   Ls*(sigma) = lerp between the two levels of sigma_host[0..K-1] that
+ *                bracket sigma (clamped outside, right-hand segment at an
+ *                interior knot), K >= 2, sigma strictly increasing;
+ *   Lr = kd Ld + ks Ls0(sigma) + Ls1(sigma);
+ *   loss = sum over points and channels of (Gamma(Lr) - Gamma(Lgt))^2.
+ * Writes loss (double, summed in a fixed order: bitwise reproducible) to
+ * loss_dev[0]; loss_dev must hold FIPT_LOSS_SLOTS doubles (the rest is
+ * scratch).  If grad_dev is not NULL, writes d loss / d material into
+ * grad_dev[5][grad_stride] (zero roughness gradient where clamped).  If
+ * Lr_dev is not NULL, writes Lr into Lr_dev[3][lr_stride]. */
+int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels,
+                     const float* sigma_host, const float* material, int64_t mat_stride,
+                     const float* observed, int64_t obs_stride, int32_t tonemap,
+                     double* loss_dev, float* grad_dev, int64_t grad_stride,
+                     float* Lr_dev, int64_t lr_stride, void* stream);
+
+/* out[i] = x[i] * factor_dev[0] for i < n (device float arrays, factor a
+ * device double): the chain rule step of the loss's backward pass, which
+ * scales the stored gradient by the incoming gradient without a host
+ * round trip.  x and out may alias. */
+int fipt_scale_by(const float* x, int64_t n, const double* factor_dev, float* out, void* stream);
+
+/* ---- trilinear material grid (stand-in for the paper's MLP_brdf, Eq. 14) */
+
+/* Values at n points pos[3][pos_stride] of a grid[channels][res][res][res]
+ * (x fastest) whose nodes sit at bmin + (i, j, k) (bmax - bmin) / (res - 1);
+ * positions are clamped onto the box.  out[channels][out_stride].
+ * 2 <= res <= 1024, 1 <= channels <= 8. */
+int fipt_grid_gather(const float* grid, int32_t channels, int32_t res,
+                     const float* bmin_host, const float* bmax_host, const float* pos,
+                     int64_t pos_stride, int64_t n, float* out, int64_t out_stride,
+                     void* stream);
+
+/* Adjoint of fipt_grid_gather for a fixed point set.  The plan sorts the
+ * points by grid cell once (host positions pos_host[3][n]) so the adjoint
+ * sums every node's contributions in a fixed order: results are bitwise
+ * reproducible, with no atomics.  The plan owns device memory. */
+int fipt_grid_plan_create(const float* pos_host, int64_t n, int32_t res,
+                          const float* bmin_host, const float* bmax_host,
+                          int32_t device, fipt_grid_plan* out);
+int fipt_grid_plan_destroy(fipt_grid_plan plan);
+
+/* grad_grid[channels][res^3] = sum over points of trilinear weight times
+ * grad_points[channels][gp_stride] (device), for the plan's points.
+ * Overwrites grad_grid entirely. */
+int fipt_grid_scatter(fipt_grid_plan plan, const float* grad_points, int32_t channels,
+                      int64_t gp_stride, float* grad_grid, void* stream);
+
+/* ---- serving: continuous batching of bake requests --------------------- */
+
+/* A server owns a device pool of `pool_bytes` for request outputs and a
+ * scheduler thread.  Requests are admitted first come first served while
+ * their output (3 + 6K planes x points x 4 bytes) fits in the pool and
+ * fewer than max_inflight are admitted; admitted requests are split into
+ * tiles and interleaved round-robin into persistent bake launches, so
+ * requests that arrive while others run join the next launch.  Each
+ * point's result is bitwise identical to fipt_bake with the same inputs. */
+int fipt_server_create(int32_t device, int64_t pool_bytes, int32_t max_inflight,
+                       int64_t samples_per_launch, fipt_server* out);
+
+/* Queue a request: bake `pts` (device, borrowed until completion) of scene
+ * `s` with params `p`.  Returns a ticket.  FIPT_EINVAL for invalid requests
+ * or a request larger than the whole pool. */
+int fipt_server_submit(fipt_server srv, fipt_scene s, const fipt_points* pts,
+                       const fipt_bake_params* p, uint64_t* ticket);
+
+/* FIPT_OK when the request completed (the result is ready), FIPT_EAGAIN
+ * while pending, FIPT_ECANCELED if cancelled. */
+int fipt_server_poll(fipt_server srv, uint64_t ticket);
+
+/* Block until completion or timeout_us (< 0 = forever); FIPT_EAGAIN on
+ * timeout. */
+int fipt_server_wait(fipt_server srv, uint64_t ticket, int64_t timeout_us);
+
+/* Result view of a completed request: shading planes in the server pool
+ * (device), valid until fipt_server_release.  Timestamps in microseconds of
+ * the server clock: submit, admit (output space granted) and completion. */
+int fipt_server_result(fipt_server srv, uint64_t ticket, fipt_shading* out,
+                       int64_t* t_submit_us, int64_t* t_admit_us, int64_t* t_done_us);
+
+/* Return a completed request's pool space. */
+int fipt_server_release(fipt_server srv, uint64_t ticket);
+
+/* Cancel a queued (not yet admitted) request; FIPT_EBUSY once admitted. */
+int fipt_server_cancel(fipt_server srv, uint64_t ticket);
+
+/* Counters: launches, tiles, samples baked, requests completed, pool bytes
+ * in use, requests queued (not admitted), requests in flight. */
+typedef struct fipt_server_stats {
+    int64_t launches;
+    int64_t tiles;
+    int64_t samples;
+    int64_t completed;
+    int64_t pool_in_use;
+    int64_t queued;
+    int64_t inflight;
+} fipt_server_stats;
+int fipt_server_stats_get(fipt_server srv, fipt_server_stats* out);
+
+/* Stop accepting work, finish what is admitted, free the pool. */
+int fipt_server_destroy(fipt_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIPT_H */

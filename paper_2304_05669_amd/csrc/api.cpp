@@ -1,0 +1,381 @@
+// C ABI of libfipt (declared in include/fipt.h): argument validation,
+// object lifetimes and kernel launches.  Every argument is checked before
+// anything is enqueued; errors are reported through return codes and the
+// calling thread's last-error text.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "fipt_internal.hpp"
+
+namespace fipt {
+
+namespace {
+thread_local char g_err[1024] = {0};
+}
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+}  // namespace fipt
+
+using namespace fipt;
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? FIPT_ENOMEM : FIPT_EHIP, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                              \
+    } while (0)
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    int rc = FIPT_OK;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) {
+            hipError_t e = hipSetDevice(dev);
+            if (e != hipSuccess) rc = fail(FIPT_EHIP, "hipSetDevice(%d): %s", dev, hipGetErrorString(e));
+        }
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+int dev_alloc(T** p, size_t count, int64_t* bytes) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * std::max<size_t>(count, 1));
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? FIPT_ENOMEM : FIPT_EHIP, "hipMalloc(%zu): %s",
+                    sizeof(T) * count, hipGetErrorString(e));
+    if (bytes) *bytes += (int64_t)(sizeof(T) * count);
+    return FIPT_OK;
+}
+
+void scene_free(fipt_scene s) {
+    if (!s) return;
+    if (s->d_nodes) (void)hipFree(s->d_nodes);
+    if (s->d_tris) (void)hipFree(s->d_tris);
+    if (s->d_rad) (void)hipFree(s->d_rad);
+    if (s->d_order) (void)hipFree(s->d_order);
+    if (s->d_tri_idx) (void)hipFree(s->d_tri_idx);
+    delete s;
+}
+
+int check_points(const fipt_points* pts, const char* name) {
+    if (!pts) return fail(FIPT_EINVAL, "%s is NULL", name);
+    if (!pts->planes || !pts->tri) return fail(FIPT_EINVAL, "%s has a NULL plane pointer", name);
+    if (pts->n < 1) return fail(FIPT_EINVAL, "%s->n must be >= 1, got %lld", name, (long long)pts->n);
+    if (pts->stride < pts->n)
+        return fail(FIPT_EINVAL, "%s->stride (%lld) < n (%lld)", name, (long long)pts->stride,
+                    (long long)pts->n);
+    return FIPT_OK;
+}
+
+}  // namespace
+
+namespace fipt {
+
+int check_bake_params(const fipt_bake_params* p) {
+    if (!p) return fail(FIPT_EINVAL, "params is NULL");
+    if (p->spp_d < 1 || p->spp_d > 65536)
+        return fail(FIPT_EINVAL, "spp_d must be in [1, 65536], got %d", p->spp_d);
+    if (p->spp_s < 1 || p->spp_s > 65536)
+        return fail(FIPT_EINVAL, "spp_s must be in [1, 65536], got %d", p->spp_s);
+    if (p->n_levels < 1 || p->n_levels > FIPT_MAX_LEVELS)
+        return fail(FIPT_EINVAL, "n_levels must be in [1, %d], got %d", FIPT_MAX_LEVELS, p->n_levels);
+    for (int k = 0; k < p->n_levels; ++k) {
+        const float s = p->sigma[k];
+        if (!(s > 0.0f && s <= 1.0f)) return fail(FIPT_EINVAL, "sigma[%d] = %g outside (0, 1]", k, s);
+        if (k > 0 && !(s > p->sigma[k - 1]))
+            return fail(FIPT_EINVAL, "sigma must be strictly increasing (sigma[%d] = %g)", k, s);
+    }
+    if (!(p->ray_eps > 0.0f) || !std::isfinite(p->ray_eps))
+        return fail(FIPT_EINVAL, "ray_eps must be positive and finite, got %g", p->ray_eps);
+    if (p->flags != 0) return fail(FIPT_EINVAL, "flags must be 0");
+    return FIPT_OK;
+}
+
+BakeLaunch make_bake_launch(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
+                            const fipt_shading* out) {
+    BakeLaunch b;
+    std::memset(&b, 0, sizeof(b));
+    b.sc = s->view();
+    b.pts = pts->planes;
+    b.ptri = pts->tri;
+    b.pts_stride = pts->stride;
+    b.n = pts->n;
+    b.p_offset = 0;
+    b.out = out->planes;
+    b.out_stride = out->stride;
+    b.spp_d = p->spp_d;
+    b.spp_s = p->spp_s;
+    b.K = p->n_levels;
+    for (int k = 0; k < FIPT_MAX_LEVELS; ++k) b.sigma[k] = k < p->n_levels ? p->sigma[k] : 1.0f;
+    b.seed = p->seed;
+    b.eps = p->ray_eps;
+    return b;
+}
+
+}  // namespace fipt
+
+extern "C" {
+
+const char* fipt_last_error(void) { return g_err; }
+
+int32_t fipt_version(void) { return 10000; }
+
+int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                      int32_t device, void* stream, fipt_scene* out) {
+    clear_error();
+    if (!out) return fail(FIPT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!verts || !tris) return fail(FIPT_EINVAL, "verts/tris is NULL");
+    if (n_verts < 3) return fail(FIPT_EINVAL, "n_verts must be >= 3, got %lld", (long long)n_verts);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(FIPT_EHIP, "no HIP device available");
+    if (device < 0 || device >= ndev)
+        return fail(FIPT_EINVAL, "device %d outside [0, %d)", device, ndev);
+    HostBvh bvh;
+    int rc = build_bvh(verts, n_verts, tris, n_tris, &bvh);
+    if (rc) return rc;
+    DeviceGuard g(device);
+    if (g.rc) return g.rc;
+    fipt_scene s = new fipt_scene_s();
+    s->device = device;
+    s->n_tris = n_tris;
+    s->n_verts = n_verts;
+    s->n_nodes = (int64_t)bvh.nodes.size();
+    s->max_depth = bvh.max_depth;
+    for (int k = 0; k < 3; ++k) {
+        s->bmin[k] = bvh.bmin[k];
+        s->bmax[k] = bvh.bmax[k];
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = dev_alloc(&s->d_nodes, bvh.nodes.size(), &s->bytes)) ||
+        (rc = dev_alloc(&s->d_tris, bvh.tris.size(), &s->bytes)) ||
+        (rc = dev_alloc(&s->d_rad, bvh.tris.size(), &s->bytes)) ||
+        (rc = dev_alloc(&s->d_order, bvh.order.size(), &s->bytes)) ||
+        (rc = dev_alloc(&s->d_tri_idx, (size_t)(3 * n_tris), &s->bytes))) {
+        scene_free(s);
+        return rc;
+    }
+    hipError_t e = hipMemcpyAsync(s->d_nodes, bvh.nodes.data(), sizeof(BvhNode) * bvh.nodes.size(),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_tris, bvh.tris.data(), sizeof(TriGeom) * bvh.tris.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_order, bvh.order.data(), sizeof(int32_t) * bvh.order.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_tri_idx, tris, sizeof(int32_t) * 3 * n_tris, hipMemcpyHostToDevice,
+                           st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vectors go out of scope
+    if (e != hipSuccess) {
+        scene_free(s);
+        return fail(FIPT_EHIP, "scene upload: %s", hipGetErrorString(e));
+    }
+    rc = launch_set_radiance(s->d_rad, s->d_order, s->d_tri_idx, n_tris, FIPT_CACHE_TRIANGLE,
+                             nullptr, n_tris, nullptr, stream);
+    if (rc) {
+        scene_free(s);
+        return rc;
+    }
+    *out = s;
+    return FIPT_OK;
+}
+
+int fipt_scene_set_radiance(fipt_scene s, int32_t cache_kind, const float* cache, int64_t n_cache,
+                            const float* emission, void* stream) {
+    clear_error();
+    if (!s) return fail(FIPT_EINVAL, "scene is NULL");
+    if (cache_kind != FIPT_CACHE_TRIANGLE && cache_kind != FIPT_CACHE_VERTEX)
+        return fail(FIPT_EINVAL, "unknown cache kind %d", cache_kind);
+    if (!cache) return fail(FIPT_EINVAL, "cache is NULL");
+    const int64_t want = cache_kind == FIPT_CACHE_VERTEX ? s->n_verts : s->n_tris;
+    if (n_cache != want)
+        return fail(FIPT_EINVAL, "cache has %lld entries, scene needs %lld", (long long)n_cache,
+                    (long long)want);
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    int rc = launch_set_radiance(s->d_rad, s->d_order, s->d_tri_idx, s->n_tris, cache_kind, cache,
+                                 n_cache, emission, stream);
+    if (rc == FIPT_OK) s->cache_kind = cache_kind;
+    return rc;
+}
+
+int fipt_scene_set_emission(fipt_scene s, const float* emission, void* stream) {
+    clear_error();
+    if (!s) return fail(FIPT_EINVAL, "scene is NULL");
+    if (!emission) return fail(FIPT_EINVAL, "emission is NULL");
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    return launch_set_emission(s->d_rad, s->d_order, s->n_tris, emission, stream);
+}
+
+int fipt_scene_info_get(fipt_scene s, fipt_scene_info* out) {
+    clear_error();
+    if (!s || !out) return fail(FIPT_EINVAL, "scene/out is NULL");
+    out->n_tris = s->n_tris;
+    out->n_verts = s->n_verts;
+    out->n_nodes = s->n_nodes;
+    out->device_bytes = s->bytes;
+    out->max_depth = s->max_depth;
+    out->cache_kind = s->cache_kind;
+    for (int k = 0; k < 3; ++k) {
+        out->bmin[k] = s->bmin[k];
+        out->bmax[k] = s->bmax[k];
+    }
+    return FIPT_OK;
+}
+
+int fipt_scene_destroy(fipt_scene s) {
+    clear_error();
+    if (!s) return FIPT_OK;
+    if (s->refs.load() > 0) return fail(FIPT_EBUSY, "scene referenced by %d serving requests", s->refs.load());
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    (void)hipDeviceSynchronize();
+    scene_free(s);
+    return FIPT_OK;
+}
+
+int fipt_gen_points(fipt_scene s, const fipt_camera* cams, int32_t n_cams, const fipt_points* out,
+                    void* stream) {
+    clear_error();
+    if (!s) return fail(FIPT_EINVAL, "scene is NULL");
+    if (!cams || n_cams < 1 || n_cams > kMaxCameras)
+        return fail(FIPT_EINVAL, "n_cams must be in [1, %d], got %d", kMaxCameras, n_cams);
+    int rc = check_points(out, "out");
+    if (rc) return rc;
+    std::vector<int64_t> offs(n_cams + 1, 0);
+    for (int c = 0; c < n_cams; ++c) {
+        const fipt_camera& k = cams[c];
+        if (k.width < 1 || k.height < 1)
+            return fail(FIPT_EINVAL, "camera %d has size %dx%d", c, k.width, k.height);
+        if (!(k.vfov_deg > 0.0f && k.vfov_deg < 180.0f))
+            return fail(FIPT_EINVAL, "camera %d vfov %g outside (0, 180)", c, k.vfov_deg);
+        const float f2 = k.fwd[0] * k.fwd[0] + k.fwd[1] * k.fwd[1] + k.fwd[2] * k.fwd[2];
+        const float cx = k.fwd[1] * k.up[2] - k.fwd[2] * k.up[1];
+        const float cy = k.fwd[2] * k.up[0] - k.fwd[0] * k.up[2];
+        const float cz = k.fwd[0] * k.up[1] - k.fwd[1] * k.up[0];
+        if (!(f2 > 0.0f) || !(cx * cx + cy * cy + cz * cz > 0.0f))
+            return fail(FIPT_EINVAL, "camera %d: fwd is zero or parallel to up", c);
+        offs[c + 1] = offs[c] + (int64_t)k.width * k.height;
+    }
+    if (offs[n_cams] != out->n)
+        return fail(FIPT_EINVAL, "cameras have %lld pixels, out->n is %lld", (long long)offs[n_cams],
+                    (long long)out->n);
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    CameraTable tab;
+    std::memset(&tab, 0, sizeof(tab));
+    tab.n = n_cams;
+    for (int c = 0; c < n_cams; ++c) tab.cam[c] = cams[c];
+    for (int c = 0; c <= n_cams; ++c) tab.offset[c] = offs[c];
+    return launch_gen_points(s->view(), tab, *out, stream);
+}
+
+static int bake_common(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
+                       const fipt_shading* out, uint64_t* stats, void* stream) {
+    clear_error();
+    if (!s) return fail(FIPT_EINVAL, "scene is NULL");
+    int rc = check_points(pts, "pts");
+    if (rc) return rc;
+    if ((rc = check_bake_params(p))) return rc;
+    if (!out || !out->planes) return fail(FIPT_EINVAL, "out is NULL");
+    if (out->stride < pts->n)
+        return fail(FIPT_EINVAL, "out->stride (%lld) < n (%lld)", (long long)out->stride,
+                    (long long)pts->n);
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    BakeLaunch b = make_bake_launch(s, pts, p, out);
+    return launch_bake(b, stats, stream);
+}
+
+int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
+              const fipt_shading* out, void* stream) {
+    return bake_common(s, pts, p, out, nullptr, stream);
+}
+
+int fipt_bake_traversal_stats(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
+                              const fipt_shading* out, uint64_t* stats_dev, void* stream) {
+    if (!stats_dev) {
+        clear_error();
+        return fail(FIPT_EINVAL, "stats_dev is NULL");
+    }
+    return bake_common(s, pts, p, out, stats_dev, stream);
+}
+
+int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels, const float* sigma_host,
+                     const float* material, int64_t mat_stride, const float* observed,
+                     int64_t obs_stride, int32_t tonemap, double* loss_dev, float* grad_dev,
+                     int64_t grad_stride, float* Lr_dev, int64_t lr_stride, void* stream) {
+    clear_error();
+    if (!sh || !sh->planes) return fail(FIPT_EINVAL, "shading is NULL");
+    if (n < 1) return fail(FIPT_EINVAL, "n must be >= 1, got %lld", (long long)n);
+    if (n_levels < 2 || n_levels > FIPT_MAX_LEVELS)
+        return fail(FIPT_EINVAL, "n_levels must be in [2, %d], got %d", FIPT_MAX_LEVELS, n_levels);
+    if (!sigma_host) return fail(FIPT_EINVAL, "sigma is NULL");
+    for (int k = 0; k < n_levels; ++k) {
+        if (!std::isfinite(sigma_host[k])) return fail(FIPT_EINVAL, "sigma[%d] is not finite", k);
+        if (k > 0 && !(sigma_host[k] > sigma_host[k - 1]))
+            return fail(FIPT_EINVAL, "sigma must be strictly increasing");
+    }
+    if (!material || !observed || !loss_dev)
+        return fail(FIPT_EINVAL, "material/observed/loss is NULL");
+    if (sh->stride < n || mat_stride < n || obs_stride < n)
+        return fail(FIPT_EINVAL, "a stride is smaller than n");
+    if (grad_dev && grad_stride < n) return fail(FIPT_EINVAL, "grad_stride < n");
+    if (Lr_dev && lr_stride < n) return fail(FIPT_EINVAL, "lr_stride < n");
+    if (tonemap != FIPT_TONEMAP_NONE && tonemap != FIPT_TONEMAP_LOG_SRGB)
+        return fail(FIPT_EINVAL, "unknown tonemap %d", tonemap);
+    return launch_render_loss(sh->planes, sh->stride, n, n_levels, sigma_host, material, mat_stride,
+                              observed, obs_stride, tonemap, loss_dev, grad_dev, grad_stride,
+                              Lr_dev, lr_stride, stream);
+}
+
+int fipt_scale_by(const float* x, int64_t n, const double* factor_dev, float* out, void* stream) {
+    clear_error();
+    if (!x || !factor_dev || !out) return fail(FIPT_EINVAL, "NULL argument");
+    if (n < 0) return fail(FIPT_EINVAL, "n must be >= 0");
+    if (n == 0) return FIPT_OK;
+    return launch_scale_by(x, n, factor_dev, out, stream);
+}
+
+int fipt_grid_gather(const float* grid, int32_t channels, int32_t res, const float* bmin_host,
+                     const float* bmax_host, const float* pos, int64_t pos_stride, int64_t n,
+                     float* out, int64_t out_stride, void* stream) {
+    clear_error();
+    if (!grid || !pos || !out || !bmin_host || !bmax_host) return fail(FIPT_EINVAL, "NULL argument");
+    if (channels < 1 || channels > 8) return fail(FIPT_EINVAL, "channels must be in [1, 8]");
+    if (res < 2 || res > 1024) return fail(FIPT_EINVAL, "res must be in [2, 1024]");
+    if (n < 1) return fail(FIPT_EINVAL, "n must be >= 1");
+    if (pos_stride < n || out_stride < n) return fail(FIPT_EINVAL, "a stride is smaller than n");
+    for (int k = 0; k < 3; ++k)
+        if (!(bmax_host[k] > bmin_host[k])) return fail(FIPT_EINVAL, "empty grid box on axis %d", k);
+    return launch_grid_gather(grid, channels, res, bmin_host, bmax_host, pos, pos_stride, n, out,
+                              out_stride, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,384 @@
+// HIP kernels of the bake (Eq. 6 with the Fresnel split of Eq. 7 and the
+// stage-1 radiance query of Eq. 9) and of shading-point generation, for
+// gfx950.
+//
+// Mapping: one wavefront bakes one point; its 64 lanes take 64 consecutive
+// (lobe, sample) pairs of that point, flattened over the diffuse lobe and
+// the K specular levels, so the lanes of a wave share the ray origin and
+// start traversal on the same nodes.  After each chunk of 64 samples the
+// contributions of every lobe present in the chunk are summed by a fixed
+// xor butterfly; each lane keeps the running sums of two accumulator slots
+// in registers.  The summation order depends only on the sample counts, so
+// a point's result is bitwise independent of which launch, tile or batch it
+// was baked in.
+//
+// Traversal stacks live in LDS, 32 entries per lane, lane-minor.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "device.hpp"
+#include "fipt_internal.hpp"
+
+namespace fipt {
+namespace {
+
+using dev::V3;
+using dev::v3;
+
+constexpr int kBlock = 256;             // 4 wavefronts
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ int lobe_of(int q, int spp_d, int spp_s) {
+    return q < spp_d ? 0 : 1 + (q - spp_d) / spp_s;
+}
+
+// Output plane of accumulator slot j: slot 0..2 -> Ld; slot 3 + 6k + c ->
+// Ls0 level k; slot 3 + 6k + 3 + c -> Ls1 level k.
+__device__ __forceinline__ int slot_plane(int j, int K) {
+    if (j < 3) return j;
+    const int r = j - 3, k = r / 6, c = r - 6 * k;
+    return c < 3 ? 3 + 3 * k + c : 3 + 3 * K + 3 * k + (c - 3);
+}
+
+// Bake point p of job b with the calling wavefront.
+template <bool COUNT>
+__device__ __forceinline__ void bake_point(const BakeLaunch& b, int64_t p, int lane,
+                                           int32_t* stack, uint32_t& n_rays, uint32_t& n_nodes,
+                                           uint32_t& n_tris, uint32_t& n_hits) {
+    const int K = b.K;
+    const int P = 3 + 6 * K;
+    const int64_t ps = b.pts_stride;
+    const int32_t tri = b.ptri[p];
+    V3 x = v3(b.pts[p], b.pts[ps + p], b.pts[2 * ps + p]);
+    V3 n = v3(b.pts[3 * ps + p], b.pts[4 * ps + p], b.pts[5 * ps + p]);
+    const V3 wo = v3(b.pts[6 * ps + p], b.pts[7 * ps + p], b.pts[8 * ps + p]);
+    float cos_o = dev::dot(n, wo);
+    if (tri >= 0 && cos_o < 0.0f) {
+        n = v3(-n.x, -n.y, -n.z);
+        cos_o = -cos_o;
+    }
+    const int64_t os = b.out_stride;
+    if (!(tri >= 0 && cos_o > 0.0f)) {
+        for (int j = lane; j < P; j += 64) b.out[(int64_t)j * os + p] = 0.0f;
+        return;
+    }
+    V3 ft, fb;
+    dev::make_frame(n, ft, fb);
+    const V3 o = x + b.eps * n;
+    const int64_t rng_p = p + b.p_offset;
+    const int spp_d = b.spp_d, spp_s = b.spp_s;
+    const int S = spp_d + K * spp_s;
+    float acc_a = 0.0f, acc_b = 0.0f;   // slots lane and 64 + lane
+    for (int q0 = 0; q0 < S; q0 += 64) {
+        const int q = q0 + lane;
+        const bool active = q < S;
+        const int lobe = active ? lobe_of(q, spp_d, spp_s) : -1;
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f, c4 = 0.0f, c5 = 0.0f;
+        V3 wi = v3(0.0f, 0.0f, 1.0f);
+        float w = 0.0f, F1 = 0.0f;
+        bool shoot = false;
+        if (active) {
+            const int s = lobe == 0 ? q : (q - spp_d) - (lobe - 1) * spp_s;
+            float xi1, xi2;
+            dev::lobe_uniforms(b.seed, rng_p, lobe, s, xi1, xi2);
+            float sp_, cp_;
+            sincospif(2.0f * xi2, &sp_, &cp_);
+            if (lobe == 0) {
+                // cosine-weighted direction; estimator weight 1
+                const float r = sqrtf(xi1);
+                wi = dev::to_world(ft, fb, n, r * cp_, r * sp_, sqrtf(1.0f - xi1));
+                w = 1.0f;
+                shoot = true;
+            } else {
+                // GGX half vector, density D(m)(n.m), alpha = sigma^2
+                const float sg = b.sigma[lobe - 1];
+                const float alpha = sg * sg;
+                const float a2 = alpha * alpha;
+                const float tan2 = a2 * xi1 / (1.0f - xi1);
+                const float cos_m = 1.0f / sqrtf(1.0f + tan2);
+                const float sin_m = sqrtf(tan2) * cos_m;   // accurate for tiny tilts
+                const V3 m = dev::to_world(ft, fb, n, sin_m * cp_, sin_m * sp_, cos_m);
+                const float om = dev::dot(wo, m);
+                if (om > 0.0f) {
+                    wi = (2.0f * om) * m - wo;
+                    const float ci = dev::dot(n, wi);
+                    if (ci > 0.0f) {
+                        const float G = dev::smith_g1(a2, ci) * dev::smith_g1(a2, cos_o);
+                        w = G * om / (cos_o * cos_m);
+                        const float f = 1.0f - om;
+                        const float f2 = f * f;
+                        F1 = f2 * f2 * f;
+                        shoot = true;
+                    }
+                }
+            }
+        }
+        dev::Hit h;
+        h.leaf = -1;
+        h.u = h.v = 0.0f;
+        if (shoot) {
+            if (COUNT) ++n_rays;
+            h = dev::trace<COUNT>(b.sc, o, wi, stack, kBlock, n_nodes, n_tris);
+            if (COUNT && h.leaf >= 0) ++n_hits;
+            const V3 R = dev::radiance(b.sc, h);
+            if (lobe == 0) {
+                c0 = R.x;
+                c1 = R.y;
+                c2 = R.z;
+            } else {
+                const float w0 = w * (1.0f - F1), w1 = w * F1;
+                c0 = R.x * w0;
+                c1 = R.y * w0;
+                c2 = R.z * w0;
+                c3 = R.x * w1;
+                c4 = R.y * w1;
+                c5 = R.z * w1;
+            }
+        }
+        // reduce every lobe present in this chunk
+        const int l_first = lobe_of(q0, spp_d, spp_s);
+        const int l_last = lobe_of(min(q0 + 63, S - 1), spp_d, spp_s);
+        for (int l = l_first; l <= l_last; ++l) {
+            const bool mine = lobe == l;
+            const float r0 = dev::wave_sum(mine ? c0 : 0.0f);
+            const float r1 = dev::wave_sum(mine ? c1 : 0.0f);
+            const float r2 = dev::wave_sum(mine ? c2 : 0.0f);
+            const int base = l == 0 ? 0 : 3 + 6 * (l - 1);
+            float r3 = 0.0f, r4 = 0.0f, r5 = 0.0f;
+            if (l > 0) {
+                r3 = dev::wave_sum(mine ? c3 : 0.0f);
+                r4 = dev::wave_sum(mine ? c4 : 0.0f);
+                r5 = dev::wave_sum(mine ? c5 : 0.0f);
+            }
+            const int na = lane - base, nb = lane + 64 - base;
+            const float ra = na == 0 ? r0 : na == 1 ? r1 : na == 2 ? r2 : na == 3 ? r3 : na == 4 ? r4 : r5;
+            const float rb = nb == 0 ? r0 : nb == 1 ? r1 : nb == 2 ? r2 : nb == 3 ? r3 : nb == 4 ? r4 : r5;
+            const int width = l == 0 ? 3 : 6;
+            if (na >= 0 && na < width) acc_a += ra;
+            if (nb >= 0 && nb < width) acc_b += rb;
+        }
+    }
+    if (lane < P) {
+        const float cnt = lane < 3 ? (float)spp_d : (float)spp_s;
+        b.out[(int64_t)slot_plane(lane, K) * os + p] = acc_a / cnt;
+    }
+    if (64 + lane < P) {
+        b.out[(int64_t)slot_plane(64 + lane, K) * os + p] = acc_b / (float)spp_s;
+    }
+}
+
+// Logical wavefront index with workgroups of one XCD made contiguous:
+// the dispatcher places workgroup i on XCD i % 8, so consecutive points go
+// to one XCD's L2.
+__device__ __forceinline__ int64_t xcd_wave(int lane_wave) {
+    const int64_t g = gridDim.x, i = blockIdx.x;
+    int64_t lb;
+    if ((g & 7) == 0) {
+        lb = (i & 7) * (g >> 3) + (i >> 3);
+    } else {
+        lb = i;
+    }
+    return lb * kWaves + lane_wave;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_bake(BakeLaunch b, uint64_t* stats) {
+    __shared__ int32_t s_stack[kStackSize * kBlock];
+    const int lane = threadIdx.x & 63;
+    int32_t* stack = s_stack + threadIdx.x;
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    uint32_t n_rays = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
+    for (int64_t p = xcd_wave(threadIdx.x >> 6); p < b.n; p += nw) {
+        bake_point<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
+    }
+    if (COUNT) {
+        // lane counters -> wave totals -> one 64-bit atomic per wave
+        uint64_t v[4] = {n_rays, n_nodes, n_tris, n_hits};
+        for (int k = 0; k < 4; ++k) {
+            uint64_t x = v[k];
+            for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+            if (lane == 0) atomicAdd((unsigned long long*)(stats + k), (unsigned long long)x);
+        }
+    }
+}
+
+// Serving: persistent bake over a list of tiles; each wavefront takes the
+// next point of the launch (points of all tiles enumerated in order) from a
+// counter until none is left.
+__global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, int32_t n_tiles,
+                                                       int32_t* counter) {
+    __shared__ int32_t s_stack[kStackSize * kBlock];
+    const int lane = threadIdx.x & 63;
+    int32_t* stack = s_stack + threadIdx.x;
+    uint32_t a = 0, bb = 0, c = 0, d = 0;
+    const int64_t total = tiles[n_tiles - 1].first + tiles[n_tiles - 1].job.n;
+    while (true) {
+        int32_t grab = 0;
+        if (lane == 0) grab = atomicAdd(counter, 1);
+        grab = __shfl(grab, 0, 64);
+        if ((int64_t)grab >= total) break;
+        // last tile whose first point is <= grab
+        int lo = 0, hi = n_tiles - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tiles[mid].first <= grab) lo = mid;
+            else hi = mid - 1;
+        }
+        bake_point<false>(tiles[lo].job, grab - tiles[lo].first, lane, stack, a, bb, c, d);
+    }
+}
+
+__global__ void k_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_idx,
+                               int64_t T, int kind, const float* cache, int64_t n_cache,
+                               const float* emission) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T) return;
+    const int32_t f = order[i];
+    float c[3][3];
+    for (int k = 0; k < 3; ++k) {
+        const int64_t src = kind == FIPT_CACHE_VERTEX ? (int64_t)tri_idx[3 * (int64_t)f + k] : f;
+        for (int ch = 0; ch < 3; ++ch) c[k][ch] = cache ? cache[ch * n_cache + src] : 0.0f;
+    }
+    TriRad r;
+    r.c0r = c[0][0]; r.c0g = c[0][1]; r.c0b = c[0][2];
+    r.c1r = c[1][0]; r.c1g = c[1][1]; r.c1b = c[1][2];
+    r.c2r = c[2][0]; r.c2g = c[2][1]; r.c2b = c[2][2];
+    r.ler = emission ? emission[f] : 0.0f;
+    r.leg = emission ? emission[T + f] : 0.0f;
+    r.leb = emission ? emission[2 * T + f] : 0.0f;
+    rad[i] = r;
+}
+
+__global__ void k_set_emission(TriRad* rad, const int32_t* order, int64_t T,
+                               const float* emission) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T) return;
+    const int32_t f = order[i];
+    rad[i].ler = emission[f];
+    rad[i].leg = emission[T + f];
+    rad[i].leb = emission[2 * T + f];
+}
+
+// One thread per pixel centre: camera ray -> closest hit -> shading point.
+__global__ __launch_bounds__(kBlock) void k_gen_points(DeviceScene sc, CameraTable cams,
+                                                       fipt_points out) {
+    __shared__ int32_t s_stack[kStackSize * kBlock];
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= out.n) return;
+    int c = 0;
+    while (c + 1 < cams.n && p >= cams.offset[c + 1]) ++c;
+    const fipt_camera cam = cams.cam[c];
+    const int64_t local = p - cams.offset[c];
+    const int W = cam.width, H = cam.height;
+    const int i = (int)(local % W), j = (int)(local / W);
+    V3 f = v3(cam.fwd[0], cam.fwd[1], cam.fwd[2]);
+    f = (1.0f / sqrtf(dev::dot(f, f))) * f;
+    V3 r = dev::cross(f, v3(cam.up[0], cam.up[1], cam.up[2]));
+    r = (1.0f / sqrtf(dev::dot(r, r))) * r;
+    const V3 u = dev::cross(r, f);
+    const float th = tanf(0.5f * cam.vfov_deg * 0.017453292519943295f);
+    const float aspect = (float)W / (float)H;
+    const float sx = (2.0f * ((float)i + 0.5f) / (float)W - 1.0f) * th * aspect;
+    const float sy = (1.0f - 2.0f * ((float)j + 0.5f) / (float)H) * th;
+    V3 d = f + sx * r + sy * u;
+    d = (1.0f / sqrtf(dev::dot(d, d))) * d;
+    const V3 o = v3(cam.pos[0], cam.pos[1], cam.pos[2]);
+    uint32_t z0 = 0, z1 = 0;
+    const dev::Hit h = dev::trace<false>(sc, o, d, s_stack + threadIdx.x, kBlock, z0, z1);
+    const int64_t s = out.stride;
+    float* P = out.planes;
+    if (h.leaf < 0) {
+        for (int k = 0; k < 9; ++k) P[k * s + p] = 0.0f;
+        out.tri[p] = -1;
+        return;
+    }
+    const float4* tp = reinterpret_cast<const float4*>(sc.tris + h.leaf);
+    const float4 t0 = tp[0], t1 = tp[1], t2 = tp[2];
+    V3 nn = dev::cross(v3(t1.x, t1.y, t1.z), v3(t2.x, t2.y, t2.z));
+    nn = (1.0f / sqrtf(dev::dot(nn, nn))) * nn;
+    if (dev::dot(nn, d) > 0.0f) nn = v3(-nn.x, -nn.y, -nn.z);
+    const V3 x = o + h.t * d;
+    P[0 * s + p] = x.x;
+    P[1 * s + p] = x.y;
+    P[2 * s + p] = x.z;
+    P[3 * s + p] = nn.x;
+    P[4 * s + p] = nn.y;
+    P[5 * s + p] = nn.z;
+    P[6 * s + p] = -d.x;
+    P[7 * s + p] = -d.y;
+    P[8 * s + p] = -d.z;
+    out.tri[p] = __float_as_int(t0.w);
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FIPT_EHIP, "%s launch failed: %s", what, hipGetErrorString(e));
+    return FIPT_OK;
+}
+
+int device_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
+}  // namespace
+
+int launch_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_idx, int64_t n_tris,
+                        int cache_kind, const float* cache, int64_t n_cache,
+                        const float* emission, void* stream) {
+    const int64_t blocks = (n_tris + 255) / 256;
+    hipLaunchKernelGGL(k_set_radiance, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       rad, order, tri_idx, n_tris, cache_kind, cache, n_cache, emission);
+    return check_launch("set_radiance");
+}
+
+int launch_set_emission(TriRad* rad, const int32_t* order, int64_t n_tris, const float* emission,
+                        void* stream) {
+    const int64_t blocks = (n_tris + 255) / 256;
+    hipLaunchKernelGGL(k_set_emission, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       rad, order, n_tris, emission);
+    return check_launch("set_emission");
+}
+
+int launch_gen_points(const DeviceScene& sc, const CameraTable& cams, const fipt_points& out,
+                      void* stream) {
+    const int64_t blocks = (out.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_gen_points, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream,
+                       sc, cams, out);
+    return check_launch("gen_points");
+}
+
+int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream) {
+    // persistent grid: a few waves per SIMD, multiple of 8 workgroups so
+    // the XCD remap applies
+    const int64_t want = (b.n + kWaves - 1) / kWaves;
+    int64_t cap = (int64_t)device_cus() * 8;
+    int64_t blocks = std::min(want, cap);
+    if (blocks >= 8) blocks &= ~int64_t(7);
+    if (blocks < 1) blocks = 1;
+    if (stats)
+        hipLaunchKernelGGL(k_bake<true>, dim3((unsigned)blocks), dim3(kBlock), 0,
+                           (hipStream_t)stream, b, stats);
+    else
+        hipLaunchKernelGGL(k_bake<false>, dim3((unsigned)blocks), dim3(kBlock), 0,
+                           (hipStream_t)stream, b, stats);
+    return check_launch("bake");
+}
+
+int bake_tiles_grid_hint() { return device_cus() * 8; }
+
+int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* counter_dev,
+                      int32_t grid, void* stream) {
+    hipLaunchKernelGGL(k_bake_tiles, dim3((unsigned)grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       tiles_dev, n_tiles, counter_dev);
+    return check_launch("bake_tiles");
+}
+
+}  // namespace fipt

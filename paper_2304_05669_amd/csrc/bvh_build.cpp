@@ -1,0 +1,414 @@
+// Host construction of the binary BVH the bake traverses.
+//
+// Top-down binned surface-area-heuristic build (32 bins per axis over the
+// triangle centroids), single-threaded and therefore deterministic.  Child
+// boxes are widened outward by a few units in the last place so that the
+// single-precision slab test on the GPU never rejects a box a ray actually
+// touches (flat, axis-aligned walls give boxes of zero thickness).
+//
+// The depth of internal nodes is capped at kMaxInnerDepth: when the
+// remaining budget would not suffice for a subtree built by halving, the
+// build switches to object-median splits, which need ceil(log2(n / 8))
+// further levels.  The traversal's fixed LDS stack (kStackSize entries per
+// lane) therefore can never overflow.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "fipt_internal.hpp"
+
+namespace fipt {
+namespace {
+
+struct Box {
+    float lo[3], hi[3];
+    void reset() {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = INFINITY;
+            hi[k] = -INFINITY;
+        }
+    }
+    void grow(const Box& b) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], b.lo[k]);
+            hi[k] = std::max(hi[k], b.hi[k]);
+        }
+    }
+    void grow(const float* p) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], p[k]);
+            hi[k] = std::max(hi[k], p[k]);
+        }
+    }
+    double area() const {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = std::max(0.0, (double)hi[k] - (double)lo[k]);
+        return 2.0 * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
+    }
+};
+
+struct Prim {
+    Box b;
+    float c[3];
+    int32_t id;
+};
+
+constexpr int kBins = 32;
+
+int ceil_log2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+float widen_lo(float v) {
+    float e = std::fabs(v) * 9.5367431640625e-07f + 1e-30f;  // 2^-20 relative
+    return v - e;
+}
+float widen_hi(float v) {
+    float e = std::fabs(v) * 9.5367431640625e-07f + 1e-30f;
+    return v + e;
+}
+
+class Builder {
+  public:
+    Builder(const float* verts, const int32_t* tris, int64_t n_tris, HostBvh* out)
+        : verts_(verts), tris_(tris), out_(out) {
+        prims_.resize(n_tris);
+        for (int64_t f = 0; f < n_tris; ++f) {
+            Prim& p = prims_[f];
+            p.b.reset();
+            for (int k = 0; k < 3; ++k) p.b.grow(verts + 3 * (int64_t)tris[3 * f + k]);
+            for (int k = 0; k < 3; ++k) p.c[k] = 0.5f * (p.b.lo[k] + p.b.hi[k]);
+            p.id = (int32_t)f;
+        }
+    }
+
+    void run() {
+        out_->nodes.clear();
+        out_->tris.clear();
+        out_->order.clear();
+        out_->nodes.reserve(prims_.size() / 2 + 2);
+        out_->tris.reserve(prims_.size());
+        out_->order.reserve(prims_.size());
+        max_depth_ = 0;
+        Box root_box = bounds(0, (int64_t)prims_.size());
+        // The root is always an internal node (traversal starts by fetching
+        // node 0).  A one-triangle scene references its leaf from both
+        // children.
+        int64_t n = (int64_t)prims_.size();
+        int64_t root = alloc_node();
+        if (n == 1) {
+            int32_t leaf = make_leaf(0, 1);
+            set_child(root, 0, leaf, root_box);
+            set_child(root, 1, leaf, root_box);
+        } else {
+            split_into(root, 0, n, root_box, 0);
+        }
+        out_->max_depth = max_depth_;
+        for (int k = 0; k < 3; ++k) {
+            out_->bmin[k] = root_box.lo[k];
+            out_->bmax[k] = root_box.hi[k];
+        }
+    }
+
+  private:
+    const float* verts_;
+    const int32_t* tris_;
+    HostBvh* out_;
+    std::vector<Prim> prims_;
+    int max_depth_ = 0;
+
+    Box bounds(int64_t b, int64_t e) const {
+        Box box;
+        box.reset();
+        for (int64_t i = b; i < e; ++i) box.grow(prims_[i].b);
+        return box;
+    }
+
+    int64_t alloc_node() {
+        out_->nodes.push_back(BvhNode{});
+        return (int64_t)out_->nodes.size() - 1;
+    }
+
+    int32_t make_leaf(int64_t b, int64_t e) {
+        int64_t first = (int64_t)out_->tris.size();
+        for (int64_t i = b; i < e; ++i) {
+            int32_t f = prims_[i].id;
+            const float* p0 = verts_ + 3 * (int64_t)tris_[3 * (int64_t)f + 0];
+            const float* p1 = verts_ + 3 * (int64_t)tris_[3 * (int64_t)f + 1];
+            const float* p2 = verts_ + 3 * (int64_t)tris_[3 * (int64_t)f + 2];
+            TriGeom t;
+            t.v0x = p0[0];
+            t.v0y = p0[1];
+            t.v0z = p0[2];
+            t.orig = f;
+            t.e1x = p1[0] - p0[0];
+            t.e1y = p1[1] - p0[1];
+            t.e1z = p1[2] - p0[2];
+            t.pad1 = 0.0f;
+            t.e2x = p2[0] - p0[0];
+            t.e2y = p2[1] - p0[1];
+            t.e2z = p2[2] - p0[2];
+            t.pad2 = 0.0f;
+            out_->tris.push_back(t);
+            out_->order.push_back(f);
+        }
+        return leaf_ref(first, (int)(e - b));
+    }
+
+    void set_child_raw(int64_t node, int which, int32_t ref, const Box& bx) {
+        BvhNode& nd = out_->nodes[node];
+        if (which == 0) {
+            nd.c0lx = bx.lo[0]; nd.c0hx = bx.hi[0];
+            nd.c0ly = bx.lo[1]; nd.c0hy = bx.hi[1];
+            nd.c0lz = bx.lo[2]; nd.c0hz = bx.hi[2];
+            nd.child0 = ref;
+        } else {
+            nd.c1lx = bx.lo[0]; nd.c1hx = bx.hi[0];
+            nd.c1ly = bx.lo[1]; nd.c1hy = bx.hi[1];
+            nd.c1lz = bx.lo[2]; nd.c1hz = bx.hi[2];
+            nd.child1 = ref;
+        }
+        nd.pad0 = nd.pad1 = 0;
+    }
+
+    void set_child(int64_t node, int which, int32_t ref, const Box& b) {
+        Box w;
+        for (int k = 0; k < 3; ++k) {
+            w.lo[k] = widen_lo(b.lo[k]);
+            w.hi[k] = widen_hi(b.hi[k]);
+        }
+        set_child_raw(node, which, ref, w);
+    }
+
+    // Choose a split of [b, e) (n > 1); returns the partition point.
+    int64_t choose_split(int64_t b, int64_t e, const Box& box, int depth, bool* leaf_ok) {
+        int64_t n = e - b;
+        Box cb;
+        cb.reset();
+        for (int64_t i = b; i < e; ++i) cb.grow(prims_[i].c);
+        int need = ceil_log2((n + kLeafMax - 1) / kLeafMax);
+        bool force_median = depth + need >= kMaxInnerDepth - 1;
+        int axis = 0;
+        float ext = cb.hi[0] - cb.lo[0];
+        for (int k = 1; k < 3; ++k)
+            if (cb.hi[k] - cb.lo[k] > ext) {
+                ext = cb.hi[k] - cb.lo[k];
+                axis = k;
+            }
+        *leaf_ok = false;
+        if (n <= kLeafMax && (force_median || !(ext > 0.0f))) {
+            // out of depth budget, or nothing to separate: a leaf
+            *leaf_ok = true;
+            return b + n / 2;
+        }
+        if (!(ext > 0.0f)) {
+            // all centroids coincide: split by index
+            return b + n / 2;
+        }
+        if (force_median) return median_split(b, e, axis);
+
+        // binned SAH over all three axes
+        double best_cost = INFINITY;
+        int best_axis = -1, best_bin = -1;
+        for (int a = 0; a < 3; ++a) {
+            float lo = cb.lo[a], hi = cb.hi[a];
+            if (!(hi > lo)) continue;
+            float scale = kBins / (hi - lo);
+            Box bb[kBins];
+            int64_t cnt[kBins];
+            for (int i = 0; i < kBins; ++i) {
+                bb[i].reset();
+                cnt[i] = 0;
+            }
+            for (int64_t i = b; i < e; ++i) {
+                int k = (int)((prims_[i].c[a] - lo) * scale);
+                k = std::min(std::max(k, 0), kBins - 1);
+                bb[k].grow(prims_[i].b);
+                ++cnt[k];
+            }
+            double right_area[kBins];
+            int64_t right_cnt[kBins];
+            Box acc;
+            acc.reset();
+            int64_t c = 0;
+            for (int i = kBins - 1; i > 0; --i) {
+                acc.grow(bb[i]);
+                c += cnt[i];
+                right_area[i] = acc.area();
+                right_cnt[i] = c;
+            }
+            acc.reset();
+            c = 0;
+            for (int i = 0; i < kBins - 1; ++i) {
+                acc.grow(bb[i]);
+                c += cnt[i];
+                if (c == 0 || right_cnt[i + 1] == 0) continue;
+                double cost = acc.area() * (double)c + right_area[i + 1] * (double)right_cnt[i + 1];
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_axis = a;
+                    best_bin = i;
+                }
+            }
+        }
+        double parent = box.area();
+        // SAH with traversal cost 1 and intersection cost 1 per triangle
+        double split_cost = 1.0 + (parent > 0 ? best_cost / parent : INFINITY);
+        double leaf_cost = (double)n;
+        if (n <= kLeafMax && leaf_cost <= split_cost) *leaf_ok = true;
+        if (best_axis < 0) return median_split(b, e, axis);
+        float lo = cb.lo[best_axis];
+        float scale = kBins / (cb.hi[best_axis] - lo);
+        auto mid = std::stable_partition(prims_.begin() + b, prims_.begin() + e,
+                                         [&](const Prim& p) {
+                                             int k = (int)((p.c[best_axis] - lo) * scale);
+                                             k = std::min(std::max(k, 0), kBins - 1);
+                                             return k <= best_bin;
+                                         });
+        int64_t m = mid - prims_.begin();
+        if (m == b || m == e) return median_split(b, e, axis);
+        return m;
+    }
+
+    int64_t median_split(int64_t b, int64_t e, int axis) {
+        int64_t m = b + (e - b) / 2;
+        std::nth_element(prims_.begin() + b, prims_.begin() + m, prims_.begin() + e,
+                         [axis](const Prim& x, const Prim& y) {
+                             if (x.c[axis] != y.c[axis]) return x.c[axis] < y.c[axis];
+                             return x.id < y.id;
+                         });
+        return m;
+    }
+
+    // Build the subtree over [b, e) and return its child reference.
+    int32_t build(int64_t b, int64_t e, const Box& box, int depth) {
+        int64_t n = e - b;
+        if (n <= kLeafMax) {
+            if (n == 1) return make_leaf(b, e);
+            bool leaf_ok = false;
+            // leaf test needs the split cost; reuse choose_split without
+            // committing when a leaf wins (partition order does not matter
+            // for a leaf).
+            int64_t m = choose_split(b, e, box, depth, &leaf_ok);
+            if (leaf_ok) return make_leaf(b, e);
+            int64_t node = alloc_node();
+            finish_node(node, b, m, e, depth);
+            return (int32_t)node;
+        }
+        int64_t node = alloc_node();
+        split_into(node, b, e, box, depth);
+        return (int32_t)node;
+    }
+
+    void split_into(int64_t node, int64_t b, int64_t e, const Box& box, int depth) {
+        bool leaf_ok = false;
+        int64_t m = choose_split(b, e, box, depth, &leaf_ok);
+        finish_node(node, b, m, e, depth);
+    }
+
+    void finish_node(int64_t node, int64_t b, int64_t m, int64_t e, int depth) {
+        max_depth_ = std::max(max_depth_, depth);
+        Box lb = bounds(b, m), rb = bounds(m, e);
+        int32_t l = build(b, m, lb, depth + 1);
+        int32_t r = build(m, e, rb, depth + 1);
+        set_child(node, 0, l, lb);
+        set_child(node, 1, r, rb);
+    }
+};
+
+}  // namespace
+
+int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+              HostBvh* out) {
+    if (n_tris < 1 || n_tris >= (int64_t(1) << 28))
+        return fail(FIPT_EINVAL, "n_tris must be in [1, 2^28), got %lld", (long long)n_tris);
+    for (int64_t i = 0; i < 3 * n_tris; ++i)
+        if (tris[i] < 0 || tris[i] >= n_verts)
+            return fail(FIPT_EINVAL, "triangle %lld references vertex %d outside [0, %lld)",
+                        (long long)(i / 3), tris[i], (long long)n_verts);
+    for (int64_t i = 0; i < 3 * n_verts; ++i)
+        if (!std::isfinite(verts[i]))
+            return fail(FIPT_EINVAL, "vertex %lld has a non-finite coordinate", (long long)(i / 3));
+    Builder bld(verts, tris, n_tris, out);
+    bld.run();
+    if (out->max_depth > kMaxInnerDepth)
+        return fail(FIPT_EINVAL, "BVH depth %d exceeds the traversal stack", out->max_depth);
+    return FIPT_OK;
+}
+
+}  // namespace fipt
+
+namespace {
+
+// Walk the subtree of `ref`: count triangle occurrences, check that the
+// box recorded for `ref` in its parent encloses all of its triangles, and
+// track the deepest internal node.
+int validate_subtree(const fipt::HostBvh& b, const float* verts, const int32_t* tris,
+                     int32_t ref, const float lo[3], const float hi[3], int depth,
+                     std::vector<int>& seen, int* max_depth) {
+    using namespace fipt;
+    if (ref >= 0) {
+        if (ref >= (int32_t)b.nodes.size()) return fail(FIPT_EINVAL, "child index %d out of range", ref);
+        if (depth > kMaxInnerDepth) return fail(FIPT_EINVAL, "internal node at depth %d", depth);
+        *max_depth = std::max(*max_depth, depth);
+        const BvhNode& nd = b.nodes[ref];
+        const float l0[3] = {nd.c0lx, nd.c0ly, nd.c0lz}, h0[3] = {nd.c0hx, nd.c0hy, nd.c0hz};
+        const float l1[3] = {nd.c1lx, nd.c1ly, nd.c1lz}, h1[3] = {nd.c1hx, nd.c1hy, nd.c1hz};
+        for (int k = 0; k < 3; ++k)
+            if (l0[k] < lo[k] || h0[k] > hi[k] || l1[k] < lo[k] || h1[k] > hi[k]) {
+                // children are widened independently of the parent; allow
+                // their few-ulp margin
+                const float tol = 4.0f * 9.5367431640625e-07f * std::max(std::fabs(lo[k]), std::fabs(hi[k])) + 1e-30f;
+                if (l0[k] < lo[k] - tol || h0[k] > hi[k] + tol || l1[k] < lo[k] - tol || h1[k] > hi[k] + tol)
+                    return fail(FIPT_EINVAL, "child box of node %d leaves its parent box", ref);
+            }
+        int rc = validate_subtree(b, verts, tris, nd.child0, l0, h0, depth + 1, seen, max_depth);
+        if (rc) return rc;
+        // a one-triangle scene references the same leaf twice
+        if (nd.child1 == nd.child0 && ref == 0 && b.tris.size() == 1) return FIPT_OK;
+        return validate_subtree(b, verts, tris, nd.child1, l1, h1, depth + 1, seen, max_depth);
+    }
+    const int32_t lr = ~ref;
+    const int64_t first = lr >> 3;
+    const int cnt = (lr & 7) + 1;
+    if (first + cnt > (int64_t)b.tris.size()) return fail(FIPT_EINVAL, "leaf range out of bounds");
+    for (int i = 0; i < cnt; ++i) {
+        const int32_t f = b.order[first + i];
+        if (b.tris[first + i].orig != f) return fail(FIPT_EINVAL, "leaf triangle id mismatch");
+        ++seen[f];
+        for (int v = 0; v < 3; ++v) {
+            const float* p = verts + 3 * (int64_t)tris[3 * (int64_t)f + v];
+            for (int k = 0; k < 3; ++k)
+                if (p[k] < lo[k] || p[k] > hi[k])
+                    return fail(FIPT_EINVAL, "triangle %d pokes out of its leaf box", f);
+        }
+    }
+    return FIPT_OK;
+}
+
+}  // namespace
+
+extern "C" int fipt_bvh_validate(const float* verts, int64_t n_verts, const int32_t* tris,
+                                 int64_t n_tris, int64_t* n_nodes, int32_t* max_depth) {
+    using namespace fipt;
+    clear_error();
+    if (!verts || !tris || !n_nodes || !max_depth) return fail(FIPT_EINVAL, "NULL argument");
+    if (n_verts < 3) return fail(FIPT_EINVAL, "n_verts must be >= 3");
+    HostBvh b;
+    int rc = build_bvh(verts, n_verts, tris, n_tris, &b);
+    if (rc) return rc;
+    std::vector<int> seen(n_tris, 0);
+    int depth = 0;
+    const float lo[3] = {-INFINITY, -INFINITY, -INFINITY}, hi[3] = {INFINITY, INFINITY, INFINITY};
+    rc = validate_subtree(b, verts, tris, 0, lo, hi, 0, seen, &depth);
+    if (rc) return rc;
+    for (int64_t f = 0; f < n_tris; ++f)
+        if (seen[f] != 1) return fail(FIPT_EINVAL, "triangle %lld appears %d times", (long long)f, seen[f]);
+    if ((int64_t)b.tris.size() != n_tris) return fail(FIPT_EINVAL, "leaf order has %zu triangles", b.tris.size());
+    *n_nodes = (int64_t)b.nodes.size();
+    *max_depth = depth;
+    return FIPT_OK;
+}

@@ -1,0 +1,166 @@
+// Internal declarations shared by the host code and the HIP kernels of
+// libfipt.  Nothing here is part of the public C ABI (include/fipt.h).
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fipt.h"
+
+namespace fipt {
+
+// ---- errors ---------------------------------------------------------------
+// Records a printf-style message as the calling thread's last error and
+// returns `code`.
+int fail(int code, const char* fmt, ...);
+void clear_error();
+
+// ---- BVH layout -----------------------------------------------------------
+// Binary BVH.  A node holds the boxes of both children so one 64-byte fetch
+// decides which children a ray enters.  Child reference: >= 0 -> internal
+// node index; < 0 -> leaf ~((first << 3) | (count - 1)), first = position of
+// its first triangle in leaf order, count in [1, 8].
+constexpr int kLeafMax = 8;
+constexpr int kStackSize = 32;     // LDS traversal stack entries per lane
+constexpr int kMaxInnerDepth = 30; // deepest internal node (root = 0)
+
+struct alignas(16) BvhNode {
+    float c0lx, c0hx, c0ly, c0hy;  // child 0 box, x and y
+    float c1lx, c1hx, c1ly, c1hy;  // child 1 box, x and y
+    float c0lz, c0hz, c1lz, c1hz;  // both boxes, z
+    int32_t child0, child1, pad0, pad1;
+};
+static_assert(sizeof(BvhNode) == 64, "node is one 64-byte fetch");
+
+// Triangle in leaf order: first vertex, the two edges from it, and the
+// original triangle index (for ties and for reporting).  48 bytes.
+struct alignas(16) TriGeom {
+    float v0x, v0y, v0z;
+    int32_t orig;
+    float e1x, e1y, e1z, pad1;
+    float e2x, e2y, e2z, pad2;
+};
+static_assert(sizeof(TriGeom) == 48, "triangle is three 16-byte fetches");
+
+// Radiance record in leaf order: cache value at the three corners (equal
+// for a per-triangle cache) and the triangle's emission.  48 bytes.
+struct alignas(16) TriRad {
+    float c0r, c0g, c0b, c1r;
+    float c1g, c1b, c2r, c2g;
+    float c2b, ler, leg, leb;
+};
+static_assert(sizeof(TriRad) == 48, "radiance record is three 16-byte fetches");
+
+inline int32_t leaf_ref(int64_t first, int count) {
+    return ~static_cast<int32_t>((first << 3) | (count - 1));
+}
+
+struct HostBvh {
+    std::vector<BvhNode> nodes;
+    std::vector<TriGeom> tris;   // leaf order
+    std::vector<int32_t> order;  // leaf position -> original triangle
+    int max_depth = 0;
+    float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
+};
+
+// Binned-SAH top-down build; deterministic; internal depth capped at
+// kMaxInnerDepth by switching to object-median splits when needed.
+int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+              HostBvh* out);
+
+// ---- kernels (launchers defined in the .hip files) -------------------------
+struct DeviceScene {
+    const BvhNode* nodes;
+    const TriGeom* tris;
+    const TriRad* rad;
+    int64_t n_tris;
+};
+
+int launch_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_idx,
+                        int64_t n_tris, int cache_kind, const float* cache, int64_t n_cache,
+                        const float* emission, void* stream);
+int launch_set_emission(TriRad* rad, const int32_t* order, int64_t n_tris,
+                        const float* emission, void* stream);
+// Cameras travel by value in the kernel arguments (no staging allocation).
+constexpr int kMaxCameras = 48;
+struct CameraTable {
+    fipt_camera cam[kMaxCameras];
+    int64_t offset[kMaxCameras + 1];  // first point of each camera
+    int32_t n;
+};
+int launch_gen_points(const DeviceScene& sc, const CameraTable& cams, const fipt_points& out,
+                      void* stream);
+
+struct BakeLaunch {
+    DeviceScene sc;
+    const float* pts;
+    const int32_t* ptri;
+    int64_t pts_stride;
+    int64_t n;            // points
+    int64_t p_offset;     // added to the point index for the RNG counter
+    float* out;
+    int64_t out_stride;
+    int32_t spp_d, spp_s, K;
+    float sigma[FIPT_MAX_LEVELS];
+    uint64_t seed;
+    float eps;
+};
+int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream);
+
+// Serving: a tile is a contiguous run of one request's points.
+struct TileDesc {
+    BakeLaunch job;       // job.n = points in the tile, pointers already offset
+    int64_t first;        // points of all earlier tiles in the launch
+};
+int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* counter_dev,
+                      int32_t grid, void* stream);
+int bake_tiles_grid_hint();
+
+int launch_render_loss(const float* sh, int64_t sh_stride, int64_t n, int32_t K,
+                       const float* sigma_host, const float* mat, int64_t mat_stride,
+                       const float* obs, int64_t obs_stride, int32_t tone, double* loss,
+                       float* grad, int64_t grad_stride, float* Lr, int64_t lr_stride,
+                       void* stream);
+int launch_scale_by(const float* x, int64_t n, const double* f, float* out, void* stream);
+int launch_grid_gather(const float* grid, int32_t C, int32_t R, const float* bmin,
+                       const float* bmax, const float* pos, int64_t pos_stride, int64_t n,
+                       float* out, int64_t out_stride, void* stream);
+
+struct GridPlanDev {
+    int32_t res;
+    int64_t n_points;
+    float bmin[3], bmax[3];
+    int32_t* perm;          // [n] points sorted by cell (stable)
+    int32_t* cell_start;    // [n_occ + 1] ranges into perm
+    int32_t* cell_id;       // [n_occ] linear cell index (x fastest, res-1 per axis)
+    int64_t n_occ;
+    int32_t* node_id;       // [n_act] active node linear index
+    int32_t* node_start;    // [n_act + 1] ranges into node_src
+    int32_t* node_src;      // [entries] (occupied cell index << 3) | corner
+    int64_t n_act;
+    float* pos;             // [3][n_points] positions of the plan's points
+    double* partials;       // [n_occ][8][8] scratch (corner x channel)
+};
+int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_t gp_stride,
+                        float* grad_grid, void* stream);
+
+}  // namespace fipt
+
+struct fipt_scene_s {
+    int32_t device = 0;
+    int64_t n_tris = 0, n_verts = 0, n_nodes = 0;
+    int32_t max_depth = 0;
+    int32_t cache_kind = -1;
+    float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
+    fipt::BvhNode* d_nodes = nullptr;
+    fipt::TriGeom* d_tris = nullptr;
+    fipt::TriRad* d_rad = nullptr;
+    int32_t* d_order = nullptr;    // leaf position -> original triangle
+    int32_t* d_tri_idx = nullptr;  // original [T][3] vertex indices
+    int64_t bytes = 0;
+    std::atomic<int> refs{0};      // serving requests referencing the scene
+    fipt::DeviceScene view() const { return {d_nodes, d_tris, d_rad, n_tris}; }
+};

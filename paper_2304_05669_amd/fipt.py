@@ -1,0 +1,518 @@
+"""Python binding of libfipt (include/fipt.h).
+
+Argument marshalling only: every function here checks tensor shapes, dtypes
+and devices, then calls the C entry point of the same name (``fipt_*``) on
+torch's current HIP stream.  All computation happens in the library's HIP
+kernels; nothing falls back to the CPU.  If libfipt.so has not been built,
+loading fails with an error naming the build step.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfipt.so")
+
+OK, EINVAL, ENOMEM, EHIP, EBUSY, EAGAIN, ECANCELED = 0, -1, -2, -3, -4, -5, -6
+MAX_LEVELS = 16
+LOSS_SLOTS = 2049
+CACHE_TRIANGLE, CACHE_VERTEX = 0, 1
+TONEMAP_NONE, TONEMAP_LOG_SRGB = 0, 1
+
+# every entry point declared in include/fipt.h
+EXPORTS = (
+    "fipt_last_error", "fipt_version", "fipt_scene_create", "fipt_scene_set_radiance",
+    "fipt_scene_set_emission", "fipt_scene_info_get", "fipt_bvh_validate", "fipt_scene_destroy",
+    "fipt_gen_points",
+    "fipt_bake", "fipt_bake_traversal_stats", "fipt_render_loss", "fipt_scale_by",
+    "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
+    "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
+    "fipt_server_result", "fipt_server_release", "fipt_server_cancel", "fipt_server_stats_get",
+    "fipt_server_destroy",
+)
+
+
+class FiptError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fipt error {code}: {msg}")
+        self.code = code
+
+
+class Camera(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("fwd", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class Points(C.Structure):
+    _fields_ = [("planes", C.c_void_p), ("tri", C.c_void_p), ("n", C.c_int64),
+                ("stride", C.c_int64)]
+
+
+class Shading(C.Structure):
+    _fields_ = [("planes", C.c_void_p), ("stride", C.c_int64)]
+
+
+class BakeParams(C.Structure):
+    _fields_ = [("spp_d", C.c_int32), ("spp_s", C.c_int32), ("n_levels", C.c_int32),
+                ("sigma", C.c_float * MAX_LEVELS), ("seed", C.c_uint64), ("ray_eps", C.c_float),
+                ("flags", C.c_int32)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_tris", C.c_int64), ("n_verts", C.c_int64), ("n_nodes", C.c_int64),
+                ("device_bytes", C.c_int64), ("max_depth", C.c_int32), ("cache_kind", C.c_int32),
+                ("bmin", C.c_float * 3), ("bmax", C.c_float * 3)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("tiles", C.c_int64), ("samples", C.c_int64),
+                ("completed", C.c_int64), ("pool_in_use", C.c_int64), ("queued", C.c_int64),
+                ("inflight", C.c_int64)]
+
+
+_lib = None
+_vp, _i32, _i64, _u64, _f32p = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.POINTER(C.c_float)
+
+
+def lib():
+    """Load libfipt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "fipt_last_error": (C.c_char_p, []),
+        "fipt_version": (_i32, []),
+        "fipt_scene_create": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _vp, C.POINTER(_vp)]),
+        "fipt_scene_set_radiance": (C.c_int, [_vp, _i32, _vp, _i64, _vp, _vp]),
+        "fipt_scene_set_emission": (C.c_int, [_vp, _vp, _vp]),
+        "fipt_scene_info_get": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
+        "fipt_scene_destroy": (C.c_int, [_vp]),
+        "fipt_bvh_validate": (C.c_int, [_vp, _i64, _vp, _i64, C.POINTER(_i64), C.POINTER(_i32)]),
+        "fipt_gen_points": (C.c_int, [_vp, C.POINTER(Camera), _i32, C.POINTER(Points), _vp]),
+        "fipt_bake": (C.c_int, [_vp, C.POINTER(Points), C.POINTER(BakeParams), C.POINTER(Shading), _vp]),
+        "fipt_bake_traversal_stats": (C.c_int, [_vp, C.POINTER(Points), C.POINTER(BakeParams),
+                                                C.POINTER(Shading), _vp, _vp]),
+        "fipt_render_loss": (C.c_int, [C.POINTER(Shading), _i64, _i32, _f32p, _vp, _i64, _vp, _i64,
+                                       _i32, _vp, _vp, _i64, _vp, _i64, _vp]),
+        "fipt_scale_by": (C.c_int, [_vp, _i64, _vp, _vp, _vp]),
+        "fipt_grid_gather": (C.c_int, [_vp, _i32, _i32, _f32p, _f32p, _vp, _i64, _i64, _vp, _i64, _vp]),
+        "fipt_grid_plan_create": (C.c_int, [_vp, _i64, _i32, _f32p, _f32p, _i32, C.POINTER(_vp)]),
+        "fipt_grid_plan_destroy": (C.c_int, [_vp]),
+        "fipt_grid_scatter": (C.c_int, [_vp, _vp, _i32, _i64, _vp, _vp]),
+        "fipt_server_create": (C.c_int, [_i32, _i64, _i32, _i64, C.POINTER(_vp)]),
+        "fipt_server_submit": (C.c_int, [_vp, _vp, C.POINTER(Points), C.POINTER(BakeParams),
+                                         C.POINTER(_u64)]),
+        "fipt_server_poll": (C.c_int, [_vp, _u64]),
+        "fipt_server_wait": (C.c_int, [_vp, _u64, _i64]),
+        "fipt_server_result": (C.c_int, [_vp, _u64, C.POINTER(Shading), C.POINTER(_i64),
+                                         C.POINTER(_i64), C.POINTER(_i64)]),
+        "fipt_server_release": (C.c_int, [_vp, _u64]),
+        "fipt_server_cancel": (C.c_int, [_vp, _u64]),
+        "fipt_server_stats_get": (C.c_int, [_vp, C.POINTER(ServerStats)]),
+        "fipt_server_destroy": (C.c_int, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int, allow=()):
+    if rc != OK and rc not in allow:
+        raise FiptError(rc, lib().fipt_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _f32_array(v, n):
+    a = (C.c_float * n)()
+    for i, x in enumerate(v):
+        a[i] = float(x)
+    return a
+
+
+def version() -> int:
+    return int(lib().fipt_version())
+
+
+# --------------------------------------------------------------------------
+# scene
+# --------------------------------------------------------------------------
+class Scene:
+    """Triangle mesh + BVH + radiance records resident on one GPU."""
+
+    def __init__(self, verts, tris, device: int = 0):
+        import numpy as np
+        v = np.ascontiguousarray(verts, dtype=np.float32)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            _check(lib().fipt_scene_create(v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0],
+                                           device, _stream(), C.byref(h)))
+        self.handle = h
+        self.device = device
+        self.n_tris = int(t.shape[0])
+        self.n_verts = int(v.shape[0])
+
+    def set_radiance(self, cache: torch.Tensor, kind: int, emission: torch.Tensor = None):
+        """cache: [3, n] float32 GPU (n = triangles or vertices by kind);
+        emission: [3, n_tris] float32 GPU or None."""
+        ep = _dev(emission, torch.float32, "emission") if emission is not None else None
+        if emission is not None and tuple(emission.shape) != (3, self.n_tris):
+            raise ValueError("emission must be [3, n_tris]")
+        _check(lib().fipt_scene_set_radiance(self.handle, kind, _dev(cache, torch.float32, "cache"),
+                                             cache.shape[1], ep, _stream()))
+
+    def set_emission(self, emission: torch.Tensor):
+        if tuple(emission.shape) != (3, self.n_tris):
+            raise ValueError("emission must be [3, n_tris]")
+        _check(lib().fipt_scene_set_emission(self.handle, _dev(emission, torch.float32, "emission"),
+                                             _stream()))
+
+    def info(self) -> SceneInfo:
+        out = SceneInfo()
+        _check(lib().fipt_scene_info_get(self.handle, C.byref(out)))
+        return out
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().fipt_scene_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.fipt_scene_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def fipt_bvh_validate(verts, tris):
+    """Host-only: build and verify the BVH of a mesh; returns (nodes, depth)."""
+    import numpy as np
+    v = np.ascontiguousarray(verts, dtype=np.float32)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    nn, dd = C.c_int64(), C.c_int32()
+    _check(lib().fipt_bvh_validate(v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0],
+                                   C.byref(nn), C.byref(dd)))
+    return nn.value, dd.value
+
+
+def make_points(planes: torch.Tensor, tri: torch.Tensor) -> Points:
+    if planes.dim() != 2 or planes.shape[0] != 9:
+        raise ValueError("point planes must be [9, n]")
+    if tri.shape != (planes.shape[1],):
+        raise ValueError("tri must be [n]")
+    return Points(_dev(planes, torch.float32, "planes"), _dev(tri, torch.int32, "tri"),
+                  planes.shape[1], planes.shape[1])
+
+
+def make_params(spp_d: int, spp_s: int, sigma, seed: int, ray_eps: float = 1e-4) -> BakeParams:
+    p = BakeParams()
+    p.spp_d = int(spp_d)
+    p.spp_s = int(spp_s)
+    p.n_levels = len(sigma)
+    p.sigma = _f32_array(list(sigma) + [0.0] * (MAX_LEVELS - len(sigma)), MAX_LEVELS)
+    p.seed = int(seed)
+    p.ray_eps = float(ray_eps)
+    p.flags = 0
+    return p
+
+
+def fipt_gen_points(scene: Scene, cameras, planes: torch.Tensor = None, tri: torch.Tensor = None):
+    """cameras: list of synth.Camera-like objects (pos, fwd, up, vfov_deg,
+    width, height).  Returns (planes [9, n], tri [n]) GPU tensors."""
+    n = sum(c.width * c.height for c in cameras)
+    dev = torch.device("cuda", scene.device)
+    if planes is None:
+        planes = torch.empty((9, n), dtype=torch.float32, device=dev)
+    if tri is None:
+        tri = torch.empty((n,), dtype=torch.int32, device=dev)
+    pts = make_points(planes, tri)
+    # at most 48 cameras per call: offset the output pointers for more
+    first = 0
+    for c0 in range(0, len(cameras), 48):
+        group = cameras[c0:c0 + 48]
+        arr = (Camera * len(group))()
+        cnt = 0
+        for k, c in enumerate(group):
+            arr[k].pos = _f32_array(c.pos, 3)
+            arr[k].fwd = _f32_array(c.fwd, 3)
+            arr[k].up = _f32_array(c.up, 3)
+            arr[k].vfov_deg = float(c.vfov_deg)
+            arr[k].width = int(c.width)
+            arr[k].height = int(c.height)
+            cnt += c.width * c.height
+        sub = Points(pts.planes + 4 * first, pts.tri + 4 * first, cnt, n)
+        _check(lib().fipt_gen_points(scene.handle, arr, len(group), C.byref(sub), _stream()))
+        first += cnt
+    return planes, tri
+
+
+def fipt_bake(scene: Scene, planes: torch.Tensor, tri: torch.Tensor, spp_d: int, spp_s: int,
+              sigma, seed: int, ray_eps: float = 1e-4, out: torch.Tensor = None,
+              stats: torch.Tensor = None):
+    """Bake Ld, Ls0[K], Ls1[K] for the points; returns [3 + 6K, n] float32.
+    If ``stats`` (int64 GPU tensor of 4) is given, the instrumented kernel
+    adds rays, nodes, triangles and hits to it."""
+    K = len(sigma)
+    n = planes.shape[1]
+    if out is None:
+        out = torch.empty((3 + 6 * K, n), dtype=torch.float32, device=planes.device)
+    if out.shape[0] != 3 + 6 * K or out.shape[1] < n:
+        raise ValueError("out must be [3 + 6K, >= n]")
+    pts = make_points(planes, tri)
+    par = make_params(spp_d, spp_s, sigma, seed, ray_eps)
+    sh = Shading(_dev(out, torch.float32, "out"), out.shape[1])
+    if stats is None:
+        _check(lib().fipt_bake(scene.handle, C.byref(pts), C.byref(par), C.byref(sh), _stream()))
+    else:
+        _check(lib().fipt_bake_traversal_stats(scene.handle, C.byref(pts), C.byref(par), C.byref(sh),
+                                               _dev(stats, torch.int64, "stats"), _stream()))
+    return out
+
+
+# --------------------------------------------------------------------------
+# factored re-render + loss
+# --------------------------------------------------------------------------
+def fipt_render_loss(shading: torch.Tensor, material: torch.Tensor, observed: torch.Tensor, sigma,
+                     tonemap: int = TONEMAP_NONE, want_grad: bool = True, want_lr: bool = False,
+                     loss_buf: torch.Tensor = None, grad: torch.Tensor = None, lr: torch.Tensor = None):
+    """Returns (loss_buf, grad, Lr): loss_buf[0] is the loss (float64 GPU);
+    grad [5, n] and Lr [3, n] float32 GPU (or None)."""
+    K = len(sigma)
+    n = material.shape[1]
+    if shading.shape[0] != 3 + 6 * K or shading.shape[1] != n:
+        raise ValueError("shading must be [3 + 6K, n]")
+    if material.shape[0] != 5 or observed.shape != (3, n):
+        raise ValueError("material must be [5, n] and observed [3, n]")
+    dev = material.device
+    if loss_buf is None:
+        loss_buf = torch.empty((LOSS_SLOTS,), dtype=torch.float64, device=dev)
+    if want_grad and grad is None:
+        grad = torch.empty((5, n), dtype=torch.float32, device=dev)
+    if want_lr and lr is None:
+        lr = torch.empty((3, n), dtype=torch.float32, device=dev)
+    sh = Shading(_dev(shading, torch.float32, "shading"), n)
+    sig = _f32_array(sigma, K)
+    _check(lib().fipt_render_loss(
+        C.byref(sh), n, K, sig, _dev(material, torch.float32, "material"), n,
+        _dev(observed, torch.float32, "observed"), n, int(tonemap),
+        _dev(loss_buf, torch.float64, "loss_buf"),
+        _dev(grad, torch.float32, "grad") if want_grad else None, n,
+        _dev(lr, torch.float32, "lr") if want_lr else None, n, _stream()))
+    return loss_buf, (grad if want_grad else None), (lr if want_lr else None)
+
+
+def fipt_scale_by(x: torch.Tensor, factor: torch.Tensor, out: torch.Tensor = None):
+    """out = x * factor[0] (factor: one float64 on the GPU) in a HIP kernel."""
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().fipt_scale_by(_dev(x, torch.float32, "x"), x.numel(),
+                               _dev(factor, torch.float64, "factor"),
+                               _dev(out, torch.float32, "out"), _stream()))
+    return out
+
+
+class FactoredLoss(torch.autograd.Function):
+    """loss = sum (Gamma(Lr(material)) - Gamma(Lgt))^2 with the hand-written
+    gradient of the library; differentiable in ``material`` [5, n]."""
+
+    @staticmethod
+    def forward(ctx, material, shading, observed, sigma, tonemap=TONEMAP_NONE):
+        buf, grad, _ = fipt_render_loss(shading, material.detach(), observed, sigma, tonemap,
+                                        want_grad=material.requires_grad)
+        ctx.save_for_backward(grad if grad is not None else material.new_empty(0))
+        return buf[0]
+
+    @staticmethod
+    def backward(ctx, go):
+        (grad,) = ctx.saved_tensors
+        g = fipt_scale_by(grad, go.reshape(1).to(torch.float64).contiguous())
+        return g, None, None, None, None
+
+
+# --------------------------------------------------------------------------
+# trilinear material grid
+# --------------------------------------------------------------------------
+def fipt_grid_gather(grid: torch.Tensor, bmin, bmax, pos: torch.Tensor, out: torch.Tensor = None):
+    """grid [C, R, R, R] float32 GPU (x fastest), pos [3, n] -> [C, n]."""
+    Cn, R = grid.shape[0], grid.shape[1]
+    n = pos.shape[1]
+    if out is None:
+        out = torch.empty((Cn, n), dtype=torch.float32, device=grid.device)
+    _check(lib().fipt_grid_gather(_dev(grid, torch.float32, "grid"), Cn, R, _f32_array(bmin, 3),
+                                  _f32_array(bmax, 3), _dev(pos, torch.float32, "pos"), n, n,
+                                  _dev(out, torch.float32, "out"), n, _stream()))
+    return out
+
+
+class GridPlan:
+    """Deterministic adjoint of the grid gather for a fixed point set."""
+
+    def __init__(self, pos_host, res: int, bmin, bmax, device: int = 0):
+        import numpy as np
+        p = np.ascontiguousarray(pos_host, dtype=np.float32)
+        self.n = int(p.shape[1])
+        self.res = int(res)
+        h = C.c_void_p()
+        _check(lib().fipt_grid_plan_create(p.ctypes.data, self.n, self.res, _f32_array(bmin, 3),
+                                           _f32_array(bmax, 3), device, C.byref(h)))
+        self.handle = h
+
+    def scatter(self, grad_points: torch.Tensor, out: torch.Tensor = None):
+        Cn = grad_points.shape[0]
+        if out is None:
+            out = torch.empty((Cn, self.res, self.res, self.res), dtype=torch.float32,
+                              device=grad_points.device)
+        _check(lib().fipt_grid_scatter(self.handle, _dev(grad_points, torch.float32, "grad_points"),
+                                       Cn, grad_points.shape[1], _dev(out, torch.float32, "out"),
+                                       _stream()))
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.fipt_grid_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class GridGather(torch.autograd.Function):
+    """Per-point values of a trilinear grid, differentiable in the grid."""
+
+    @staticmethod
+    def forward(ctx, grid, plan: GridPlan, bmin, bmax, pos):
+        ctx.plan = plan
+        return fipt_grid_gather(grid.detach(), bmin, bmax, pos)
+
+    @staticmethod
+    def backward(ctx, go):
+        return ctx.plan.scatter(go.contiguous()), None, None, None, None
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+@dataclass
+class Result:
+    shading: torch.Tensor
+    t_submit_us: int
+    t_admit_us: int
+    t_done_us: int
+
+
+class Server:
+    """Continuous-batching bake server (fipt_server_*)."""
+
+    def __init__(self, device: int = 0, pool_bytes: int = 4 << 30, max_inflight: int = 64,
+                 samples_per_launch: int = 1 << 26):
+        h = C.c_void_p()
+        _check(lib().fipt_server_create(device, int(pool_bytes), int(max_inflight),
+                                        int(samples_per_launch), C.byref(h)))
+        self.handle = h
+        self.device = device
+        self._keep = {}
+
+    def submit(self, scene: Scene, planes: torch.Tensor, tri: torch.Tensor, spp_d, spp_s, sigma,
+               seed, ray_eps=1e-4, offset: int = 0, count: int = None) -> int:
+        """Queue the bake of points [offset, offset + count) of (planes, tri)."""
+        n_all = planes.shape[1]
+        count = n_all - offset if count is None else int(count)
+        pts = Points(_dev(planes, torch.float32, "planes") + 4 * offset,
+                     _dev(tri, torch.int32, "tri") + 4 * offset, count, n_all)
+        par = make_params(spp_d, spp_s, sigma, seed, ray_eps)
+        t = C.c_uint64()
+        _check(lib().fipt_server_submit(self.handle, scene.handle, C.byref(pts), C.byref(par),
+                                        C.byref(t)))
+        self._keep[t.value] = (planes, tri, len(sigma), count)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        return _check(lib().fipt_server_poll(self.handle, ticket), allow=(EAGAIN,)) == OK
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> bool:
+        us = -1 if timeout_s < 0 else int(timeout_s * 1e6)
+        return _check(lib().fipt_server_wait(self.handle, ticket, us), allow=(EAGAIN,)) == OK
+
+    def result(self, ticket: int, copy: bool = True) -> Result:
+        sh = Shading()
+        ts, ta, td = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().fipt_server_result(self.handle, ticket, C.byref(sh), C.byref(ts), C.byref(ta),
+                                        C.byref(td)))
+        _, _, K, count = self._keep[ticket]
+        P = 3 + 6 * K
+        t = None
+        if copy:
+            # view the pool memory through a DLPack-free wrapper: copy on the
+            # server's results by a device-to-device memcpy into a tensor
+            t = torch.empty((P, count), dtype=torch.float32, device=torch.device("cuda", self.device))
+            torch.cuda.synchronize(self.device)
+            hip = _hip()
+            rc = hip.hipMemcpy(C.c_void_p(t.data_ptr()), C.c_void_p(sh.planes),
+                               C.c_size_t(4 * P * count), 3)
+            if rc != 0:
+                raise FiptError(EHIP, f"hipMemcpy failed ({rc})")
+        return Result(t, ts.value, ta.value, td.value)
+
+    def release(self, ticket: int):
+        _check(lib().fipt_server_release(self.handle, ticket))
+        self._keep.pop(ticket, None)
+
+    def cancel(self, ticket: int):
+        _check(lib().fipt_server_cancel(self.handle, ticket))
+
+    def stats(self) -> ServerStats:
+        s = ServerStats()
+        _check(lib().fipt_server_stats_get(self.handle, C.byref(s)))
+        return s
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().fipt_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.fipt_server_destroy(self.handle)
+        except Exception:
+            pass
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = C.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.restype = C.c_int
+        _hip_lib.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    return _hip_lib

@@ -1,0 +1,93 @@
+"""The C ABI library loads, exports every entry point include/fipt.h
+declares, rejects invalid arguments before touching a GPU, and its host
+BVH builder produces valid trees (all on the CPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2304_05669_amd import fipt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fipt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fipt_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = fipt.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in fipt.h but not exported"
+    assert sorted(fipt.EXPORTS) == names
+    assert fipt.version() == 10000
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = fipt.lib()
+    out = C.c_void_p()
+    assert L.fipt_scene_create(None, 3, None, 1, 0, None, C.byref(out)) == fipt.EINVAL
+    assert b"NULL" in L.fipt_last_error()
+    assert L.fipt_bake(None, None, None, None, None) == fipt.EINVAL
+    assert L.fipt_render_loss(None, 10, 6, None, None, 10, None, 10, 0, None, None, 10, None, 10,
+                              None) == fipt.EINVAL
+    sig = (C.c_float * 2)(0.5, 0.2)
+    sh = fipt.Shading(1, 10)
+    assert L.fipt_render_loss(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, 0, 1, None, 10, None, 10,
+                              None) == fipt.EINVAL
+    assert b"increasing" in L.fipt_last_error()
+    assert L.fipt_server_create(0, 1024, 4, 1 << 20, C.byref(out)) == fipt.EINVAL
+    assert L.fipt_grid_gather(None, 5, 128, None, None, None, 1, 1, None, 1, None) == fipt.EINVAL
+    assert L.fipt_scale_by(None, 1, None, None, None) == fipt.EINVAL
+    assert L.fipt_scene_info_get(None, None) == fipt.EINVAL
+    assert L.fipt_server_poll(None, 1) == fipt.EINVAL
+
+
+@pytest.mark.parametrize("name", ["tiny", "room", "degenerate", "skewed"])
+def test_bvh_builder_invariants(name):
+    if name == "tiny":
+        sc = synth.tiny_box()
+        v, t = sc.verts, sc.tris
+    elif name == "room":
+        sc = synth.room(n_cams=1, width=2, height=2)
+        v, t = sc.verts, sc.tris
+    elif name == "degenerate":
+        # 5000 identical triangles: no split separates them
+        v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+        t = np.zeros((5000, 3), np.int32)
+        t[:, 1] = 1
+        t[:, 2] = 2
+    else:
+        # exponentially spaced slivers: a pathological SAH input that must
+        # still respect the depth cap
+        n = 20000
+        x = np.geomspace(1e-6, 1e3, n).astype(np.float32)
+        v = np.zeros((3 * n, 3), np.float32)
+        v[0::3, 0] = x
+        v[1::3, 0] = x
+        v[1::3, 1] = 1e-3
+        v[2::3, 0] = x
+        v[2::3, 2] = 1e-3
+        t = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    nodes, depth = fipt.fipt_bvh_validate(v, t)
+    assert nodes >= 1 and 0 <= depth <= 30
+    assert nodes <= max(1, len(t))
+
+
+def test_bvh_rejects_bad_meshes():
+    v = np.zeros((3, 3), np.float32)
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bvh_validate(v, np.array([[0, 1, 3]], np.int32))
+    v2 = v.copy()
+    v2[1, 0] = np.nan
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bvh_validate(v2, np.array([[0, 1, 2]], np.int32))
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bvh_validate(v, np.zeros((0, 3), np.int32))

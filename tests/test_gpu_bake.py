@@ -1,0 +1,192 @@
+"""GPU parity of shading-point generation and the bake against the oracle,
+through the C ABI (Python binding).
+
+Sizes: the whole tiny box (4096 points, 448 lobe samples each); sampled
+points of the full room (189k triangles, 1,843,200 points, 896 samples per
+point, the configuration the benchmark times) and of the 2M-triangle room
+(1,000,000 points, 1792 samples per point); ragged and degenerate cases."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import bake as ob
+from paper_2304_05669_amd import fipt
+from tests.parity import assert_bake_parity, bake_report
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def _scene(sc):
+    s = fipt.Scene(sc.verts, sc.tris, device=0)
+    kind = fipt.CACHE_VERTEX if sc.cache_kind == "vertex" else fipt.CACHE_TRIANGLE
+    s.set_radiance(torch.from_numpy(sc.cache).to(DEV), kind, torch.from_numpy(sc.emission).to(DEV))
+    return s
+
+
+@pytest.fixture(scope="module")
+def tiny_gpu(tiny):
+    s = _scene(tiny)
+    yield s
+    s.destroy()
+
+
+def _bake(scene, pts, tri, spp_d, spp_s, sigma, seed):
+    out = fipt.fipt_bake(scene, torch.from_numpy(pts).to(DEV), torch.from_numpy(tri).to(DEV),
+                         spp_d, spp_s, sigma, seed)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_tiny_points_match_oracle(tiny, tiny_gpu, tiny_points):
+    pts, tri, prim = tiny_points
+    planes, tri_g = fipt.fipt_gen_points(tiny_gpu, tiny.cameras)
+    torch.cuda.synchronize()
+    P = planes.cpu().numpy().astype(np.float64)
+    T = tri_g.cpu().numpy()
+    clean = prim["n_outcomes"] == 1
+    assert clean.sum() > 3900
+    np.testing.assert_array_equal(T[clean], prim["tri"][clean])
+    np.testing.assert_allclose(P[0:3, clean], prim["points"][0:3, clean], atol=2e-6)
+    np.testing.assert_allclose(P[3:6, clean], prim["points"][3:6, clean], atol=1e-6)
+    np.testing.assert_allclose(P[6:9, clean], prim["points"][6:9, clean], atol=1e-6)
+    # ambiguous pixels (on an edge): still a valid hit on one of the candidates
+    assert (T[~clean] >= -1).all()
+
+
+def test_tiny_bake_parity(tiny, tiny_gpu, tiny_points, tiny_oracle):
+    pts, tri, _ = tiny_points
+    want = ob.bake(tiny_oracle, pts, tri, spp_d=tiny.spp, spp_s=tiny.spp, seed=tiny.seed)
+    got = _bake(tiny_gpu, pts, tri, tiny.spp, tiny.spp, tiny.sigma, tiny.seed)
+    r = assert_bake_parity(got, want)
+    print("tiny box parity:", r)
+
+
+def test_bake_is_deterministic(tiny, tiny_gpu, tiny_points):
+    pts, tri, _ = tiny_points
+    a = _bake(tiny_gpu, pts, tri, 64, 64, tiny.sigma, 11)
+    b = _bake(tiny_gpu, pts, tri, 64, 64, tiny.sigma, 11)
+    np.testing.assert_array_equal(a, b)
+    c = _bake(tiny_gpu, pts, tri, 64, 64, tiny.sigma, 12)
+    assert np.any(a != c)
+
+
+@pytest.mark.parametrize("spp_d,spp_s,sigma", [
+    (37, 5, (0.1, 0.5, 0.9)),                   # chunks mixing several lobes
+    (1, 1, (0.3,)),                              # one sample, one level
+    (130, 17, tuple(np.linspace(0.05, 1.0, 16))),  # the maximum number of levels
+    (256, 64, (0.02, 1.0)),
+])
+def test_sample_count_shapes(tiny, tiny_gpu, tiny_points, tiny_oracle, spp_d, spp_s, sigma):
+    pts, tri, _ = tiny_points
+    idx = np.arange(0, 4096, 7)
+    want = ob.bake(tiny_oracle, pts, tri, idx=idx, spp_d=spp_d, spp_s=spp_s, sigma=sigma, seed=3)
+    got = _bake(tiny_gpu, pts, tri, spp_d, spp_s, sigma, 3)[:, idx]
+    assert_bake_parity(got, want, min_frac=0.995)
+
+
+def test_ragged_and_degenerate_points(tiny, tiny_gpu, tiny_points, tiny_oracle):
+    pts, tri, _ = tiny_points
+    # a ragged count (not a multiple of the 4 wavefronts per workgroup), with
+    # invalid points: no surface, and a view direction in the surface plane
+    n = 4093
+    p2 = np.ascontiguousarray(pts[:, :n].copy())
+    t2 = np.ascontiguousarray(tri[:n].copy())
+    t2[5] = -1
+    p2[6:9, 9] = (1.0, 0.0, 0.0)     # wo in the plane of a floor point...
+    t2[9] = 0
+    p2[3:6, 9] = (0.0, 0.0, 1.0)     # ...with an upward normal: n.wo = 0
+    want = ob.bake(tiny_oracle, p2, t2, spp_d=24, spp_s=8, seed=5)
+    got = _bake(tiny_gpu, p2, t2, 24, 8, tiny.sigma, 5)
+    assert np.all(got[:, 5] == 0.0) and np.all(got[:, 9] == 0.0)
+    assert_bake_parity(got, want, min_frac=0.998)
+    # a single point
+    one = _bake(tiny_gpu, np.ascontiguousarray(pts[:, 100:101]), np.ascontiguousarray(tri[100:101]),
+                64, 64, tiny.sigma, 5)
+    w1 = ob.bake(tiny_oracle, np.ascontiguousarray(pts[:, 100:101]), np.ascontiguousarray(tri[100:101]),
+                 spp_d=64, spp_s=64, seed=5)
+    assert_bake_parity(one, w1, min_frac=1.0)
+
+
+def test_invalid_arguments_raise(tiny, tiny_gpu, tiny_points):
+    pts, tri, _ = tiny_points
+    planes = torch.from_numpy(pts).to(DEV)
+    tri_d = torch.from_numpy(tri).to(DEV)
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bake(tiny_gpu, planes, tri_d, 0, 4, tiny.sigma, 1)
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bake(tiny_gpu, planes, tri_d, 4, 4, (0.5, 0.2), 1)       # not increasing
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bake(tiny_gpu, planes, tri_d, 4, 4, (0.0, 0.2), 1)       # sigma = 0
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bake(tiny_gpu, planes, tri_d, 4, 4, tuple([0.5] * 17), 1)
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bake(tiny_gpu, planes[:, :0].contiguous(), tri_d[:0].contiguous(), 4, 4, tiny.sigma, 1)
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_bake(tiny_gpu, planes, tri_d, 4, 4, tiny.sigma, 1, ray_eps=0.0)
+
+
+def test_traversal_counters(tiny, tiny_gpu, tiny_points):
+    pts, tri, _ = tiny_points
+    stats = torch.zeros(4, dtype=torch.int64, device=DEV)
+    a = fipt.fipt_bake(tiny_gpu, torch.from_numpy(pts).to(DEV), torch.from_numpy(tri).to(DEV),
+                       64, 64, tiny.sigma, 2, stats=stats)
+    b = _bake(tiny_gpu, pts, tri, 64, 64, tiny.sigma, 2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.cpu().numpy(), b)
+    rays, nodes, tris, hits = [int(v) for v in stats.cpu()]
+    assert 0 < rays <= 4096 * 448
+    assert hits <= rays and hits > 0.99 * rays      # a closed box
+    assert nodes >= rays and tris >= hits
+
+
+def _sampled_room_parity(sc, n_sample, seed):
+    """Full-size bake with the benchmark's launch; oracle on sampled points.
+    The sampled points' oracle shading points are written into the GPU
+    point buffer so both sides bake identical inputs; the GPU's own shading
+    points at those pixels are checked against the oracle's separately."""
+    scene = _scene(sc)
+    planes, tri_g = fipt.fipt_gen_points(scene, sc.cameras)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(sc.n_points, n_sample, replace=False)).astype(np.int64)
+    osc = ob.OracleScene(sc)
+    prim = ob.primary(osc, idx=idx)
+    # shading points: GPU vs oracle at the sampled pixels
+    Pg = planes[:, torch.from_numpy(idx).to(DEV)].cpu().numpy().astype(np.float64)
+    Tg = tri_g[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    clean = prim["n_outcomes"] == 1
+    np.testing.assert_array_equal(Tg[clean], prim["tri"][clean])
+    np.testing.assert_allclose(Pg[0:3, clean], prim["points"][0:3, clean], atol=2e-5)
+    # identical bake inputs at the sampled pixels
+    p32, t32 = ob.points_f32(prim)
+    planes[:, torch.from_numpy(idx).to(DEV)] = torch.from_numpy(p32).to(DEV)
+    tri_g[torch.from_numpy(idx).to(DEV)] = torch.from_numpy(t32).to(DEV)
+    out = fipt.fipt_bake(scene, planes, tri_g, sc.spp, sc.spp, sc.sigma, sc.seed)
+    torch.cuda.synchronize()
+    got = out[:, torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    full_p = np.zeros((9, sc.n_points), np.float32)
+    full_t = np.full(sc.n_points, -1, np.int32)
+    full_p[:, idx] = p32
+    full_t[idx] = t32
+    want = ob.bake(osc, full_p, full_t, idx=idx, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed)
+    scene.destroy()
+    return got, want
+
+
+def test_room_full_size_sampled_parity():
+    sc = synth.room()
+    got, want = _sampled_room_parity(sc, 32, seed=41)
+    r = bake_report(got, want)
+    print("room parity:", r)
+    assert_bake_parity(got, want, min_frac=31 / 32)
+
+
+def test_large_room_full_size_sampled_parity():
+    sc = synth.large_room()
+    got, want = _sampled_room_parity(sc, 8, seed=43)
+    r = bake_report(got, want)
+    print("large room parity:", r)
+    assert_bake_parity(got, want, min_frac=7 / 8)

@@ -1,0 +1,159 @@
+"""GPU parity of the factored re-render, loss and gradient and of the
+trilinear material grid and its adjoint, through the C ABI.
+
+Sizes: 100,003 points (many workgroups and a ragged tail) and the full
+differentiation workload of 1,843,200 points; a 128^3 grid."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import render as orr
+from paper_2304_05669_amd import fipt
+from tests.parity import assert_close_rel
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+SIG = synth.SIGMA_GRID
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+@pytest.mark.parametrize("n", [1, 63, 100003, 1843200])
+@pytest.mark.parametrize("tone", [0, 1])
+def test_render_loss_parity(n, tone):
+    sh = synth.random_shading(n, 6, seed=n % 97)
+    mat = synth.random_materials(n, seed=n % 89 + 1)
+    obs = synth.random_observations(n, seed=n % 83 + 2)
+    loss_o, grad_o, lr_o = orr.loss_and_grad(sh, mat, obs, SIG, tone)
+    buf, grad, lr = fipt.fipt_render_loss(_t(sh), _t(mat), _t(obs), SIG, tone, want_grad=True,
+                                          want_lr=True)
+    torch.cuda.synchronize()
+    loss_g = float(buf[0].item())
+    assert abs(loss_g - loss_o) <= 1e-6 * abs(loss_o), (loss_g, loss_o)
+    assert_close_rel(grad.cpu().numpy(), grad_o, 1e-4, what="gradient")
+    assert_close_rel(lr.cpu().numpy(), lr_o, 1e-5, what="Lr")
+    # same inputs, same bits
+    buf2, grad2, _ = fipt.fipt_render_loss(_t(sh), _t(mat), _t(obs), SIG, tone)
+    torch.cuda.synchronize()
+    assert float(buf2[0].item()) == loss_g
+    assert torch.equal(grad2, grad)
+
+
+def test_loss_only_and_knots():
+    n = 4096
+    sh = synth.random_shading(n, 6, seed=1)
+    mat = synth.random_materials(n, seed=2)
+    mat[3, :6] = SIG                       # exactly on every knot
+    mat[3, 6] = 0.0                        # below the grid
+    mat[3, 7] = 1.5                        # above the grid
+    obs = synth.random_observations(n, seed=3)
+    loss_o, grad_o, lr_o = orr.loss_and_grad(sh, mat, obs, SIG)
+    buf, grad, lr = fipt.fipt_render_loss(_t(sh), _t(mat), _t(obs), SIG, want_grad=False,
+                                          want_lr=True)
+    torch.cuda.synchronize()
+    assert grad is None
+    assert abs(float(buf[0].item()) - loss_o) <= 1e-6 * loss_o
+    assert_close_rel(lr.cpu().numpy(), lr_o, 1e-5, what="Lr")
+    _, grad, _ = fipt.fipt_render_loss(_t(sh), _t(mat), _t(obs), SIG)
+    g = grad.cpu().numpy()
+    assert g[3, 6] == 0.0 and g[3, 7] == 0.0
+    assert_close_rel(g, grad_o, 1e-4, what="gradient at knots")
+
+
+def test_autograd_function_and_finite_differences():
+    n = 2000
+    sh = _t(synth.random_shading(n, 6, seed=4))
+    matn = synth.random_materials(n, seed=5)
+    # keep roughness away from knots so sigma +- eps stays in one segment
+    d = np.abs(matn[3][:, None] - np.asarray(SIG)[None, :]).min(axis=1)
+    matn[3, d < 2e-3] += 5e-3
+    obs = _t(synth.random_observations(n, seed=6))
+    mat = _t(matn).requires_grad_(True)
+    loss = fipt.FactoredLoss.apply(mat, sh, obs, SIG, 0)
+    (3.0 * loss).backward()
+    g = mat.grad.cpu().numpy().astype(np.float64)
+    _, grad_o, _ = orr.loss_and_grad(sh.cpu().numpy(), matn, obs.cpu().numpy(), SIG)
+    assert_close_rel(g, 3.0 * grad_o, 1e-4, what="autograd gradient")
+    # central differences of the GPU loss itself (eps 1e-3)
+    eps = 1e-3
+    rng = np.random.default_rng(0)
+    for p in rng.choice(n, 12, replace=False):
+        for c in range(5):
+            mp = matn.copy()
+            mm = matn.copy()
+            mp[c, p] += eps
+            mm[c, p] -= eps
+            lp = float(fipt.fipt_render_loss(sh, _t(mp), obs, SIG, want_grad=False)[0][0].item())
+            lm = float(fipt.fipt_render_loss(sh, _t(mm), obs, SIG, want_grad=False)[0][0].item())
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - g[c, p] / 3.0) <= 2e-3 * max(1.0, abs(fd)), (p, c, fd, g[c, p] / 3.0)
+
+
+def test_grid_gather_parity():
+    R = 128
+    grid = synth.material_grid(R, seed=11)
+    bmin = np.array([0.0, 0.0, 0.0], np.float32)
+    bmax = np.array([6.0, 5.0, 3.0], np.float32)
+    rng = np.random.default_rng(12)
+    n = 100003
+    pos = rng.uniform(-0.2, 1.1, size=(3, n)) * bmax[:, None]
+    pos = pos.astype(np.float32)
+    got = fipt.fipt_grid_gather(_t(grid), bmin, bmax, _t(pos))
+    torch.cuda.synchronize()
+    want = orr.grid_gather(grid, pos, bmin, bmax)
+    assert_close_rel(got.cpu().numpy(), want, 2e-5, what="grid gather")
+
+
+def test_grid_scatter_parity_and_determinism():
+    R = 128
+    bmin = np.array([0.0, 0.0, 0.0], np.float32)
+    bmax = np.array([6.0, 5.0, 3.0], np.float32)
+    rng = np.random.default_rng(13)
+    n = 200000
+    # points clustered on a few planes like surface points
+    pos = rng.uniform(0, 1, size=(3, n)) * bmax[:, None]
+    pos[2, : n // 2] = 0.0
+    pos[0, n // 2: 3 * n // 4] = 6.0
+    pos = pos.astype(np.float32)
+    gp = rng.standard_normal((5, n)).astype(np.float32)
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    got = plan.scatter(_t(gp))
+    again = plan.scatter(_t(gp))
+    torch.cuda.synchronize()
+    assert torch.equal(got, again)
+    want = orr.grid_scatter(gp, pos, bmin, bmax, R)
+    # the float64 sums are rounded once to float32
+    assert_close_rel(got.cpu().numpy().reshape(5, -1), want.reshape(5, -1), 1e-5, what="grid scatter")
+
+
+def test_grid_gather_autograd_end_to_end():
+    """Loss of the factored render with the material read from a grid:
+    d loss / d grid through GridGather + FactoredLoss equals the oracle's
+    scatter of its per-point gradient."""
+    R = 32
+    n = 50000
+    bmin = np.zeros(3, np.float32)
+    bmax = np.array([6.0, 5.0, 3.0], np.float32)
+    rng = np.random.default_rng(14)
+    pos = (rng.uniform(0, 1, size=(3, n)) * bmax[:, None]).astype(np.float32)
+    grid = synth.material_grid(R, seed=15)
+    sh = synth.random_shading(n, 6, seed=16)
+    obs = synth.random_observations(n, seed=17)
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    G = _t(grid).requires_grad_(True)
+    mat = fipt.GridGather.apply(G, plan, bmin, bmax, _t(pos))
+    loss = fipt.FactoredLoss.apply(mat, _t(sh), _t(obs), SIG, 0)
+    loss.backward()
+    mat_o = orr.grid_gather(grid, pos, bmin, bmax)
+    loss_o, grad_o, _ = orr.loss_and_grad(sh, mat_o, obs, SIG)
+    gg_o = orr.grid_scatter(grad_o, pos, bmin, bmax, R)
+    assert abs(float(loss.item()) - loss_o) <= 1e-5 * loss_o
+    # per-point gradients carry float32 rounding; compare node sums against
+    # the sum of absolute contributions
+    absg = orr.grid_scatter(np.abs(grad_o), pos, bmin, bmax, R)
+    err = np.abs(G.grad.cpu().numpy().astype(np.float64) - gg_o)
+    assert np.all(err <= 1e-4 * absg + 1e-6 * np.abs(gg_o).max())

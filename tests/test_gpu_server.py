@@ -1,0 +1,132 @@
+"""Continuous-batching bake server: every request's result is bitwise the
+same as a plain bake of that request alone, whatever it was batched with;
+memory admission, cancellation, release and scene pinning."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2304_05669_amd import fipt
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def _scene(sc):
+    s = fipt.Scene(sc.verts, sc.tris, device=0)
+    kind = fipt.CACHE_VERTEX if sc.cache_kind == "vertex" else fipt.CACHE_TRIANGLE
+    s.set_radiance(torch.from_numpy(sc.cache).to(DEV), kind, torch.from_numpy(sc.emission).to(DEV))
+    return s
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    tiny = synth.tiny_box()
+    room = synth.room(n_cams=2, width=160, height=120)
+    out = []
+    for sc in (tiny, room):
+        s = _scene(sc)
+        planes, tri = fipt.fipt_gen_points(s, sc.cameras)
+        out.append((sc, s, planes, tri))
+    torch.cuda.synchronize()
+    yield out
+    for _, s, _, _ in out:
+        s.destroy()
+
+
+def _alone(scene, planes, tri, off, cnt, spp_d, spp_s, sigma, seed):
+    p = planes[:, off:off + cnt].contiguous()
+    t = tri[off:off + cnt].contiguous()
+    out = fipt.fipt_bake(scene, p, t, spp_d, spp_s, sigma, seed)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_alone_equals_mix(scenes):
+    reqs = [
+        # scene, offset, count, spp_d, spp_s, sigma, seed
+        (0, 0, 4096, 64, 64, synth.SIGMA_GRID, 1),
+        (1, 100, 20000, 16, 16, synth.SIGMA_GRID, 2),
+        (0, 17, 1000, 37, 5, (0.1, 0.5, 0.9), 3),
+        (1, 5000, 7777, 128, 32, (0.05, 0.3, 0.6, 1.0), 4),
+        (1, 0, 38400, 24, 24, synth.SIGMA_GRID, 5),
+        (0, 4000, 96, 200, 3, (0.02,), 6),
+    ]
+    srv = fipt.Server(device=0, pool_bytes=256 << 20, max_inflight=8, samples_per_launch=1 << 22)
+    try:
+        tickets = []
+        for k, (si, off, cnt, sd, ss, sig, seed) in enumerate(reqs):
+            sc, s, planes, tri = scenes[si]
+            tickets.append(srv.submit(s, planes, tri, sd, ss, sig, seed, offset=off, count=cnt))
+            if k == 2:
+                time.sleep(0.01)          # later requests arrive while others run
+        for t in tickets:
+            assert srv.wait(t, timeout_s=120.0)
+        st = srv.stats()
+        assert st.completed == len(reqs) and st.launches >= 1
+        for t, (si, off, cnt, sd, ss, sig, seed) in zip(tickets, reqs):
+            sc, s, planes, tri = scenes[si]
+            res = srv.result(t)
+            ref = _alone(s, planes, tri, off, cnt, sd, ss, sig, seed)
+            assert torch.equal(res.shading, ref), f"request {t} differs from its plain bake"
+            assert res.t_submit_us <= res.t_admit_us <= res.t_done_us
+            srv.release(t)
+        assert srv.stats().pool_in_use == 0
+    finally:
+        srv.destroy()
+
+
+def test_memory_admission_and_cancel(scenes):
+    sc, s, planes, tri = scenes[1]
+    n = planes.shape[1]
+    per = (3 + 6 * 6) * 4 * 9000          # bytes of one 9000-point request
+    srv = fipt.Server(device=0, pool_bytes=2 * per + (1 << 20), max_inflight=8,
+                      samples_per_launch=1 << 20)
+    try:
+        ts = [srv.submit(s, planes, tri, 64, 64, synth.SIGMA_GRID, 10 + k, offset=k * 1000,
+                         count=9000) for k in range(5)]
+        st = srv.stats()
+        assert st.inflight <= 2          # only two outputs fit in the pool
+        # the last one is still queued behind the pool limit: cancel it
+        try:
+            srv.cancel(ts[-1])
+            cancelled = True
+        except fipt.FiptError as e:
+            assert e.code == fipt.EBUSY
+            cancelled = False
+        for t in ts[:-1]:
+            assert srv.wait(t, timeout_s=120.0)
+            srv.release(t)
+        if cancelled:
+            with pytest.raises(fipt.FiptError) as ei:
+                srv.poll(ts[-1])
+            assert ei.value.code == fipt.ECANCELED
+            srv.release(ts[-1])
+        else:
+            assert srv.wait(ts[-1], timeout_s=120.0)
+            srv.release(ts[-1])
+        assert srv.stats().pool_in_use == 0
+        with pytest.raises(fipt.FiptError):   # larger than the whole pool
+            srv.submit(s, planes, tri, 4, 4, synth.SIGMA_GRID, 1, offset=0, count=n)
+    finally:
+        srv.destroy()
+
+
+def test_scene_pinned_while_requests_reference_it():
+    sc = synth.tiny_box()
+    s = _scene(sc)
+    planes, tri = fipt.fipt_gen_points(s, sc.cameras)
+    srv = fipt.Server(device=0, pool_bytes=64 << 20, max_inflight=4, samples_per_launch=1 << 20)
+    try:
+        t = srv.submit(s, planes, tri, 256, 256, sc.sigma, 1)
+        with pytest.raises(fipt.FiptError) as ei:
+            s.destroy()
+        assert ei.value.code == fipt.EBUSY
+        assert srv.wait(t, timeout_s=60.0)
+        srv.release(t)
+    finally:
+        srv.destroy()
+    s.destroy()
