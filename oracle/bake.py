@@ -200,7 +200,9 @@ def bake(osc: OracleScene, pts: np.ndarray, tri: np.ndarray, idx=None,
     n_ambiguous (number of ambiguous samples)."""
     if sigma is None:
         sigma = osc.scene.sigma
-    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    # the library receives its roughness levels in single precision; the
+    # oracle promotes exactly those values
+    sigma = np.ascontiguousarray(np.asarray(sigma, dtype=np.float32), dtype=np.float64)
     K = len(sigma)
     pts = np.ascontiguousarray(pts, dtype=np.float32)
     tri = np.ascontiguousarray(tri, dtype=np.int32)

@@ -70,15 +70,15 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     // cell of every point, exactly as the device computes it
     const int64_t cr = res - 1;
     std::vector<std::pair<int64_t, int32_t>> key(n);
-    float scale[3];
-    for (int k = 0; k < 3; ++k) scale[k] = (float)(res - 1) / (bmax[k] - bmin[k]);
-    const float top = (float)(res - 1);
+    double scale[3];
+    for (int k = 0; k < 3; ++k) scale[k] = (double)(res - 1) / ((double)bmax[k] - (double)bmin[k]);
+    const double top = (double)(res - 1);
     for (int64_t p = 0; p < n; ++p) {
         int64_t idx[3];
         for (int k = 0; k < 3; ++k) {
             const float x = pos[k * n + p];
             if (!std::isfinite(x)) return fail(FIPT_EINVAL, "point %lld has a non-finite position", (long long)p);
-            const float u = std::fmin(std::fmax((x - bmin[k]) * scale[k], 0.0f), top);
+            const double u = std::fmin(std::fmax(((double)x - (double)bmin[k]) * scale[k], 0.0), top);
             idx[k] = std::min<int64_t>((int64_t)std::floor(u), res - 2);
         }
         key[p] = {idx[0] + cr * (idx[1] + cr * idx[2]), (int32_t)p};

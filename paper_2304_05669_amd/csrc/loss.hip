@@ -4,7 +4,8 @@
 //
 // All of these are streaming kernels bound by HBM bandwidth: one thread per
 // point, structure-of-arrays planes so every load and store of a wavefront
-// is one contiguous 256-byte segment.  The loss is summed per thread in
+// is one contiguous 256-byte segment.  Storage is float32; the render-loss
+// arithmetic runs in float64 (free at this arithmetic intensity).  The loss is summed per thread in
 // double, reduced per workgroup in a fixed butterfly order and finally
 // summed over workgroups in index order by one workgroup, so it is bitwise
 // reproducible for a given point count.
@@ -23,26 +24,30 @@ constexpr int kMaxPartials = FIPT_LOSS_SLOTS - 1;
 
 struct SigmaTable {
     float s[FIPT_MAX_LEVELS];
-    float inv_gap[FIPT_MAX_LEVELS];  // 1 / (s[j+1] - s[j])
+    double inv_gap[FIPT_MAX_LEVELS];  // 1 / (s[j+1] - s[j])
 };
 
-__device__ __forceinline__ float srgb_oetf(float x) {
-    return x <= 0.0031308f ? 12.92f * x : 1.055f * powf(x, 1.0f / 2.4f) - 0.055f;
+// Tone maps in double: the per-point arithmetic of this kernel runs in
+// float64, which costs nothing here (a few dozen operations per point
+// against ~200 bytes of traffic) and removes the float32 cancellation in
+// Lr - Lgt that would otherwise dominate the gradient of well-fit points.
+__device__ __forceinline__ double srgb_oetf(double x) {
+    return x <= 0.0031308 ? 12.92 * x : 1.055 * pow(x, 1.0 / 2.4) - 0.055;
 }
-__device__ __forceinline__ float srgb_oetf_d(float x) {
-    return x <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * powf(x, 1.0f / 2.4f - 1.0f);
+__device__ __forceinline__ double srgb_oetf_d(double x) {
+    return x <= 0.0031308 ? 12.92 : (1.055 / 2.4) * pow(x, 1.0 / 2.4 - 1.0);
 }
 
 template <int TONE>
-__device__ __forceinline__ float tone(float x) {
+__device__ __forceinline__ double tone(double x) {
     if (TONE == 0) return x;
-    return srgb_oetf(log1pf(fmaxf(x, 0.0f)));
+    return srgb_oetf(log1p(fmax(x, 0.0)));
 }
 template <int TONE>
-__device__ __forceinline__ float tone_d(float x) {
-    if (TONE == 0) return 1.0f;
-    if (!(x > 0.0f)) return 0.0f;
-    return srgb_oetf_d(log1pf(x)) / (1.0f + x);
+__device__ __forceinline__ double tone_d(double x) {
+    if (TONE == 0) return 1.0;
+    if (!(x > 0.0)) return 0.0;
+    return srgb_oetf_d(log1p(x)) / (1.0 + x);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -66,52 +71,52 @@ __global__ __launch_bounds__(kBlock) void k_render_loss(
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += stride) {
-        const float ar = mat[p], ag = mat[ms + p], ab = mat[2 * ms + p];
-        const float sg = mat[3 * ms + p], m = mat[4 * ms + p];
+        const double a[3] = {mat[p], mat[ms + p], mat[2 * ms + p]};
+        const float sg = mat[3 * ms + p];
+        const double m = mat[4 * ms + p];
         // bracket: largest j with s_j <= sigma, clamped to [0, K-2]
         int j = 0;
         for (int k = 1; k < K - 1; ++k) j = (tab.s[k] <= sg) ? k : j;
         const bool clamped = (sg < tab.s[0]) | (sg > tab.s[K - 1]);
-        const float t = fminf(fmaxf((sg - tab.s[j]) * tab.inv_gap[j], 0.0f), 1.0f);
-        const float ld[3] = {sh[p], sh[ss + p], sh[2 * ss + p]};
+        const double t = fmin(fmax(((double)sg - (double)tab.s[j]) * tab.inv_gap[j], 0.0), 1.0);
         const float* s0j = sh + (3 + 3 * j) * ss + p;
         const float* s1j = sh + (3 + 3 * K + 3 * j) * ss + p;
-        float a[3] = {ar, ag, ab};
-        float dsig = 0.0f, dm = 0.0f;
-        float da[3];
-        float lr[3];
-        float l = 0.0f;
+        double dsig = 0.0, dm = 0.0;
+        double da[3], lr[3];
+        double l = 0.0;
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float A0 = s0j[c * ss], B0 = s0j[(c + 3) * ss];
-            const float A1 = s1j[c * ss], B1 = s1j[(c + 3) * ss];
-            const float L0 = A0 + t * (B0 - A0);
-            const float L1 = A1 + t * (B1 - A1);
-            const float kd = a[c] * (1.0f - m);
-            const float ks = 0.04f * (1.0f - m) + a[c] * m;
-            const float r = kd * ld[c] + ks * L0 + L1;
+            const double ld = sh[c * ss + p];
+            const double A0 = s0j[c * ss], B0 = s0j[(c + 3) * ss];
+            const double A1 = s1j[c * ss], B1 = s1j[(c + 3) * ss];
+            const double L0 = (1.0 - t) * A0 + t * B0;
+            const double L1 = (1.0 - t) * A1 + t * B1;
+            const double kd = a[c] * (1.0 - m);
+            const double ks = 0.04 * (1.0 - m) + a[c] * m;
+            const double r = kd * ld + ks * L0 + L1;
             lr[c] = r;
-            const float y = obs[c * os + p];
-            const float res = tone<TONE>(r) - tone<TONE>(y);
+            const double y = obs[c * os + p];
+            const double res = tone<TONE>(r) - tone<TONE>(y);
             l += res * res;
             if (GRAD) {
-                const float g = 2.0f * res * tone_d<TONE>(r);
-                da[c] = g * ((1.0f - m) * ld[c] + m * L0);
-                dm += g * (-a[c] * ld[c] + (a[c] - 0.04f) * L0);
+                const double g = 2.0 * res * tone_d<TONE>(r);
+                da[c] = g * ((1.0 - m) * ld + m * L0);
+                dm += g * (-a[c] * ld + (a[c] - 0.04) * L0);
                 dsig += g * (ks * (B0 - A0) + (B1 - A1));
             }
         }
-        acc += (double)l;
+        acc += l;
         if (GRAD) {
-            grad[p] = da[0];
-            grad[gs + p] = da[1];
-            grad[2 * gs + p] = da[2];
-            grad[3 * gs + p] = clamped ? 0.0f : dsig * tab.inv_gap[j];
-            grad[4 * gs + p] = dm;
+            grad[p] = (float)da[0];
+            grad[gs + p] = (float)da[1];
+            grad[2 * gs + p] = (float)da[2];
+            grad[3 * gs + p] = clamped ? 0.0f : (float)(dsig * tab.inv_gap[j]);
+            grad[4 * gs + p] = (float)dm;
         }
         if (LR) {
-            Lr[p] = lr[0];
-            Lr[ls + p] = lr[1];
-            Lr[2 * ls + p] = lr[2];
+            Lr[p] = (float)lr[0];
+            Lr[ls + p] = (float)lr[1];
+            Lr[2 * ls + p] = (float)lr[2];
         }
     }
     const double tot = block_sum(acc, s_red);
@@ -131,24 +136,18 @@ __global__ __launch_bounds__(kBlock) void k_final_sum(const double* partials, in
 }
 
 // ---- trilinear grid --------------------------------------------------------
+// Grid coordinates and weights are computed in float64: both grid kernels
+// are bound by memory traffic, and float32 coordinates would carry an
+// absolute error of ~1e-5 in the cell fraction (about one unit in the last
+// place of res - 1).
 struct GridFrame {
-    float lo[3];
-    float scale[3];   // (res - 1) / (bmax - bmin)
+    double lo[3];
+    double scale[3];   // (res - 1) / (bmax - bmin)
     int res;
 };
 
-__device__ __forceinline__ void cell_of(const GridFrame& g, float x, float y, float z, int& i,
-                                        int& j, int& k, float& fx, float& fy, float& fz) {
-    const float top = (float)(g.res - 1);
-    const float ux = fminf(fmaxf((x - g.lo[0]) * g.scale[0], 0.0f), top);
-    const float uy = fminf(fmaxf((y - g.lo[1]) * g.scale[1], 0.0f), top);
-    const float uz = fminf(fmaxf((z - g.lo[2]) * g.scale[2], 0.0f), top);
-    i = min((int)floorf(ux), g.res - 2);
-    j = min((int)floorf(uy), g.res - 2);
-    k = min((int)floorf(uz), g.res - 2);
-    fx = ux - (float)i;
-    fy = uy - (float)j;
-    fz = uz - (float)k;
+__device__ __forceinline__ double grid_u(const GridFrame& g, float x, int axis) {
+    return fmin(fmax(((double)x - g.lo[axis]) * g.scale[axis], 0.0), (double)(g.res - 1));
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_gather(const float* __restrict__ grid, int C,
@@ -157,23 +156,26 @@ __global__ __launch_bounds__(kBlock) void k_grid_gather(const float* __restrict_
                                                         float* __restrict__ out, int64_t os) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
-    int i, j, k;
-    float fx, fy, fz;
-    cell_of(g, pos[p], pos[ps + p], pos[2 * ps + p], i, j, k, fx, fy, fz);
+    const double ux = grid_u(g, pos[p], 0), uy = grid_u(g, pos[ps + p], 1),
+                 uz = grid_u(g, pos[2 * ps + p], 2);
+    const int i = min((int)floor(ux), g.res - 2);
+    const int j = min((int)floor(uy), g.res - 2);
+    const int k = min((int)floor(uz), g.res - 2);
+    const double fx = ux - i, fy = uy - j, fz = uz - k;
     const int64_t R = g.res;
     const int64_t plane = R * R * R;
     const int64_t base = i + R * (j + R * (int64_t)k);
     const int64_t dy = R, dz = R * R;
-    const float w000 = (1 - fx) * (1 - fy) * (1 - fz), w100 = fx * (1 - fy) * (1 - fz);
-    const float w010 = (1 - fx) * fy * (1 - fz), w110 = fx * fy * (1 - fz);
-    const float w001 = (1 - fx) * (1 - fy) * fz, w101 = fx * (1 - fy) * fz;
-    const float w011 = (1 - fx) * fy * fz, w111 = fx * fy * fz;
+    const double w000 = (1 - fx) * (1 - fy) * (1 - fz), w100 = fx * (1 - fy) * (1 - fz);
+    const double w010 = (1 - fx) * fy * (1 - fz), w110 = fx * fy * (1 - fz);
+    const double w001 = (1 - fx) * (1 - fy) * fz, w101 = fx * (1 - fy) * fz;
+    const double w011 = (1 - fx) * fy * fz, w111 = fx * fy * fz;
     for (int c = 0; c < C; ++c) {
         const float* G = grid + c * plane + base;
-        const float v = w000 * G[0] + w100 * G[1] + w010 * G[dy] + w110 * G[dy + 1] +
-                        w001 * G[dz] + w101 * G[dz + 1] + w011 * G[dz + dy] +
-                        w111 * G[dz + dy + 1];
-        out[c * os + p] = v;
+        const double v = w000 * G[0] + w100 * G[1] + w010 * G[dy] + w110 * G[dy + 1] +
+                         w001 * G[dz] + w101 * G[dz + 1] + w011 * G[dz + dy] +
+                         w111 * G[dz + dy + 1];
+        out[c * os + p] = (float)v;
     }
 }
 
@@ -192,25 +194,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter_cells(GridPlanDev plan, Grid
         for (int ch = 0; ch < C; ++ch) acc[c][ch] = 0.0;
     const int64_t n = plan.n_points;
     const float* pos = plan.pos;
-    // the plan fixed the cell; fractions are taken relative to it
+    // the plan fixed the cell (with the same float64 arithmetic)
     const int32_t cid = plan.cell_id[m];
     const int cr = g.res - 1;
     const int ci = cid % cr, cj = (cid / cr) % cr, ck = cid / (cr * cr);
-    const float top = (float)(g.res - 1);
     for (int32_t q = plan.cell_start[m]; q < plan.cell_start[m + 1]; ++q) {
         const int32_t p = plan.perm[q];
-        const float fx = fminf(fmaxf((pos[p] - g.lo[0]) * g.scale[0], 0.0f), top) - (float)ci;
-        const float fy = fminf(fmaxf((pos[n + p] - g.lo[1]) * g.scale[1], 0.0f), top) - (float)cj;
-        const float fz = fminf(fmaxf((pos[2 * n + p] - g.lo[2]) * g.scale[2], 0.0f), top) - (float)ck;
-        const float w[8] = {(1 - fx) * (1 - fy) * (1 - fz), fx * (1 - fy) * (1 - fz),
-                            (1 - fx) * fy * (1 - fz),       fx * fy * (1 - fz),
-                            (1 - fx) * (1 - fy) * fz,       fx * (1 - fy) * fz,
-                            (1 - fx) * fy * fz,             fx * fy * fz};
+        const double fx = grid_u(g, pos[p], 0) - ci;
+        const double fy = grid_u(g, pos[n + p], 1) - cj;
+        const double fz = grid_u(g, pos[2 * n + p], 2) - ck;
+        const double w[8] = {(1 - fx) * (1 - fy) * (1 - fz), fx * (1 - fy) * (1 - fz),
+                             (1 - fx) * fy * (1 - fz),       fx * fy * (1 - fz),
+                             (1 - fx) * (1 - fy) * fz,       fx * (1 - fy) * fz,
+                             (1 - fx) * fy * fz,             fx * fy * fz};
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) {
             const double v = (double)gp[ch * gs + p];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[c][ch] += (double)w[c] * v;
+            for (int c = 0; c < 8; ++c) acc[c][ch] += w[c] * v;
         }
     }
     double* dst = plan.partials + m * 64;
@@ -273,7 +274,7 @@ int launch_render_loss(const float* sh, int64_t ss, int64_t n, int32_t K, const 
     SigmaTable tab;
     for (int k = 0; k < FIPT_MAX_LEVELS; ++k) {
         tab.s[k] = k < K ? sigma[k] : 0.0f;
-        tab.inv_gap[k] = (k + 1 < K) ? 1.0f / (sigma[k + 1] - sigma[k]) : 0.0f;
+        tab.inv_gap[k] = (k + 1 < K) ? 1.0 / ((double)sigma[k + 1] - (double)sigma[k]) : 0.0;
     }
     const int64_t want = (n + kBlock - 1) / kBlock;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, kMaxPartials));
@@ -310,7 +311,7 @@ static GridFrame make_frame(const float* bmin, const float* bmax, int R) {
     GridFrame g;
     for (int k = 0; k < 3; ++k) {
         g.lo[k] = bmin[k];
-        g.scale[k] = (float)(R - 1) / (bmax[k] - bmin[k]);
+        g.scale[k] = (double)(R - 1) / ((double)bmax[k] - (double)bmin[k]);
     }
     g.res = R;
     return g;

@@ -236,8 +236,9 @@ def make_params(spp_d: int, spp_s: int, sigma, seed: int, ray_eps: float = 1e-4)
     p = BakeParams()
     p.spp_d = int(spp_d)
     p.spp_s = int(spp_s)
+    # the C ABI validates n_levels (an over-long table is rejected there)
     p.n_levels = len(sigma)
-    p.sigma = _f32_array(list(sigma) + [0.0] * (MAX_LEVELS - len(sigma)), MAX_LEVELS)
+    p.sigma = _f32_array(list(sigma)[:MAX_LEVELS], MAX_LEVELS)
     p.seed = int(seed)
     p.ray_eps = float(ray_eps)
     p.flags = 0

@@ -15,7 +15,8 @@ from tests.parity import assert_close_rel
 pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda", 0)
-SIG = synth.SIGMA_GRID
+# the library takes roughness knots in single precision; so does the oracle
+SIG = tuple(float(s) for s in np.asarray(synth.SIGMA_GRID, np.float32))
 
 
 def _t(a, dtype=torch.float32):
