@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=0)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--no-counters", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 1 GiB device-to-device copies (counter scaling and "
+                         "achievable HBM bandwidth) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the hot path has no multi-GPU leg); "
@@ -199,6 +202,22 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = 1 << 28                                      # 1 GiB of float32
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 5
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                          "copy_ms": ms, "copy_gbs": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
 
     t_setup = time.perf_counter()
     sc = synth.room()

@@ -169,6 +169,287 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, int64_t p, int l
     }
 }
 
+// ---------------------------------------------------------------------------
+// Bake of one point with dynamic sample refill (K <= kRefillMaxK).
+//
+// The chunked bake above keeps a lane idle from the moment its ray finishes
+// until the slowest ray of its 64-sample chunk does; with incoherent rays
+// the slowest is several times the average.  Here every lane owns one ray
+// at a time and, once a batch of lanes has finished, those lanes fold their
+// results into per-lane accumulators and take the next samples of the point
+// (handed out in lane order by a ballot, so the assignment depends only on
+// the inputs).  Traversal is while-while: all lanes descend inner nodes
+// until each sits on a leaf or is done, then test their leaves together.
+// At the end of the point one fixed butterfly sums the accumulators.
+constexpr int kRefillMaxK = 10;      // 3 + 6K output slots fit the 64 lanes
+constexpr int32_t kDone = INT_MIN;   // never a valid leaf reference (< 2^28 triangles)
+constexpr int kRefillMin = 16;       // refill once this many lanes are free
+
+enum LaneState { kIdle = 0, kTracing = 1, kFinished = 2 };
+
+template <bool COUNT>
+__device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p, int lane,
+                                                  int32_t* stack, uint32_t& n_rays,
+                                                  uint32_t& n_nodes, uint32_t& n_tris,
+                                                  uint32_t& n_hits) {
+    const int K = b.K;
+    const int P = 3 + 6 * K;
+    const int64_t ps = b.pts_stride;
+    const int32_t tri = b.ptri[p];
+    V3 x = v3(b.pts[p], b.pts[ps + p], b.pts[2 * ps + p]);
+    V3 n = v3(b.pts[3 * ps + p], b.pts[4 * ps + p], b.pts[5 * ps + p]);
+    const V3 wo = v3(b.pts[6 * ps + p], b.pts[7 * ps + p], b.pts[8 * ps + p]);
+    float cos_o = dev::dot(n, wo);
+    if (tri >= 0 && cos_o < 0.0f) {
+        n = v3(-n.x, -n.y, -n.z);
+        cos_o = -cos_o;
+    }
+    const int64_t os = b.out_stride;
+    if (!(tri >= 0 && cos_o > 0.0f)) {
+        for (int j = lane; j < P; j += 64) b.out[(int64_t)j * os + p] = 0.0f;
+        return;
+    }
+    V3 ft, fb;
+    dev::make_frame(n, ft, fb);
+    const V3 o = x + b.eps * n;
+    const int64_t rng_p = p + b.p_offset;
+    const int spp_d = b.spp_d, spp_s = b.spp_s;
+    const int S = spp_d + K * spp_s;
+    const DeviceScene& sc = b.sc;
+
+    // Lane j owns output slot j (slot layout as slot_plane).  Each lane sums
+    // its contributions for its current lobe in cur[]; a lane's lobes only
+    // increase (samples are handed out in order), so when it moves on, its
+    // partial sums for the old lobe are flushed: all lanes leaving the same
+    // lobe at once are summed by the fixed butterfly and the owners add the
+    // totals.  Everything depends only on the inputs, so results are
+    // reproducible bit for bit.
+    float own = 0.0f;
+    float cur0 = 0.0f, cur1 = 0.0f, cur2 = 0.0f, cur3 = 0.0f, cur4 = 0.0f, cur5 = 0.0f;
+    int cur_lobe = -1;
+    auto flush = [&](bool need) {
+        uint64_t m = __ballot(need);
+        while (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            const int l = __shfl(cur_lobe, leader, 64);
+            const bool in = need && cur_lobe == l;
+            m &= ~__ballot(in);
+            const float s0 = dev::wave_sum(in ? cur0 : 0.0f);
+            const float s1 = dev::wave_sum(in ? cur1 : 0.0f);
+            const float s2 = dev::wave_sum(in ? cur2 : 0.0f);
+            float s3 = 0.0f, s4 = 0.0f, s5 = 0.0f;
+            if (l > 0) {
+                s3 = dev::wave_sum(in ? cur3 : 0.0f);
+                s4 = dev::wave_sum(in ? cur4 : 0.0f);
+                s5 = dev::wave_sum(in ? cur5 : 0.0f);
+            }
+            const int r = lane - (l == 0 ? 0 : 3 + 6 * (l - 1));
+            if (r >= 0 && r < (l == 0 ? 3 : 6))
+                own += r == 0 ? s0 : r == 1 ? s1 : r == 2 ? s2 : r == 3 ? s3 : r == 4 ? s4 : s5;
+        }
+    };
+
+    int state = kIdle;
+    int lobe = 0;
+    float w0 = 0.0f, w1 = 0.0f;       // weights of the Ls0 / Ls1 (or Ld) contributions
+    V3 d = v3(0.0f, 0.0f, 1.0f);
+    float ix = 0.0f, iy = 0.0f, iz = 0.0f, oxi = 0.0f, oyi = 0.0f, ozi = 0.0f;
+    int32_t ref = kDone;
+    int sp = 0;
+    dev::Hit h;
+    h.leaf = -1;
+    h.t = INFINITY;
+    h.u = h.v = 0.0f;
+    int32_t best_orig = INT_MAX;
+    int next_q = 0;                   // wave-uniform: next sample to hand out
+
+    while (true) {
+        // ---- fold finished rays and refill free lanes ----------------------
+        const uint64_t tracing = __ballot(state == kTracing);
+        const int n_free = 64 - __popcll(tracing);
+        if (n_free >= kRefillMin || tracing == 0) {
+            const bool done = state == kFinished;
+            flush(done && cur_lobe >= 0 && cur_lobe != lobe);
+            if (done) {
+                const V3 R = dev::radiance(sc, h);
+                if (COUNT && h.leaf >= 0) ++n_hits;
+                if (cur_lobe != lobe) {
+                    cur0 = cur1 = cur2 = cur3 = cur4 = cur5 = 0.0f;
+                    cur_lobe = lobe;
+                }
+                // diffuse: w0 = 1 and w1 = 0
+                cur0 += R.x * w0;
+                cur1 += R.y * w0;
+                cur2 += R.z * w0;
+                cur3 += R.x * w1;
+                cur4 += R.y * w1;
+                cur5 += R.z * w1;
+                state = kIdle;
+            }
+            if (next_q >= S && tracing == 0) break;
+            const uint64_t free_mask = ~tracing;
+            if (next_q < S) {
+                if (state == kIdle) {
+                    const int rank = __popcll(free_mask & ((1ull << lane) - 1ull));
+                    const int q = next_q + rank;
+                    if (q < S) {
+                        lobe = lobe_of(q, spp_d, spp_s);
+                        const int s = lobe == 0 ? q : (q - spp_d) - (lobe - 1) * spp_s;
+                        float xi1, xi2;
+                        dev::lobe_uniforms(b.seed, rng_p, lobe, s, xi1, xi2);
+                        float sp_, cp_;
+                        sincospif(2.0f * xi2, &sp_, &cp_);
+                        bool shoot = false;
+                        if (lobe == 0) {
+                            const float r = sqrtf(xi1);
+                            d = dev::to_world(ft, fb, n, r * cp_, r * sp_, sqrtf(1.0f - xi1));
+                            w0 = 1.0f;
+                            w1 = 0.0f;
+                            shoot = true;
+                        } else {
+                            const float sg = b.sigma[lobe - 1];
+                            const float alpha = sg * sg;
+                            const float a2 = alpha * alpha;
+                            const float tan2 = a2 * xi1 / (1.0f - xi1);
+                            const float cos_m = 1.0f / sqrtf(1.0f + tan2);
+                            const float sin_m = sqrtf(tan2) * cos_m;
+                            const V3 m = dev::to_world(ft, fb, n, sin_m * cp_, sin_m * sp_, cos_m);
+                            const float om = dev::dot(wo, m);
+                            if (om > 0.0f) {
+                                d = (2.0f * om) * m - wo;
+                                const float ci = dev::dot(n, d);
+                                if (ci > 0.0f) {
+                                    const float G = dev::smith_g1(a2, ci) * dev::smith_g1(a2, cos_o);
+                                    const float w = G * om / (cos_o * cos_m);
+                                    const float f = 1.0f - om;
+                                    const float f2 = f * f;
+                                    const float F1 = f2 * f2 * f;
+                                    w0 = w * (1.0f - F1);
+                                    w1 = w * F1;
+                                    shoot = true;
+                                }
+                            }
+                        }
+                        if (shoot) {
+                            if (COUNT) ++n_rays;
+                            const float dx = fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x);
+                            const float dy = fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y);
+                            const float dz = fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z);
+                            ix = __builtin_amdgcn_rcpf(dx);
+                            iy = __builtin_amdgcn_rcpf(dy);
+                            iz = __builtin_amdgcn_rcpf(dz);
+                            oxi = o.x * ix;
+                            oyi = o.y * iy;
+                            ozi = o.z * iz;
+                            ref = 0;
+                            sp = 0;
+                            h.leaf = -1;
+                            h.t = INFINITY;
+                            h.u = h.v = 0.0f;
+                            best_orig = INT_MAX;
+                            state = kTracing;
+                        }
+                        // an invalid specular sample counts as zero: the lane
+                        // stays idle and takes another sample next time
+                    }
+                }
+                next_q = min(S, next_q + n_free);
+            }
+        }
+        // ---- traversal: inner nodes until every lane sits on a leaf -------
+        while (true) {
+            const bool inner = state == kTracing && ref >= 0;
+            if (!__any(inner)) break;
+            if (inner) {
+                if (COUNT) ++n_nodes;
+                const float4* np = reinterpret_cast<const float4*>(sc.nodes + ref);
+                const float4 na = np[0];
+                const float4 nb = np[1];
+                const float4 nc = np[2];
+                const int4 cc = reinterpret_cast<const int4*>(np)[3];
+                const float a_lx = fmaf(na.x, ix, -oxi), a_hx = fmaf(na.y, ix, -oxi);
+                const float a_ly = fmaf(na.z, iy, -oyi), a_hy = fmaf(na.w, iy, -oyi);
+                const float a_lz = fmaf(nc.x, iz, -ozi), a_hz = fmaf(nc.y, iz, -ozi);
+                const float b_lx = fmaf(nb.x, ix, -oxi), b_hx = fmaf(nb.y, ix, -oxi);
+                const float b_ly = fmaf(nb.z, iy, -oyi), b_hy = fmaf(nb.w, iy, -oyi);
+                const float b_lz = fmaf(nc.z, iz, -ozi), b_hz = fmaf(nc.w, iz, -ozi);
+                const float tmin0 = fmaxf(fmaxf(fminf(a_lx, a_hx), fminf(a_ly, a_hy)),
+                                          fmaxf(fminf(a_lz, a_hz), 0.0f));
+                const float tmax0 = fminf(fminf(fmaxf(a_lx, a_hx), fmaxf(a_ly, a_hy)),
+                                          fminf(fmaxf(a_lz, a_hz), h.t));
+                const float tmin1 = fmaxf(fmaxf(fminf(b_lx, b_hx), fminf(b_ly, b_hy)),
+                                          fmaxf(fminf(b_lz, b_hz), 0.0f));
+                const float tmax1 = fminf(fminf(fmaxf(b_lx, b_hx), fmaxf(b_ly, b_hy)),
+                                          fminf(fmaxf(b_lz, b_hz), h.t));
+                const bool hit0 = tmin0 <= tmax0;
+                const bool hit1 = tmin1 <= tmax1;
+                if (hit0 && hit1) {
+                    const bool first0 = tmin0 <= tmin1;
+                    stack[sp * kBlock] = first0 ? cc.y : cc.x;
+                    ++sp;
+                    ref = first0 ? cc.x : cc.y;
+                } else if (hit0) {
+                    ref = cc.x;
+                } else if (hit1) {
+                    ref = cc.y;
+                } else if (sp == 0) {
+                    ref = kDone;
+                } else {
+                    --sp;
+                    ref = stack[sp * kBlock];
+                }
+            }
+        }
+        // ---- leaves ---------------------------------------------------------
+        if (state == kTracing && ref != kDone) {
+            const int32_t lr = ~ref;
+            const int32_t first = lr >> 3;
+            const int32_t cnt = (lr & 7) + 1;
+            for (int i = 0; i < cnt; ++i) {
+                if (COUNT) ++n_tris;
+                const float4* tp = reinterpret_cast<const float4*>(sc.tris + first + i);
+                const float4 t0 = tp[0];
+                const float4 t1 = tp[1];
+                const float4 t2 = tp[2];
+                const V3 e1 = v3(t1.x, t1.y, t1.z);
+                const V3 e2 = v3(t2.x, t2.y, t2.z);
+                const V3 pv = dev::cross(d, e2);
+                const float det = dev::dot(e1, pv);
+                if (det == 0.0f) continue;
+                const float inv = __builtin_amdgcn_rcpf(det);
+                const V3 s = o - v3(t0.x, t0.y, t0.z);
+                const float u = dev::dot(s, pv) * inv;
+                const V3 qv = dev::cross(s, e1);
+                const float v = dev::dot(d, qv) * inv;
+                const float t = dev::dot(e2, qv) * inv;
+                const int32_t orig = __float_as_int(t0.w);
+                const bool inside = (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t > 0.0f);
+                const bool nearer = (t < h.t) | ((t == h.t) & (orig < best_orig));
+                if (inside & nearer) {
+                    h.t = t;
+                    h.u = u;
+                    h.v = v;
+                    h.leaf = first + i;
+                    best_orig = orig;
+                }
+            }
+            if (sp == 0) {
+                ref = kDone;
+            } else {
+                --sp;
+                ref = stack[sp * kBlock];
+            }
+        }
+        if (state == kTracing && ref == kDone) state = kFinished;
+    }
+    // ---- flush what is left, then every owner writes its plane -----------
+    flush(cur_lobe >= 0);
+    if (lane < P) {
+        const float cnt = lane < 3 ? (float)spp_d : (float)spp_s;
+        b.out[(int64_t)slot_plane(lane, K) * os + p] = own / cnt;
+    }
+}
+
 // Logical wavefront index with workgroups of one XCD made contiguous:
 // the dispatcher places workgroup i on XCD i % 8, so consecutive points go
 // to one XCD's L2.
@@ -183,15 +464,26 @@ __device__ __forceinline__ int64_t xcd_wave(int lane_wave) {
     return lb * kWaves + lane_wave;
 }
 
-template <bool COUNT>
+// The point index is the same in every lane of a wavefront; saying so lets
+// the compiler keep the point's data in scalar registers.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <bool COUNT, bool REFILL>
 __global__ __launch_bounds__(kBlock) void k_bake(BakeLaunch b, uint64_t* stats) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
     const int64_t nw = (int64_t)gridDim.x * kWaves;
     uint32_t n_rays = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
-    for (int64_t p = xcd_wave(threadIdx.x >> 6); p < b.n; p += nw) {
-        bake_point<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
+    for (int64_t p = wave_uniform(xcd_wave(threadIdx.x >> 6)); p < b.n; p += nw) {
+        if (REFILL)
+            bake_point_refill<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
+        else
+            bake_point<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
     }
     if (COUNT) {
         // lane counters -> wave totals -> one 64-bit atomic per wave
@@ -217,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, in
     while (true) {
         int32_t grab = 0;
         if (lane == 0) grab = atomicAdd(counter, 1);
-        grab = __shfl(grab, 0, 64);
+        grab = __builtin_amdgcn_readfirstlane(grab);
         if ((int64_t)grab >= total) break;
         // last tile whose first point is <= grab
         int lo = 0, hi = n_tiles - 1;
@@ -226,7 +518,11 @@ __global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, in
             if (tiles[mid].first <= grab) lo = mid;
             else hi = mid - 1;
         }
-        bake_point<false>(tiles[lo].job, grab - tiles[lo].first, lane, stack, a, bb, c, d);
+        const BakeLaunch& job = tiles[lo].job;
+        if (job.K <= kRefillMaxK)
+            bake_point_refill<false>(job, grab - tiles[lo].first, lane, stack, a, bb, c, d);
+        else
+            bake_point<false>(job, grab - tiles[lo].first, lane, stack, a, bb, c, d);
     }
 }
 
@@ -363,12 +659,17 @@ int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream) {
     int64_t blocks = std::min(want, cap);
     if (blocks >= 8) blocks &= ~int64_t(7);
     if (blocks < 1) blocks = 1;
-    if (stats)
-        hipLaunchKernelGGL(k_bake<true>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                           (hipStream_t)stream, b, stats);
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    hipStream_t st = (hipStream_t)stream;
+    const bool refill = b.K <= kRefillMaxK;
+    if (stats && refill)
+        hipLaunchKernelGGL((k_bake<true, true>), grid, block, 0, st, b, stats);
+    else if (stats)
+        hipLaunchKernelGGL((k_bake<true, false>), grid, block, 0, st, b, stats);
+    else if (refill)
+        hipLaunchKernelGGL((k_bake<false, true>), grid, block, 0, st, b, stats);
     else
-        hipLaunchKernelGGL(k_bake<false>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                           (hipStream_t)stream, b, stats);
+        hipLaunchKernelGGL((k_bake<false, false>), grid, block, 0, st, b, stats);
     return check_launch("bake");
 }
 
