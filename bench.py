@@ -31,7 +31,42 @@ import synth  # noqa: E402
 from paper_2304_05669_amd import fipt  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# operation per lane per cycle (packed FP32 instructions are not used)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic VALU operations per unit of bake work
+OPS_PER_NODE = 38      # two slab tests: 12 FMA, 24 min/max, 2 compares
+OPS_PER_TRI = 40       # Moller-Trumbore: 2 cross products, 4 dots, reciprocal, compares
+OPS_PER_SAMPLE = 180   # Philox4x32-10 (~100 integer ops) + direction and weights
+OPS_PER_HIT = 12       # radiance: barycentric blend of the corner cache + emission
+# render-loss bytes per point: material 20 + Ld 12 + two bracketing levels
+# of Ls0/Ls1 48 + Lgt 12 + gradient 20
+LOSS_BYTES_PER_POINT = 112
 SHADING_PLANES = 39
+COUNTERS = os.path.join(ROOT, "profiles", "counters_room.json")
+KERNEL_SOURCES = ("bake.hip", "device.hpp", "loss.hip", "fipt_internal.hpp")
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2304_05669_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken from the kernels as they are now (else None)."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if c.get("sources_sha") != sources_sha():
+        return {}
+    return {k: v.get("hbm_bytes_per_launch") for k, v in c.get("kernels", {}).items()}
 
 
 def log(*a):
@@ -71,8 +106,10 @@ def traversal_bytes(scene, planes, tri, sc, out):
     rays, nodes, tris, hits = [int(v) for v in stats.cpu()]
     n = planes.shape[1]
     P = 3 + 6 * len(sc.sigma)
+    samples = n * sc.spp * (1 + len(sc.sigma))
     total = nodes * 64 + tris * 48 + hits * 48 + n * 40 + n * P * 4
-    return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, bytes=total,
+    ops = nodes * OPS_PER_NODE + tris * OPS_PER_TRI + samples * OPS_PER_SAMPLE + hits * OPS_PER_HIT
+    return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, bytes=total, ops=ops,
                 nodes_per_ray=nodes / max(rays, 1), tris_per_ray=tris / max(rays, 1))
 
 
@@ -188,7 +225,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--no-counters", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -292,11 +329,9 @@ def main():
         trav = traversal_bytes(scene, planes, tri, sc, shading)
         log(f"traversal: {trav}")
     bake_bytes = trav["bytes"] if trav else None
-    achieved = bake_bytes / (t_bake * 1e-3) / 1e9 if trav else None
-    # render-loss: Ld + all 12 level planes x 3 channels (a per-point
-    # roughness touches every level's cache lines) + material + Lgt + grad
-    loss_bytes_pt = 4 * (P + 5 + 3 + 5)
-    loss_gbs = N * loss_bytes_pt / (t_loss * 1e-3) / 1e9
+    bake_tops = trav["ops"] / (t_bake * 1e-3) / 1e12 if trav else None
+    loss_gbs = N * LOSS_BYTES_PER_POINT / (t_loss * 1e-3) / 1e9
+    traffic = measured_traffic()
 
     cpu = None
     if not args.no_cpu:
@@ -333,12 +368,16 @@ def main():
         "render_loss_gbs": loss_gbs,
         "loss": loss_value,
         "traversal": trav,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
-                     "kernel": "k_bake", "algorithmic_bytes_per_launch": bake_bytes},
+        "roofline": {"bound": "alu", "achieved": bake_tops, "peak": PEAK_VALU_TOPS,
+                     "unit": "Tops/s", "frac": bake_tops / PEAK_VALU_TOPS if trav else None,
+                     "traffic": traffic.get("k_bake"), "kernel": "k_bake",
+                     "ops_per_launch": trav["ops"] if trav else None,
+                     "effective_traversal_gbs": bake_bytes / (t_bake * 1e-3) / 1e9 if trav else None,
+                     "traversal_bytes_per_launch": bake_bytes},
         "roofline_render_loss": {"bound": "hbm", "achieved": loss_gbs, "peak": PEAK_HBM_GBS,
                                  "unit": "GB/s", "frac": loss_gbs / PEAK_HBM_GBS,
-                                 "bytes_per_point": loss_bytes_pt},
+                                 "traffic": traffic.get("k_render_loss"),
+                                 "bytes_per_point": LOSS_BYTES_PER_POINT, "kernel": "k_render_loss"},
         "cpu_baseline": cpu,
         "serving": serving,
     }

@@ -185,40 +185,34 @@ template <int C>
 __global__ __launch_bounds__(kBlock) void k_scatter_cells(GridPlanDev plan, GridFrame g,
                                                           const float* __restrict__ gp,
                                                           int64_t gs) {
-    const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // eight consecutive threads share one occupied cell, one per corner, so
+    // the cell's point loads are broadcast within each group of eight
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t m = tid >> 3;
+    const int corner = (int)(tid & 7);
     if (m >= plan.n_occ) return;
-    double acc[8][C];
+    double acc[C];
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) acc[c][ch] = 0.0;
+    for (int ch = 0; ch < C; ++ch) acc[ch] = 0.0;
     const int64_t n = plan.n_points;
     const float* pos = plan.pos;
     // the plan fixed the cell (with the same float64 arithmetic)
     const int32_t cid = plan.cell_id[m];
     const int cr = g.res - 1;
     const int ci = cid % cr, cj = (cid / cr) % cr, ck = cid / (cr * cr);
+    const bool hx = corner & 1, hy = (corner >> 1) & 1, hz = corner >> 2;
     for (int32_t q = plan.cell_start[m]; q < plan.cell_start[m + 1]; ++q) {
         const int32_t p = plan.perm[q];
         const double fx = grid_u(g, pos[p], 0) - ci;
         const double fy = grid_u(g, pos[n + p], 1) - cj;
         const double fz = grid_u(g, pos[2 * n + p], 2) - ck;
-        const double w[8] = {(1 - fx) * (1 - fy) * (1 - fz), fx * (1 - fy) * (1 - fz),
-                             (1 - fx) * fy * (1 - fz),       fx * fy * (1 - fz),
-                             (1 - fx) * (1 - fy) * fz,       fx * (1 - fy) * fz,
-                             (1 - fx) * fy * fz,             fx * fy * fz};
+        const double w = (hx ? fx : 1 - fx) * (hy ? fy : 1 - fy) * (hz ? fz : 1 - fz);
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) {
-            const double v = (double)gp[ch * gs + p];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc[c][ch] += w[c] * v;
-        }
+        for (int ch = 0; ch < C; ++ch) acc[ch] += w * (double)gp[ch * gs + p];
     }
-    double* dst = plan.partials + m * 64;
+    double* dst = plan.partials + m * 64 + corner * 8;
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) dst[c * 8 + ch] = acc[c][ch];
+    for (int ch = 0; ch < C; ++ch) dst[ch] = acc[ch];
 }
 
 // Adjoint, pass 2: per active node, the sum of its corner partials in the
@@ -337,7 +331,7 @@ int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_
     int rc = check("grid_scatter fill");
     if (rc) return rc;
     if (p.n_occ == 0) return FIPT_OK;
-    const unsigned cb = (unsigned)((p.n_occ + kBlock - 1) / kBlock);
+    const unsigned cb = (unsigned)((8 * p.n_occ + kBlock - 1) / kBlock);
     switch (C) {
 #define FIPT_SC(N) case N: hipLaunchKernelGGL(k_scatter_cells<N>, dim3(cb), dim3(kBlock), 0, st, p, g, gp, gs); break
         FIPT_SC(1); FIPT_SC(2); FIPT_SC(3); FIPT_SC(4);
