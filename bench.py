@@ -44,29 +44,35 @@ OPS_PER_HIT = 12       # radiance: barycentric blend of the corner cache + emiss
 LOSS_BYTES_PER_POINT = 112
 SHADING_PLANES = 39
 COUNTERS = os.path.join(ROOT, "profiles", "counters_room.json")
-KERNEL_SOURCES = ("bake.hip", "device.hpp", "loss.hip", "fipt_internal.hpp")
+# the sources each measured kernel is built from
+KERNEL_SOURCES = {
+    "k_bake": ("bake.hip", "device.hpp", "fipt_internal.hpp"),
+    "k_render_loss": ("loss.hip", "fipt_internal.hpp"),
+}
 
 
-def sources_sha():
+def sources_sha(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2304_05669_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken from the kernels as they are now (else None)."""
+    """HBM bytes per launch from the committed counter summary, for each
+    kernel whose sources are unchanged since the counters were taken."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return {}
-    if c.get("sources_sha") != sources_sha():
-        return {}
-    return {k: v.get("hbm_bytes_per_launch") for k, v in c.get("kernels", {}).items()}
+    out = {}
+    for k, v in c.get("kernels", {}).items():
+        if k in KERNEL_SOURCES and v.get("sources_sha") == sources_sha(k):
+            out[k] = v.get("hbm_bytes_per_launch")
+    return out
 
 
 def log(*a):

@@ -134,15 +134,18 @@ struct GridPlanDev {
     int64_t n_points;
     float bmin[3], bmax[3];
     int32_t* perm;          // [n] points sorted by cell (stable)
-    int32_t* cell_start;    // [n_occ + 1] ranges into perm
-    int32_t* cell_id;       // [n_occ] linear cell index (x fastest, res-1 per axis)
-    int64_t n_occ;
+    int32_t* seg_start;     // [n_seg + 1] segment ranges into perm (<= 48 points each)
+    int32_t* seg_cell;      // [n_seg] segment's linear cell index (x fastest, res-1 per axis)
+    int64_t n_seg;
+    int32_t* cell_seg;      // [n_cell + 1] ranges of each occupied cell's segments
+    int64_t n_cell;
     int32_t* node_id;       // [n_act] active node linear index
     int32_t* node_start;    // [n_act + 1] ranges into node_src
     int32_t* node_src;      // [entries] (occupied cell index << 3) | corner
     int64_t n_act;
-    float* pos;             // [3][n_points] positions of the plan's points
-    double* partials;       // [n_occ][8][8] scratch (corner x channel)
+    float* pos;             // [3][n_points] positions in sorted (perm) order
+    double* seg_part;       // [n_seg][8][channels] scratch (room for 8 channels)
+    double* cell_part;      // [n_cell][8][channels] scratch
 };
 int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_t gp_stride,
                         float* grad_grid, void* stream);

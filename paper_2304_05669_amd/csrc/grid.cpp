@@ -1,11 +1,13 @@
 // Host set-up of the deterministic adjoint of the trilinear material grid
 // (fipt_grid_plan_*) and the scatter entry point.
 //
-// The plan sorts the points by grid cell once.  The adjoint then runs in two
-// passes with no atomics: every occupied cell sums weight * gradient of its
-// points into its eight corners (points in index order), then every node
-// adjacent to an occupied cell sums its corner partials (cells in index
-// order).  The result is bitwise reproducible.
+// The plan sorts the points by grid cell once and cuts every cell's run into
+// segments of at most 48 points.  The adjoint then runs in three passes
+// with no atomics: every segment sums weight * gradient of its points into
+// the eight corners of its cell (points in index order), every occupied
+// cell sums its segments (in order), and every node next to an occupied
+// cell sums the corner partials of at most eight cells (in order).  The
+// result is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,8 +30,8 @@ namespace {
 
 void plan_free(fipt_grid_plan p) {
     if (!p) return;
-    void* ptrs[] = {p->d.perm, p->d.cell_start, p->d.cell_id, p->d.node_id,
-                    p->d.node_start, p->d.node_src, p->d.pos, p->d.partials};
+    void* ptrs[] = {p->d.perm, p->d.seg_start, p->d.seg_cell, p->d.cell_seg, p->d.node_id,
+                    p->d.node_start, p->d.node_src, p->d.pos, p->d.seg_part, p->d.cell_part};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -84,15 +86,25 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
         key[p] = {idx[0] + cr * (idx[1] + cr * idx[2]), (int32_t)p};
     }
     std::sort(key.begin(), key.end());
-    std::vector<int32_t> perm(n), cell_start, cell_id;
+    // segments: runs of at most kSegmentMax points of one cell, so a cell
+    // seen by many pixels does not serialise on one thread
+    constexpr int64_t kSegmentMax = 48;
+    std::vector<int32_t> perm(n), seg_start, seg_cell, cell_seg, cell_id;
     for (int64_t q = 0; q < n; ++q) {
         perm[q] = key[q].second;
-        if (q == 0 || key[q].first != key[q - 1].first) {
-            cell_start.push_back((int32_t)q);
-            cell_id.push_back((int32_t)key[q].first);
+        const bool new_cell = q == 0 || key[q].first != key[q - 1].first;
+        if (new_cell || q - seg_start.back() >= kSegmentMax) {
+            if (new_cell) {
+                cell_seg.push_back((int32_t)seg_start.size());
+                cell_id.push_back((int32_t)key[q].first);
+            }
+            seg_start.push_back((int32_t)q);
+            seg_cell.push_back((int32_t)key[q].first);
         }
     }
-    cell_start.push_back((int32_t)n);
+    seg_start.push_back((int32_t)n);
+    cell_seg.push_back((int32_t)seg_cell.size());
+    const int64_t S = (int64_t)seg_cell.size();
     const int64_t M = (int64_t)cell_id.size();
     std::vector<std::pair<int64_t, int32_t>> nk;
     nk.reserve(8 * M);
@@ -114,7 +126,10 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
         }
     }
     node_start.push_back((int32_t)nk.size());
-    std::vector<float> pcopy(pos, pos + 3 * n);
+    // positions stored in sorted order: the adjoint reads them contiguously
+    std::vector<float> pcopy(3 * n);
+    for (int k = 0; k < 3; ++k)
+        for (int64_t q = 0; q < n; ++q) pcopy[k * n + q] = pos[k * n + perm[q]];
 
     int prev = -1;
     (void)hipGetDevice(&prev);
@@ -129,24 +144,28 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
         d.bmin[k] = bmin[k];
         d.bmax[k] = bmax[k];
     }
-    d.n_occ = M;
+    d.n_seg = S;
+    d.n_cell = M;
     d.n_act = (int64_t)node_id.size();
     int rc;
-    if ((rc = upload(&d.perm, perm, &p->bytes)) || (rc = upload(&d.cell_start, cell_start, &p->bytes)) ||
-        (rc = upload(&d.cell_id, cell_id, &p->bytes)) || (rc = upload(&d.node_id, node_id, &p->bytes)) ||
+    if ((rc = upload(&d.perm, perm, &p->bytes)) || (rc = upload(&d.seg_start, seg_start, &p->bytes)) ||
+        (rc = upload(&d.seg_cell, seg_cell, &p->bytes)) || (rc = upload(&d.cell_seg, cell_seg, &p->bytes)) ||
+        (rc = upload(&d.node_id, node_id, &p->bytes)) ||
         (rc = upload(&d.node_start, node_start, &p->bytes)) ||
         (rc = upload(&d.node_src, node_src, &p->bytes)) || (rc = upload(&d.pos, pcopy, &p->bytes))) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return rc;
     }
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d.partials), sizeof(double) * 64 * std::max<int64_t>(M, 1));
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d.seg_part), sizeof(double) * 64 * std::max<int64_t>(S, 1));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void**>(&d.cell_part), sizeof(double) * 64 * std::max<int64_t>(M, 1));
     if (e != hipSuccess) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return fail(FIPT_ENOMEM, "hipMalloc partials: %s", hipGetErrorString(e));
     }
-    p->bytes += (int64_t)(sizeof(double) * 64 * M);
+    p->bytes += (int64_t)(sizeof(double) * 64 * (S + M));
     if (prev >= 0) (void)hipSetDevice(prev);
     *out = p;
     return FIPT_OK;

@@ -179,44 +179,61 @@ __global__ __launch_bounds__(kBlock) void k_grid_gather(const float* __restrict_
     }
 }
 
-// Adjoint, pass 1: per occupied cell, the eight corner sums of
-// weight * gradient over the cell's points (taken in index order), double.
+// Adjoint, pass 1: per segment, the eight corner sums of weight * gradient
+// over the segment's points (taken in index order), double.
 template <int C>
-__global__ __launch_bounds__(kBlock) void k_scatter_cells(GridPlanDev plan, GridFrame g,
+__global__ __launch_bounds__(kBlock) void k_scatter_segments(GridPlanDev plan, GridFrame g,
                                                           const float* __restrict__ gp,
                                                           int64_t gs) {
-    // eight consecutive threads share one occupied cell, one per corner, so
-    // the cell's point loads are broadcast within each group of eight
+    // eight consecutive threads share one segment, one per corner, so the
+    // segment's point loads are broadcast within each group of eight
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t m = tid >> 3;
     const int corner = (int)(tid & 7);
-    if (m >= plan.n_occ) return;
+    if (m >= plan.n_seg) return;
     double acc[C];
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) acc[ch] = 0.0;
     const int64_t n = plan.n_points;
     const float* pos = plan.pos;
     // the plan fixed the cell (with the same float64 arithmetic)
-    const int32_t cid = plan.cell_id[m];
+    const int32_t cid = plan.seg_cell[m];
     const int cr = g.res - 1;
     const int ci = cid % cr, cj = (cid / cr) % cr, ck = cid / (cr * cr);
     const bool hx = corner & 1, hy = (corner >> 1) & 1, hz = corner >> 2;
-    for (int32_t q = plan.cell_start[m]; q < plan.cell_start[m + 1]; ++q) {
+    // positions are stored in sorted order; gradients come in point order
+    for (int32_t q = plan.seg_start[m]; q < plan.seg_start[m + 1]; ++q) {
         const int32_t p = plan.perm[q];
-        const double fx = grid_u(g, pos[p], 0) - ci;
-        const double fy = grid_u(g, pos[n + p], 1) - cj;
-        const double fz = grid_u(g, pos[2 * n + p], 2) - ck;
+        const double fx = grid_u(g, pos[q], 0) - ci;
+        const double fy = grid_u(g, pos[n + q], 1) - cj;
+        const double fz = grid_u(g, pos[2 * n + q], 2) - ck;
         const double w = (hx ? fx : 1 - fx) * (hy ? fy : 1 - fy) * (hz ? fz : 1 - fz);
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) acc[ch] += w * (double)gp[ch * gs + p];
     }
-    double* dst = plan.partials + m * 64 + corner * 8;
+    double* dst = plan.seg_part + (m * 8 + corner) * C;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) dst[ch] = acc[ch];
 }
 
-// Adjoint, pass 2: per active node, the sum of its corner partials in the
-// plan's fixed order.
+// Adjoint, pass 2: per occupied cell and corner, the sum of its segments'
+// partials in order.
+__global__ __launch_bounds__(kBlock) void k_scatter_combine(GridPlanDev plan, int C) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t m = tid >> 3;
+    const int corner = (int)(tid & 7);
+    if (m >= plan.n_cell) return;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t g = plan.cell_seg[m]; g < plan.cell_seg[m + 1]; ++g) {
+        const double* pp = plan.seg_part + ((int64_t)g * 8 + corner) * C;
+        for (int ch = 0; ch < C; ++ch) s[ch] += pp[ch];
+    }
+    double* dst = plan.cell_part + (m * 8 + corner) * C;
+    for (int ch = 0; ch < C; ++ch) dst[ch] = s[ch];
+}
+
+// Adjoint, pass 3: per active node, the sum of at most eight cell partials
+// in the plan's fixed order.
 __global__ __launch_bounds__(kBlock) void k_scatter_nodes(GridPlanDev plan, int C,
                                                           const double* __restrict__ part,
                                                           float* __restrict__ out) {
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_nodes(GridPlanDev plan, int 
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int32_t e = plan.node_start[a]; e < plan.node_start[a + 1]; ++e) {
         const int32_t src = plan.node_src[e];
-        const double* pp = part + (int64_t)(src >> 3) * 64 + (src & 7) * 8;
+        const double* pp = part + ((int64_t)(src >> 3) * 8 + (src & 7)) * C;
         for (int ch = 0; ch < C; ++ch) s[ch] += pp[ch];
     }
     const int32_t node = plan.node_id[a];
@@ -330,20 +347,24 @@ int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_
                        0, st, grad_grid, total);
     int rc = check("grid_scatter fill");
     if (rc) return rc;
-    if (p.n_occ == 0) return FIPT_OK;
-    const unsigned cb = (unsigned)((8 * p.n_occ + kBlock - 1) / kBlock);
+    if (p.n_seg == 0) return FIPT_OK;
+    const unsigned cb = (unsigned)((8 * p.n_seg + kBlock - 1) / kBlock);
     switch (C) {
-#define FIPT_SC(N) case N: hipLaunchKernelGGL(k_scatter_cells<N>, dim3(cb), dim3(kBlock), 0, st, p, g, gp, gs); break
+#define FIPT_SC(N) case N: hipLaunchKernelGGL(k_scatter_segments<N>, dim3(cb), dim3(kBlock), 0, st, p, g, gp, gs); break
         FIPT_SC(1); FIPT_SC(2); FIPT_SC(3); FIPT_SC(4);
         FIPT_SC(5); FIPT_SC(6); FIPT_SC(7); FIPT_SC(8);
 #undef FIPT_SC
         default: return fail(FIPT_EINVAL, "channels must be in [1, 8]");
     }
+    rc = check("grid_scatter segments");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scatter_combine, dim3((unsigned)((8 * p.n_cell + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, p, C);
     rc = check("grid_scatter cells");
     if (rc) return rc;
     if (p.n_act == 0) return FIPT_OK;
     hipLaunchKernelGGL(k_scatter_nodes, dim3((unsigned)((p.n_act + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, st, p, C, (const double*)p.partials, grad_grid);
+                       dim3(kBlock), 0, st, p, C, (const double*)p.cell_part, grad_grid);
     return check("grid_scatter nodes");
 }
 
