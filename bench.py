@@ -35,7 +35,8 @@ PEAK_HBM_GBS = 8000.0
 # operation per lane per cycle (packed FP32 instructions are not used)
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic VALU operations per unit of bake work
-OPS_PER_NODE = 38      # two slab tests: 12 FMA, 24 min/max, 2 compares
+OPS_PER_NODE = 81      # 4-wide node: four slab tests (6 FMA, 12 min/max, 1 compare
+                       # each) and a five-comparator ordering of the hit children
 OPS_PER_TRI = 40       # Moller-Trumbore: 2 cross products, 4 dots, reciprocal, compares
 OPS_PER_SAMPLE = 180   # Philox4x32-10 (~100 integer ops) + direction and weights
 OPS_PER_HIT = 12       # radiance: barycentric blend of the corner cache + emission
@@ -104,19 +105,21 @@ def setup_room(sc, dev):
 
 def traversal_bytes(scene, planes, tri, sc, out):
     """Algorithmic bytes of one bake launch, from the instrumented kernel:
-    64 B per BVH node fetched, 48 B per triangle tested, 48 B radiance
+    128 B per 4-wide BVH node fetched, 48 B per triangle tested, 48 B radiance
     record per hit, 40 B per point read and 156 B per point written."""
-    stats = torch.zeros(4, dtype=torch.int64, device=planes.device)
+    stats = torch.zeros(6, dtype=torch.int64, device=planes.device)
     fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out, stats=stats)
     torch.cuda.synchronize()
-    rays, nodes, tris, hits = [int(v) for v in stats.cpu()]
+    rays, nodes, tris, hits, node_steps, tri_steps = [int(v) for v in stats.cpu()]
     n = planes.shape[1]
     P = 3 + 6 * len(sc.sigma)
     samples = n * sc.spp * (1 + len(sc.sigma))
-    total = nodes * 64 + tris * 48 + hits * 48 + n * 40 + n * P * 4
+    total = nodes * 128 + tris * 48 + hits * 48 + n * 40 + n * P * 4
     ops = nodes * OPS_PER_NODE + tris * OPS_PER_TRI + samples * OPS_PER_SAMPLE + hits * OPS_PER_HIT
     return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, bytes=total, ops=ops,
-                nodes_per_ray=nodes / max(rays, 1), tris_per_ray=tris / max(rays, 1))
+                nodes_per_ray=nodes / max(rays, 1), tris_per_ray=tris / max(rays, 1),
+                node_loop_lane_use=nodes / max(64 * node_steps, 1),
+                tri_loop_lane_use=tris / max(64 * tri_steps, 1))
 
 
 def cpu_baseline(sc, planes, tri, budget_s):

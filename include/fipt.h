@@ -128,12 +128,17 @@ typedef struct fipt_scene_info {
     float bmax[3];
 } fipt_scene_info;
 
-/* Per-launch traversal counters (fipt_bake_traversal_stats). */
+/* Per-launch traversal counters (fipt_bake_traversal_stats).  The two step
+ * counts are per wavefront (one per loop iteration of a whole wavefront), so
+ * nodes / (64 node_steps) and tris / (64 tri_steps) are the fractions of
+ * lanes doing useful work in the node and triangle loops. */
 typedef struct fipt_traversal_stats {
     uint64_t rays;          /* rays cast                                     */
-    uint64_t nodes;         /* BVH nodes fetched                             */
-    uint64_t tris;          /* triangles tested                              */
+    uint64_t nodes;         /* BVH nodes fetched (lane count)                */
+    uint64_t tris;          /* triangles tested (lane count)                 */
     uint64_t hits;          /* rays that hit a surface                       */
+    uint64_t node_steps;    /* wavefront iterations of the node loop         */
+    uint64_t tri_steps;     /* wavefront iterations of the triangle loop     */
 } fipt_traversal_stats;
 
 /* ---- library ----------------------------------------------------------- */
@@ -208,7 +213,7 @@ int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
               const fipt_shading* out, void* stream);
 
 /* Same bake, instrumented: also accumulates traversal counters into
- * `stats_dev` (device, 4 uint64 in fipt_traversal_stats order, added to).
+ * `stats_dev` (device, 6 uint64 in fipt_traversal_stats order, added to).
  * Slower than fipt_bake; meant for measuring algorithmic bytes per ray. */
 int fipt_bake_traversal_stats(fipt_scene s, const fipt_points* pts,
                               const fipt_bake_params* p, const fipt_shading* out,

@@ -164,14 +164,14 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris, 
     s->device = device;
     s->n_tris = n_tris;
     s->n_verts = n_verts;
-    s->n_nodes = (int64_t)bvh.nodes.size();
+    s->n_nodes = (int64_t)bvh.nodes4.size();
     s->max_depth = bvh.max_depth;
     for (int k = 0; k < 3; ++k) {
         s->bmin[k] = bvh.bmin[k];
         s->bmax[k] = bvh.bmax[k];
     }
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = dev_alloc(&s->d_nodes, bvh.nodes.size(), &s->bytes)) ||
+    if ((rc = dev_alloc(&s->d_nodes, bvh.nodes4.size(), &s->bytes)) ||
         (rc = dev_alloc(&s->d_tris, bvh.tris.size(), &s->bytes)) ||
         (rc = dev_alloc(&s->d_rad, bvh.tris.size(), &s->bytes)) ||
         (rc = dev_alloc(&s->d_order, bvh.order.size(), &s->bytes)) ||
@@ -179,8 +179,8 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris, 
         scene_free(s);
         return rc;
     }
-    hipError_t e = hipMemcpyAsync(s->d_nodes, bvh.nodes.data(), sizeof(BvhNode) * bvh.nodes.size(),
-                                  hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(s->d_nodes, bvh.nodes4.data(),
+                                  sizeof(Bvh4Node) * bvh.nodes4.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->d_tris, bvh.tris.data(), sizeof(TriGeom) * bvh.tris.size(),
                            hipMemcpyHostToDevice, st);

@@ -182,8 +182,8 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, int64_t p, int l
 // until each sits on a leaf or is done, then test their leaves together.
 // At the end of the point one fixed butterfly sums the accumulators.
 constexpr int kRefillMaxK = 10;      // 3 + 6K output slots fit the 64 lanes
-constexpr int32_t kDone = INT_MIN;   // never a valid leaf reference (< 2^28 triangles)
-constexpr int kRefillMin = 16;       // refill once this many lanes are free
+using dev::kDone;
+constexpr int kRefillMin = 32;       // refill once this many lanes are free
 
 enum LaneState { kIdle = 0, kTracing = 1, kFinished = 2 };
 
@@ -191,7 +191,8 @@ template <bool COUNT>
 __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p, int lane,
                                                   int32_t* stack, uint32_t& n_rays,
                                                   uint32_t& n_nodes, uint32_t& n_tris,
-                                                  uint32_t& n_hits) {
+                                                  uint32_t& n_hits, uint32_t& n_node_steps,
+                                                  uint32_t& n_tri_steps) {
     const int K = b.K;
     const int P = 3 + 6 * K;
     const int64_t ps = b.pts_stride;
@@ -360,44 +361,10 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
         while (true) {
             const bool inner = state == kTracing && ref >= 0;
             if (!__any(inner)) break;
+            if (COUNT && lane == 0) ++n_node_steps;
             if (inner) {
                 if (COUNT) ++n_nodes;
-                const float4* np = reinterpret_cast<const float4*>(sc.nodes + ref);
-                const float4 na = np[0];
-                const float4 nb = np[1];
-                const float4 nc = np[2];
-                const int4 cc = reinterpret_cast<const int4*>(np)[3];
-                const float a_lx = fmaf(na.x, ix, -oxi), a_hx = fmaf(na.y, ix, -oxi);
-                const float a_ly = fmaf(na.z, iy, -oyi), a_hy = fmaf(na.w, iy, -oyi);
-                const float a_lz = fmaf(nc.x, iz, -ozi), a_hz = fmaf(nc.y, iz, -ozi);
-                const float b_lx = fmaf(nb.x, ix, -oxi), b_hx = fmaf(nb.y, ix, -oxi);
-                const float b_ly = fmaf(nb.z, iy, -oyi), b_hy = fmaf(nb.w, iy, -oyi);
-                const float b_lz = fmaf(nc.z, iz, -ozi), b_hz = fmaf(nc.w, iz, -ozi);
-                const float tmin0 = fmaxf(fmaxf(fminf(a_lx, a_hx), fminf(a_ly, a_hy)),
-                                          fmaxf(fminf(a_lz, a_hz), 0.0f));
-                const float tmax0 = fminf(fminf(fmaxf(a_lx, a_hx), fmaxf(a_ly, a_hy)),
-                                          fminf(fmaxf(a_lz, a_hz), h.t));
-                const float tmin1 = fmaxf(fmaxf(fminf(b_lx, b_hx), fminf(b_ly, b_hy)),
-                                          fmaxf(fminf(b_lz, b_hz), 0.0f));
-                const float tmax1 = fminf(fminf(fmaxf(b_lx, b_hx), fmaxf(b_ly, b_hy)),
-                                          fminf(fmaxf(b_lz, b_hz), h.t));
-                const bool hit0 = tmin0 <= tmax0;
-                const bool hit1 = tmin1 <= tmax1;
-                if (hit0 && hit1) {
-                    const bool first0 = tmin0 <= tmin1;
-                    stack[sp * kBlock] = first0 ? cc.y : cc.x;
-                    ++sp;
-                    ref = first0 ? cc.x : cc.y;
-                } else if (hit0) {
-                    ref = cc.x;
-                } else if (hit1) {
-                    ref = cc.y;
-                } else if (sp == 0) {
-                    ref = kDone;
-                } else {
-                    --sp;
-                    ref = stack[sp * kBlock];
-                }
+                dev::node4_step(sc.nodes, ref, sp, stack, kBlock, ix, iy, iz, oxi, oyi, ozi, h.t);
             }
         }
         // ---- leaves ---------------------------------------------------------
@@ -407,31 +374,8 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
             const int32_t cnt = (lr & 7) + 1;
             for (int i = 0; i < cnt; ++i) {
                 if (COUNT) ++n_tris;
-                const float4* tp = reinterpret_cast<const float4*>(sc.tris + first + i);
-                const float4 t0 = tp[0];
-                const float4 t1 = tp[1];
-                const float4 t2 = tp[2];
-                const V3 e1 = v3(t1.x, t1.y, t1.z);
-                const V3 e2 = v3(t2.x, t2.y, t2.z);
-                const V3 pv = dev::cross(d, e2);
-                const float det = dev::dot(e1, pv);
-                if (det == 0.0f) continue;
-                const float inv = __builtin_amdgcn_rcpf(det);
-                const V3 s = o - v3(t0.x, t0.y, t0.z);
-                const float u = dev::dot(s, pv) * inv;
-                const V3 qv = dev::cross(s, e1);
-                const float v = dev::dot(d, qv) * inv;
-                const float t = dev::dot(e2, qv) * inv;
-                const int32_t orig = __float_as_int(t0.w);
-                const bool inside = (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t > 0.0f);
-                const bool nearer = (t < h.t) | ((t == h.t) & (orig < best_orig));
-                if (inside & nearer) {
-                    h.t = t;
-                    h.u = u;
-                    h.v = v;
-                    h.leaf = first + i;
-                    best_orig = orig;
-                }
+                if (COUNT && __builtin_amdgcn_readfirstlane(lane) == lane) ++n_tri_steps;
+                dev::tri_test(sc.tris, first + i, o, d, h, best_orig);
             }
             if (sp == 0) {
                 ref = kDone;
@@ -478,17 +422,18 @@ __global__ __launch_bounds__(kBlock) void k_bake(BakeLaunch b, uint64_t* stats) 
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
     const int64_t nw = (int64_t)gridDim.x * kWaves;
-    uint32_t n_rays = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
+    uint32_t n_rays = 0, n_nodes = 0, n_tris = 0, n_hits = 0, n_node_steps = 0, n_tri_steps = 0;
     for (int64_t p = wave_uniform(xcd_wave(threadIdx.x >> 6)); p < b.n; p += nw) {
         if (REFILL)
-            bake_point_refill<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
+            bake_point_refill<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits,
+                                     n_node_steps, n_tri_steps);
         else
             bake_point<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
     }
     if (COUNT) {
         // lane counters -> wave totals -> one 64-bit atomic per wave
-        uint64_t v[4] = {n_rays, n_nodes, n_tris, n_hits};
-        for (int k = 0; k < 4; ++k) {
+        uint64_t v[6] = {n_rays, n_nodes, n_tris, n_hits, n_node_steps, n_tri_steps};
+        for (int k = 0; k < 6; ++k) {
             uint64_t x = v[k];
             for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
             if (lane == 0) atomicAdd((unsigned long long*)(stats + k), (unsigned long long)x);
@@ -504,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, in
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
-    uint32_t a = 0, bb = 0, c = 0, d = 0;
+    uint32_t a = 0, bb = 0, c = 0, d = 0, e = 0, f = 0;   // counters, unused here
     const int64_t total = tiles[n_tiles - 1].first + tiles[n_tiles - 1].job.n;
     while (true) {
         int32_t grab = 0;
@@ -520,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, in
         }
         const BakeLaunch& job = tiles[lo].job;
         if (job.K <= kRefillMaxK)
-            bake_point_refill<false>(job, grab - tiles[lo].first, lane, stack, a, bb, c, d);
+            bake_point_refill<false>(job, grab - tiles[lo].first, lane, stack, a, bb, c, d, e, f);
         else
             bake_point<false>(job, grab - tiles[lo].first, lane, stack, a, bb, c, d);
     }

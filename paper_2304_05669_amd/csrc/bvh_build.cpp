@@ -319,6 +319,119 @@ class Builder {
     }
 };
 
+// Collapse of the binary tree into 4-wide nodes.  A 4-wide node takes the
+// two children of a binary node and repeatedly replaces the internal child
+// of largest surface area by its own two children, up to four.  A node with
+// c children pushes at most c - 1 stack entries, so an expansion is taken
+// only if the pushes of this node plus the binary depth of every child
+// (what that child costs if nothing below it is collapsed) stay within the
+// remaining budget; the root's budget is the stack size.
+class Collapser {
+  public:
+    explicit Collapser(HostBvh* b) : b_(b) {
+        const int64_t n = (int64_t)b->nodes.size();
+        need_.assign(n, 0);
+        // children follow their parent in depth-first order
+        for (int64_t i = n - 1; i >= 0; --i) {
+            const BvhNode& nd = b->nodes[i];
+            need_[i] = 1 + std::max(need(nd.child0), need(nd.child1));
+        }
+    }
+
+    void run() {
+        b_->nodes4.clear();
+        b_->nodes4.reserve(b_->nodes.size() / 2 + 1);
+        max_push_ = 0;
+        collapse(0, kStackSize, 0);
+        b_->max_push4 = max_push_;
+    }
+
+  private:
+    struct Child {
+        int32_t ref;
+        float lo[3], hi[3];
+    };
+    HostBvh* b_;
+    std::vector<int> need_;
+    int max_push_ = 0;
+
+    int need(int32_t ref) const { return ref >= 0 ? need_[ref] : 0; }
+
+    static double area(const Child& c) {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = std::max(0.0, (double)c.hi[k] - (double)c.lo[k]);
+        return d[0] * d[1] + d[1] * d[2] + d[2] * d[0];
+    }
+
+    void children_of(int32_t ref, Child out[2]) const {
+        const BvhNode& nd = b_->nodes[ref];
+        out[0] = {nd.child0, {nd.c0lx, nd.c0ly, nd.c0lz}, {nd.c0hx, nd.c0hy, nd.c0hz}};
+        out[1] = {nd.child1, {nd.c1lx, nd.c1ly, nd.c1lz}, {nd.c1hx, nd.c1hy, nd.c1hz}};
+    }
+
+    int cost(const std::vector<Child>& c) const {
+        int m = 0;
+        for (const Child& x : c) m = std::max(m, need(x.ref));
+        return (int)c.size() - 1 + m;
+    }
+
+    int32_t collapse(int32_t ref, int budget, int pushed) {
+        if (ref < 0) {
+            max_push_ = std::max(max_push_, pushed);
+            return ref;
+        }
+        Child two[2];
+        children_of(ref, two);
+        std::vector<Child> c(two, two + 2);
+        while (c.size() < 4) {
+            std::vector<int> order;
+            for (int i = 0; i < (int)c.size(); ++i)
+                if (c[i].ref >= 0) order.push_back(i);
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int b) { return area(c[a]) > area(c[b]); });
+            bool expanded = false;
+            for (int i : order) {
+                std::vector<Child> trial;
+                for (int j = 0; j < (int)c.size(); ++j)
+                    if (j != i) trial.push_back(c[j]);
+                Child g[2];
+                children_of(c[i].ref, g);
+                trial.insert(trial.begin() + i, g, g + 2);
+                if (cost(trial) <= budget) {
+                    c = trial;
+                    expanded = true;
+                    break;
+                }
+            }
+            if (!expanded) break;
+        }
+        const int32_t idx = (int32_t)b_->nodes4.size();
+        b_->nodes4.push_back(Bvh4Node{});
+        const int pushes = (int)c.size() - 1;
+        int32_t refs[4];
+        for (int i = 0; i < (int)c.size(); ++i)
+            refs[i] = collapse(c[i].ref, budget - pushes, pushed + pushes);
+        Bvh4Node& nd = b_->nodes4[idx];
+        for (int i = 0; i < 4; ++i) {
+            if (i < (int)c.size()) {
+                nd.lox[i] = c[i].lo[0];
+                nd.loy[i] = c[i].lo[1];
+                nd.loz[i] = c[i].lo[2];
+                nd.hix[i] = c[i].hi[0];
+                nd.hiy[i] = c[i].hi[1];
+                nd.hiz[i] = c[i].hi[2];
+                nd.child[i] = refs[i];
+            } else {
+                nd.lox[i] = nd.loy[i] = nd.loz[i] = INFINITY;
+                nd.hix[i] = nd.hiy[i] = nd.hiz[i] = -INFINITY;
+                nd.child[i] = kEmptyChild;
+            }
+            nd.pad[i] = 0;
+        }
+        return idx;
+    }
+};
+
 }  // namespace
 
 int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
@@ -336,12 +449,70 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
     bld.run();
     if (out->max_depth > kMaxInnerDepth)
         return fail(FIPT_EINVAL, "BVH depth %d exceeds the traversal stack", out->max_depth);
+    Collapser col(out);
+    col.run();
+    if (out->max_push4 > kStackSize)
+        return fail(FIPT_EINVAL, "4-wide BVH needs %d stack entries", out->max_push4);
     return FIPT_OK;
 }
 
 }  // namespace fipt
 
 namespace {
+
+// Walk the 4-wide node `idx`: every used slot's box encloses the boxes of
+// the child node (up to the widening margin) or the vertices of the leaf's
+// triangles; count triangle occurrences and the stack pushes on each path.
+int validate4(const fipt::HostBvh& b, const float* verts, const int32_t* tris, int32_t idx,
+              int pushed, std::vector<int>& seen, int* max_push) {
+    using namespace fipt;
+    if (idx < 0 || idx >= (int32_t)b.nodes4.size())
+        return fail(FIPT_EINVAL, "4-wide child index %d out of range", idx);
+    const Bvh4Node& nd = b.nodes4[idx];
+    int used = 0;
+    for (int i = 0; i < 4; ++i) used += nd.child[i] != kEmptyChild;
+    if (used < 1) return fail(FIPT_EINVAL, "4-wide node %d has no children", idx);
+    const int here = pushed + used - 1;
+    for (int i = 0; i < 4; ++i) {
+        const int32_t c = nd.child[i];
+        if (c == kEmptyChild) continue;
+        const float lo[3] = {nd.lox[i], nd.loy[i], nd.loz[i]};
+        const float hi[3] = {nd.hix[i], nd.hiy[i], nd.hiz[i]};
+        if (c >= 0) {
+            const Bvh4Node& ch = b.nodes4[c];
+            for (int j = 0; j < 4; ++j) {
+                if (ch.child[j] == kEmptyChild) continue;
+                const float clo[3] = {ch.lox[j], ch.loy[j], ch.loz[j]};
+                const float chi[3] = {ch.hix[j], ch.hiy[j], ch.hiz[j]};
+                for (int k = 0; k < 3; ++k) {
+                    const float tol = 4.0f * 9.5367431640625e-07f *
+                                          std::max(std::fabs(lo[k]), std::fabs(hi[k])) + 1e-30f;
+                    if (clo[k] < lo[k] - tol || chi[k] > hi[k] + tol)
+                        return fail(FIPT_EINVAL, "4-wide node %d leaves its parent box", c);
+                }
+            }
+            int rc = validate4(b, verts, tris, c, here, seen, max_push);
+            if (rc) return rc;
+        } else {
+            const int32_t lr = ~c;
+            const int64_t first = lr >> 3;
+            const int cnt = (lr & 7) + 1;
+            if (first + cnt > (int64_t)b.tris.size()) return fail(FIPT_EINVAL, "leaf range out of bounds");
+            for (int t = 0; t < cnt; ++t) {
+                const int32_t f = b.order[first + t];
+                ++seen[f];
+                for (int v = 0; v < 3; ++v) {
+                    const float* p = verts + 3 * (int64_t)tris[3 * (int64_t)f + v];
+                    for (int k = 0; k < 3; ++k)
+                        if (p[k] < lo[k] || p[k] > hi[k])
+                            return fail(FIPT_EINVAL, "triangle %d pokes out of its 4-wide leaf box", f);
+                }
+            }
+            *max_push = std::max(*max_push, here);
+        }
+    }
+    return FIPT_OK;
+}
 
 // Walk the subtree of `ref`: count triangle occurrences, check that the
 // box recorded for `ref` in its parent encloses all of its triangles, and
@@ -408,7 +579,17 @@ extern "C" int fipt_bvh_validate(const float* verts, int64_t n_verts, const int3
     for (int64_t f = 0; f < n_tris; ++f)
         if (seen[f] != 1) return fail(FIPT_EINVAL, "triangle %lld appears %d times", (long long)f, seen[f]);
     if ((int64_t)b.tris.size() != n_tris) return fail(FIPT_EINVAL, "leaf order has %zu triangles", b.tris.size());
-    *n_nodes = (int64_t)b.nodes.size();
+    // the 4-wide tree the GPU traverses
+    std::vector<int> seen4(n_tris, 0);
+    int pushes = 0;
+    rc = validate4(b, verts, tris, 0, 0, seen4, &pushes);
+    if (rc) return rc;
+    for (int64_t f = 0; f < n_tris; ++f)
+        if (seen4[f] != (n_tris == 1 ? 2 : 1))
+            return fail(FIPT_EINVAL, "4-wide tree: triangle %lld appears %d times", (long long)f, seen4[f]);
+    if (pushes > kStackSize || pushes != b.max_push4)
+        return fail(FIPT_EINVAL, "4-wide tree needs %d stack entries (builder said %d)", pushes, b.max_push4);
+    *n_nodes = (int64_t)b.nodes4.size();
     *max_depth = depth;
     return FIPT_OK;
 }

@@ -78,10 +78,109 @@ struct Hit {
     float t, u, v;
 };
 
-// Closest hit along o + t d, t > 0.  `stack` points at this lane's first
-// LDS stack slot; consecutive slots are `stride` ints apart (lane-minor, so
-// a wave's pushes and pops hit distinct banks).  Exact distance ties go to
-// the lower original triangle index.
+// End-of-traversal marker: never a node index or a leaf reference (< 2^28
+// triangles).
+constexpr int32_t kDone = INT_MIN;
+
+// Slab test of one child box against [0, tmax]; returns the entry distance,
+// or +inf when the box is missed.
+__device__ __forceinline__ float box_entry(float lx, float hx, float ly, float hy, float lz,
+                                           float hz, float ix, float iy, float iz, float oxi,
+                                           float oyi, float ozi, float tmax) {
+    const float t0x = fmaf(lx, ix, -oxi), t1x = fmaf(hx, ix, -oxi);
+    const float t0y = fmaf(ly, iy, -oyi), t1y = fmaf(hy, iy, -oyi);
+    const float t0z = fmaf(lz, iz, -ozi), t1z = fmaf(hz, iz, -ozi);
+    const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+    const float tout = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    return tmin <= tout ? tmin : INFINITY;
+}
+
+__device__ __forceinline__ void order2(float& ka, int32_t& ca, float& kb, int32_t& cb) {
+    const bool s = kb < ka;
+    const float k = s ? kb : ka;
+    kb = s ? ka : kb;
+    ka = k;
+    const int32_t c = s ? cb : ca;
+    cb = s ? ca : cb;
+    ca = c;
+}
+
+// One step of closest-hit traversal at 4-wide node `ref`: the hit children
+// are visited nearest first; the nearest becomes `ref`, the others are
+// pushed farthest first.  With no child hit, the next entry is popped
+// (kDone when the stack is empty).
+__device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, int& sp,
+                                           int32_t* stack, int stride, float ix, float iy,
+                                           float iz, float oxi, float oyi, float ozi,
+                                           float tmax) {
+    const float4* np = reinterpret_cast<const float4*>(nodes + ref);
+    const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+    const int4 ch = reinterpret_cast<const int4*>(np)[6];
+    float k0 = box_entry(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ix, iy, iz, oxi, oyi, ozi, tmax);
+    float k1 = box_entry(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ix, iy, iz, oxi, oyi, ozi, tmax);
+    float k2 = box_entry(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ix, iy, iz, oxi, oyi, ozi, tmax);
+    float k3 = box_entry(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ix, iy, iz, oxi, oyi, ozi, tmax);
+    int32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
+    if (c0 == kEmptyChild) k0 = INFINITY;
+    if (c1 == kEmptyChild) k1 = INFINITY;
+    if (c2 == kEmptyChild) k2 = INFINITY;
+    if (c3 == kEmptyChild) k3 = INFINITY;
+    const int hits = (k0 < INFINITY) + (k1 < INFINITY) + (k2 < INFINITY) + (k3 < INFINITY);
+    // sorting network on four keys
+    order2(k0, c0, k1, c1);
+    order2(k2, c2, k3, c3);
+    order2(k0, c0, k2, c2);
+    order2(k1, c1, k3, c3);
+    order2(k1, c1, k2, c2);
+    if (hits == 0) {
+        if (sp == 0) {
+            ref = kDone;
+        } else {
+            --sp;
+            ref = stack[sp * stride];
+        }
+        return;
+    }
+    if (hits > 3) stack[(sp++) * stride] = c3;
+    if (hits > 2) stack[(sp++) * stride] = c2;
+    if (hits > 1) stack[(sp++) * stride] = c1;
+    ref = c0;
+}
+
+// Triangle test (Moller-Trumbore) of leaf-order triangle `i`; updates the
+// closest hit, exact distance ties going to the lower original index.
+__device__ __forceinline__ void tri_test(const TriGeom* tris, int32_t i, V3 o, V3 d, Hit& h,
+                                         int32_t& best_orig) {
+    const float4* tp = reinterpret_cast<const float4*>(tris + i);
+    const float4 t0 = tp[0];
+    const float4 t1 = tp[1];
+    const float4 t2 = tp[2];
+    const V3 e1 = v3(t1.x, t1.y, t1.z);
+    const V3 e2 = v3(t2.x, t2.y, t2.z);
+    const V3 pv = cross(d, e2);
+    const float det = dot(e1, pv);
+    if (det == 0.0f) return;
+    const float inv = __builtin_amdgcn_rcpf(det);
+    const V3 s = o - v3(t0.x, t0.y, t0.z);
+    const float u = dot(s, pv) * inv;
+    const V3 q = cross(s, e1);
+    const float v = dot(d, q) * inv;
+    const float t = dot(e2, q) * inv;
+    const int32_t orig = __float_as_int(t0.w);
+    const bool inside = (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t > 0.0f);
+    const bool nearer = (t < h.t) | ((t == h.t) & (orig < best_orig));
+    if (inside & nearer) {
+        h.t = t;
+        h.u = u;
+        h.v = v;
+        h.leaf = i;
+        best_orig = orig;
+    }
+}
+
+// Closest hit along o + t d, t > 0, one ray per lane.  `stack` points at
+// this lane's first LDS stack slot; consecutive slots are `stride` ints
+// apart (lane-minor, so a wave's pushes and pops hit distinct banks).
 template <bool COUNT>
 __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t* stack,
                                      int stride, uint32_t& n_nodes, uint32_t& n_tris) {
@@ -98,79 +197,24 @@ __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t*
     int32_t best_orig = INT_MAX;
     int32_t ref = 0;
     int sp = 0;
-    while (true) {
+    while (ref != kDone) {
         if (ref >= 0) {
             if (COUNT) ++n_nodes;
-            const float4* np = reinterpret_cast<const float4*>(sc.nodes + ref);
-            const float4 a = np[0];
-            const float4 b = np[1];
-            const float4 c = np[2];
-            const int4 cc = reinterpret_cast<const int4*>(np)[3];
-            const float a_lx = fmaf(a.x, ix, -ox), a_hx = fmaf(a.y, ix, -ox);
-            const float a_ly = fmaf(a.z, iy, -oy), a_hy = fmaf(a.w, iy, -oy);
-            const float a_lz = fmaf(c.x, iz, -oz), a_hz = fmaf(c.y, iz, -oz);
-            const float b_lx = fmaf(b.x, ix, -ox), b_hx = fmaf(b.y, ix, -ox);
-            const float b_ly = fmaf(b.z, iy, -oy), b_hy = fmaf(b.w, iy, -oy);
-            const float b_lz = fmaf(c.z, iz, -oz), b_hz = fmaf(c.w, iz, -oz);
-            const float tmin0 = fmaxf(fmaxf(fminf(a_lx, a_hx), fminf(a_ly, a_hy)),
-                                      fmaxf(fminf(a_lz, a_hz), 0.0f));
-            const float tmax0 = fminf(fminf(fmaxf(a_lx, a_hx), fmaxf(a_ly, a_hy)),
-                                      fminf(fmaxf(a_lz, a_hz), h.t));
-            const float tmin1 = fmaxf(fmaxf(fminf(b_lx, b_hx), fminf(b_ly, b_hy)),
-                                      fmaxf(fminf(b_lz, b_hz), 0.0f));
-            const float tmax1 = fminf(fminf(fmaxf(b_lx, b_hx), fmaxf(b_ly, b_hy)),
-                                      fminf(fmaxf(b_lz, b_hz), h.t));
-            const bool hit0 = tmin0 <= tmax0;
-            const bool hit1 = tmin1 <= tmax1;
-            if (hit0 && hit1) {
-                const bool first0 = tmin0 <= tmin1;
-                stack[sp * stride] = first0 ? cc.y : cc.x;
-                ++sp;
-                ref = first0 ? cc.x : cc.y;
-            } else if (hit0) {
-                ref = cc.x;
-            } else if (hit1) {
-                ref = cc.y;
-            } else {
-                if (sp == 0) break;
-                --sp;
-                ref = stack[sp * stride];
-            }
+            node4_step(sc.nodes, ref, sp, stack, stride, ix, iy, iz, ox, oy, oz, h.t);
         } else {
             const int32_t lr = ~ref;
             const int32_t first = lr >> 3;
             const int32_t cnt = (lr & 7) + 1;
             for (int i = 0; i < cnt; ++i) {
                 if (COUNT) ++n_tris;
-                const float4* tp = reinterpret_cast<const float4*>(sc.tris + first + i);
-                const float4 t0 = tp[0];
-                const float4 t1 = tp[1];
-                const float4 t2 = tp[2];
-                const V3 e1 = v3(t1.x, t1.y, t1.z);
-                const V3 e2 = v3(t2.x, t2.y, t2.z);
-                const V3 pv = cross(d, e2);
-                const float det = dot(e1, pv);
-                if (det == 0.0f) continue;
-                const float inv = __builtin_amdgcn_rcpf(det);
-                const V3 s = o - v3(t0.x, t0.y, t0.z);
-                const float u = dot(s, pv) * inv;
-                const V3 q = cross(s, e1);
-                const float v = dot(d, q) * inv;
-                const float t = dot(e2, q) * inv;
-                const int32_t orig = __float_as_int(t0.w);
-                const bool inside = (u >= 0.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t > 0.0f);
-                const bool nearer = (t < h.t) | ((t == h.t) & (orig < best_orig));
-                if (inside & nearer) {
-                    h.t = t;
-                    h.u = u;
-                    h.v = v;
-                    h.leaf = first + i;
-                    best_orig = orig;
-                }
+                tri_test(sc.tris, first + i, o, d, h, best_orig);
             }
-            if (sp == 0) break;
-            --sp;
-            ref = stack[sp * stride];
+            if (sp == 0) {
+                ref = kDone;
+            } else {
+                --sp;
+                ref = stack[sp * stride];
+            }
         }
     }
     return h;

@@ -58,11 +58,28 @@ inline int32_t leaf_ref(int64_t first, int count) {
     return ~static_cast<int32_t>((first << 3) | (count - 1));
 }
 
+// 4-wide BVH collapsed from the binary one: one 128-byte node holds the
+// boxes of up to four children (as structure of arrays) and their
+// references (same encoding; kEmptyChild marks an unused slot).  The
+// collapse keeps the stack pushes along every root-to-leaf path within
+// kStackSize, so the traversal stack still cannot overflow.
+constexpr int32_t kEmptyChild = -2147483647;   // INT32_MIN + 1: never a leaf reference
+struct alignas(16) Bvh4Node {
+    float lox[4], hix[4];
+    float loy[4], hiy[4];
+    float loz[4], hiz[4];
+    int32_t child[4];
+    int32_t pad[4];
+};
+static_assert(sizeof(Bvh4Node) == 128, "4-wide node is one 128-byte line");
+
 struct HostBvh {
     std::vector<BvhNode> nodes;
+    std::vector<Bvh4Node> nodes4;
     std::vector<TriGeom> tris;   // leaf order
     std::vector<int32_t> order;  // leaf position -> original triangle
     int max_depth = 0;
+    int max_push4 = 0;           // most stack pushes on a path of the 4-wide tree
     float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
 };
 
@@ -73,7 +90,7 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
 
 // ---- kernels (launchers defined in the .hip files) -------------------------
 struct DeviceScene {
-    const BvhNode* nodes;
+    const Bvh4Node* nodes;
     const TriGeom* tris;
     const TriRad* rad;
     int64_t n_tris;
@@ -158,7 +175,7 @@ struct fipt_scene_s {
     int32_t max_depth = 0;
     int32_t cache_kind = -1;
     float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
-    fipt::BvhNode* d_nodes = nullptr;
+    fipt::Bvh4Node* d_nodes = nullptr;   // 4-wide nodes
     fipt::TriGeom* d_tris = nullptr;
     fipt::TriRad* d_rad = nullptr;
     int32_t* d_order = nullptr;    // leaf position -> original triangle

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfipt.so")
+# FIPT_LIBRARY may point at another build of the same library
+LIB_PATH = os.environ.get("FIPT_LIBRARY", os.path.join(HERE, "libfipt.so"))
 
 OK, EINVAL, ENOMEM, EHIP, EBUSY, EAGAIN, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 MAX_LEVELS = 16
@@ -279,8 +280,11 @@ def fipt_bake(scene: Scene, planes: torch.Tensor, tri: torch.Tensor, spp_d: int,
               sigma, seed: int, ray_eps: float = 1e-4, out: torch.Tensor = None,
               stats: torch.Tensor = None):
     """Bake Ld, Ls0[K], Ls1[K] for the points; returns [3 + 6K, n] float32.
-    If ``stats`` (int64 GPU tensor of 4) is given, the instrumented kernel
-    adds rays, nodes, triangles and hits to it."""
+    If ``stats`` (int64 GPU tensor of 6) is given, the instrumented kernel
+    adds rays, nodes, triangles, hits, node-loop and triangle-loop
+    wavefront steps to it."""
+    if stats is not None and tuple(stats.shape) != (6,):
+        raise ValueError("stats must be an int64 tensor of 6")
     K = len(sigma)
     n = planes.shape[1]
     if out is None:
