@@ -254,7 +254,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
     int lobe = 0;
     float w0 = 0.0f, w1 = 0.0f;       // weights of the Ls0 / Ls1 (or Ld) contributions
     V3 d = v3(0.0f, 0.0f, 1.0f);
-    float ix = 0.0f, iy = 0.0f, iz = 0.0f, oxi = 0.0f, oyi = 0.0f, ozi = 0.0f;
+    dev::RaySlab rs = dev::ray_slab(o, d);
     int32_t ref = kDone;
     int sp = 0;
     dev::Hit h;
@@ -333,15 +333,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
                         }
                         if (shoot) {
                             if (COUNT) ++n_rays;
-                            const float dx = fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x);
-                            const float dy = fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y);
-                            const float dz = fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z);
-                            ix = __builtin_amdgcn_rcpf(dx);
-                            iy = __builtin_amdgcn_rcpf(dy);
-                            iz = __builtin_amdgcn_rcpf(dz);
-                            oxi = o.x * ix;
-                            oyi = o.y * iy;
-                            ozi = o.z * iz;
+                            rs = dev::ray_slab(o, d);
                             ref = 0;
                             sp = 0;
                             h.leaf = -1;
@@ -364,7 +356,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
             if (COUNT && lane == 0) ++n_node_steps;
             if (inner) {
                 if (COUNT) ++n_nodes;
-                dev::node4_step(sc.nodes, ref, sp, stack, kBlock, ix, iy, iz, oxi, oyi, ozi, h.t);
+                dev::node4_step(sc.nodes, ref, sp, stack, kBlock, rs, h.t);
             }
         }
         // ---- leaves ---------------------------------------------------------

@@ -453,6 +453,10 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
     col.run();
     if (out->max_push4 > kStackSize)
         return fail(FIPT_EINVAL, "4-wide BVH needs %d stack entries", out->max_push4);
+    // the traversal addresses nodes by 32-bit byte offsets
+    if ((int64_t)out->nodes4.size() > kMaxNodes4)
+        return fail(FIPT_EINVAL, "4-wide BVH has %zu nodes (at most %lld)", out->nodes4.size(),
+                    (long long)kMaxNodes4);
     return FIPT_OK;
 }
 
@@ -470,7 +474,17 @@ int validate4(const fipt::HostBvh& b, const float* verts, const int32_t* tris, i
         return fail(FIPT_EINVAL, "4-wide child index %d out of range", idx);
     const Bvh4Node& nd = b.nodes4[idx];
     int used = 0;
-    for (int i = 0; i < 4; ++i) used += nd.child[i] != kEmptyChild;
+    for (int i = 0; i < 4; ++i) {
+        if (nd.child[i] != kEmptyChild) {
+            ++used;
+            continue;
+        }
+        // the traversal relies on unused slots holding an inverted box
+        const bool inverted = nd.lox[i] == INFINITY && nd.loy[i] == INFINITY &&
+                              nd.loz[i] == INFINITY && nd.hix[i] == -INFINITY &&
+                              nd.hiy[i] == -INFINITY && nd.hiz[i] == -INFINITY;
+        if (!inverted) return fail(FIPT_EINVAL, "4-wide node %d: unused slot %d has a box", idx, i);
+    }
     if (used < 1) return fail(FIPT_EINVAL, "4-wide node %d has no children", idx);
     const int here = pushed + used - 1;
     for (int i = 0; i < 4; ++i) {

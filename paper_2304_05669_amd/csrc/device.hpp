@@ -82,17 +82,43 @@ struct Hit {
 // triangles).
 constexpr int32_t kDone = INT_MIN;
 
-// Slab test of one child box against [0, tmax]; returns the entry distance,
-// or +inf when the box is missed.
-__device__ __forceinline__ float box_entry(float lx, float hx, float ly, float hy, float lz,
-                                           float hz, float ix, float iy, float iz, float oxi,
-                                           float oyi, float ozi, float tmax) {
-    const float t0x = fmaf(lx, ix, -oxi), t1x = fmaf(hx, ix, -oxi);
-    const float t0y = fmaf(ly, iy, -oyi), t1y = fmaf(hy, iy, -oyi);
-    const float t0z = fmaf(lz, iz, -ozi), t1z = fmaf(hz, iz, -ozi);
-    const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-    const float tout = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
-    return tmin <= tout ? tmin : INFINITY;
+// Per-ray constants of the slab test: inverse direction, origin times
+// inverse direction, and for each axis the byte offset inside a node of the
+// near-plane vector (the low bounds when the direction component is
+// positive, else the high bounds; the far-plane vector is the other one of
+// the pair, 16 bytes away).
+struct RaySlab {
+    float ix, iy, iz, oxi, oyi, ozi;
+    uint32_t nx, ny, nz;
+};
+__device__ __forceinline__ RaySlab ray_slab(V3 o, V3 d) {
+    const float dx = fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x);
+    const float dy = fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y);
+    const float dz = fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z);
+    RaySlab r;
+    r.ix = __builtin_amdgcn_rcpf(dx);
+    r.iy = __builtin_amdgcn_rcpf(dy);
+    r.iz = __builtin_amdgcn_rcpf(dz);
+    r.oxi = o.x * r.ix;
+    r.oyi = o.y * r.iy;
+    r.ozi = o.z * r.iz;
+    r.nx = (__float_as_uint(r.ix) >> 31) << 4;
+    r.ny = 32u + ((__float_as_uint(r.iy) >> 31) << 4);
+    r.nz = 64u + ((__float_as_uint(r.iz) >> 31) << 4);
+    return r;
+}
+
+// Slab test of one child box given its near and far planes, against
+// [0, tmax]; returns the entry distance, or +inf when the box is missed.
+// An unused slot (low bounds +inf, high bounds -inf) has near distance +inf
+// and far distance -inf whatever the direction, so it is always missed.
+__device__ __forceinline__ float box_entry(float nx, float fx, float ny, float fy, float nz,
+                                           float fz, const RaySlab& r, float tmax) {
+    const float tn = fmaxf(fmaxf(fmaf(nx, r.ix, -r.oxi), fmaf(ny, r.iy, -r.oyi)),
+                           fmaxf(fmaf(nz, r.iz, -r.ozi), 0.0f));
+    const float tf = fminf(fminf(fmaf(fx, r.ix, -r.oxi), fmaf(fy, r.iy, -r.oyi)),
+                           fminf(fmaf(fz, r.iz, -r.ozi), tmax));
+    return tn <= tf ? tn : INFINITY;
 }
 
 __device__ __forceinline__ void order2(float& ka, int32_t& ca, float& kb, int32_t& cb) {
@@ -105,26 +131,32 @@ __device__ __forceinline__ void order2(float& ka, int32_t& ca, float& kb, int32_
     ca = c;
 }
 
+__device__ __forceinline__ float4 node_vec(const Bvh4Node* nodes, uint32_t off) {
+    return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(nodes) + off);
+}
+
 // One step of closest-hit traversal at 4-wide node `ref`: the hit children
 // are visited nearest first; the nearest becomes `ref`, the others are
 // pushed farthest first.  With no child hit, the next entry is popped
-// (kDone when the stack is empty).
+// (kDone when the stack is empty).  Node byte offsets fit 32 bits (the
+// builder rejects trees of more than kMaxNodes4 nodes).
 __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, int& sp,
-                                           int32_t* stack, int stride, float ix, float iy,
-                                           float iz, float oxi, float oyi, float ozi,
+                                           int32_t* stack, int stride, const RaySlab& r,
                                            float tmax) {
-    const float4* np = reinterpret_cast<const float4*>(nodes + ref);
-    const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-    const int4 ch = reinterpret_cast<const int4*>(np)[6];
-    float k0 = box_entry(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ix, iy, iz, oxi, oyi, ozi, tmax);
-    float k1 = box_entry(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ix, iy, iz, oxi, oyi, ozi, tmax);
-    float k2 = box_entry(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ix, iy, iz, oxi, oyi, ozi, tmax);
-    float k3 = box_entry(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ix, iy, iz, oxi, oyi, ozi, tmax);
+    const uint32_t base = (uint32_t)ref << 7;
+    const uint32_t ox = base + r.nx, oy = base + r.ny, oz = base + r.nz;
+    const float4 nx = node_vec(nodes, ox), fx = node_vec(nodes, ox ^ 16u);
+    const float4 ny = node_vec(nodes, oy), fy = node_vec(nodes, oy ^ 16u);
+    const float4 nz = node_vec(nodes, oz), fz = node_vec(nodes, oz ^ 16u);
+    const int4 ch = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(nodes) + base + 96u);
+    float k0 = box_entry(nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, r, tmax);
+    float k1 = box_entry(nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, r, tmax);
+    float k2 = box_entry(nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, r, tmax);
+    float k3 = box_entry(nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, r, tmax);
     int32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
-    if (c0 == kEmptyChild) k0 = INFINITY;
-    if (c1 == kEmptyChild) k1 = INFINITY;
-    if (c2 == kEmptyChild) k2 = INFINITY;
-    if (c3 == kEmptyChild) k3 = INFINITY;
+    // keep the child load in the same batch as the box loads (otherwise it
+    // is sunk below the miss branch and costs a second memory round trip)
+    asm volatile("" : : "v"(c0), "v"(c1), "v"(c2), "v"(c3));
     const int hits = (k0 < INFINITY) + (k1 < INFINITY) + (k2 < INFINITY) + (k3 < INFINITY);
     // sorting network on four keys
     order2(k0, c0, k1, c1);
@@ -184,12 +216,7 @@ __device__ __forceinline__ void tri_test(const TriGeom* tris, int32_t i, V3 o, V
 template <bool COUNT>
 __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t* stack,
                                      int stride, uint32_t& n_nodes, uint32_t& n_tris) {
-    const float dx = fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x);
-    const float dy = fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y);
-    const float dz = fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z);
-    const float ix = __builtin_amdgcn_rcpf(dx), iy = __builtin_amdgcn_rcpf(dy),
-                iz = __builtin_amdgcn_rcpf(dz);
-    const float ox = o.x * ix, oy = o.y * iy, oz = o.z * iz;
+    const RaySlab r = ray_slab(o, d);
     Hit h;
     h.leaf = -1;
     h.t = INFINITY;
@@ -200,7 +227,7 @@ __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t*
     while (ref != kDone) {
         if (ref >= 0) {
             if (COUNT) ++n_nodes;
-            node4_step(sc.nodes, ref, sp, stack, stride, ix, iy, iz, ox, oy, oz, h.t);
+            node4_step(sc.nodes, ref, sp, stack, stride, r, h.t);
         } else {
             const int32_t lr = ~ref;
             const int32_t first = lr >> 3;

@@ -72,6 +72,7 @@ struct alignas(16) Bvh4Node {
     int32_t pad[4];
 };
 static_assert(sizeof(Bvh4Node) == 128, "4-wide node is one 128-byte line");
+constexpr int64_t kMaxNodes4 = int64_t(1) << 25;   // node byte offsets stay below 2^32
 
 struct HostBvh {
     std::vector<BvhNode> nodes;
