@@ -178,12 +178,13 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, int64_t p, int l
 // at a time and, once a batch of lanes has finished, those lanes fold their
 // results into per-lane accumulators and take the next samples of the point
 // (handed out in lane order by a ballot, so the assignment depends only on
-// the inputs).  Traversal is while-while: all lanes descend inner nodes
-// until each sits on a leaf or is done, then test their leaves together.
+// the inputs).  Traversal is while-while with speculation: a lane that
+// reaches a leaf parks it and keeps descending while other lanes are still
+// looking for theirs; then all lanes test their parked leaves together.
 // At the end of the point one fixed butterfly sums the accumulators.
 constexpr int kRefillMaxK = 10;      // 3 + 6K output slots fit the 64 lanes
 using dev::kDone;
-constexpr int kRefillMin = 32;       // refill once this many lanes are free
+constexpr int kRefillMin = 48;       // refill once this many lanes are free
 
 enum LaneState { kIdle = 0, kTracing = 1, kFinished = 2 };
 
@@ -349,10 +350,20 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
                 next_q = min(S, next_q + n_free);
             }
         }
-        // ---- traversal: inner nodes until every lane sits on a leaf -------
+        // ---- traversal: inner nodes until every lane has parked a leaf ----
+        int32_t pend = kDone;
         while (true) {
+            if (state == kTracing && ref < 0 && ref != kDone && pend == kDone) {
+                pend = ref;
+                if (sp == 0) {
+                    ref = kDone;
+                } else {
+                    --sp;
+                    ref = stack[sp * kBlock];
+                }
+            }
             const bool inner = state == kTracing && ref >= 0;
-            if (!__any(inner)) break;
+            if (!__any(inner && pend == kDone)) break;
             if (COUNT && lane == 0) ++n_node_steps;
             if (inner) {
                 if (COUNT) ++n_nodes;
@@ -360,20 +371,14 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
             }
         }
         // ---- leaves ---------------------------------------------------------
-        if (state == kTracing && ref != kDone) {
-            const int32_t lr = ~ref;
+        if (state == kTracing && pend != kDone) {
+            const int32_t lr = ~pend;
             const int32_t first = lr >> 3;
             const int32_t cnt = (lr & 7) + 1;
             for (int i = 0; i < cnt; ++i) {
                 if (COUNT) ++n_tris;
                 if (COUNT && __builtin_amdgcn_readfirstlane(lane) == lane) ++n_tri_steps;
                 dev::tri_test(sc.tris, first + i, o, d, h, best_orig);
-            }
-            if (sp == 0) {
-                ref = kDone;
-            } else {
-                --sp;
-                ref = stack[sp * kBlock];
             }
         }
         if (state == kTracing && ref == kDone) state = kFinished;
