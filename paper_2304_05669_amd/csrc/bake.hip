@@ -180,11 +180,13 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, int64_t p, int l
 // (handed out in lane order by a ballot, so the assignment depends only on
 // the inputs).  Traversal is while-while with speculation: a lane that
 // reaches a leaf parks it and keeps descending while other lanes are still
-// looking for theirs; then all lanes test their parked leaves together.
+// looking for theirs; once only a few lanes are still searching, all lanes
+// test their parked leaves together.
 // At the end of the point one fixed butterfly sums the accumulators.
 constexpr int kRefillMaxK = 10;      // 3 + 6K output slots fit the 64 lanes
 using dev::kDone;
 constexpr int kRefillMin = 48;       // refill once this many lanes are free
+constexpr int kSearchMin = 8;        // leave the node loop below this many searchers
 
 enum LaneState { kIdle = 0, kTracing = 1, kFinished = 2 };
 
@@ -363,7 +365,11 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
                 }
             }
             const bool inner = state == kTracing && ref >= 0;
-            if (!__any(inner && pend == kDone)) break;
+            // Stop descending once fewer than kSearchMin lanes are still
+            // looking for a leaf and some lane has one to test: the rest would
+            // otherwise idle while the last few rays search.
+            const uint64_t searching = __ballot(inner && pend == kDone);
+            if (searching == 0 || (__popcll(searching) < kSearchMin && __any(pend != kDone))) break;
             if (COUNT && lane == 0) ++n_node_steps;
             if (inner) {
                 if (COUNT) ++n_nodes;
