@@ -80,7 +80,8 @@ typedef struct fipt_camera {
  *           the viewer;
  *   tri:    index of the triangle x lies on, or -1 for "no surface" (the
  *           bake writes zeros for such points);
- *   n:      number of points; stride: elements between planes (>= n). */
+ *   n:      number of points, 1 <= n < 2^31; stride: elements between
+ *           planes (>= n). */
 typedef struct fipt_points {
     float* planes;
     int32_t* tri;
@@ -208,7 +209,10 @@ int fipt_gen_points(fipt_scene s, const fipt_camera* cams, int32_t n_cams,
  * w = G(wi, wo) (wo.m) / ((n.wo)(n.m)) with separable Smith G, F1 =
  * (1 - wi.m)^5, F0 = 1 - F1, and samples with wo.m <= 0 or n.wi <= 0 count
  * as zero.  Points with tri < 0 or n.wo = 0 get zeros.  `out` must hold
- * 3 + 6K planes of at least pts->n elements.  Asynchronous on `stream`. */
+ * 3 + 6K planes of at least pts->n elements.  Asynchronous on `stream`;
+ * takes 32 bytes of stream-ordered device memory (hipMallocAsync) for its
+ * work counters and frees them on the same stream (FIPT_ENOMEM if that
+ * allocation fails). */
 int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
               const fipt_shading* out, void* stream);
 

@@ -83,7 +83,8 @@ void scene_free(fipt_scene s) {
 int check_points(const fipt_points* pts, const char* name) {
     if (!pts) return fail(FIPT_EINVAL, "%s is NULL", name);
     if (!pts->planes || !pts->tri) return fail(FIPT_EINVAL, "%s has a NULL plane pointer", name);
-    if (pts->n < 1) return fail(FIPT_EINVAL, "%s->n must be >= 1, got %lld", name, (long long)pts->n);
+    if (pts->n < 1 || pts->n > INT32_MAX)
+        return fail(FIPT_EINVAL, "%s->n must be in [1, 2^31), got %lld", name, (long long)pts->n);
     if (pts->stride < pts->n)
         return fail(FIPT_EINVAL, "%s->stride (%lld) < n (%lld)", name, (long long)pts->stride,
                     (long long)pts->n);

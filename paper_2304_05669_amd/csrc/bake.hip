@@ -44,7 +44,7 @@ __device__ __forceinline__ int slot_plane(int j, int K) {
 
 // Bake point p of job b with the calling wavefront.
 template <bool COUNT>
-__device__ __forceinline__ void bake_point(const BakeLaunch& b, int64_t p, int lane,
+__device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sigma, int64_t p, int lane,
                                            int32_t* stack, uint32_t& n_rays, uint32_t& n_nodes,
                                            uint32_t& n_tris, uint32_t& n_hits) {
     const int K = b.K;
@@ -93,7 +93,7 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, int64_t p, int l
                 shoot = true;
             } else {
                 // GGX half vector, density D(m)(n.m), alpha = sigma^2
-                const float sg = b.sigma[lobe - 1];
+                const float sg = sigma[lobe - 1];
                 const float alpha = sg * sg;
                 const float a2 = alpha * alpha;
                 const float tan2 = a2 * xi1 / (1.0f - xi1);
@@ -191,7 +191,8 @@ constexpr int kSearchMin = 8;        // leave the node loop below this many sear
 enum LaneState { kIdle = 0, kTracing = 1, kFinished = 2 };
 
 template <bool COUNT>
-__device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p, int lane,
+__device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const float* sigma, int64_t p,
+                                                  int lane,
                                                   int32_t* stack, uint32_t& n_rays,
                                                   uint32_t& n_nodes, uint32_t& n_tris,
                                                   uint32_t& n_hits, uint32_t& n_node_steps,
@@ -311,7 +312,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
                             w1 = 0.0f;
                             shoot = true;
                         } else {
-                            const float sg = b.sigma[lobe - 1];
+                            const float sg = sigma[lobe - 1];
                             const float alpha = sg * sg;
                             const float a2 = alpha * alpha;
                             const float tan2 = a2 * xi1 / (1.0f - xi1);
@@ -397,20 +398,6 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, int64_t p
     }
 }
 
-// Logical wavefront index with workgroups of one XCD made contiguous:
-// the dispatcher places workgroup i on XCD i % 8, so consecutive points go
-// to one XCD's L2.
-__device__ __forceinline__ int64_t xcd_wave(int lane_wave) {
-    const int64_t g = gridDim.x, i = blockIdx.x;
-    int64_t lb;
-    if ((g & 7) == 0) {
-        lb = (i & 7) * (g >> 3) + (i >> 3);
-    } else {
-        lb = i;
-    }
-    return lb * kWaves + lane_wave;
-}
-
 // The point index is the same in every lane of a wavefront; saying so lets
 // the compiler keep the point's data in scalar registers.
 __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
@@ -419,19 +406,40 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Dynamic point hand-out.  The points of a launch are cut into kXcdCount
+// contiguous shares, one per XCD, each with its own counter: a wavefront
+// takes the next point of its XCD's share, so each XCD's L2 sees one
+// contiguous run of points; when that share is used up it takes points from
+// the other shares in turn.  Returns -1 once every share is exhausted
+// (`tried` counts the shares found empty).  Each point's result does not
+// depend on which wavefront bakes it.
+__device__ __forceinline__ int64_t next_point(int32_t* counters, int home, int& tried,
+                                              int64_t total, int lane) {
+    while (tried < kXcdCount) {
+        const int x = (home + tried) % kXcdCount;
+        int32_t grab = 0;
+        if (lane == 0) grab = atomicAdd(counters + x, 1);
+        const int64_t p = total * x / kXcdCount + __builtin_amdgcn_readfirstlane(grab);
+        if (p < total * (x + 1) / kXcdCount) return p;
+        ++tried;
+    }
+    return -1;
+}
+
 template <bool COUNT, bool REFILL>
-__global__ __launch_bounds__(kBlock) void k_bake(BakeLaunch b, uint64_t* stats) {
+__global__ __launch_bounds__(kBlock) void k_bake(BakeLaunch b, int32_t* counters, uint64_t* stats) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
-    const int64_t nw = (int64_t)gridDim.x * kWaves;
     uint32_t n_rays = 0, n_nodes = 0, n_tris = 0, n_hits = 0, n_node_steps = 0, n_tri_steps = 0;
-    for (int64_t p = wave_uniform(xcd_wave(threadIdx.x >> 6)); p < b.n; p += nw) {
+    const int home = (int)(blockIdx.x % kXcdCount);   // the XCD this workgroup runs on
+    int tried = 0;
+    for (int64_t p; (p = next_point(counters, home, tried, b.n, lane)) >= 0;) {
         if (REFILL)
-            bake_point_refill<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits,
+            bake_point_refill<COUNT>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits,
                                      n_node_steps, n_tri_steps);
         else
-            bake_point<COUNT>(b, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
+            bake_point<COUNT>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
     }
     if (COUNT) {
         // lane counters -> wave totals -> one 64-bit atomic per wave
@@ -444,33 +452,59 @@ __global__ __launch_bounds__(kBlock) void k_bake(BakeLaunch b, uint64_t* stats) 
     }
 }
 
-// Serving: persistent bake over a list of tiles; each wavefront takes the
-// next point of the launch (points of all tiles enumerated in order) from a
-// counter until none is left.
+// A job read from the tile table, its fields made wave-uniform so they stay
+// in scalar registers for the whole point (read through the table, the
+// compiler reloads them inside the traversal loop).  The roughness levels
+// are not copied: they are read from the table by lane-varying index.
+__device__ __forceinline__ BakeLaunch uniform_job(const BakeLaunch& j) {
+    auto up = [](const void* v) { return (const void*)wave_uniform((int64_t)v); };
+    auto u32 = [](int32_t v) { return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v); };
+    BakeLaunch b;
+    b.sc.nodes = static_cast<const Bvh4Node*>(up(j.sc.nodes));
+    b.sc.tris = static_cast<const TriGeom*>(up(j.sc.tris));
+    b.sc.rad = static_cast<const TriRad*>(up(j.sc.rad));
+    b.sc.n_tris = wave_uniform(j.sc.n_tris);
+    b.pts = static_cast<const float*>(up(j.pts));
+    b.ptri = static_cast<const int32_t*>(up(j.ptri));
+    b.pts_stride = wave_uniform(j.pts_stride);
+    b.n = wave_uniform(j.n);
+    b.p_offset = wave_uniform(j.p_offset);
+    b.out = const_cast<float*>(static_cast<const float*>(up(j.out)));
+    b.out_stride = wave_uniform(j.out_stride);
+    b.spp_d = u32(j.spp_d);
+    b.spp_s = u32(j.spp_s);
+    b.K = u32(j.K);
+    b.seed = (uint64_t)wave_uniform((int64_t)j.seed);
+    b.eps = __int_as_float(u32(__float_as_int(j.eps)));
+    return b;
+}
+
+// Serving: persistent bake over a list of tiles; the points of the launch
+// (all tiles' points enumerated in order) are handed out as in k_bake.
 __global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, int32_t n_tiles,
-                                                       int32_t* counter) {
+                                                       int32_t* counters) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
     uint32_t a = 0, bb = 0, c = 0, d = 0, e = 0, f = 0;   // counters, unused here
     const int64_t total = tiles[n_tiles - 1].first + tiles[n_tiles - 1].job.n;
-    while (true) {
-        int32_t grab = 0;
-        if (lane == 0) grab = atomicAdd(counter, 1);
-        grab = __builtin_amdgcn_readfirstlane(grab);
-        if ((int64_t)grab >= total) break;
-        // last tile whose first point is <= grab
+    const int home = (int)(blockIdx.x % kXcdCount);       // the XCD this workgroup runs on
+    int tried = 0;
+    for (int64_t p; (p = next_point(counters, home, tried, total, lane)) >= 0;) {
+        // last tile whose first point is <= p
         int lo = 0, hi = n_tiles - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (tiles[mid].first <= grab) lo = mid;
+            if (tiles[mid].first <= p) lo = mid;
             else hi = mid - 1;
         }
-        const BakeLaunch& job = tiles[lo].job;
+        const BakeLaunch job = uniform_job(tiles[lo].job);
+        const float* sigma = tiles[lo].job.sigma;
+        const int64_t q = p - tiles[lo].first;
         if (job.K <= kRefillMaxK)
-            bake_point_refill<false>(job, grab - tiles[lo].first, lane, stack, a, bb, c, d, e, f);
+            bake_point_refill<false>(job, sigma, q, lane, stack, a, bb, c, d, e, f);
         else
-            bake_point<false>(job, grab - tiles[lo].first, lane, stack, a, bb, c, d);
+            bake_point<false>(job, sigma, q, lane, stack, a, bb, c, d);
     }
 }
 
@@ -600,33 +634,47 @@ int launch_gen_points(const DeviceScene& sc, const CameraTable& cams, const fipt
 }
 
 int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream) {
-    // persistent grid: a few waves per SIMD, multiple of 8 workgroups so
-    // the XCD remap applies
+    // persistent grid: up to two rounds of resident workgroups, a multiple
+    // of kXcdCount so every XCD gets the same number of workgroups
     const int64_t want = (b.n + kWaves - 1) / kWaves;
-    int64_t cap = (int64_t)device_cus() * 8;
-    int64_t blocks = std::min(want, cap);
-    if (blocks >= 8) blocks &= ~int64_t(7);
-    if (blocks < 1) blocks = 1;
+    int64_t blocks = std::min(want, (int64_t)device_cus() * 8);
+    blocks = std::max<int64_t>(kXcdCount, (blocks + kXcdCount - 1) / kXcdCount * kXcdCount);
     const dim3 grid((unsigned)blocks), block(kBlock);
     hipStream_t st = (hipStream_t)stream;
+    // kXcdCount point counters, stream-ordered so concurrent calls on other
+    // streams never share them
+    int32_t* counters = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&counters), sizeof(int32_t) * kXcdCount, st);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? FIPT_ENOMEM : FIPT_EHIP, "bake counters: %s",
+                    hipGetErrorString(e));
+    e = hipMemsetAsync(counters, 0, sizeof(int32_t) * kXcdCount, st);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(counters, st);
+        return fail(FIPT_EHIP, "bake counters: %s", hipGetErrorString(e));
+    }
     const bool refill = b.K <= kRefillMaxK;
     if (stats && refill)
-        hipLaunchKernelGGL((k_bake<true, true>), grid, block, 0, st, b, stats);
+        hipLaunchKernelGGL((k_bake<true, true>), grid, block, 0, st, b, counters, stats);
     else if (stats)
-        hipLaunchKernelGGL((k_bake<true, false>), grid, block, 0, st, b, stats);
+        hipLaunchKernelGGL((k_bake<true, false>), grid, block, 0, st, b, counters, stats);
     else if (refill)
-        hipLaunchKernelGGL((k_bake<false, true>), grid, block, 0, st, b, stats);
+        hipLaunchKernelGGL((k_bake<false, true>), grid, block, 0, st, b, counters, stats);
     else
-        hipLaunchKernelGGL((k_bake<false, false>), grid, block, 0, st, b, stats);
-    return check_launch("bake");
+        hipLaunchKernelGGL((k_bake<false, false>), grid, block, 0, st, b, counters, stats);
+    const int rc = check_launch("bake");
+    e = hipFreeAsync(counters, st);
+    if (rc != FIPT_OK) return rc;
+    if (e != hipSuccess) return fail(FIPT_EHIP, "bake counters: %s", hipGetErrorString(e));
+    return FIPT_OK;
 }
 
 int bake_tiles_grid_hint() { return device_cus() * 8; }
 
-int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* counter_dev,
+int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* counters_dev,
                       int32_t grid, void* stream) {
     hipLaunchKernelGGL(k_bake_tiles, dim3((unsigned)grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       tiles_dev, n_tiles, counter_dev);
+                       tiles_dev, n_tiles, counters_dev);
     return check_launch("bake_tiles");
 }
 

@@ -131,8 +131,26 @@ __device__ __forceinline__ void order2(float& ka, int32_t& ca, float& kb, int32_
     ca = c;
 }
 
+// Load through a pointer known to address global memory.  Scene and point
+// pointers that the serving kernel reads from a tile table are generic as far
+// as the compiler can tell; loading through a global-qualified pointer gives
+// global loads with a scalar base instead of flat loads (which also wait on
+// the LDS counter the traversal stack uses).
+// (The load goes through a native vector type: HIP's float4 is a class,
+// copied through a generic pointer, which would drop the address space.)
+typedef float gfloat4 __attribute__((ext_vector_type(4)));
+typedef int gint4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_global(const float4* p) {
+    const gfloat4 v = *(const __attribute__((address_space(1))) gfloat4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int4 load_global(const int4* p) {
+    const gint4 v = *(const __attribute__((address_space(1))) gint4*)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ float4 node_vec(const Bvh4Node* nodes, uint32_t off) {
-    return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(nodes) + off);
+    return load_global(reinterpret_cast<const float4*>(reinterpret_cast<const char*>(nodes) + off));
 }
 
 // One step of closest-hit traversal at 4-wide node `ref`: the hit children
@@ -148,7 +166,7 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
     const float4 nx = node_vec(nodes, ox), fx = node_vec(nodes, ox ^ 16u);
     const float4 ny = node_vec(nodes, oy), fy = node_vec(nodes, oy ^ 16u);
     const float4 nz = node_vec(nodes, oz), fz = node_vec(nodes, oz ^ 16u);
-    const int4 ch = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(nodes) + base + 96u);
+    const int4 ch = load_global(reinterpret_cast<const int4*>(reinterpret_cast<const char*>(nodes) + base + 96u));
     float k0 = box_entry(nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, r, tmax);
     float k1 = box_entry(nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, r, tmax);
     float k2 = box_entry(nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, r, tmax);
@@ -184,9 +202,9 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
 __device__ __forceinline__ void tri_test(const TriGeom* tris, int32_t i, V3 o, V3 d, Hit& h,
                                          int32_t& best_orig) {
     const float4* tp = reinterpret_cast<const float4*>(tris + i);
-    const float4 t0 = tp[0];
-    const float4 t1 = tp[1];
-    const float4 t2 = tp[2];
+    const float4 t0 = load_global(tp);
+    const float4 t1 = load_global(tp + 1);
+    const float4 t2 = load_global(tp + 2);
     const V3 e1 = v3(t1.x, t1.y, t1.z);
     const V3 e2 = v3(t2.x, t2.y, t2.z);
     const V3 pv = cross(d, e2);
@@ -252,9 +270,9 @@ __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t*
 __device__ __forceinline__ V3 radiance(const DeviceScene& sc, const Hit& h) {
     if (h.leaf < 0) return v3(0.0f, 0.0f, 0.0f);
     const float4* rp = reinterpret_cast<const float4*>(sc.rad + h.leaf);
-    const float4 r0 = rp[0];
-    const float4 r1 = rp[1];
-    const float4 r2 = rp[2];
+    const float4 r0 = load_global(rp);
+    const float4 r1 = load_global(rp + 1);
+    const float4 r2 = load_global(rp + 2);
     const float w0 = 1.0f - h.u - h.v;
     return v3(w0 * r0.x + h.u * r0.w + h.v * r1.z + r2.y,
               w0 * r0.y + h.u * r1.x + h.v * r1.w + r2.z,

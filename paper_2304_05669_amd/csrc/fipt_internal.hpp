@@ -128,12 +128,17 @@ struct BakeLaunch {
 };
 int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream);
 
+// MI355X has 8 XCDs (dies, each with its own L2); the dispatcher places
+// workgroup i of a launch on XCD i % kXcdCount.
+constexpr int kXcdCount = 8;
+
 // Serving: a tile is a contiguous run of one request's points.
 struct TileDesc {
     BakeLaunch job;       // job.n = points in the tile, pointers already offset
     int64_t first;        // points of all earlier tiles in the launch
 };
-int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* counter_dev,
+// counters_dev: kXcdCount zeroed int32 counters.
+int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* counters_dev,
                       int32_t grid, void* stream);
 int bake_tiles_grid_hint();
 

@@ -6,8 +6,9 @@
 // one tile from every admitted request that still has unassigned points,
 // the samples of a launch shared evenly between them (processor sharing:
 // a small request finishes within a launch or two even while large ones
-// are running).  Two launches are kept queued on the server's stream so the
-// GPU never waits for the host; a request that arrives meanwhile joins the
+// are running).  Two launches are kept in flight, each on its own stream,
+// so the GPU never waits for the host and one launch's last wavefronts
+// overlap the next launch's first; a request that arrives meanwhile joins the
 // next launch that is built.  Completion is detected from each launch's
 // event; a request is done when all its points' tiles have completed.
 //
@@ -64,7 +65,8 @@ struct TileRec {
 struct Slot {
     TileDesc* host = nullptr;   // pinned
     TileDesc* dev = nullptr;
-    int32_t* counter = nullptr;
+    int32_t* counter = nullptr;   // kXcdCount point counters
+    hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
     std::vector<TileRec> recs;
@@ -77,7 +79,6 @@ constexpr int64_t kAlign = 256;
 
 struct fipt_server_s {
     int32_t device = 0;
-    hipStream_t stream = nullptr;
     char* pool = nullptr;
     int64_t pool_bytes = 0;
     int32_t max_inflight = 0;
@@ -247,11 +248,12 @@ struct fipt_server_s {
                 }
                 if (nt == 0) break;
                 hipError_t e = hipMemcpyAsync(s.dev, s.host, sizeof(TileDesc) * nt,
-                                              hipMemcpyHostToDevice, stream);
-                if (e == hipSuccess) e = hipMemsetAsync(s.counter, 0, sizeof(int32_t), stream);
-                int rc = e == hipSuccess ? launch_bake_tiles(s.dev, nt, s.counter, grid, stream)
+                                              hipMemcpyHostToDevice, s.stream);
+                if (e == hipSuccess)
+                    e = hipMemsetAsync(s.counter, 0, sizeof(int32_t) * kXcdCount, s.stream);
+                int rc = e == hipSuccess ? launch_bake_tiles(s.dev, nt, s.counter, grid, s.stream)
                                          : FIPT_EHIP;
-                if (rc == FIPT_OK) e = hipEventRecord(s.done, stream);
+                if (rc == FIPT_OK) e = hipEventRecord(s.done, s.stream);
                 if (e != hipSuccess || rc != FIPT_OK) {
                     std::lock_guard<std::mutex> lk(mu);
                     worker_error = e != hipSuccess ? hipGetErrorString(e) : "tile launch failed";
@@ -284,9 +286,9 @@ void server_free(fipt_server s) {
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.counter) (void)hipFree(sl.counter);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     if (s->pool) (void)hipFree(s->pool);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
 
@@ -315,13 +317,15 @@ int fipt_server_create(int32_t device, int64_t pool_bytes, int32_t max_inflight,
     s->samples_per_launch = samples_per_launch;
     s->grid = bake_tiles_grid_hint();
     s->t0 = std::chrono::steady_clock::now();
-    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->pool), pool_bytes);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&s->pool), pool_bytes);
     for (int i = 0; i < kSlots && e == hipSuccess; ++i) {
         Slot& sl = s->slots[i];
-        e = hipHostMalloc(reinterpret_cast<void**>(&sl.host), sizeof(TileDesc) * max_inflight, 0);
+        e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&sl.host), sizeof(TileDesc) * max_inflight, 0);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.dev), sizeof(TileDesc) * max_inflight);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.counter), sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void**>(&sl.counter), sizeof(int32_t) * kXcdCount);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
@@ -472,7 +476,7 @@ int fipt_server_destroy(fipt_server srv) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(srv->device);
-    (void)hipStreamSynchronize(srv->stream);
+    for (Slot& sl : srv->slots) (void)hipStreamSynchronize(sl.stream);
     for (auto& kv : srv->reqs) kv.second.scene->refs.fetch_sub(1);
     server_free(srv);
     if (prev >= 0) (void)hipSetDevice(prev);
