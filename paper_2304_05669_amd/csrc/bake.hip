@@ -30,8 +30,17 @@ using dev::v3;
 constexpr int kBlock = 256;             // 4 wavefronts
 constexpr int kWaves = kBlock / 64;
 
+// Lobe of flattened sample q: 0 for the first spp_d (diffuse) samples, then
+// 1 + (q - spp_d) / spp_s.  The quotient is below 17 and r < 2^20 (spp <=
+// 65536, K <= 16), so the float estimate is off by at most one, at exact
+// multiples, and the correction makes it exact.
 __device__ __forceinline__ int lobe_of(int q, int spp_d, int spp_s) {
-    return q < spp_d ? 0 : 1 + (q - spp_d) / spp_s;
+    if (q < spp_d) return 0;
+    const int r = q - spp_d;
+    int l = (int)((float)r * __builtin_amdgcn_rcpf((float)spp_s));
+    if ((int)__umul24((unsigned)l, (unsigned)spp_s) > r) --l;
+    else if ((int)__umul24((unsigned)(l + 1), (unsigned)spp_s) <= r) ++l;
+    return 1 + l;
 }
 
 // Output plane of accumulator slot j: slot 0..2 -> Ld; slot 3 + 6k + c ->
@@ -87,8 +96,8 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sig
             sincospif(2.0f * xi2, &sp_, &cp_);
             if (lobe == 0) {
                 // cosine-weighted direction; estimator weight 1
-                const float r = sqrtf(xi1);
-                wi = dev::to_world(ft, fb, n, r * cp_, r * sp_, sqrtf(1.0f - xi1));
+                const float r = dev::sqrt_hw(xi1);
+                wi = dev::to_world(ft, fb, n, r * cp_, r * sp_, dev::sqrt_hw(1.0f - xi1));
                 w = 1.0f;
                 shoot = true;
             } else {
@@ -96,9 +105,9 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sig
                 const float sg = sigma[lobe - 1];
                 const float alpha = sg * sg;
                 const float a2 = alpha * alpha;
-                const float tan2 = a2 * xi1 / (1.0f - xi1);
-                const float cos_m = 1.0f / sqrtf(1.0f + tan2);
-                const float sin_m = sqrtf(tan2) * cos_m;   // accurate for tiny tilts
+                const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
+                const float cos_m = rsqrtf(1.0f + tan2);
+                const float sin_m = dev::sqrt_hw(tan2) * cos_m;   // accurate for tiny tilts
                 const V3 m = dev::to_world(ft, fb, n, sin_m * cp_, sin_m * sp_, cos_m);
                 const float om = dev::dot(wo, m);
                 if (om > 0.0f) {
@@ -106,7 +115,7 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sig
                     const float ci = dev::dot(n, wi);
                     if (ci > 0.0f) {
                         const float G = dev::smith_g1(a2, ci) * dev::smith_g1(a2, cos_o);
-                        w = G * om / (cos_o * cos_m);
+                        w = G * om * dev::rcp(cos_o * cos_m);
                         const float f = 1.0f - om;
                         const float f2 = f * f;
                         F1 = f2 * f2 * f;
@@ -306,8 +315,8 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                         sincospif(2.0f * xi2, &sp_, &cp_);
                         bool shoot = false;
                         if (lobe == 0) {
-                            const float r = sqrtf(xi1);
-                            d = dev::to_world(ft, fb, n, r * cp_, r * sp_, sqrtf(1.0f - xi1));
+                            const float r = dev::sqrt_hw(xi1);
+                            d = dev::to_world(ft, fb, n, r * cp_, r * sp_, dev::sqrt_hw(1.0f - xi1));
                             w0 = 1.0f;
                             w1 = 0.0f;
                             shoot = true;
@@ -315,9 +324,9 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                             const float sg = sigma[lobe - 1];
                             const float alpha = sg * sg;
                             const float a2 = alpha * alpha;
-                            const float tan2 = a2 * xi1 / (1.0f - xi1);
-                            const float cos_m = 1.0f / sqrtf(1.0f + tan2);
-                            const float sin_m = sqrtf(tan2) * cos_m;
+                            const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
+                            const float cos_m = rsqrtf(1.0f + tan2);
+                            const float sin_m = dev::sqrt_hw(tan2) * cos_m;
                             const V3 m = dev::to_world(ft, fb, n, sin_m * cp_, sin_m * sp_, cos_m);
                             const float om = dev::dot(wo, m);
                             if (om > 0.0f) {
@@ -325,7 +334,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                                 const float ci = dev::dot(n, d);
                                 if (ci > 0.0f) {
                                     const float G = dev::smith_g1(a2, ci) * dev::smith_g1(a2, cos_o);
-                                    const float w = G * om / (cos_o * cos_m);
+                                    const float w = G * om * dev::rcp(cos_o * cos_m);
                                     const float f = 1.0f - om;
                                     const float f2 = f * f;
                                     const float F1 = f2 * f2 * f;

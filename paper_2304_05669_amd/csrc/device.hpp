@@ -32,10 +32,11 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32 x 32 -> 64-bit multiply gives both halves of a product
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)m0, hi0 = (uint32_t)(m0 >> 32);
+        const uint32_t lo1 = (uint32_t)m1, hi1 = (uint32_t)(m1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -66,10 +67,18 @@ __device__ __forceinline__ V3 to_world(V3 t, V3 b, V3 n, float lx, float ly, flo
               t.z * lx + b.z * ly + n.z * lz);
 }
 
+// Reciprocal by the hardware approximation (about 1 ulp): sampling
+// directions and weights tolerate it, and a correctly rounded division
+// costs ten times as many instructions.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Square root by the hardware approximation (about 1 ulp), for the same
+// reason; inputs here are never denormal.
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Smith G1 of GGX written as 2 c / (c + sqrt(alpha^2 + (1 - alpha^2) c^2)),
 // c = n.v > 0 (algebraically 2 / (1 + sqrt(1 + alpha^2 tan^2))).
 __device__ __forceinline__ float smith_g1(float a2, float c) {
-    return 2.0f * c / (c + sqrtf(a2 + (1.0f - a2) * c * c));
+    return 2.0f * c * rcp(c + sqrt_hw(a2 + (1.0f - a2) * c * c));
 }
 
 // ---- BVH traversal ---------------------------------------------------------
