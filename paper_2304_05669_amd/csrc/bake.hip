@@ -199,6 +199,12 @@ constexpr int kSearchMin = 8;        // leave the node loop below this many sear
 
 enum LaneState { kIdle = 0, kTracing = 1, kFinished = 2 };
 
+// A leaf reference: negative but not kDone (INT_MIN).  No leaf encodes to
+// INT_MIN, which would need first = 2^28 - 1 with 8 triangles.
+__device__ __forceinline__ bool is_leaf(int32_t ref) {
+    return (uint32_t)ref > (uint32_t)kDone;
+}
+
 template <bool COUNT>
 __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const float* sigma, int64_t p,
                                                   int lane,
@@ -242,12 +248,12 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
     float cur0 = 0.0f, cur1 = 0.0f, cur2 = 0.0f, cur3 = 0.0f, cur4 = 0.0f, cur5 = 0.0f;
     int cur_lobe = -1;
     auto flush = [&](bool need) {
-        uint64_t m = __ballot(need);
+        uint64_t m = dev::ballot(need);
         while (m) {
             const int leader = __ffsll((unsigned long long)m) - 1;
             const int l = __shfl(cur_lobe, leader, 64);
             const bool in = need && cur_lobe == l;
-            m &= ~__ballot(in);
+            m &= ~dev::ballot(in);
             const float s0 = dev::wave_sum(in ? cur0 : 0.0f);
             const float s1 = dev::wave_sum(in ? cur1 : 0.0f);
             const float s2 = dev::wave_sum(in ? cur2 : 0.0f);
@@ -279,7 +285,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
 
     while (true) {
         // ---- fold finished rays and refill free lanes ----------------------
-        const uint64_t tracing = __ballot(state == kTracing);
+        const uint64_t tracing = dev::ballot(state == kTracing);
         const int n_free = 64 - __popcll(tracing);
         if (n_free >= kRefillMin || tracing == 0) {
             const bool done = state == kFinished;
@@ -363,9 +369,11 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
             }
         }
         // ---- traversal: inner nodes until every lane has parked a leaf ----
+        // Lanes that are not tracing hold ref == kDone, so ref alone tells a
+        // lane's position: >= 0 an inner node, other negative values a leaf.
         int32_t pend = kDone;
         while (true) {
-            if (state == kTracing && ref < 0 && ref != kDone && pend == kDone) {
+            if (is_leaf(ref) && pend == kDone) {
                 pend = ref;
                 if (sp == 0) {
                     ref = kDone;
@@ -374,12 +382,13 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                     ref = stack[sp * kBlock];
                 }
             }
-            const bool inner = state == kTracing && ref >= 0;
+            const bool inner = ref >= 0;
             // Stop descending once fewer than kSearchMin lanes are still
             // looking for a leaf and some lane has one to test: the rest would
             // otherwise idle while the last few rays search.
-            const uint64_t searching = __ballot(inner && pend == kDone);
-            if (searching == 0 || (__popcll(searching) < kSearchMin && __any(pend != kDone))) break;
+            const uint64_t searching = dev::ballot(inner && pend == kDone);
+            if (searching == 0 || (__popcll(searching) < kSearchMin && dev::ballot(pend != kDone) != 0))
+                break;
             if (COUNT && lane == 0) ++n_node_steps;
             if (inner) {
                 if (COUNT) ++n_nodes;
@@ -387,7 +396,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
             }
         }
         // ---- leaves ---------------------------------------------------------
-        if (state == kTracing && pend != kDone) {
+        if (pend != kDone) {
             const int32_t lr = ~pend;
             const int32_t first = lr >> 3;
             const int32_t cnt = (lr & 7) + 1;

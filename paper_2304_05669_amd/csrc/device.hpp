@@ -288,6 +288,10 @@ __device__ __forceinline__ V3 radiance(const DeviceScene& sc, const Hit& h) {
               w0 * r0.z + h.u * r1.y + h.v * r2.x + r2.w);
 }
 
+// Lanes of the wave where p holds (the wave64 ballot on a boolean; HIP's
+// int-valued __ballot costs two extra instructions per call).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // Sum over the 64 lanes of a wave by a fixed xor butterfly: every lane ends
 // with the same, order-fixed total.
 __device__ __forceinline__ float wave_sum(float v) {
