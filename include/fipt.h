@@ -210,9 +210,10 @@ int fipt_gen_points(fipt_scene s, const fipt_camera* cams, int32_t n_cams,
  * (1 - wi.m)^5, F0 = 1 - F1, and samples with wo.m <= 0 or n.wi <= 0 count
  * as zero.  Points with tri < 0 or n.wo = 0 get zeros.  `out` must hold
  * 3 + 6K planes of at least pts->n elements.  Asynchronous on `stream`;
- * takes 32 bytes of stream-ordered device memory (hipMallocAsync) for its
- * work counters and frees them on the same stream (FIPT_ENOMEM if that
- * allocation fails). */
+ * allocates nothing: its work counters come from a ring of 16 slots held by
+ * the scene, and the call makes `stream` wait until the previous launch
+ * that used the same slot has finished, so concurrent calls on any streams
+ * are safe. */
 int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
               const fipt_shading* out, void* stream);
 

@@ -77,6 +77,9 @@ void scene_free(fipt_scene s) {
     if (s->d_rad) (void)hipFree(s->d_rad);
     if (s->d_order) (void)hipFree(s->d_order);
     if (s->d_tri_idx) (void)hipFree(s->d_tri_idx);
+    if (s->d_counters) (void)hipFree(s->d_counters);
+    for (hipEvent_t& e : s->slot_done)
+        if (e) (void)hipEventDestroy(e);
     delete s;
 }
 
@@ -176,9 +179,17 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris, 
         (rc = dev_alloc(&s->d_tris, bvh.tris.size(), &s->bytes)) ||
         (rc = dev_alloc(&s->d_rad, bvh.tris.size(), &s->bytes)) ||
         (rc = dev_alloc(&s->d_order, bvh.order.size(), &s->bytes)) ||
-        (rc = dev_alloc(&s->d_tri_idx, (size_t)(3 * n_tris), &s->bytes))) {
+        (rc = dev_alloc(&s->d_tri_idx, (size_t)(3 * n_tris), &s->bytes)) ||
+        (rc = dev_alloc(&s->d_counters, (size_t)kBakeSlots * kXcdCount, &s->bytes))) {
         scene_free(s);
         return rc;
+    }
+    for (hipEvent_t& ev : s->slot_done) {
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            scene_free(s);
+            return fail(FIPT_EHIP, "scene events: %s", hipGetErrorString(e));
+        }
     }
     hipError_t e = hipMemcpyAsync(s->d_nodes, bvh.nodes4.data(),
                                   sizeof(Bvh4Node) * bvh.nodes4.size(), hipMemcpyHostToDevice, st);
@@ -311,7 +322,18 @@ static int bake_common(fipt_scene s, const fipt_points* pts, const fipt_bake_par
     DeviceGuard g(s->device);
     if (g.rc) return g.rc;
     BakeLaunch b = make_bake_launch(s, pts, p, out);
-    return launch_bake(b, stats, stream);
+    // take the next counter slot; wait (on the stream) for its last user
+    std::lock_guard<std::mutex> lk(s->slot_mu);
+    const int k = s->next_slot;
+    s->next_slot = (k + 1) % kBakeSlots;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamWaitEvent(st, s->slot_done[k], 0);
+    if (e != hipSuccess) return fail(FIPT_EHIP, "bake slot wait: %s", hipGetErrorString(e));
+    rc = launch_bake(b, s->d_counters + (size_t)k * kXcdCount, stats, stream);
+    if (rc) return rc;
+    e = hipEventRecord(s->slot_done[k], st);
+    if (e != hipSuccess) return fail(FIPT_EHIP, "bake slot event: %s", hipGetErrorString(e));
+    return FIPT_OK;
 }
 
 int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,

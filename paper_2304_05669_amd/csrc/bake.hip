@@ -526,6 +526,10 @@ __global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, in
     }
 }
 
+__global__ void k_zero_counters(int32_t* counters) {
+    if (threadIdx.x < kXcdCount) counters[threadIdx.x] = 0;
+}
+
 __global__ void k_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_idx,
                                int64_t T, int kind, const float* cache, int64_t n_cache,
                                const float* emission) {
@@ -651,7 +655,7 @@ int launch_gen_points(const DeviceScene& sc, const CameraTable& cams, const fipt
     return check_launch("gen_points");
 }
 
-int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream) {
+int launch_bake(const BakeLaunch& b, int32_t* counters, uint64_t* stats, void* stream) {
     // persistent grid: up to two rounds of resident workgroups, a multiple
     // of kXcdCount so every XCD gets the same number of workgroups
     const int64_t want = (b.n + kWaves - 1) / kWaves;
@@ -659,18 +663,8 @@ int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream) {
     blocks = std::max<int64_t>(kXcdCount, (blocks + kXcdCount - 1) / kXcdCount * kXcdCount);
     const dim3 grid((unsigned)blocks), block(kBlock);
     hipStream_t st = (hipStream_t)stream;
-    // kXcdCount point counters, stream-ordered so concurrent calls on other
-    // streams never share them
-    int32_t* counters = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&counters), sizeof(int32_t) * kXcdCount, st);
-    if (e != hipSuccess)
-        return fail(e == hipErrorOutOfMemory ? FIPT_ENOMEM : FIPT_EHIP, "bake counters: %s",
-                    hipGetErrorString(e));
-    e = hipMemsetAsync(counters, 0, sizeof(int32_t) * kXcdCount, st);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(counters, st);
-        return fail(FIPT_EHIP, "bake counters: %s", hipGetErrorString(e));
-    }
+    // zeroed by a kernel, not a memset node, so a caller may capture the call
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, counters);
     const bool refill = b.K <= kRefillMaxK;
     if (stats && refill)
         hipLaunchKernelGGL((k_bake<true, true>), grid, block, 0, st, b, counters, stats);
@@ -680,11 +674,7 @@ int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream) {
         hipLaunchKernelGGL((k_bake<false, true>), grid, block, 0, st, b, counters, stats);
     else
         hipLaunchKernelGGL((k_bake<false, false>), grid, block, 0, st, b, counters, stats);
-    const int rc = check_launch("bake");
-    e = hipFreeAsync(counters, st);
-    if (rc != FIPT_OK) return rc;
-    if (e != hipSuccess) return fail(FIPT_EHIP, "bake counters: %s", hipGetErrorString(e));
-    return FIPT_OK;
+    return check_launch("bake");
 }
 
 int bake_tiles_grid_hint() { return device_cus() * 8; }

@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "fipt.h"
 
 namespace fipt {
@@ -126,7 +128,9 @@ struct BakeLaunch {
     uint64_t seed;
     float eps;
 };
-int launch_bake(const BakeLaunch& b, uint64_t* stats, void* stream);
+// counters_dev: kXcdCount int32 point counters owned by this launch; the
+// launcher zeroes them on `stream` before the kernel.
+int launch_bake(const BakeLaunch& b, int32_t* counters_dev, uint64_t* stats, void* stream);
 
 // MI355X has 8 XCDs (dies, each with its own L2); the dispatcher places
 // workgroup i of a launch on XCD i % kXcdCount.
@@ -175,6 +179,11 @@ int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_
 
 }  // namespace fipt
 
+// Work-counter slots of a scene's bakes: each fipt_bake call takes the next
+// slot and first makes its stream wait for the slot's previous launch, so
+// no two launches in flight share counters, on any streams.
+constexpr int kBakeSlots = 16;
+
 struct fipt_scene_s {
     int32_t device = 0;
     int64_t n_tris = 0, n_verts = 0, n_nodes = 0;
@@ -186,6 +195,10 @@ struct fipt_scene_s {
     fipt::TriRad* d_rad = nullptr;
     int32_t* d_order = nullptr;    // leaf position -> original triangle
     int32_t* d_tri_idx = nullptr;  // original [T][3] vertex indices
+    int32_t* d_counters = nullptr;  // [kBakeSlots][kXcdCount]
+    hipEvent_t slot_done[kBakeSlots] = {};
+    int next_slot = 0;
+    std::mutex slot_mu;
     int64_t bytes = 0;
     std::atomic<int> refs{0};      // serving requests referencing the scene
     fipt::DeviceScene view() const { return {d_nodes, d_tris, d_rad, n_tris}; }

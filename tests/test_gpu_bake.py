@@ -73,6 +73,24 @@ def test_bake_is_deterministic(tiny, tiny_gpu, tiny_points):
     assert np.any(a != c)
 
 
+def test_concurrent_bakes_on_several_streams(tiny, tiny_gpu, tiny_points):
+    """More bakes of one scene than it has work-counter slots (16), spread
+    over four streams: every result equals the single-stream bake bit for
+    bit (no two launches in flight share counters)."""
+    pts, tri, _ = tiny_points
+    P, T = torch.from_numpy(pts).to(DEV), torch.from_numpy(tri).to(DEV)
+    want = _bake(tiny_gpu, pts, tri, 32, 32, tiny.sigma, 5)
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    torch.cuda.synchronize()
+    outs = []
+    for i in range(24):
+        with torch.cuda.stream(streams[i % 4]):
+            outs.append(fipt.fipt_bake(tiny_gpu, P, T, 32, 32, tiny.sigma, 5))
+    torch.cuda.synchronize()
+    for o in outs:
+        np.testing.assert_array_equal(o.cpu().numpy(), want)
+
+
 @pytest.mark.parametrize("spp_d,spp_s,sigma", [
     (37, 5, (0.1, 0.5, 0.9)),                   # chunks mixing several lobes
     (1, 1, (0.3,)),                              # one sample, one level
