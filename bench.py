@@ -227,6 +227,108 @@ def run_serving(dev, n_requests, rate, log_every=20):
                            gsamples_per_s=samples / t_single / 1e9))
 
 
+def copy_bandwidth(dev, n=1 << 28, reps=5):
+    """Achievable HBM bandwidth: a 1 GiB float32 device-to-device copy."""
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 8 * n / (ms * 1e-3) / 1e9, ms
+
+
+def loss_timing(shading, mat, obs, sigma, reps=10, flush=None):
+    """Mean fused render + loss + gradient time (ms) over ``reps`` launches;
+    with ``flush`` (a >= 512 MB tensor) the caches are refilled by reading it
+    before each launch (reads, so no dirty lines are left to write back), and
+    the kernel's inputs come from HBM."""
+    n = shading.shape[1]
+    grad = torch.empty((5, n), dtype=torch.float32, device=shading.device)
+    buf = torch.empty((fipt.LOSS_SLOTS,), dtype=torch.float64, device=shading.device)
+    fipt.fipt_render_loss(shading, mat, obs, sigma, loss_buf=buf, grad=grad)
+    tm = Timer()
+    for _ in range(reps):
+        if flush is not None:
+            flush.sum()
+        tm.mark("a")
+        fipt.fipt_render_loss(shading, mat, obs, sigma, loss_buf=buf, grad=grad)
+        tm.mark("b")
+    torch.cuda.synchronize()
+    return float(np.mean(tm.spans("a", "b")))
+
+
+def run_large(dev, rebakes, copy_gbs):
+    """The emitter loop on the ~2M-triangle room: ``rebakes`` bakes of
+    1,000,000 points x 256 spp x 7 lobes, each after uploading that
+    iteration's per-triangle emission; then the fused loss + gradient on the
+    last bake's shadings."""
+    t0 = time.perf_counter()
+    sc = synth.large_room()
+    scene = setup_room(sc, dev)
+    planes, tri = fipt.fipt_gen_points(scene, sc.cameras)
+    N = planes.shape[1]
+    K = len(sc.sigma)
+    S = sc.spp * (1 + K)
+    sched = [torch.from_numpy(e).to(dev) for e in synth.emission_schedule(sc.emission, rebakes)]
+    out = torch.empty((3 + 6 * K, N), dtype=torch.float32, device=dev)
+    fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out)   # warm-up
+    torch.cuda.synchronize()
+    log(f"large room setup {time.perf_counter() - t0:.1f} s: {sc.n_tris} triangles, {N} points")
+    tm = Timer()
+    t1 = time.perf_counter()
+    for i, le in enumerate(sched):
+        tm.mark("a")
+        scene.set_emission(le)
+        tm.mark("b")
+        fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out)
+        tm.mark("c")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    log(f"large room: {rebakes} re-bakes in {wall:.2f} s")
+    t_bake = float(np.mean(tm.spans("b", "c")))
+    t_emis = float(np.mean(tm.spans("a", "b")))
+    trav = traversal_bytes(scene, planes, tri, sc, out)
+    # material gathered from a 128^3 grid over the room (as in the
+    # differentiation workload), observations synthetic
+    grid = torch.from_numpy(synth.material_grid(128, seed=1007)).to(dev)
+    mat = fipt.fipt_grid_gather(grid, sc.bmin.tolist(), sc.bmax.tolist(), planes[0:3].contiguous())
+    obs = torch.from_numpy(synth.random_observations(N)).to(dev)
+    flush = torch.ones((1 << 27,), dtype=torch.float32, device=dev)      # 512 MB
+    t_warm = loss_timing(out, mat, obs, sc.sigma)
+    t_cold = loss_timing(out, mat, obs, sc.sigma, flush=flush)
+    del flush
+    scene.destroy()
+    gbs = lambda ms: N * LOSS_BYTES_PER_POINT / (ms * 1e-3) / 1e9
+    eff = trav["bytes"] / (t_bake * 1e-3) / 1e9
+    return {
+        "workload": f"large room: {sc.n_tris:,} triangles, {len(sc.cameras)} cameras x 250x250 = "
+                    f"{N:,} points, {sc.spp} spp per lobe, {K} roughness levels, {rebakes} re-bakes "
+                    "with per-triangle emission updated before each",
+        "rebakes": rebakes,
+        "ms_per_rebake": wall * 1e3 / rebakes,
+        "bake_ms": t_bake,
+        "set_emission_ms": t_emis,
+        "gsamples_per_s": N * S / (t_bake * 1e-3) / 1e9,
+        "rays_per_s": trav["rays"] / (t_bake * 1e-3),
+        "traversal": trav,
+        "effective_traversal_gbs": eff,
+        "effective_traversal_frac_of_achievable_hbm": eff / copy_gbs,
+        "loss_grad": {"points": N, "warm_ms": t_warm, "cold_ms": t_cold,
+                      "warm_gbs": gbs(t_warm), "cold_gbs": gbs(t_cold),
+                      "warm_frac_of_achievable_hbm": gbs(t_warm) / copy_gbs,
+                      "cold_frac_of_achievable_hbm": gbs(t_cold) / copy_gbs,
+                      "bytes_per_point": LOSS_BYTES_PER_POINT,
+                      "material": "gathered from a 128^3 grid (spatially coherent roughness)"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +339,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--no-counters", action="store_true")
+    ap.add_argument("--large-rebakes", type=int, default=10,
+                    help="re-bakes of the ~2M-triangle emitter loop (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device-to-device copies (counter scaling and "
                          "achievable HBM bandwidth) and exit")
@@ -250,20 +354,12 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         n = 1 << 28                                      # 1 GiB of float32
-        x = torch.ones(n, dtype=torch.float32, device=dev)
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(5):
-            y.copy_(x)
-        b.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / 5
+        gbs, ms = copy_bandwidth(dev, n)
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
-                          "copy_ms": ms, "copy_gbs": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+                          "copy_ms": ms, "copy_gbs": gbs}), flush=True)
         return
+    copy_gbs, _ = copy_bandwidth(dev)
+    log(f"achievable HBM bandwidth (1 GiB copy): {copy_gbs:.0f} GB/s")
 
     t_setup = time.perf_counter()
     sc = synth.room()
@@ -342,6 +438,16 @@ def main():
     loss_gbs = N * LOSS_BYTES_PER_POINT / (t_loss * 1e-3) / 1e9
     traffic = measured_traffic()
 
+    flush = torch.ones((1 << 27,), dtype=torch.float32, device=dev)      # 512 MB
+    t_loss_cold = loss_timing(shading, mat, obs, sc.sigma, flush=flush)
+    del flush
+
+    large = None
+    if args.large_rebakes > 0:
+        large = run_large(dev, args.large_rebakes, copy_gbs)
+        log(f"large room: {large['gsamples_per_s']:.2f} Gsamples/s, "
+            f"{large['effective_traversal_gbs']:.0f} GB/s effective traversal")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: timing the oracle on a bounded sample ...")
@@ -375,6 +481,9 @@ def main():
         "loss_grad_points_per_s": N / ((t_loss + t_gather + t_scatter) * 1e-3),
         "render_loss_points_per_s": N / (t_loss * 1e-3),
         "render_loss_gbs": loss_gbs,
+        "render_loss_cold_ms": t_loss_cold,
+        "render_loss_cold_gbs": N * LOSS_BYTES_PER_POINT / (t_loss_cold * 1e-3) / 1e9,
+        "achievable_hbm_gbs": copy_gbs,
         "loss": loss_value,
         "traversal": trav,
         "roofline": {"bound": "alu", "achieved": bake_tops, "peak": PEAK_VALU_TOPS,
@@ -389,6 +498,7 @@ def main():
                                  "bytes_per_point": LOSS_BYTES_PER_POINT, "kernel": "k_render_loss"},
         "cpu_baseline": cpu,
         "serving": serving,
+        "large_room": large,
     }
     print(json.dumps(out), flush=True)
 

@@ -18,6 +18,7 @@ from .scenes import (  # noqa: F401
     random_observations,
     observation_noise,
     serving_trace,
+    emission_schedule,
     icosphere,
     SERVING_TRIANGLES,
     SIGMA_GRID,

@@ -466,3 +466,19 @@ def serving_trace(n_requests: int, rate: float, room_points, seed: int = 1104,
         out.append(dict(arrival=t, room=r, offset=off, count=n, spp=spp,
                         seed=5000 + i))
     return out
+
+
+def emission_schedule(emission: np.ndarray, n_iter: int, seed: int = 2105) -> list:
+    """Per-triangle emission for each of ``n_iter`` re-bakes of the emitter
+    loop: iteration i scales every emissive triangle's radiance by its own
+    factor drawn uniformly in [0.5, 1.5] (a stand-in for the re-estimated
+    emission); non-emissive triangles stay at zero.  float32 [3, T] each."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lit = np.any(emission > 0, axis=0)
+    out = []
+    for _ in range(n_iter):
+        f = np.ones(emission.shape[1], dtype=np.float32)
+        f[lit] = rng.uniform(0.5, 1.5, size=int(lit.sum())).astype(np.float32)
+        out.append((emission * f[None, :]).astype(np.float32))
+    return out
+
