@@ -148,10 +148,9 @@ def cpu_baseline(sc, planes, tri, budget_s):
                        f"brute-force float64 over all {sc.n_tris} triangles, {dt:.1f} s")
 
 
-def run_serving(dev, n_requests, rate, log_every=20):
-    """Replay a Poisson trace of bake requests over eight resident rooms,
-    through the server and one request at a time; latency = completion -
-    arrival."""
+def serving_setup(dev):
+    """Eight resident rooms (18,860 ... 1,980,160 triangles) and their camera
+    points."""
     rooms = synth.serving_rooms()
     scenes, pts = [], []
     for r in rooms:
@@ -160,11 +159,17 @@ def run_serving(dev, n_requests, rate, log_every=20):
         scenes.append(s)
         pts.append((planes, tri))
     torch.cuda.synchronize()
-    trace = synth.serving_trace(n_requests, rate, [p[0].shape[1] for p in pts])
-    sig = synth.SIGMA_GRID
-    samples = sum(q["count"] * q["spp"] * (1 + len(sig)) for q in trace)
+    return rooms, scenes, pts
 
-    # continuous batching
+
+def trace_samples(trace):
+    return sum(q["count"] * q["spp"] * (1 + len(synth.SIGMA_GRID)) for q in trace)
+
+
+def serve_batched(scenes, pts, trace, log_every=20, tag="serving"):
+    """Replay ``trace`` through the continuous-batching server; latency =
+    completion - submission (at the request's arrival time)."""
+    sig = synth.SIGMA_GRID
     srv = fipt.Server(device=0, pool_bytes=8 << 30, max_inflight=64, samples_per_launch=1 << 26)
     t0 = time.perf_counter()
     tickets = [None] * len(trace)
@@ -175,9 +180,8 @@ def run_serving(dev, n_requests, rate, log_every=20):
             if d > 0:
                 time.sleep(d)
             planes, tri = pts[q["room"]]
-            tickets[i] = (srv.submit(scenes[q["room"]], planes, tri, q["spp"], q["spp"], sig,
-                                     q["seed"], offset=q["offset"], count=q["count"]),
-                          time.perf_counter())
+            tickets[i] = srv.submit(scenes[q["room"]], planes, tri, q["spp"], q["spp"], sig,
+                                    q["seed"], offset=q["offset"], count=q["count"])
 
     th = threading.Thread(target=feeder)
     th.start()
@@ -185,21 +189,28 @@ def run_serving(dev, n_requests, rate, log_every=20):
     for i in range(len(trace)):
         while tickets[i] is None:
             time.sleep(1e-4)
-        t, _ = tickets[i]
+        t = tickets[i]
         srv.wait(t)
         res = srv.result(t, copy=False)
         lat.append((res.t_done_us - res.t_submit_us) / 1e3)
         srv.release(t)
         if (i + 1) % log_every == 0:
-            log(f"serving: {i + 1}/{len(trace)} requests done")
+            log(f"{tag}: {i + 1}/{len(trace)} requests done")
     th.join()
-    t_batched = time.perf_counter() - t0
+    makespan = time.perf_counter() - t0
     st = srv.stats()
     srv.destroy()
+    return dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                makespan_s=makespan, gsamples_per_s=trace_samples(trace) / makespan / 1e9,
+                launches=int(st.launches), tiles=int(st.tiles))
 
-    # one at a time, FIFO, same arrivals
-    out = torch.empty((SHADING_PLANES, 2_000_000), dtype=torch.float32, device=dev)
-    lat1 = []
+
+def serve_single(scenes, pts, trace, log_every=20, tag="one-at-a-time"):
+    """The same trace served one request at a time, FIFO, with fipt_bake."""
+    sig = synth.SIGMA_GRID
+    out = torch.empty((SHADING_PLANES, max(q["count"] for q in trace)), dtype=torch.float32,
+                      device=pts[0][0].device)
+    lat = []
     t0 = time.perf_counter()
     for i, q in enumerate(trace):
         d = t0 + q["arrival"] - time.perf_counter()
@@ -210,21 +221,55 @@ def run_serving(dev, n_requests, rate, log_every=20):
         fipt.fipt_bake(scenes[q["room"]], planes[:, o:o + c].contiguous(), tri[o:o + c].contiguous(),
                        q["spp"], q["spp"], sig, q["seed"], out=out)
         torch.cuda.synchronize()
-        lat1.append((time.perf_counter() - (t0 + q["arrival"])) * 1e3)
+        lat.append((time.perf_counter() - (t0 + q["arrival"])) * 1e3)
         if (i + 1) % log_every == 0:
-            log(f"one-at-a-time: {i + 1}/{len(trace)} requests done")
-    t_single = time.perf_counter() - t0
+            log(f"{tag}: {i + 1}/{len(trace)} requests done")
+    makespan = time.perf_counter() - t0
+    return dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                makespan_s=makespan, gsamples_per_s=trace_samples(trace) / makespan / 1e9)
+
+
+def run_serving(dev, n_requests, rate, log_every=20):
+    """Replay a Poisson trace of bake requests over eight resident rooms,
+    through the server and one request at a time."""
+    rooms, scenes, pts = serving_setup(dev)
+    trace = synth.serving_trace(n_requests, rate, [p[0].shape[1] for p in pts])
+    batched = serve_batched(scenes, pts, trace, log_every)
+    single = serve_single(scenes, pts, trace, log_every)
     for s in scenes:
         s.destroy()
-    return dict(
-        requests=len(trace), rate_per_s=rate, rooms=[r.n_tris for r in rooms],
-        lobe_samples=samples,
-        batched=dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                     makespan_s=t_batched, gsamples_per_s=samples / t_batched / 1e9,
-                     launches=int(st.launches), tiles=int(st.tiles)),
-        one_at_a_time=dict(p50_ms=float(np.percentile(lat1, 50)),
-                           p99_ms=float(np.percentile(lat1, 99)), makespan_s=t_single,
-                           gsamples_per_s=samples / t_single / 1e9))
+    return dict(requests=len(trace), rate_per_s=rate, rooms=[r.n_tris for r in rooms],
+                lobe_samples=trace_samples(trace), batched=batched, one_at_a_time=single)
+
+
+def serving_study(dev, n_trace, rate, n_sweep):
+    """Capacity (all requests arriving at once), the Poisson trace at
+    ``rate``, and a rate sweep at 0.5, 0.7 and 0.9 of capacity; each served
+    batched and one at a time."""
+    rooms, scenes, pts = serving_setup(dev)
+    sizes = [p[0].shape[1] for p in pts]
+    burst = synth.serving_trace(n_sweep, 1e9, sizes, seed=1105)
+    cap = serve_batched(scenes, pts, burst, 50, "capacity")
+    cap_rps = n_sweep / cap["makespan_s"]
+    log(f"capacity: {cap_rps:.1f} requests/s, {cap['gsamples_per_s']:.2f} Gsamples/s")
+    trace = synth.serving_trace(n_trace, rate, sizes)
+    main_b = serve_batched(scenes, pts, trace, 100, f"rate {rate:g}")
+    main_s = serve_single(scenes, pts, trace, 100, f"rate {rate:g} one-at-a-time")
+    sweep = []
+    for f in (0.5, 0.7, 0.9):
+        r = f * cap_rps
+        tr = synth.serving_trace(n_sweep, r, sizes, seed=1106)
+        b = serve_batched(scenes, pts, tr, 100, f"{f:g} x capacity")
+        s1 = serve_single(scenes, pts, tr, 100, f"{f:g} x capacity one-at-a-time")
+        sweep.append(dict(load=f, rate_per_s=r, requests=n_sweep, lobe_samples=trace_samples(tr),
+                          batched=b, one_at_a_time=s1))
+    for s in scenes:
+        s.destroy()
+    return dict(rooms=[r.n_tris for r in rooms],
+                capacity=dict(requests=n_sweep, requests_per_s=cap_rps, **cap),
+                trace=dict(requests=n_trace, rate_per_s=rate, lobe_samples=trace_samples(trace),
+                           batched=main_b, one_at_a_time=main_s),
+                sweep=sweep)
 
 
 def copy_bandwidth(dev, n=1 << 28, reps=5):
@@ -339,6 +384,11 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--no-counters", action="store_true")
+    ap.add_argument("--serving-study", action="store_true",
+                    help="only run the serving study (capacity, the --serving-trace-requests "
+                         "trace at --serving-rate, a load sweep) and print its JSON")
+    ap.add_argument("--serving-trace-requests", type=int, default=2000)
+    ap.add_argument("--serving-sweep-requests", type=int, default=300)
     ap.add_argument("--large-rebakes", type=int, default=10,
                     help="re-bakes of the ~2M-triangle emitter loop (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -357,6 +407,10 @@ def main():
         gbs, ms = copy_bandwidth(dev, n)
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
                           "copy_ms": ms, "copy_gbs": gbs}), flush=True)
+        return
+    if args.serving_study:
+        print(json.dumps(serving_study(dev, args.serving_trace_requests, args.serving_rate,
+                                       args.serving_sweep_requests)), flush=True)
         return
     copy_gbs, _ = copy_bandwidth(dev)
     log(f"achievable HBM bandwidth (1 GiB copy): {copy_gbs:.0f} GB/s")

@@ -283,8 +283,10 @@ int fipt_grid_scatter(fipt_grid_plan plan, const float* grad_points, int32_t cha
  * scheduler thread.  Requests are admitted first come first served while
  * their output (3 + 6K planes x points x 4 bytes) fits in the pool and
  * fewer than max_inflight are admitted; admitted requests are split into
- * tiles and interleaved round-robin into persistent bake launches, so
- * requests that arrive while others run join the next launch.  Each
+ * tiles (contiguous runs of points) placed into persistent bake launches of
+ * up to samples_per_launch lobe samples: first every request whose
+ * remaining work fits in one launch, whole, then the others in admission
+ * order.  Requests that arrive while others run join the next launch.  Each
  * point's result is bitwise identical to fipt_bake with the same inputs. */
 int fipt_server_create(int32_t device, int64_t pool_bytes, int32_t max_inflight,
                        int64_t samples_per_launch, fipt_server* out);

@@ -3,14 +3,15 @@
 // A scheduler thread admits queued requests first come first served while
 // their output fits in the server's device pool and the in-flight limit
 // allows, then fills each launch of the persistent tile-bake kernel with
-// one tile from every admitted request that still has unassigned points,
-// the samples of a launch shared evenly between them (processor sharing:
-// a small request finishes within a launch or two even while large ones
-// are running).  Two launches are kept in flight, each on its own stream,
-// so the GPU never waits for the host and one launch's last wavefronts
-// overlap the next launch's first; a request that arrives meanwhile joins the
-// next launch that is built.  Completion is detected from each launch's
-// event; a request is done when all its points' tiles have completed.
+// tiles (contiguous runs of one request's points): first every request
+// whose remaining work fits in one launch, whole, then the other requests
+// in admission order.  Small requests thus finish within a launch or two
+// even while large ones run, and large ones keep first-come-first-served
+// order.  Two launches are kept in flight, each on its own stream, so the
+// GPU never waits for the host and one launch's last wavefronts overlap
+// the next launch's first; a request that arrives meanwhile joins the next
+// launch that is built.  Completion is detected from each launch's event;
+// a request is done when all its points' tiles have completed.
 //
 // A tile's points carry their index within the request into the random
 // number counter, so every point's result is bitwise identical to
@@ -153,7 +154,13 @@ struct fipt_server_s {
         }
     }
 
-    // caller holds mu; fills slot s, returns number of tiles
+    // caller holds mu; fills slot s, returns number of tiles.
+    // A launch carries up to samples_per_launch lobe samples.  Requests whose
+    // unassigned work fits in one launch ("small") go first, in admission
+    // order, each taken whole; the rest of the budget goes to the other
+    // requests in admission order.  Small requests (and the last launch of a
+    // large one) so finish within the next launch, while large requests
+    // keep first-come-first-served order and are not slowed by sharing.
     int build(Slot& s) {
         s.recs.clear();
         std::vector<Request*> work;
@@ -162,11 +169,28 @@ struct fipt_server_s {
             if (r.next_point < r.n) work.push_back(&r);
         }
         if (work.empty()) return 0;
-        const int64_t share = std::max<int64_t>(1, samples_per_launch / (int64_t)work.size());
+        int64_t budget = samples_per_launch;
+        std::vector<int64_t> take(work.size(), 0);
+        auto left = [&](size_t i) { return work[i]->n - work[i]->next_point - take[i]; };
+        for (size_t i = 0; i < work.size(); ++i) {
+            const int64_t need = left(i) * work[i]->samples_per_point();
+            if (need <= samples_per_launch && need <= budget) {
+                take[i] = left(i);
+                budget -= need;
+            }
+        }
+        for (size_t i = 0; i < work.size() && budget > 0; ++i) {
+            const int64_t spp = work[i]->samples_per_point();
+            const int64_t pts = std::min(left(i), budget / spp);
+            take[i] += pts;
+            budget -= pts * spp;
+        }
+        if (std::all_of(take.begin(), take.end(), [](int64_t x) { return x == 0; }))
+            take[0] = 1;   // one point can exceed a tiny launch budget: make progress
         int nt = 0;
-        for (Request* r : work) {
-            int64_t pts = std::max<int64_t>(64, share / std::max<int64_t>(1, r->samples_per_point()));
-            pts = std::min(pts, r->n - r->next_point);
+        for (size_t i = 0; i < work.size(); ++i) {
+            if (take[i] == 0) continue;
+            Request* r = work[i];
             fipt_shading out;
             out.planes = reinterpret_cast<float*>(pool + r->pool_off);
             out.stride = r->n;
@@ -175,12 +199,12 @@ struct fipt_server_s {
             b.pts += p0;
             b.ptri += p0;
             b.out += p0;
-            b.n = pts;
+            b.n = take[i];
             b.p_offset = p0;
             s.host[nt].job = b;
             s.host[nt].first = 0;
-            s.recs.push_back({r->ticket, pts});
-            r->next_point += pts;
+            s.recs.push_back({r->ticket, take[i]});
+            r->next_point += take[i];
             ++nt;
         }
         int64_t acc = 0;

@@ -79,6 +79,27 @@ def test_alone_equals_mix(scenes):
         srv.destroy()
 
 
+def test_small_requests_first_large_in_order(scenes):
+    """Launch filling: a request whose remaining work fits in one launch goes
+    first; larger ones keep submission order.  Two large requests (several
+    launches each) then a small one: the small one completes first, and the
+    large ones complete in the order they were submitted."""
+    _, s, planes, tri = scenes[1]
+    srv = fipt.Server(device=0, pool_bytes=256 << 20, max_inflight=8, samples_per_launch=1 << 22)
+    try:
+        big1 = srv.submit(s, planes, tri, 64, 64, synth.SIGMA_GRID, 11, offset=0, count=38400)
+        big2 = srv.submit(s, planes, tri, 64, 64, synth.SIGMA_GRID, 12, offset=0, count=38400)
+        small = srv.submit(s, planes, tri, 16, 16, synth.SIGMA_GRID, 13, offset=100, count=96)
+        for t in (big1, big2, small):
+            assert srv.wait(t, timeout_s=120.0)
+        done = {t: srv.result(t, copy=False).t_done_us for t in (big1, big2, small)}
+        assert done[small] < done[big1] < done[big2], done
+        for t in (big1, big2, small):
+            srv.release(t)
+    finally:
+        srv.destroy()
+
+
 def test_memory_admission_and_cancel(scenes):
     sc, s, planes, tri = scenes[1]
     n = planes.shape[1]
