@@ -27,8 +27,10 @@ namespace {
 using dev::V3;
 using dev::v3;
 
-constexpr int kBlock = 256;             // 4 wavefronts
+constexpr int kBlock = 64;              // one wavefront: a finished wave frees its LDS at once
 constexpr int kWaves = kBlock / 64;
+// persistent grids: two rounds of the 16 wavefronts a CU holds at once
+constexpr int kGridWavesPerCu = 32;
 
 // Lobe of flattened sample q: 0 for the first spp_d (diffuse) samples, then
 // 1 + (q - spp_d) / spp_s.  The quotient is below 17 and r < 2^20 (spp <=
@@ -444,8 +446,13 @@ __device__ __forceinline__ int64_t next_point(int32_t* counters, int home, int& 
     return -1;
 }
 
+// Five wavefronts per SIMD (at most 96 VGPRs; the LDS stacks of 20 one-wave
+// workgroups fit a CU's 160 KB) measured ~3 % faster than four.
+#define FIPT_BAKE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(5, 8)))
+
 template <bool COUNT, bool REFILL>
-__global__ __launch_bounds__(kBlock) void k_bake(BakeLaunch b, int32_t* counters, uint64_t* stats) {
+__global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake(BakeLaunch b, int32_t* counters,
+                                                                     uint64_t* stats) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
@@ -499,8 +506,9 @@ __device__ __forceinline__ BakeLaunch uniform_job(const BakeLaunch& j) {
 
 // Serving: persistent bake over a list of tiles; the points of the launch
 // (all tiles' points enumerated in order) are handed out as in k_bake.
-__global__ __launch_bounds__(kBlock) void k_bake_tiles(const TileDesc* tiles, int32_t n_tiles,
-                                                       int32_t* counters) {
+__global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake_tiles(const TileDesc* tiles,
+                                                                           int32_t n_tiles,
+                                                                           int32_t* counters) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
@@ -659,7 +667,7 @@ int launch_bake(const BakeLaunch& b, int32_t* counters, uint64_t* stats, void* s
     // persistent grid: up to two rounds of resident workgroups, a multiple
     // of kXcdCount so every XCD gets the same number of workgroups
     const int64_t want = (b.n + kWaves - 1) / kWaves;
-    int64_t blocks = std::min(want, (int64_t)device_cus() * 8);
+    int64_t blocks = std::min(want, (int64_t)device_cus() * kGridWavesPerCu / kWaves);
     blocks = std::max<int64_t>(kXcdCount, (blocks + kXcdCount - 1) / kXcdCount * kXcdCount);
     const dim3 grid((unsigned)blocks), block(kBlock);
     hipStream_t st = (hipStream_t)stream;
@@ -677,7 +685,7 @@ int launch_bake(const BakeLaunch& b, int32_t* counters, uint64_t* stats, void* s
     return check_launch("bake");
 }
 
-int bake_tiles_grid_hint() { return device_cus() * 8; }
+int bake_tiles_grid_hint() { return device_cus() * kGridWavesPerCu / kWaves; }
 
 int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* counters_dev,
                       int32_t grid, void* stream) {
