@@ -12,9 +12,11 @@
 // further levels.  The traversal's fixed LDS stack (kStackSize entries per
 // lane) therefore can never overflow.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <vector>
 
 #include "fipt_internal.hpp"
 
@@ -432,6 +434,208 @@ class Collapser {
     }
 };
 
+
+// Surface-area-guided collapse of the binary tree into 4-wide nodes, by
+// dynamic programming over the binary tree (the scheme of Ylitie et al.,
+// HPG 2017, for 8-wide trees, here with 4 slots).  For a binary node x let
+// C(x) be the least expected cost of x as a 4-wide node of its own and
+// D(x, j) the least expected cost of covering x's subtree with at most j
+// children of the 4-wide node above it:
+//   C(x)    = A(x) c_node + min over k of D(l, k) + D(r, 4 - k)
+//   D(x, 1) = C(x)
+//   D(x, j) = min(D(x, j - 1), min over k of D(l, k) + D(r, j - k))
+// where l, r are x's children, a leaf costs A(leaf) c_tri n_tris in any
+// number of slots, and A is a box's surface area (proportional to the
+// chance that a ray enters it).  c_node is the cost of one 4-wide node step
+// and c_tri that of one triangle test, in the same unit.
+//
+// The unconstrained optimum can push more entries on a path than the
+// traversal stack holds, so the tree is built top-down under a push budget:
+// at each 4-wide node, among the ways of covering its two children with 2,
+// 3 or 4 slots (each slot's subtree taken as the table prescribes), the
+// cheapest is chosen whose slots can still be built within the remaining
+// budget at one push per binary level (their binary depth).  Covering the
+// two children themselves always qualifies, so the build never fails, and
+// no path pushes more than kStackSize entries.
+class OptimalCollapser {
+  public:
+    static constexpr double kNodeCost = 1.0;
+    static constexpr double kTriCost = 0.4;
+
+    explicit OptimalCollapser(HostBvh* b) : b_(b) {}
+
+    void run() {
+        const int64_t n = (int64_t)b_->nodes.size();
+        C_.assign(n, 0.0);
+        D_.assign(n, {0.0, 0.0, 0.0, 0.0, 0.0});
+        how_.assign(n, {0, 0, 0, 0, 0});
+        need_.assign(n, 0);
+        // children follow their parent in depth-first order
+        for (int64_t i = n - 1; i >= 0; --i) solve((int32_t)i);
+        b_->nodes4.clear();
+        b_->nodes4.reserve(n / 2 + 1);
+        max_push_ = 0;
+        build(0, kStackSize, 0);
+        b_->max_push4 = max_push_;
+    }
+
+  private:
+    struct Slot {
+        int32_t ref;
+        float lo[3], hi[3];
+    };
+    HostBvh* b_;
+    std::vector<double> C_;
+    std::vector<std::array<double, 5>> D_;   // index j = 1..4
+    std::vector<std::array<int, 5>> how_;    // D: 0 itself, -1 fewer slots, k split
+    std::vector<int> need_;                  // binary depth: pushes with 2-wide nodes only
+    int max_push_ = 0;
+
+    static double area(const float* lo, const float* hi) {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = std::max(0.0, (double)hi[k] - (double)lo[k]);
+        return 2.0 * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
+    }
+    Slot slot(int32_t node, int which) const {
+        const BvhNode& nd = b_->nodes[node];
+        if (which == 0) return {nd.child0, {nd.c0lx, nd.c0ly, nd.c0lz}, {nd.c0hx, nd.c0hy, nd.c0hz}};
+        return {nd.child1, {nd.c1lx, nd.c1ly, nd.c1lz}, {nd.c1hx, nd.c1hy, nd.c1hz}};
+    }
+    double cost(const Slot& s, int j) const {
+        if (s.ref >= 0) return D_[s.ref][j];
+        const int count = ((~s.ref) & 7) + 1;
+        return area(s.lo, s.hi) * kTriCost * count;
+    }
+    int need(const Slot& s) const { return s.ref >= 0 ? need_[s.ref] : 0; }
+    void solve(int32_t x) {
+        const Slot l = slot(x, 0), r = slot(x, 1);
+        need_[x] = 1 + std::max(need(l), need(r));
+        float lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(l.lo[k], r.lo[k]);
+            hi[k] = std::max(l.hi[k], r.hi[k]);
+        }
+        double best = INFINITY;
+        for (int k = 1; k <= 3; ++k) best = std::min(best, cost(l, k) + cost(r, 4 - k));
+        C_[x] = area(lo, hi) * kNodeCost + best;
+        D_[x][1] = C_[x];
+        how_[x][1] = 0;
+        for (int j = 2; j <= 4; ++j) {
+            double d = D_[x][j - 1];
+            int h = -1;
+            for (int k = 1; k < j; ++k) {
+                const double c = cost(l, k) + cost(r, j - k);
+                if (c < d) {
+                    d = c;
+                    h = k;
+                }
+            }
+            D_[x][j] = d;
+            how_[x][j] = h;
+        }
+    }
+    // the binary subtrees (or leaves) that cover slot s with at most j slots
+    void cover(const Slot& s, int j, std::vector<Slot>& out) const {
+        if (s.ref < 0) {
+            out.push_back(s);
+            return;
+        }
+        while (j > 1 && how_[s.ref][j] == -1) --j;
+        if (j == 1 || how_[s.ref][j] == 0) {
+            out.push_back(s);
+            return;
+        }
+        const int k = how_[s.ref][j];
+        cover(slot(s.ref, 0), k, out);
+        cover(slot(s.ref, 1), j - k, out);
+    }
+    // 4-wide node for binary node x, at most `budget` pushes on any path
+    // from it down (need_[x] <= budget holds on entry)
+    int32_t build(int32_t x, int budget, int pushed) {
+        const Slot l = slot(x, 0), r = slot(x, 1);
+        std::vector<Slot> c, trial;
+        double best = INFINITY;
+        for (int total = 2; total <= 4; ++total) {
+            for (int k = 1; k < total; ++k) {
+                trial.clear();
+                cover(l, k, trial);
+                cover(r, total - k, trial);
+                const int left = budget - ((int)trial.size() - 1);
+                bool fits = true;
+                for (const Slot& t : trial) fits = fits && need(t) <= left;
+                const double cst = cost(l, k) + cost(r, total - k);
+                if (fits && cst < best) {
+                    best = cst;
+                    c = trial;
+                }
+            }
+        }
+        if (c.empty()) c = {l, r};   // unreachable: two children always fit
+        const int32_t idx = (int32_t)b_->nodes4.size();
+        b_->nodes4.push_back(Bvh4Node{});
+        const int pushes = (int)c.size() - 1;
+        int32_t refs[4];
+        for (int i = 0; i < (int)c.size(); ++i) {
+            if (c[i].ref >= 0) {
+                refs[i] = build(c[i].ref, budget - pushes, pushed + pushes);
+            } else {
+                refs[i] = c[i].ref;
+                max_push_ = std::max(max_push_, pushed + pushes);
+            }
+        }
+        Bvh4Node& nd = b_->nodes4[idx];
+        for (int i = 0; i < 4; ++i) {
+            if (i < (int)c.size()) {
+                nd.lox[i] = c[i].lo[0];
+                nd.loy[i] = c[i].lo[1];
+                nd.loz[i] = c[i].lo[2];
+                nd.hix[i] = c[i].hi[0];
+                nd.hiy[i] = c[i].hi[1];
+                nd.hiz[i] = c[i].hi[2];
+                nd.child[i] = refs[i];
+            } else {
+                nd.lox[i] = nd.loy[i] = nd.loz[i] = INFINITY;
+                nd.hix[i] = nd.hiy[i] = nd.hiz[i] = -INFINITY;
+                nd.child[i] = kEmptyChild;
+            }
+            nd.pad[i] = 0;
+        }
+        return idx;
+    }
+};
+// Expected traversal cost of a 4-wide tree in the units of OptimalCollapser:
+// every node is entered with probability (its box area / the root's), costing
+// one node step; every leaf, likewise, costs kTriCost per triangle.
+double sah_cost4(const std::vector<Bvh4Node>& nodes) {
+    auto area = [](float lx, float ly, float lz, float hx, float hy, float hz) {
+        const double dx = std::max(0.0, (double)hx - lx), dy = std::max(0.0, (double)hy - ly),
+                     dz = std::max(0.0, (double)hz - lz);
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    };
+    const Bvh4Node& r = nodes[0];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < 4; ++i) {
+        if (r.child[i] == kEmptyChild) continue;
+        lo[0] = std::min(lo[0], r.lox[i]);
+        lo[1] = std::min(lo[1], r.loy[i]);
+        lo[2] = std::min(lo[2], r.loz[i]);
+        hi[0] = std::max(hi[0], r.hix[i]);
+        hi[1] = std::max(hi[1], r.hiy[i]);
+        hi[2] = std::max(hi[2], r.hiz[i]);
+    }
+    const double root = std::max(area(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]), 1e-30);
+    double c = OptimalCollapser::kNodeCost;
+    for (const Bvh4Node& n : nodes) {
+        for (int i = 0; i < 4; ++i) {
+            if (n.child[i] == kEmptyChild) continue;
+            const double p = area(n.lox[i], n.loy[i], n.loz[i], n.hix[i], n.hiy[i], n.hiz[i]) / root;
+            c += n.child[i] >= 0 ? p * OptimalCollapser::kNodeCost
+                                 : p * OptimalCollapser::kTriCost * (((~n.child[i]) & 7) + 1);
+        }
+    }
+    return c;
+}
+
 }  // namespace
 
 int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
@@ -449,8 +653,20 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
     bld.run();
     if (out->max_depth > kMaxInnerDepth)
         return fail(FIPT_EINVAL, "BVH depth %d exceeds the traversal stack", out->max_depth);
-    Collapser col(out);
-    col.run();
+    // two collapses under the stack budget; keep the one of lower expected
+    // cost (the surface-area-guided one wins unless the binary tree is so
+    // deep that the budget forces narrow nodes near the root)
+    OptimalCollapser opt(out);
+    opt.run();
+    std::vector<Bvh4Node> guided;
+    guided.swap(out->nodes4);
+    const int guided_push = out->max_push4;
+    Collapser greedy(out);
+    greedy.run();
+    if (sah_cost4(guided) < sah_cost4(out->nodes4)) {
+        out->nodes4.swap(guided);
+        out->max_push4 = guided_push;
+    }
     if (out->max_push4 > kStackSize)
         return fail(FIPT_EINVAL, "4-wide BVH needs %d stack entries", out->max_push4);
     // the traversal addresses nodes by 32-bit byte offsets
