@@ -47,7 +47,7 @@ SHADING_PLANES = 39
 COUNTERS = os.path.join(ROOT, "profiles", "counters_room.json")
 # the sources each measured kernel is built from
 KERNEL_SOURCES = {
-    "k_bake": ("bake.hip", "device.hpp", "fipt_internal.hpp"),
+    "k_bake": ("bake.hip", "device.hpp", "fipt_internal.hpp", "bvh_build.cpp"),
     "k_render_loss": ("loss.hip", "fipt_internal.hpp"),
 }
 
