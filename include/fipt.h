@@ -189,6 +189,22 @@ int fipt_bvh_validate(const float* verts, int64_t n_verts, const int32_t* tris, 
  * references it. */
 int fipt_scene_destroy(fipt_scene s);
 
+/* ---- ray casting (the closest-hit query of Eq. 9) ----------------------- */
+
+/* Closest hit of each of n rays, the query the bake and the point
+ * generation run, exposed for callers that trace their own rays and for
+ * checking the traversal against other implementations:
+ *   rays:     device float planes [6][stride]: origin x, y, z, direction
+ *             x, y, z (any non-zero length); hits have t > 0 along o + t d;
+ *   hit_tri:  device int32 [n]: original index of the nearest triangle
+ *             (exact ties in t go to the lower index), -1 on a miss;
+ *   hit_tuv:  device float planes [3][hit_stride] or NULL: t and the
+ *             barycentric weights u, v of the triangle's second and third
+ *             vertices (0 on a miss).
+ * 1 <= n < 2^31, stride >= n, hit_stride >= n.  Asynchronous on `stream`. */
+int fipt_cast_rays(fipt_scene s, const float* rays, int64_t n, int64_t stride, int32_t* hit_tri,
+                   float* hit_tuv, int64_t hit_stride, void* stream);
+
 /* ---- shading points ---------------------------------------------------- */
 
 /* For every pixel centre of every camera (host array of n_cams, at most 48
@@ -216,6 +232,17 @@ int fipt_gen_points(fipt_scene s, const fipt_camera* cams, int32_t n_cams,
  * are safe. */
 int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
               const fipt_shading* out, void* stream);
+
+/* The two uniforms (xi1, xi2) in [0, 1) that the bake draws for lobe `lobe`
+ * (0 diffuse, k >= 1 roughness level k - 1) and samples 0 .. n_samples - 1 of
+ * the points whose counter indices are p0 .. p0 + n_points - 1, with key
+ * `seed`: Philox4x32-10 on the counter (p low, p high, lobe, sample), each
+ * uniform the top 24 bits of one output word times 2^-24.
+ * out: device float [2][n_points][n_samples] (xi1 block, then xi2 block).
+ * For checking the random streams against other implementations;
+ * n_points * n_samples must be in [1, 2^31).  Asynchronous on `stream`. */
+int fipt_lobe_uniforms(uint64_t seed, int64_t p0, int64_t n_points, int32_t lobe,
+                       int32_t n_samples, float* out, void* stream);
 
 /* Same bake, instrumented: also accumulates traversal counters into
  * `stats_dev` (device, 6 uint64 in fipt_traversal_stats order, added to).

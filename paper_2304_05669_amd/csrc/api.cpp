@@ -308,6 +308,31 @@ int fipt_gen_points(fipt_scene s, const fipt_camera* cams, int32_t n_cams, const
     return launch_gen_points(s->view(), tab, *out, stream);
 }
 
+int fipt_cast_rays(fipt_scene s, const float* rays, int64_t n, int64_t stride, int32_t* hit_tri,
+                   float* hit_tuv, int64_t hit_stride, void* stream) {
+    clear_error();
+    if (!s) return fail(FIPT_EINVAL, "scene is NULL");
+    if (!rays || !hit_tri) return fail(FIPT_EINVAL, "rays/hit_tri is NULL");
+    if (n < 1 || n > INT32_MAX) return fail(FIPT_EINVAL, "n must be in [1, 2^31), got %lld", (long long)n);
+    if (stride < n) return fail(FIPT_EINVAL, "stride (%lld) < n (%lld)", (long long)stride, (long long)n);
+    if (hit_tuv && hit_stride < n)
+        return fail(FIPT_EINVAL, "hit_stride (%lld) < n (%lld)", (long long)hit_stride, (long long)n);
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    return launch_cast_rays(s->view(), rays, n, stride, hit_tri, hit_tuv, hit_stride, stream);
+}
+
+int fipt_lobe_uniforms(uint64_t seed, int64_t p0, int64_t n_points, int32_t lobe,
+                       int32_t n_samples, float* out, void* stream) {
+    clear_error();
+    if (!out) return fail(FIPT_EINVAL, "out is NULL");
+    if (n_points < 1 || n_samples < 1 || n_points * (int64_t)n_samples > INT32_MAX)
+        return fail(FIPT_EINVAL, "n_points x n_samples must be in [1, 2^31)");
+    if (p0 < 0) return fail(FIPT_EINVAL, "p0 must be >= 0");
+    if (lobe < 0 || lobe > FIPT_MAX_LEVELS) return fail(FIPT_EINVAL, "lobe must be in [0, %d]", FIPT_MAX_LEVELS);
+    return launch_lobe_uniforms(seed, p0, n_points, lobe, n_samples, out, stream);
+}
+
 static int bake_common(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
                        const fipt_shading* out, uint64_t* stats, void* stream) {
     clear_error();

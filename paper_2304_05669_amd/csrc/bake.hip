@@ -534,6 +534,36 @@ __global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake_tiles(const
     }
 }
 
+// One ray per thread: closest hit with the bake's traversal.
+__global__ __launch_bounds__(kBlock) void k_cast_rays(DeviceScene sc, const float* rays,
+                                                      int64_t n, int64_t stride, int32_t* hit_tri,
+                                                      float* hit_tuv, int64_t hit_stride) {
+    __shared__ int32_t s_stack[kStackSize * kBlock];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const V3 o = v3(rays[i], rays[stride + i], rays[2 * stride + i]);
+    const V3 d = v3(rays[3 * stride + i], rays[4 * stride + i], rays[5 * stride + i]);
+    uint32_t z0 = 0, z1 = 0;
+    const dev::Hit h = dev::trace<false>(sc, o, d, s_stack + threadIdx.x, kBlock, z0, z1);
+    hit_tri[i] = h.leaf >= 0 ? sc.tris[h.leaf].orig : -1;
+    if (hit_tuv) {
+        hit_tuv[i] = h.leaf >= 0 ? h.t : 0.0f;
+        hit_tuv[hit_stride + i] = h.u;
+        hit_tuv[2 * hit_stride + i] = h.v;
+    }
+}
+
+// xi1, xi2 of (point p0 + i / n_samples, lobe, sample i % n_samples).
+__global__ void k_lobe_uniforms(uint64_t seed, int64_t p0, int64_t total, int32_t lobe,
+                                int32_t n_samples, float* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    float xi1, xi2;
+    dev::lobe_uniforms(seed, p0 + i / n_samples, lobe, (int)(i % n_samples), xi1, xi2);
+    out[i] = xi1;
+    out[total + i] = xi2;
+}
+
 __global__ void k_zero_counters(int32_t* counters) {
     if (threadIdx.x < kXcdCount) counters[threadIdx.x] = 0;
 }
@@ -661,6 +691,22 @@ int launch_gen_points(const DeviceScene& sc, const CameraTable& cams, const fipt
     hipLaunchKernelGGL(k_gen_points, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream,
                        sc, cams, out);
     return check_launch("gen_points");
+}
+
+int launch_cast_rays(const DeviceScene& sc, const float* rays, int64_t n, int64_t stride,
+                     int32_t* hit_tri, float* hit_tuv, int64_t hit_stride, void* stream) {
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_cast_rays, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream,
+                       sc, rays, n, stride, hit_tri, hit_tuv, hit_stride);
+    return check_launch("cast_rays");
+}
+
+int launch_lobe_uniforms(uint64_t seed, int64_t p0, int64_t n_points, int32_t lobe,
+                         int32_t n_samples, float* out, void* stream) {
+    const int64_t total = n_points * n_samples;
+    hipLaunchKernelGGL(k_lobe_uniforms, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, seed, p0, total, lobe, n_samples, out);
+    return check_launch("lobe_uniforms");
 }
 
 int launch_bake(const BakeLaunch& b, int32_t* counters, uint64_t* stats, void* stream) {

@@ -113,6 +113,10 @@ struct CameraTable {
 };
 int launch_gen_points(const DeviceScene& sc, const CameraTable& cams, const fipt_points& out,
                       void* stream);
+int launch_cast_rays(const DeviceScene& sc, const float* rays, int64_t n, int64_t stride,
+                     int32_t* hit_tri, float* hit_tuv, int64_t hit_stride, void* stream);
+int launch_lobe_uniforms(uint64_t seed, int64_t p0, int64_t n_points, int32_t lobe,
+                         int32_t n_samples, float* out, void* stream);
 
 struct BakeLaunch {
     DeviceScene sc;

@@ -28,8 +28,8 @@ TONEMAP_NONE, TONEMAP_LOG_SRGB = 0, 1
 EXPORTS = (
     "fipt_last_error", "fipt_version", "fipt_scene_create", "fipt_scene_set_radiance",
     "fipt_scene_set_emission", "fipt_scene_info_get", "fipt_bvh_validate", "fipt_scene_destroy",
-    "fipt_gen_points",
-    "fipt_bake", "fipt_bake_traversal_stats", "fipt_render_loss", "fipt_scale_by",
+    "fipt_cast_rays", "fipt_gen_points",
+    "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_render_loss", "fipt_scale_by",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
     "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
     "fipt_server_result", "fipt_server_release", "fipt_server_cancel", "fipt_server_stats_get",
@@ -97,6 +97,8 @@ def lib():
         "fipt_scene_info_get": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
         "fipt_scene_destroy": (C.c_int, [_vp]),
         "fipt_bvh_validate": (C.c_int, [_vp, _i64, _vp, _i64, C.POINTER(_i64), C.POINTER(_i32)]),
+        "fipt_cast_rays": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _i64, _vp]),
+        "fipt_lobe_uniforms": (C.c_int, [_u64, _i64, _i64, _i32, _i32, _vp, _vp]),
         "fipt_gen_points": (C.c_int, [_vp, C.POINTER(Camera), _i32, C.POINTER(Points), _vp]),
         "fipt_bake": (C.c_int, [_vp, C.POINTER(Points), C.POINTER(BakeParams), C.POINTER(Shading), _vp]),
         "fipt_bake_traversal_stats": (C.c_int, [_vp, C.POINTER(Points), C.POINTER(BakeParams),
@@ -244,6 +246,32 @@ def make_params(spp_d: int, spp_s: int, sigma, seed: int, ray_eps: float = 1e-4)
     p.ray_eps = float(ray_eps)
     p.flags = 0
     return p
+
+
+def fipt_cast_rays(scene: Scene, rays: torch.Tensor, want_tuv: bool = True):
+    """rays: float32 GPU tensor [6, n] (origin xyz, direction xyz).  Returns
+    (tri [n] int32: original triangle index or -1, tuv [3, n] float32 or
+    None) of the closest hits."""
+    if rays.dim() != 2 or rays.shape[0] != 6:
+        raise ValueError("rays must be [6, n]")
+    n = rays.shape[1]
+    tri = torch.empty((n,), dtype=torch.int32, device=rays.device)
+    tuv = torch.empty((3, n), dtype=torch.float32, device=rays.device) if want_tuv else None
+    _check(lib().fipt_cast_rays(scene.handle, _dev(rays, torch.float32, "rays"), n, rays.stride(0),
+                                _dev(tri, torch.int32, "tri"),
+                                _dev(tuv, torch.float32, "tuv") if want_tuv else None, n,
+                                _stream()))
+    return tri, tuv
+
+
+def fipt_lobe_uniforms(seed: int, p0: int, n_points: int, lobe: int, n_samples: int,
+                       device: int = 0) -> torch.Tensor:
+    """The bake's uniforms for lobe ``lobe``, samples 0..n_samples-1 of the
+    points p0..p0+n_points-1: float32 GPU tensor [2, n_points, n_samples]."""
+    out = torch.empty((2, n_points, n_samples), dtype=torch.float32, device=torch.device("cuda", device))
+    _check(lib().fipt_lobe_uniforms(int(seed) & ((1 << 64) - 1), int(p0), int(n_points), int(lobe),
+                                    int(n_samples), _dev(out, torch.float32, "out"), _stream()))
+    return out
 
 
 def fipt_gen_points(scene: Scene, cameras, planes: torch.Tensor = None, tri: torch.Tensor = None):

@@ -48,6 +48,10 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_scale_by(None, 1, None, None, None) == fipt.EINVAL
     assert L.fipt_scene_info_get(None, None) == fipt.EINVAL
     assert L.fipt_server_poll(None, 1) == fipt.EINVAL
+    assert L.fipt_cast_rays(None, None, 1, 1, None, None, 1, None) == fipt.EINVAL
+    assert L.fipt_lobe_uniforms(1, 0, 0, 0, 4, 1, None) == fipt.EINVAL
+    assert L.fipt_lobe_uniforms(1, 0, 4, 17, 4, 1, None) == fipt.EINVAL
+    assert L.fipt_lobe_uniforms(1, 0, 1 << 16, 0, 1 << 15, 1, None) == fipt.EINVAL
 
 
 @pytest.mark.parametrize("name", ["tiny", "room", "degenerate", "skewed"])
