@@ -300,7 +300,8 @@ int fipt_grid_plan_destroy(fipt_grid_plan plan);
 
 /* grad_grid[channels][res^3] = sum over points of trilinear weight times
  * grad_points[channels][gp_stride] (device), for the plan's points.
- * Overwrites grad_grid entirely. */
+ * Overwrites grad_grid entirely.  Uses the plan's scratch buffers, so calls
+ * with the same plan must not overlap (one stream, or ordered streams). */
 int fipt_grid_scatter(fipt_grid_plan plan, const float* grad_points, int32_t channels,
                       int64_t gp_stride, float* grad_grid, void* stream);
 

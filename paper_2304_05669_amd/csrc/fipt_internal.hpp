@@ -177,6 +177,11 @@ struct GridPlanDev {
     float* pos;             // [3][n_points] positions in sorted (perm) order
     double* seg_part;       // [n_seg][8][channels] scratch (room for 8 channels)
     double* cell_part;      // [n_cell][8][channels] scratch
+    int32_t* seg_row;       // [n_seg] where a segment's partials go: row of cell_part if
+                            // its cell has one segment, else -1 - (its row of seg_part)
+    int32_t* multi_cell;    // [n_multi] occupied cells with two or more segments
+    int64_t n_multi;
+    float* gp_rec;          // [n_points][8] scratch: per-point gradient records
 };
 int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_t gp_stride,
                         float* grad_grid, void* stream);

@@ -2,12 +2,15 @@
 // (fipt_grid_plan_*) and the scatter entry point.
 //
 // The plan sorts the points by grid cell once and cuts every cell's run into
-// segments of at most 48 points.  The adjoint then runs in three passes
-// with no atomics: every segment sums weight * gradient of its points into
-// the eight corners of its cell (points in index order), every occupied
-// cell sums its segments (in order), and every node next to an occupied
-// cell sums the corner partials of at most eight cells (in order).  The
-// result is bitwise reproducible.
+// segments of at most 48 points.  The adjoint then runs with no atomics:
+// the per-point gradient planes are first copied into 32-byte records (so
+// the cell-ordered pass reads one line per point, not one per channel);
+// every segment sums weight * gradient of its points into the eight corners
+// of its cell (points in index order), straight into the cell's partials
+// when the cell has a single segment; every cell with several segments sums
+// them (in order); and every node next to an occupied cell sums the corner
+// partials of at most eight cells (in order).  The result is bitwise
+// reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,8 +33,10 @@ namespace {
 
 void plan_free(fipt_grid_plan p) {
     if (!p) return;
-    void* ptrs[] = {p->d.perm, p->d.seg_start, p->d.seg_cell, p->d.cell_seg, p->d.node_id,
-                    p->d.node_start, p->d.node_src, p->d.pos, p->d.seg_part, p->d.cell_part};
+    void* ptrs[] = {p->d.perm,      p->d.seg_start, p->d.seg_cell, p->d.cell_seg,
+                    p->d.node_id,   p->d.node_start, p->d.node_src, p->d.pos,
+                    p->d.seg_part,  p->d.cell_part, p->d.seg_row,  p->d.multi_cell,
+                    p->d.gp_rec};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -106,6 +111,17 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     cell_seg.push_back((int32_t)seg_cell.size());
     const int64_t S = (int64_t)seg_cell.size();
     const int64_t M = (int64_t)cell_id.size();
+    // a cell with one segment takes its partials straight from pass 1
+    std::vector<int32_t> seg_row(S), multi_cell;
+    for (int64_t m = 0; m < M; ++m) {
+        const int32_t g0 = cell_seg[m], g1 = cell_seg[m + 1];
+        if (g1 - g0 == 1) {
+            seg_row[g0] = (int32_t)m;
+        } else {
+            multi_cell.push_back((int32_t)m);
+            for (int32_t g = g0; g < g1; ++g) seg_row[g] = -1 - g;
+        }
+    }
     std::vector<std::pair<int64_t, int32_t>> nk;
     nk.reserve(8 * M);
     for (int64_t m = 0; m < M; ++m) {
@@ -146,13 +162,16 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     }
     d.n_seg = S;
     d.n_cell = M;
+    d.n_multi = (int64_t)multi_cell.size();
     d.n_act = (int64_t)node_id.size();
     int rc;
     if ((rc = upload(&d.perm, perm, &p->bytes)) || (rc = upload(&d.seg_start, seg_start, &p->bytes)) ||
         (rc = upload(&d.seg_cell, seg_cell, &p->bytes)) || (rc = upload(&d.cell_seg, cell_seg, &p->bytes)) ||
         (rc = upload(&d.node_id, node_id, &p->bytes)) ||
         (rc = upload(&d.node_start, node_start, &p->bytes)) ||
-        (rc = upload(&d.node_src, node_src, &p->bytes)) || (rc = upload(&d.pos, pcopy, &p->bytes))) {
+        (rc = upload(&d.node_src, node_src, &p->bytes)) || (rc = upload(&d.pos, pcopy, &p->bytes)) ||
+        (rc = upload(&d.seg_row, seg_row, &p->bytes)) ||
+        (rc = upload(&d.multi_cell, multi_cell, &p->bytes))) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return rc;
@@ -160,12 +179,13 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&d.seg_part), sizeof(double) * 64 * std::max<int64_t>(S, 1));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void**>(&d.cell_part), sizeof(double) * 64 * std::max<int64_t>(M, 1));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.gp_rec), sizeof(float) * 8 * n);
     if (e != hipSuccess) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return fail(FIPT_ENOMEM, "hipMalloc partials: %s", hipGetErrorString(e));
     }
-    p->bytes += (int64_t)(sizeof(double) * 64 * (S + M));
+    p->bytes += (int64_t)(sizeof(double) * 64 * (S + M) + sizeof(float) * 8 * n);
     if (prev >= 0) (void)hipSetDevice(prev);
     *out = p;
     return FIPT_OK;

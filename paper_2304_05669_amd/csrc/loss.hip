@@ -182,9 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_gather(const float* __restrict_
 // Adjoint, pass 1: per segment, the eight corner sums of weight * gradient
 // over the segment's points (taken in index order), double.
 template <int C>
-__global__ __launch_bounds__(kBlock) void k_scatter_segments(GridPlanDev plan, GridFrame g,
-                                                          const float* __restrict__ gp,
-                                                          int64_t gs) {
+__global__ __launch_bounds__(kBlock) void k_scatter_segments(GridPlanDev plan, GridFrame g) {
     // eight consecutive threads share one segment, one per corner, so the
     // segment's point loads are broadcast within each group of eight
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -201,28 +199,76 @@ __global__ __launch_bounds__(kBlock) void k_scatter_segments(GridPlanDev plan, G
     const int cr = g.res - 1;
     const int ci = cid % cr, cj = (cid / cr) % cr, ck = cid / (cr * cr);
     const bool hx = corner & 1, hy = (corner >> 1) & 1, hz = corner >> 2;
-    // positions are stored in sorted order; gradients come in point order
-    for (int32_t q = plan.seg_start[m]; q < plan.seg_start[m + 1]; ++q) {
-        const int32_t p = plan.perm[q];
-        const double fx = grid_u(g, pos[q], 0) - ci;
-        const double fy = grid_u(g, pos[n + q], 1) - cj;
-        const double fz = grid_u(g, pos[2 * n + q], 2) - ck;
-        const double w = (hx ? fx : 1 - fx) * (hy ? fy : 1 - fy) * (hz ? fz : 1 - fz);
+    // Positions are stored in sorted order; gradients come in point order.
+    // Eight points at a time: their loads are issued together (the gradient
+    // loads depend on the permutation), then added in point order.
+    const int32_t q1 = plan.seg_start[m + 1];
+    const float4* rec = reinterpret_cast<const float4*>(plan.gp_rec);
+    for (int32_t q = plan.seg_start[m]; q < q1; q += 8) {
+        int32_t pp[8];
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) acc[ch] += w * (double)gp[ch * gs + p];
+        for (int u = 0; u < 8; ++u) pp[u] = plan.perm[min(q + u, q1 - 1)];
+        double w[8];
+        float gv[8][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t qq = min(q + u, q1 - 1);
+            const double fx = grid_u(g, pos[qq], 0) - ci;
+            const double fy = grid_u(g, pos[n + qq], 1) - cj;
+            const double fz = grid_u(g, pos[2 * n + qq], 2) - ck;
+            w[u] = (hx ? fx : 1 - fx) * (hy ? fy : 1 - fy) * (hz ? fz : 1 - fz);
+            const float4 r0 = rec[2 * (int64_t)pp[u]];
+            gv[u][0] = r0.x;
+            gv[u][1] = r0.y;
+            gv[u][2] = r0.z;
+            gv[u][3] = r0.w;
+            if (C > 4) {
+                const float4 r1 = rec[2 * (int64_t)pp[u] + 1];
+                gv[u][4] = r1.x;
+                gv[u][5] = r1.y;
+                gv[u][6] = r1.z;
+                gv[u][7] = r1.w;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (q + u < q1) {
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) acc[ch] += w[u] * (double)gv[u][ch];
+            }
+        }
     }
-    double* dst = plan.seg_part + (m * 8 + corner) * C;
+    const int32_t row = plan.seg_row[m];
+    double* dst = row >= 0 ? plan.cell_part + ((int64_t)row * 8 + corner) * C
+                           : plan.seg_part + ((int64_t)(-1 - row) * 8 + corner) * C;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) dst[ch] = acc[ch];
 }
 
-// Adjoint, pass 2: per occupied cell and corner, the sum of its segments'
-// partials in order.
+// Adjoint, pass 0: per-point gradient planes into 32-byte records (channel
+// ch of point p at rec[8 p + ch]; unused channels zero), both sides
+// coalesced.
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_scatter_records(const float* __restrict__ gp, int64_t gs,
+                                                          int64_t n, float* __restrict__ rec) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    float v[8];
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) v[ch] = ch < C ? gp[ch * gs + p] : 0.0f;
+    float4* r = reinterpret_cast<float4*>(rec) + 2 * p;
+    r[0] = make_float4(v[0], v[1], v[2], v[3]);
+    r[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+// Adjoint, pass 2: per occupied cell with several segments and corner, the
+// sum of its segments' partials in order.
 __global__ __launch_bounds__(kBlock) void k_scatter_combine(GridPlanDev plan, int C) {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t m = tid >> 3;
+    const int64_t i = tid >> 3;
     const int corner = (int)(tid & 7);
-    if (m >= plan.n_cell) return;
+    if (i >= plan.n_multi) return;
+    const int64_t m = plan.multi_cell[i];
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int32_t g = plan.cell_seg[m]; g < plan.cell_seg[m + 1]; ++g) {
         const double* pp = plan.seg_part + ((int64_t)g * 8 + corner) * C;
@@ -348,9 +394,15 @@ int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_
     int rc = check("grid_scatter fill");
     if (rc) return rc;
     if (p.n_seg == 0) return FIPT_OK;
+    const unsigned rb = (unsigned)((p.n_points + kBlock - 1) / kBlock);
     const unsigned cb = (unsigned)((8 * p.n_seg + kBlock - 1) / kBlock);
     switch (C) {
-#define FIPT_SC(N) case N: hipLaunchKernelGGL(k_scatter_segments<N>, dim3(cb), dim3(kBlock), 0, st, p, g, gp, gs); break
+#define FIPT_SC(N)                                                                                \
+    case N:                                                                                       \
+        hipLaunchKernelGGL(k_scatter_records<N>, dim3(rb), dim3(kBlock), 0, st, gp, gs, p.n_points, \
+                           p.gp_rec);                                                             \
+        hipLaunchKernelGGL(k_scatter_segments<N>, dim3(cb), dim3(kBlock), 0, st, p, g);            \
+        break
         FIPT_SC(1); FIPT_SC(2); FIPT_SC(3); FIPT_SC(4);
         FIPT_SC(5); FIPT_SC(6); FIPT_SC(7); FIPT_SC(8);
 #undef FIPT_SC
@@ -358,10 +410,12 @@ int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_
     }
     rc = check("grid_scatter segments");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_scatter_combine, dim3((unsigned)((8 * p.n_cell + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, st, p, C);
-    rc = check("grid_scatter cells");
-    if (rc) return rc;
+    if (p.n_multi > 0) {
+        hipLaunchKernelGGL(k_scatter_combine, dim3((unsigned)((8 * p.n_multi + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, p, C);
+        rc = check("grid_scatter cells");
+        if (rc) return rc;
+    }
     if (p.n_act == 0) return FIPT_OK;
     hipLaunchKernelGGL(k_scatter_nodes, dim3((unsigned)((p.n_act + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, p, C, (const double*)p.cell_part, grad_grid);
