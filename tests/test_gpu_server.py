@@ -54,6 +54,7 @@ def test_alone_equals_mix(scenes):
         (1, 5000, 7777, 128, 32, (0.05, 0.3, 0.6, 1.0), 4),
         (1, 0, 38400, 24, 24, synth.SIGMA_GRID, 5),
         (0, 4000, 96, 200, 3, (0.02,), 6),
+        (1, 9000, 3000, 20, 9, tuple(np.linspace(0.05, 1.0, 12)), 7),   # K > 10: chunked path
     ]
     srv = fipt.Server(device=0, pool_bytes=256 << 20, max_inflight=8, samples_per_launch=1 << 22)
     try:
