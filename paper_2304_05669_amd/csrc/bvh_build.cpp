@@ -341,8 +341,8 @@ class Collapser {
     }
 
     void run() {
-        b_->nodes4.clear();
-        b_->nodes4.reserve(b_->nodes.size() / 2 + 1);
+        b_->wide4.clear();
+        b_->wide4.reserve(b_->nodes.size() / 2 + 1);
         max_push_ = 0;
         collapse(0, kStackSize, 0);
         b_->max_push4 = max_push_;
@@ -407,28 +407,27 @@ class Collapser {
             }
             if (!expanded) break;
         }
-        const int32_t idx = (int32_t)b_->nodes4.size();
-        b_->nodes4.push_back(Bvh4Node{});
+        const int32_t idx = (int32_t)b_->wide4.size();
+        b_->wide4.push_back(Wide4{});
         const int pushes = (int)c.size() - 1;
         int32_t refs[4];
         for (int i = 0; i < (int)c.size(); ++i)
             refs[i] = collapse(c[i].ref, budget - pushes, pushed + pushes);
-        Bvh4Node& nd = b_->nodes4[idx];
+        Wide4& nd = b_->wide4[idx];
         for (int i = 0; i < 4; ++i) {
             if (i < (int)c.size()) {
-                nd.lox[i] = c[i].lo[0];
-                nd.loy[i] = c[i].lo[1];
-                nd.loz[i] = c[i].lo[2];
-                nd.hix[i] = c[i].hi[0];
-                nd.hiy[i] = c[i].hi[1];
-                nd.hiz[i] = c[i].hi[2];
+                for (int k = 0; k < 3; ++k) {
+                    nd.lo[k][i] = c[i].lo[k];
+                    nd.hi[k][i] = c[i].hi[k];
+                }
                 nd.child[i] = refs[i];
             } else {
-                nd.lox[i] = nd.loy[i] = nd.loz[i] = INFINITY;
-                nd.hix[i] = nd.hiy[i] = nd.hiz[i] = -INFINITY;
+                for (int k = 0; k < 3; ++k) {
+                    nd.lo[k][i] = INFINITY;
+                    nd.hi[k][i] = -INFINITY;
+                }
                 nd.child[i] = kEmptyChild;
             }
-            nd.pad[i] = 0;
         }
         return idx;
     }
@@ -472,8 +471,8 @@ class OptimalCollapser {
         need_.assign(n, 0);
         // children follow their parent in depth-first order
         for (int64_t i = n - 1; i >= 0; --i) solve((int32_t)i);
-        b_->nodes4.clear();
-        b_->nodes4.reserve(n / 2 + 1);
+        b_->wide4.clear();
+        b_->wide4.reserve(n / 2 + 1);
         max_push_ = 0;
         build(0, kStackSize, 0);
         b_->max_push4 = max_push_;
@@ -571,8 +570,8 @@ class OptimalCollapser {
             }
         }
         if (c.empty()) c = {l, r};   // unreachable: two children always fit
-        const int32_t idx = (int32_t)b_->nodes4.size();
-        b_->nodes4.push_back(Bvh4Node{});
+        const int32_t idx = (int32_t)b_->wide4.size();
+        b_->wide4.push_back(Wide4{});
         const int pushes = (int)c.size() - 1;
         int32_t refs[4];
         for (int i = 0; i < (int)c.size(); ++i) {
@@ -583,22 +582,21 @@ class OptimalCollapser {
                 max_push_ = std::max(max_push_, pushed + pushes);
             }
         }
-        Bvh4Node& nd = b_->nodes4[idx];
+        Wide4& nd = b_->wide4[idx];
         for (int i = 0; i < 4; ++i) {
             if (i < (int)c.size()) {
-                nd.lox[i] = c[i].lo[0];
-                nd.loy[i] = c[i].lo[1];
-                nd.loz[i] = c[i].lo[2];
-                nd.hix[i] = c[i].hi[0];
-                nd.hiy[i] = c[i].hi[1];
-                nd.hiz[i] = c[i].hi[2];
+                for (int k = 0; k < 3; ++k) {
+                    nd.lo[k][i] = c[i].lo[k];
+                    nd.hi[k][i] = c[i].hi[k];
+                }
                 nd.child[i] = refs[i];
             } else {
-                nd.lox[i] = nd.loy[i] = nd.loz[i] = INFINITY;
-                nd.hix[i] = nd.hiy[i] = nd.hiz[i] = -INFINITY;
+                for (int k = 0; k < 3; ++k) {
+                    nd.lo[k][i] = INFINITY;
+                    nd.hi[k][i] = -INFINITY;
+                }
                 nd.child[i] = kEmptyChild;
             }
-            nd.pad[i] = 0;
         }
         return idx;
     }
@@ -606,34 +604,96 @@ class OptimalCollapser {
 // Expected traversal cost of a 4-wide tree in the units of OptimalCollapser:
 // every node is entered with probability (its box area / the root's), costing
 // one node step; every leaf, likewise, costs kTriCost per triangle.
-double sah_cost4(const std::vector<Bvh4Node>& nodes) {
-    auto area = [](float lx, float ly, float lz, float hx, float hy, float hz) {
-        const double dx = std::max(0.0, (double)hx - lx), dy = std::max(0.0, (double)hy - ly),
-                     dz = std::max(0.0, (double)hz - lz);
-        return 2.0 * (dx * dy + dy * dz + dz * dx);
+double sah_cost4(const std::vector<Wide4>& nodes) {
+    auto area = [](const float* lo, const float* hi) {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = std::max(0.0, (double)hi[k] - (double)lo[k]);
+        return 2.0 * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
     };
-    const Bvh4Node& r = nodes[0];
+    const Wide4& r = nodes[0];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = 0; i < 4; ++i) {
         if (r.child[i] == kEmptyChild) continue;
-        lo[0] = std::min(lo[0], r.lox[i]);
-        lo[1] = std::min(lo[1], r.loy[i]);
-        lo[2] = std::min(lo[2], r.loz[i]);
-        hi[0] = std::max(hi[0], r.hix[i]);
-        hi[1] = std::max(hi[1], r.hiy[i]);
-        hi[2] = std::max(hi[2], r.hiz[i]);
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], r.lo[k][i]);
+            hi[k] = std::max(hi[k], r.hi[k][i]);
+        }
     }
-    const double root = std::max(area(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]), 1e-30);
+    const double root = std::max(area(lo, hi), 1e-30);
     double c = OptimalCollapser::kNodeCost;
-    for (const Bvh4Node& n : nodes) {
+    for (const Wide4& n : nodes) {
         for (int i = 0; i < 4; ++i) {
             if (n.child[i] == kEmptyChild) continue;
-            const double p = area(n.lox[i], n.loy[i], n.loz[i], n.hix[i], n.hiy[i], n.hiz[i]) / root;
+            const float sl[3] = {n.lo[0][i], n.lo[1][i], n.lo[2][i]};
+            const float sh[3] = {n.hi[0][i], n.hi[1][i], n.hi[2][i]};
+            const double p = area(sl, sh) / root;
             c += n.child[i] >= 0 ? p * OptimalCollapser::kNodeCost
                                  : p * OptimalCollapser::kTriCost * (((~n.child[i]) & 7) + 1);
         }
     }
     return c;
+}
+
+// ---- the device encoding of the 4-wide nodes --------------------------------
+double half_value(uint16_t h) {   // non-negative finite halves only
+    const int e = (h >> 10) & 31, m = h & 1023;
+    return e == 0 ? std::ldexp((double)m, -24) : std::ldexp((double)(1024 + m), e - 25);
+}
+
+// The half nearest to v (0 <= v <= 65504), then stepped to the largest half
+// <= v (up = false) or the smallest half >= v (up = true).  Bit patterns of
+// non-negative halves increase with their values.
+uint16_t half_bound(double v, bool up) {
+    uint16_t h;
+    if (v < 6.103515625e-05) {
+        h = (uint16_t)std::llround(v * 16777216.0);   // subnormal step 2^-24
+    } else {
+        int ex;
+        const double fr = std::frexp(v, &ex);           // v = fr 2^ex, fr in [0.5, 1)
+        long m = std::llround((fr * 2.0 - 1.0) * 1024.0);
+        int E = ex - 1 + 15;
+        if (m == 1024) {
+            m = 0;
+            ++E;
+        }
+        h = (uint16_t)((E << 10) | m);
+    }
+    if (up) {
+        while (half_value(h) < v) ++h;
+    } else {
+        while (h > 0 && half_value(h) > v) --h;
+    }
+    return h;
+}
+
+Bvh4Node encode4(const Wide4& w) {
+    Bvh4Node n;
+    std::memset(&n, 0, sizeof(n));
+    for (int k = 0; k < 3; ++k) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < 4; ++i) {
+            if (w.child[i] == kEmptyChild) continue;
+            lo = std::min(lo, (double)w.lo[k][i]);
+            hi = std::max(hi, (double)w.hi[k][i]);
+        }
+        // offsets in [0, 2^15]: well inside the half range
+        const double ext = hi - lo;
+        int e = ext > 0.0 ? (int)std::ceil(std::log2(ext)) - 15 : -30;
+        e = std::min(std::max(e, -100), 100);
+        n.org[k] = (float)lo;
+        n.ex[k] = (int8_t)e;
+        for (int i = 0; i < 4; ++i) {
+            if (w.child[i] == kEmptyChild) {
+                n.q[k][i] = 0x7C00;       // +inf
+                n.q[k][4 + i] = 0xFC00;   // -inf
+                continue;
+            }
+            n.q[k][i] = half_bound(std::ldexp((double)w.lo[k][i] - lo, -e), false);
+            n.q[k][4 + i] = half_bound(std::ldexp((double)w.hi[k][i] - lo, -e), true);
+        }
+    }
+    for (int i = 0; i < 4; ++i) n.child[i] = w.child[i];
+    return n;
 }
 
 }  // namespace
@@ -658,15 +718,17 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
     // deep that the budget forces narrow nodes near the root)
     OptimalCollapser opt(out);
     opt.run();
-    std::vector<Bvh4Node> guided;
-    guided.swap(out->nodes4);
+    std::vector<Wide4> guided;
+    guided.swap(out->wide4);
     const int guided_push = out->max_push4;
     Collapser greedy(out);
     greedy.run();
-    if (sah_cost4(guided) < sah_cost4(out->nodes4)) {
-        out->nodes4.swap(guided);
+    if (sah_cost4(guided) < sah_cost4(out->wide4)) {
+        out->wide4.swap(guided);
         out->max_push4 = guided_push;
     }
+    out->nodes4.resize(out->wide4.size());
+    for (size_t i = 0; i < out->wide4.size(); ++i) out->nodes4[i] = encode4(out->wide4[i]);
     if (out->max_push4 > kStackSize)
         return fail(FIPT_EINVAL, "4-wide BVH needs %d stack entries", out->max_push4);
     // the traversal addresses nodes by 32-bit byte offsets
@@ -680,44 +742,52 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
 
 namespace {
 
-// Walk the 4-wide node `idx`: every used slot's box encloses the boxes of
-// the child node (up to the widening margin) or the vertices of the leaf's
-// triangles; count triangle occurrences and the stack pushes on each path.
+// Walk the 4-wide node `idx`: every used slot's single-precision box
+// encloses the boxes of the child node (up to the widening margin) or the
+// vertices of the leaf's triangles, its decoded device box (origin plus
+// half-precision offsets) encloses the single-precision one, unused slots
+// encode an inverted box; count triangle occurrences and the stack pushes
+// on each path.
 int validate4(const fipt::HostBvh& b, const float* verts, const int32_t* tris, int32_t idx,
               int pushed, std::vector<int>& seen, int* max_push) {
     using namespace fipt;
-    if (idx < 0 || idx >= (int32_t)b.nodes4.size())
+    if (idx < 0 || idx >= (int32_t)b.nodes4.size() || b.nodes4.size() != b.wide4.size())
         return fail(FIPT_EINVAL, "4-wide child index %d out of range", idx);
-    const Bvh4Node& nd = b.nodes4[idx];
+    const Wide4& nd = b.wide4[idx];
+    const Bvh4Node& en = b.nodes4[idx];
     int used = 0;
     for (int i = 0; i < 4; ++i) {
+        if (en.child[i] != nd.child[i]) return fail(FIPT_EINVAL, "4-wide node %d: child mismatch", idx);
         if (nd.child[i] != kEmptyChild) {
             ++used;
             continue;
         }
         // the traversal relies on unused slots holding an inverted box
-        const bool inverted = nd.lox[i] == INFINITY && nd.loy[i] == INFINITY &&
-                              nd.loz[i] == INFINITY && nd.hix[i] == -INFINITY &&
-                              nd.hiy[i] == -INFINITY && nd.hiz[i] == -INFINITY;
-        if (!inverted) return fail(FIPT_EINVAL, "4-wide node %d: unused slot %d has a box", idx, i);
+        for (int k = 0; k < 3; ++k)
+            if (en.q[k][i] != 0x7C00 || en.q[k][4 + i] != 0xFC00)
+                return fail(FIPT_EINVAL, "4-wide node %d: unused slot %d has a box", idx, i);
     }
     if (used < 1) return fail(FIPT_EINVAL, "4-wide node %d has no children", idx);
     const int here = pushed + used - 1;
     for (int i = 0; i < 4; ++i) {
         const int32_t c = nd.child[i];
         if (c == kEmptyChild) continue;
-        const float lo[3] = {nd.lox[i], nd.loy[i], nd.loz[i]};
-        const float hi[3] = {nd.hix[i], nd.hiy[i], nd.hiz[i]};
+        const float lo[3] = {nd.lo[0][i], nd.lo[1][i], nd.lo[2][i]};
+        const float hi[3] = {nd.hi[0][i], nd.hi[1][i], nd.hi[2][i]};
+        for (int k = 0; k < 3; ++k) {
+            const double dlo = (double)en.org[k] + std::ldexp(half_value(en.q[k][i]), en.ex[k]);
+            const double dhi = (double)en.org[k] + std::ldexp(half_value(en.q[k][4 + i]), en.ex[k]);
+            if (!(dlo <= (double)lo[k] && dhi >= (double)hi[k]))
+                return fail(FIPT_EINVAL, "4-wide node %d: encoded slot %d does not enclose its box", idx, i);
+        }
         if (c >= 0) {
-            const Bvh4Node& ch = b.nodes4[c];
+            const Wide4& ch = b.wide4[c];
             for (int j = 0; j < 4; ++j) {
                 if (ch.child[j] == kEmptyChild) continue;
-                const float clo[3] = {ch.lox[j], ch.loy[j], ch.loz[j]};
-                const float chi[3] = {ch.hix[j], ch.hiy[j], ch.hiz[j]};
                 for (int k = 0; k < 3; ++k) {
                     const float tol = 4.0f * 9.5367431640625e-07f *
                                           std::max(std::fabs(lo[k]), std::fabs(hi[k])) + 1e-30f;
-                    if (clo[k] < lo[k] - tol || chi[k] > hi[k] + tol)
+                    if (ch.lo[k][j] < lo[k] - tol || ch.hi[k][j] > hi[k] + tol)
                         return fail(FIPT_EINVAL, "4-wide node %d leaves its parent box", c);
                 }
             }

@@ -91,14 +91,10 @@ struct Hit {
 // triangles).
 constexpr int32_t kDone = INT_MIN;
 
-// Per-ray constants of the slab test: inverse direction, origin times
-// inverse direction, and for each axis the byte offset inside a node of the
-// near-plane vector (the low bounds when the direction component is
-// positive, else the high bounds; the far-plane vector is the other one of
-// the pair, 16 bytes away).
+// Per-ray constants of the slab test: inverse direction and origin times
+// inverse direction.
 struct RaySlab {
     float ix, iy, iz, oxi, oyi, ozi;
-    uint32_t nx, ny, nz;
 };
 __device__ __forceinline__ RaySlab ray_slab(V3 o, V3 d) {
     const float dx = fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x);
@@ -111,23 +107,7 @@ __device__ __forceinline__ RaySlab ray_slab(V3 o, V3 d) {
     r.oxi = o.x * r.ix;
     r.oyi = o.y * r.iy;
     r.ozi = o.z * r.iz;
-    r.nx = (__float_as_uint(r.ix) >> 31) << 4;
-    r.ny = 32u + ((__float_as_uint(r.iy) >> 31) << 4);
-    r.nz = 64u + ((__float_as_uint(r.iz) >> 31) << 4);
     return r;
-}
-
-// Slab test of one child box given its near and far planes, against
-// [0, tmax]; returns the entry distance, or +inf when the box is missed.
-// An unused slot (low bounds +inf, high bounds -inf) has near distance +inf
-// and far distance -inf whatever the direction, so it is always missed.
-__device__ __forceinline__ float box_entry(float nx, float fx, float ny, float fy, float nz,
-                                           float fz, const RaySlab& r, float tmax) {
-    const float tn = fmaxf(fmaxf(fmaf(nx, r.ix, -r.oxi), fmaf(ny, r.iy, -r.oyi)),
-                           fmaxf(fmaf(nz, r.iz, -r.ozi), 0.0f));
-    const float tf = fminf(fminf(fmaf(fx, r.ix, -r.oxi), fmaf(fy, r.iy, -r.oyi)),
-                           fminf(fmaf(fz, r.iz, -r.ozi), tmax));
-    return tn <= tf ? tn : INFINITY;
 }
 
 __device__ __forceinline__ void order2(float& ka, int32_t& ca, float& kb, int32_t& cb) {
@@ -158,8 +138,26 @@ __device__ __forceinline__ int4 load_global(const int4* p) {
     return make_int4(v.x, v.y, v.z, v.w);
 }
 
-__device__ __forceinline__ float4 node_vec(const Bvh4Node* nodes, uint32_t off) {
-    return load_global(reinterpret_cast<const float4*>(reinterpret_cast<const char*>(nodes) + off));
+// The low / high half of a 32-bit word as a float (folded into the
+// mixed-precision FMA that consumes it).
+__device__ __forceinline__ float half_lo(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
+}
+__device__ __forceinline__ float half_hi(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+// Slab test of one child box against [0, tmax] from its near and far
+// planes as half-precision offsets: the distance to plane org + off 2^e is
+// fma(off, ix 2^e, org ix - o ix).  Returns the entry distance, or +inf
+// when the box is missed.  An unused slot (low offsets +inf, high -inf) has
+// near distance +inf and far distance -inf whatever the direction.
+__device__ __forceinline__ float box_entry(float nx, float fx, float ny, float fy, float nz,
+                                           float fz, float ax, float bx, float ay, float by,
+                                           float az, float bz, float tmax) {
+    const float tn = fmaxf(fmaxf(fmaf(nx, ax, bx), fmaf(ny, ay, by)), fmaxf(fmaf(nz, az, bz), 0.0f));
+    const float tf = fminf(fminf(fmaf(fx, ax, bx), fmaf(fy, ay, by)), fminf(fmaf(fz, az, bz), tmax));
+    return tn <= tf ? tn : INFINITY;
 }
 
 // One step of closest-hit traversal at 4-wide node `ref`: the hit children
@@ -170,20 +168,41 @@ __device__ __forceinline__ float4 node_vec(const Bvh4Node* nodes, uint32_t off) 
 __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, int& sp,
                                            int32_t* stack, int stride, const RaySlab& r,
                                            float tmax) {
-    const uint32_t base = (uint32_t)ref << 7;
-    const uint32_t ox = base + r.nx, oy = base + r.ny, oz = base + r.nz;
-    const float4 nx = node_vec(nodes, ox), fx = node_vec(nodes, ox ^ 16u);
-    const float4 ny = node_vec(nodes, oy), fy = node_vec(nodes, oy ^ 16u);
-    const float4 nz = node_vec(nodes, oz), fz = node_vec(nodes, oz ^ 16u);
-    const int4 ch = load_global(reinterpret_cast<const int4*>(reinterpret_cast<const char*>(nodes) + base + 96u));
-    float k0 = box_entry(nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, r, tmax);
-    float k1 = box_entry(nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, r, tmax);
-    float k2 = box_entry(nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, r, tmax);
-    float k3 = box_entry(nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, r, tmax);
+    const char* nb = reinterpret_cast<const char*>(nodes) + ((uint32_t)ref << 7);
+    const int4 qx = load_global(reinterpret_cast<const int4*>(nb));
+    const int4 qy = load_global(reinterpret_cast<const int4*>(nb + 16));
+    const int4 qz = load_global(reinterpret_cast<const int4*>(nb + 32));
+    const float4 og = load_global(reinterpret_cast<const float4*>(nb + 48));
+    const int4 ch = load_global(reinterpret_cast<const int4*>(nb + 64));
     int32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
     // keep the child load in the same batch as the box loads (otherwise it
     // is sunk below the miss branch and costs a second memory round trip)
     asm volatile("" : : "v"(c0), "v"(c1), "v"(c2), "v"(c3));
+    // per axis: scale and offset of the half-precision planes
+    const int32_t eb = __float_as_int(og.w);
+    const float ax = __builtin_amdgcn_ldexpf(r.ix, (eb << 24) >> 24);
+    const float ay = __builtin_amdgcn_ldexpf(r.iy, (eb << 16) >> 24);
+    const float az = __builtin_amdgcn_ldexpf(r.iz, (eb << 8) >> 24);
+    const float bx = fmaf(og.x, r.ix, -r.oxi);
+    const float by = fmaf(og.y, r.iy, -r.oyi);
+    const float bz = fmaf(og.z, r.iz, -r.ozi);
+    // near planes are the low bounds for a positive direction component,
+    // else the high bounds: words (lo0|lo1, lo2|lo3, hi0|hi1, hi2|hi3)
+    const bool sx = r.ix < 0.0f, sy = r.iy < 0.0f, sz = r.iz < 0.0f;
+    const uint32_t nx01 = sx ? qx.z : qx.x, nx23 = sx ? qx.w : qx.y;
+    const uint32_t fx01 = sx ? qx.x : qx.z, fx23 = sx ? qx.y : qx.w;
+    const uint32_t ny01 = sy ? qy.z : qy.x, ny23 = sy ? qy.w : qy.y;
+    const uint32_t fy01 = sy ? qy.x : qy.z, fy23 = sy ? qy.y : qy.w;
+    const uint32_t nz01 = sz ? qz.z : qz.x, nz23 = sz ? qz.w : qz.y;
+    const uint32_t fz01 = sz ? qz.x : qz.z, fz23 = sz ? qz.y : qz.w;
+    float k0 = box_entry(half_lo(nx01), half_lo(fx01), half_lo(ny01), half_lo(fy01), half_lo(nz01),
+                         half_lo(fz01), ax, bx, ay, by, az, bz, tmax);
+    float k1 = box_entry(half_hi(nx01), half_hi(fx01), half_hi(ny01), half_hi(fy01), half_hi(nz01),
+                         half_hi(fz01), ax, bx, ay, by, az, bz, tmax);
+    float k2 = box_entry(half_lo(nx23), half_lo(fx23), half_lo(ny23), half_lo(fy23), half_lo(nz23),
+                         half_lo(fz23), ax, bx, ay, by, az, bz, tmax);
+    float k3 = box_entry(half_hi(nx23), half_hi(fx23), half_hi(ny23), half_hi(fy23), half_hi(nz23),
+                         half_hi(fz23), ax, bx, ay, by, az, bz, tmax);
     const int hits = (k0 < INFINITY) + (k1 < INFINITY) + (k2 < INFINITY) + (k3 < INFINITY);
     // sorting network on four keys
     order2(k0, c0, k1, c1);

@@ -60,29 +60,43 @@ inline int32_t leaf_ref(int64_t first, int count) {
     return ~static_cast<int32_t>((first << 3) | (count - 1));
 }
 
-// 4-wide BVH collapsed from the binary one: one 128-byte node holds the
-// boxes of up to four children (as structure of arrays) and their
-// references (same encoding; kEmptyChild marks an unused slot).  The
-// collapse keeps the stack pushes along every root-to-leaf path within
-// kStackSize, so the traversal stack still cannot overflow.
+// 4-wide BVH collapsed from the binary one.  The collapse works on Wide4
+// nodes: the single-precision boxes of up to four children (structure of
+// arrays) and their references (same encoding as the binary tree;
+// kEmptyChild marks an unused slot).  It keeps the stack pushes along every
+// root-to-leaf path within kStackSize, so the traversal stack cannot
+// overflow.
 constexpr int32_t kEmptyChild = -2147483647;   // INT32_MIN + 1: never a leaf reference
-struct alignas(16) Bvh4Node {
-    float lox[4], hix[4];
-    float loy[4], hiy[4];
-    float loz[4], hiz[4];
+struct Wide4 {
+    float lo[3][4], hi[3][4];   // [axis][slot]
     int32_t child[4];
-    int32_t pad[4];
+};
+
+// The device form of a 4-wide node, 128 bytes of which the traversal reads
+// the first 80 in five 16-byte loads.  Per axis, q[axis] holds the slots'
+// low bounds then high bounds as half-precision offsets from org[axis] in
+// units of 2^ex[axis]:  bound = org + offset * 2^ex.  The offsets are
+// rounded outward (lows down, highs up), so every decoded box contains the
+// single-precision box it encodes; an unused slot has low +inf and high
+// -inf, which no ray enters.
+struct alignas(16) Bvh4Node {
+    uint16_t q[3][8];    // bytes 0..47: x, y, z; each lo[0..3], hi[0..3]
+    float org[3];        // bytes 48..59
+    int8_t ex[4];        // bytes 60..63 (ex[3] unused)
+    int32_t child[4];    // bytes 64..79
+    int32_t pad[12];
 };
 static_assert(sizeof(Bvh4Node) == 128, "4-wide node is one 128-byte line");
 constexpr int64_t kMaxNodes4 = int64_t(1) << 25;   // node byte offsets stay below 2^32
 
 struct HostBvh {
     std::vector<BvhNode> nodes;
-    std::vector<Bvh4Node> nodes4;
-    std::vector<TriGeom> tris;   // leaf order
-    std::vector<int32_t> order;  // leaf position -> original triangle
+    std::vector<Wide4> wide4;      // the collapse, single precision
+    std::vector<Bvh4Node> nodes4;  // its device encoding
+    std::vector<TriGeom> tris;     // leaf order
+    std::vector<int32_t> order;    // leaf position -> original triangle
     int max_depth = 0;
-    int max_push4 = 0;           // most stack pushes on a path of the 4-wide tree
+    int max_push4 = 0;             // most stack pushes on a path of the 4-wide tree
     float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
 };
 
