@@ -666,21 +666,33 @@ uint16_t half_bound(double v, bool up) {
     return h;
 }
 
+// signed directed rounding: largest half <= v (up = false) or smallest >= v
+uint16_t half_bound_signed(double v, bool up) {
+    if (v >= 0.0) return half_bound(v, up);
+    return (uint16_t)(0x8000u | half_bound(-v, !up));
+}
+
 Bvh4Node encode4(const Wide4& w) {
     Bvh4Node n;
     std::memset(&n, 0, sizeof(n));
     for (int k = 0; k < 3; ++k) {
-        double lo = INFINITY, hi = -INFINITY;
+        // origin: the low bound of the thinnest child, whose bounds then
+        // encode almost exactly (flat walls stay thin)
+        double org = 0.0, thin = INFINITY, lo = INFINITY, hi = -INFINITY;
         for (int i = 0; i < 4; ++i) {
             if (w.child[i] == kEmptyChild) continue;
             lo = std::min(lo, (double)w.lo[k][i]);
             hi = std::max(hi, (double)w.hi[k][i]);
+            const double t = (double)w.hi[k][i] - (double)w.lo[k][i];
+            if (t < thin) {
+                thin = t;
+                org = w.lo[k][i];
+            }
         }
-        // offsets in [0, 2^15]: well inside the half range
-        const double ext = hi - lo;
-        int e = ext > 0.0 ? (int)std::ceil(std::log2(ext)) - 15 : -30;
+        const double span = std::max(org - lo, hi - org);
+        int e = span > 0.0 ? (int)std::ceil(std::log2(span)) - 15 : -30;
         e = std::min(std::max(e, -100), 100);
-        n.org[k] = (float)lo;
+        n.org[k] = (float)org;
         n.ex[k] = (int8_t)e;
         for (int i = 0; i < 4; ++i) {
             if (w.child[i] == kEmptyChild) {
@@ -688,8 +700,8 @@ Bvh4Node encode4(const Wide4& w) {
                 n.q[k][4 + i] = 0xFC00;   // -inf
                 continue;
             }
-            n.q[k][i] = half_bound(std::ldexp((double)w.lo[k][i] - lo, -e), false);
-            n.q[k][4 + i] = half_bound(std::ldexp((double)w.hi[k][i] - lo, -e), true);
+            n.q[k][i] = half_bound_signed(std::ldexp((double)w.lo[k][i] - org, -e), false);
+            n.q[k][4 + i] = half_bound_signed(std::ldexp((double)w.hi[k][i] - org, -e), true);
         }
     }
     for (int i = 0; i < 4; ++i) n.child[i] = w.child[i];
@@ -775,8 +787,9 @@ int validate4(const fipt::HostBvh& b, const float* verts, const int32_t* tris, i
         const float lo[3] = {nd.lo[0][i], nd.lo[1][i], nd.lo[2][i]};
         const float hi[3] = {nd.hi[0][i], nd.hi[1][i], nd.hi[2][i]};
         for (int k = 0; k < 3; ++k) {
-            const double dlo = (double)en.org[k] + std::ldexp(half_value(en.q[k][i]), en.ex[k]);
-            const double dhi = (double)en.org[k] + std::ldexp(half_value(en.q[k][4 + i]), en.ex[k]);
+            auto sv = [](uint16_t h) { return (h & 0x8000u) ? -half_value(h & 0x7FFFu) : half_value(h); };
+            const double dlo = (double)en.org[k] + std::ldexp(sv(en.q[k][i]), en.ex[k]);
+            const double dhi = (double)en.org[k] + std::ldexp(sv(en.q[k][4 + i]), en.ex[k]);
             if (!(dlo <= (double)lo[k] && dhi >= (double)hi[k]))
                 return fail(FIPT_EINVAL, "4-wide node %d: encoded slot %d does not enclose its box", idx, i);
         }

@@ -74,11 +74,14 @@ struct Wide4 {
 
 // The device form of a 4-wide node, 128 bytes of which the traversal reads
 // the first 80 in five 16-byte loads.  Per axis, q[axis] holds the slots'
-// low bounds then high bounds as half-precision offsets from org[axis] in
-// units of 2^ex[axis]:  bound = org + offset * 2^ex.  The offsets are
-// rounded outward (lows down, highs up), so every decoded box contains the
-// single-precision box it encodes; an unused slot has low +inf and high
-// -inf, which no ray enters.
+// low bounds then high bounds as signed half-precision offsets from
+// org[axis] in units of 2^ex[axis]:  bound = org + offset * 2^ex.  The
+// origin is the low bound of the slot thinnest on that axis, so a flat box
+// (a wall, a floor) keeps its thickness and a ray leaving such a surface does
+// not start inside it; other bounds carry the half-precision error of their
+// distance from the origin.  Offsets are rounded outward (lows down, highs
+// up), so every decoded box contains the single-precision box it encodes;
+// an unused slot has low +inf and high -inf, which no ray enters.
 struct alignas(16) Bvh4Node {
     uint16_t q[3][8];    // bytes 0..47: x, y, z; each lo[0..3], hi[0..3]
     float org[3];        // bytes 48..59
