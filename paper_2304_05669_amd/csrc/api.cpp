@@ -170,6 +170,7 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris, 
     s->n_verts = n_verts;
     s->n_nodes = (int64_t)bvh.nodes4.size();
     s->max_depth = bvh.max_depth;
+    s->box_scale = std::ldexp(1.0f, bvh.box_exp);
     for (int k = 0; k < 3; ++k) {
         s->bmin[k] = bvh.bmin[k];
         s->bmax[k] = bvh.bmax[k];

@@ -275,7 +275,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
     int lobe = 0;
     float w0 = 0.0f, w1 = 0.0f;       // weights of the Ls0 / Ls1 (or Ld) contributions
     V3 d = v3(0.0f, 0.0f, 1.0f);
-    dev::RaySlab rs = dev::ray_slab(o, d);
+    dev::RaySlab rs = dev::ray_slab(o, d, sc.box_scale);
     int32_t ref = kDone;
     int sp = 0;
     dev::Hit h;
@@ -354,7 +354,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                         }
                         if (shoot) {
                             if (COUNT) ++n_rays;
-                            rs = dev::ray_slab(o, d);
+                            rs = dev::ray_slab(o, d, sc.box_scale);
                             ref = 0;
                             sp = 0;
                             h.leaf = -1;
@@ -489,6 +489,7 @@ __device__ __forceinline__ BakeLaunch uniform_job(const BakeLaunch& j) {
     b.sc.tris = static_cast<const TriGeom*>(up(j.sc.tris));
     b.sc.rad = static_cast<const TriRad*>(up(j.sc.rad));
     b.sc.n_tris = wave_uniform(j.sc.n_tris);
+    b.sc.box_scale = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(j.sc.box_scale)));
     b.pts = static_cast<const float*>(up(j.pts));
     b.ptri = static_cast<const int32_t*>(up(j.ptri));
     b.pts_stride = wave_uniform(j.pts_stride);

@@ -672,36 +672,60 @@ uint16_t half_bound_signed(double v, bool up) {
     return (uint16_t)(0x8000u | half_bound(-v, !up));
 }
 
-Bvh4Node encode4(const Wide4& w) {
+// Per axis, the origin is the low bound of the thinnest used child, whose
+// bounds then encode almost exactly (flat walls stay thin).
+double node_origin(const Wide4& w, int k) {
+    double org = 0.0, thin = INFINITY;
+    for (int i = 0; i < 4; ++i) {
+        if (w.child[i] == kEmptyChild) continue;
+        const double t = (double)w.hi[k][i] - (double)w.lo[k][i];
+        if (t < thin) {
+            thin = t;
+            org = w.lo[k][i];
+        }
+    }
+    return org;
+}
+
+// The scene-wide exponent E of the half-precision offsets: every offset
+// from a node origin, in units of 2^E, stays within the half range (2^15 <
+// 65504).  A half carries 11 significant bits wherever it is normal, so one
+// exponent for the whole tree loses nothing against one per node; offsets
+// below 2^(E-14) fall into the subnormal range and are still rounded
+// outward.  E is kept large enough that the scaled origins are normal
+// single-precision numbers.
+int box_exponent(const std::vector<Wide4>& nodes) {
+    double span = 0.0, mag = 0.0;
+    for (const Wide4& w : nodes)
+        for (int k = 0; k < 3; ++k) {
+            const double org = node_origin(w, k);
+            for (int i = 0; i < 4; ++i) {
+                if (w.child[i] == kEmptyChild) continue;
+                span = std::max(span, std::max(org - (double)w.lo[k][i], (double)w.hi[k][i] - org));
+                mag = std::max(mag, std::fabs(org));
+            }
+        }
+    int e = span > 0.0 ? (int)std::ceil(std::log2(span)) - 15 : -30;
+    if (mag > 0.0) e = std::max(e, (int)std::ceil(std::log2(mag)) - 120);
+    return std::min(std::max(e, -120), 100);
+}
+
+Bvh4Node encode4(const Wide4& w, int e) {
     Bvh4Node n;
     std::memset(&n, 0, sizeof(n));
     for (int k = 0; k < 3; ++k) {
-        // origin: the low bound of the thinnest child, whose bounds then
-        // encode almost exactly (flat walls stay thin)
-        double org = 0.0, thin = INFINITY, lo = INFINITY, hi = -INFINITY;
-        for (int i = 0; i < 4; ++i) {
-            if (w.child[i] == kEmptyChild) continue;
-            lo = std::min(lo, (double)w.lo[k][i]);
-            hi = std::max(hi, (double)w.hi[k][i]);
-            const double t = (double)w.hi[k][i] - (double)w.lo[k][i];
-            if (t < thin) {
-                thin = t;
-                org = w.lo[k][i];
-            }
-        }
-        const double span = std::max(org - lo, hi - org);
-        int e = span > 0.0 ? (int)std::ceil(std::log2(span)) - 15 : -30;
-        e = std::min(std::max(e, -100), 100);
-        n.org[k] = (float)org;
-        n.ex[k] = (int8_t)e;
+        // the stored origin, in units of 2^e (exact: a power-of-two scaling
+        // of a normal number); offsets are taken from it as stored
+        n.org[k] = (float)std::ldexp(node_origin(w, k), -e);
+        const double org = (double)n.org[k];
         for (int i = 0; i < 4; ++i) {
             if (w.child[i] == kEmptyChild) {
                 n.q[k][i] = 0x7C00;       // +inf
                 n.q[k][4 + i] = 0xFC00;   // -inf
                 continue;
             }
-            n.q[k][i] = half_bound_signed(std::ldexp((double)w.lo[k][i] - org, -e), false);
-            n.q[k][4 + i] = half_bound_signed(std::ldexp((double)w.hi[k][i] - org, -e), true);
+            n.q[k][i] = half_bound_signed(std::ldexp((double)w.lo[k][i], -e) - org, false);
+            n.q[k][4 + i] = half_bound_signed(std::ldexp((double)w.hi[k][i], -e) - org, true);
         }
     }
     for (int i = 0; i < 4; ++i) n.child[i] = w.child[i];
@@ -739,8 +763,10 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
         out->wide4.swap(guided);
         out->max_push4 = guided_push;
     }
+    out->box_exp = box_exponent(out->wide4);
     out->nodes4.resize(out->wide4.size());
-    for (size_t i = 0; i < out->wide4.size(); ++i) out->nodes4[i] = encode4(out->wide4[i]);
+    for (size_t i = 0; i < out->wide4.size(); ++i)
+        out->nodes4[i] = encode4(out->wide4[i], out->box_exp);
     if (out->max_push4 > kStackSize)
         return fail(FIPT_EINVAL, "4-wide BVH needs %d stack entries", out->max_push4);
     // the traversal addresses nodes by 32-bit byte offsets
@@ -788,8 +814,8 @@ int validate4(const fipt::HostBvh& b, const float* verts, const int32_t* tris, i
         const float hi[3] = {nd.hi[0][i], nd.hi[1][i], nd.hi[2][i]};
         for (int k = 0; k < 3; ++k) {
             auto sv = [](uint16_t h) { return (h & 0x8000u) ? -half_value(h & 0x7FFFu) : half_value(h); };
-            const double dlo = (double)en.org[k] + std::ldexp(sv(en.q[k][i]), en.ex[k]);
-            const double dhi = (double)en.org[k] + std::ldexp(sv(en.q[k][4 + i]), en.ex[k]);
+            const double dlo = std::ldexp((double)en.org[k] + sv(en.q[k][i]), b.box_exp);
+            const double dhi = std::ldexp((double)en.org[k] + sv(en.q[k][4 + i]), b.box_exp);
             if (!(dlo <= (double)lo[k] && dhi >= (double)hi[k]))
                 return fail(FIPT_EINVAL, "4-wide node %d: encoded slot %d does not enclose its box", idx, i);
         }

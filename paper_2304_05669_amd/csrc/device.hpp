@@ -91,22 +91,26 @@ struct Hit {
 // triangles).
 constexpr int32_t kDone = INT_MIN;
 
-// Per-ray constants of the slab test: inverse direction and origin times
-// inverse direction.
+// Per-ray constants of the slab test against node bounds in units of
+// `scale`: the inverse direction times the unit (a power of two, so the
+// product is exact) and the origin times the inverse direction.
 struct RaySlab {
-    float ix, iy, iz, oxi, oyi, ozi;
+    float ax, ay, az, oxi, oyi, ozi;
 };
-__device__ __forceinline__ RaySlab ray_slab(V3 o, V3 d) {
+__device__ __forceinline__ RaySlab ray_slab(V3 o, V3 d, float scale) {
     const float dx = fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x);
     const float dy = fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y);
     const float dz = fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z);
+    const float ix = __builtin_amdgcn_rcpf(dx);
+    const float iy = __builtin_amdgcn_rcpf(dy);
+    const float iz = __builtin_amdgcn_rcpf(dz);
     RaySlab r;
-    r.ix = __builtin_amdgcn_rcpf(dx);
-    r.iy = __builtin_amdgcn_rcpf(dy);
-    r.iz = __builtin_amdgcn_rcpf(dz);
-    r.oxi = o.x * r.ix;
-    r.oyi = o.y * r.iy;
-    r.ozi = o.z * r.iz;
+    r.ax = ix * scale;
+    r.ay = iy * scale;
+    r.az = iz * scale;
+    r.oxi = o.x * ix;
+    r.oyi = o.y * iy;
+    r.ozi = o.z * iz;
     return r;
 }
 
@@ -148,10 +152,11 @@ __device__ __forceinline__ float half_hi(uint32_t w) {
 }
 
 // Slab test of one child box against [0, tmax] from its near and far
-// planes as half-precision offsets: the distance to plane org + off 2^e is
-// fma(off, ix 2^e, org ix - o ix).  Returns the entry distance, or +inf
-// when the box is missed.  An unused slot (low offsets +inf, high -inf) has
-// near distance +inf and far distance -inf whatever the direction.
+// planes as half-precision offsets from the node origin: the distance to
+// plane (org + off) 2^E is fma(off, a, org a - o ix) with a = ix 2^E.
+// Returns the entry distance, or +inf when the box is missed.  An unused
+// slot (low offsets +inf, high -inf) has near distance +inf and far
+// distance -inf whatever the direction.
 __device__ __forceinline__ float box_entry(float nx, float fx, float ny, float fy, float nz,
                                            float fz, float ax, float bx, float ay, float by,
                                            float az, float bz, float tmax) {
@@ -178,17 +183,14 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
     // keep the child load in the same batch as the box loads (otherwise it
     // is sunk below the miss branch and costs a second memory round trip)
     asm volatile("" : : "v"(c0), "v"(c1), "v"(c2), "v"(c3));
-    // per axis: scale and offset of the half-precision planes
-    const int32_t eb = __float_as_int(og.w);
-    const float ax = __builtin_amdgcn_ldexpf(r.ix, (eb << 24) >> 24);
-    const float ay = __builtin_amdgcn_ldexpf(r.iy, (eb << 16) >> 24);
-    const float az = __builtin_amdgcn_ldexpf(r.iz, (eb << 8) >> 24);
-    const float bx = fmaf(og.x, r.ix, -r.oxi);
-    const float by = fmaf(og.y, r.iy, -r.oyi);
-    const float bz = fmaf(og.z, r.iz, -r.ozi);
+    // per axis: distance at the node origin
+    const float ax = r.ax, ay = r.ay, az = r.az;
+    const float bx = fmaf(og.x, ax, -r.oxi);
+    const float by = fmaf(og.y, ay, -r.oyi);
+    const float bz = fmaf(og.z, az, -r.ozi);
     // near planes are the low bounds for a positive direction component,
     // else the high bounds: words (lo0|lo1, lo2|lo3, hi0|hi1, hi2|hi3)
-    const bool sx = r.ix < 0.0f, sy = r.iy < 0.0f, sz = r.iz < 0.0f;
+    const bool sx = ax < 0.0f, sy = ay < 0.0f, sz = az < 0.0f;
     const uint32_t nx01 = sx ? qx.z : qx.x, nx23 = sx ? qx.w : qx.y;
     const uint32_t fx01 = sx ? qx.x : qx.z, fx23 = sx ? qx.y : qx.w;
     const uint32_t ny01 = sy ? qy.z : qy.x, ny23 = sy ? qy.w : qy.y;
@@ -203,14 +205,14 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
                          half_lo(fz23), ax, bx, ay, by, az, bz, tmax);
     float k3 = box_entry(half_hi(nx23), half_hi(fx23), half_hi(ny23), half_hi(fy23), half_hi(nz23),
                          half_hi(fz23), ax, bx, ay, by, az, bz, tmax);
-    const int hits = (k0 < INFINITY) + (k1 < INFINITY) + (k2 < INFINITY) + (k3 < INFINITY);
-    // sorting network on four keys
+    // sorting network on four keys; a missed child keeps key +inf and sorts
+    // last, so the sorted keys say which children to visit
     order2(k0, c0, k1, c1);
     order2(k2, c2, k3, c3);
     order2(k0, c0, k2, c2);
     order2(k1, c1, k3, c3);
     order2(k1, c1, k2, c2);
-    if (hits == 0) {
+    if (!(k0 < INFINITY)) {
         if (sp == 0) {
             ref = kDone;
         } else {
@@ -219,9 +221,9 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
         }
         return;
     }
-    if (hits > 3) stack[(sp++) * stride] = c3;
-    if (hits > 2) stack[(sp++) * stride] = c2;
-    if (hits > 1) stack[(sp++) * stride] = c1;
+    if (k3 < INFINITY) stack[(sp++) * stride] = c3;
+    if (k2 < INFINITY) stack[(sp++) * stride] = c2;
+    if (k1 < INFINITY) stack[(sp++) * stride] = c1;
     ref = c0;
 }
 
@@ -262,7 +264,7 @@ __device__ __forceinline__ void tri_test(const TriGeom* tris, int32_t i, V3 o, V
 template <bool COUNT>
 __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t* stack,
                                      int stride, uint32_t& n_nodes, uint32_t& n_tris) {
-    const RaySlab r = ray_slab(o, d);
+    const RaySlab r = ray_slab(o, d, sc.box_scale);
     Hit h;
     h.leaf = -1;
     h.t = INFINITY;

@@ -73,19 +73,20 @@ struct Wide4 {
 };
 
 // The device form of a 4-wide node, 128 bytes of which the traversal reads
-// the first 80 in five 16-byte loads.  Per axis, q[axis] holds the slots'
-// low bounds then high bounds as signed half-precision offsets from
-// org[axis] in units of 2^ex[axis]:  bound = org + offset * 2^ex.  The
-// origin is the low bound of the slot thinnest on that axis, so a flat box
-// (a wall, a floor) keeps its thickness and a ray leaving such a surface does
-// not start inside it; other bounds carry the half-precision error of their
+// the first 80 in five 16-byte loads.  Bounds are in units of 2^E, one
+// exponent E for the whole tree (HostBvh::box_exp).  Per axis, q[axis]
+// holds the slots' low bounds then high bounds as signed half-precision
+// offsets from org[axis]:  bound = (org + offset) 2^E.  The origin is the
+// low bound of the slot thinnest on that axis, so a flat box (a wall, a
+// floor) keeps its thickness and a ray leaving such a surface does not
+// start inside it; other bounds carry the half-precision error of their
 // distance from the origin.  Offsets are rounded outward (lows down, highs
 // up), so every decoded box contains the single-precision box it encodes;
 // an unused slot has low +inf and high -inf, which no ray enters.
 struct alignas(16) Bvh4Node {
     uint16_t q[3][8];    // bytes 0..47: x, y, z; each lo[0..3], hi[0..3]
     float org[3];        // bytes 48..59
-    int8_t ex[4];        // bytes 60..63 (ex[3] unused)
+    int32_t spare;       // bytes 60..63
     int32_t child[4];    // bytes 64..79
     int32_t pad[12];
 };
@@ -100,6 +101,7 @@ struct HostBvh {
     std::vector<int32_t> order;    // leaf position -> original triangle
     int max_depth = 0;
     int max_push4 = 0;             // most stack pushes on a path of the 4-wide tree
+    int box_exp = 0;               // nodes4 bounds are in units of 2^box_exp
     float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
 };
 
@@ -114,6 +116,7 @@ struct DeviceScene {
     const TriGeom* tris;
     const TriRad* rad;
     int64_t n_tris;
+    float box_scale;   // 2^E: the unit of the node bounds
 };
 
 int launch_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_idx,
@@ -215,6 +218,7 @@ struct fipt_scene_s {
     int64_t n_tris = 0, n_verts = 0, n_nodes = 0;
     int32_t max_depth = 0;
     int32_t cache_kind = -1;
+    float box_scale = 1.0f;        // 2^E of the node bounds
     float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
     fipt::Bvh4Node* d_nodes = nullptr;   // 4-wide nodes
     fipt::TriGeom* d_tris = nullptr;
@@ -227,5 +231,5 @@ struct fipt_scene_s {
     std::mutex slot_mu;
     int64_t bytes = 0;
     std::atomic<int> refs{0};      // serving requests referencing the scene
-    fipt::DeviceScene view() const { return {d_nodes, d_tris, d_rad, n_tris}; }
+    fipt::DeviceScene view() const { return {d_nodes, d_tris, d_rad, n_tris, box_scale}; }
 };
