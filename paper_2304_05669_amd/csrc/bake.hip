@@ -196,7 +196,7 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sig
 // At the end of the point one fixed butterfly sums the accumulators.
 constexpr int kRefillMaxK = 10;      // 3 + 6K output slots fit the 64 lanes
 using dev::kDone;
-constexpr int kRefillMin = 48;       // refill once this many lanes are free
+constexpr int kRefillMin = 40;       // refill once this many lanes are free
 constexpr int kSearchMin = 8;        // leave the node loop below this many searchers
 
 enum LaneState { kIdle = 0, kTracing = 1, kFinished = 2 };
@@ -277,7 +277,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
     V3 d = v3(0.0f, 0.0f, 1.0f);
     dev::RaySlab rs = dev::ray_slab(o, d, sc.box_scale);
     int32_t ref = kDone;
-    int sp = 0;
+    int32_t* top = stack;
     dev::Hit h;
     h.leaf = -1;
     h.t = INFINITY;
@@ -356,7 +356,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                             if (COUNT) ++n_rays;
                             rs = dev::ray_slab(o, d, sc.box_scale);
                             ref = 0;
-                            sp = 0;
+                            top = stack;
                             h.leaf = -1;
                             h.t = INFINITY;
                             h.u = h.v = 0.0f;
@@ -377,24 +377,22 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
         while (true) {
             if (is_leaf(ref) && pend == kDone) {
                 pend = ref;
-                if (sp == 0) {
-                    ref = kDone;
-                } else {
-                    --sp;
-                    ref = stack[sp * kBlock];
-                }
+                dev::stack_pop(ref, top, stack, kBlock);
             }
             const bool inner = ref >= 0;
             // Stop descending once fewer than kSearchMin lanes are still
             // looking for a leaf and some lane has one to test: the rest would
             // otherwise idle while the last few rays search.
-            const uint64_t searching = dev::ballot(inner && pend == kDone);
-            if (searching == 0 || (__popcll(searching) < kSearchMin && dev::ballot(pend != kDone) != 0))
+            // (two ballots and a 32-bit count keep the test in scalar code)
+            const uint64_t searching = dev::ballot(inner) & dev::ballot(pend == kDone);
+            const int n_searching = __builtin_popcount((uint32_t)searching) +
+                                    __builtin_popcount((uint32_t)(searching >> 32));
+            if (searching == 0 || (n_searching < kSearchMin && dev::ballot(pend != kDone) != 0))
                 break;
             if (COUNT && lane == 0) ++n_node_steps;
             if (inner) {
                 if (COUNT) ++n_nodes;
-                dev::node4_step(sc.nodes, ref, sp, stack, kBlock, rs, h.t);
+                dev::node4_step(sc.nodes, ref, top, stack, kBlock, rs, h.t);
             }
         }
         // ---- leaves ---------------------------------------------------------

@@ -165,13 +165,26 @@ __device__ __forceinline__ float box_entry(float nx, float fx, float ny, float f
     return tn <= tf ? tn : INFINITY;
 }
 
+// Pop the next entry of a lane's stack into `ref` (kDone when it is
+// empty).  `top` is the lane's next free slot, `bottom` its first; slots
+// are `stride` ints apart.
+__device__ __forceinline__ void stack_pop(int32_t& ref, int32_t*& top, const int32_t* bottom,
+                                          int stride) {
+    if (top == bottom) {
+        ref = kDone;
+    } else {
+        top -= stride;
+        ref = *top;
+    }
+}
+
 // One step of closest-hit traversal at 4-wide node `ref`: the hit children
 // are visited nearest first; the nearest becomes `ref`, the others are
 // pushed farthest first.  With no child hit, the next entry is popped
 // (kDone when the stack is empty).  Node byte offsets fit 32 bits (the
 // builder rejects trees of more than kMaxNodes4 nodes).
-__device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, int& sp,
-                                           int32_t* stack, int stride, const RaySlab& r,
+__device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, int32_t*& top,
+                                           const int32_t* bottom, int stride, const RaySlab& r,
                                            float tmax) {
     const char* nb = reinterpret_cast<const char*>(nodes) + ((uint32_t)ref << 7);
     const int4 qx = load_global(reinterpret_cast<const int4*>(nb));
@@ -213,17 +226,21 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
     order2(k1, c1, k3, c3);
     order2(k1, c1, k2, c2);
     if (!(k0 < INFINITY)) {
-        if (sp == 0) {
-            ref = kDone;
-        } else {
-            --sp;
-            ref = stack[sp * stride];
-        }
+        stack_pop(ref, top, bottom, stride);
         return;
     }
-    if (k3 < INFINITY) stack[(sp++) * stride] = c3;
-    if (k2 < INFINITY) stack[(sp++) * stride] = c2;
-    if (k1 < INFINITY) stack[(sp++) * stride] = c1;
+    if (k3 < INFINITY) {
+        *top = c3;
+        top += stride;
+    }
+    if (k2 < INFINITY) {
+        *top = c2;
+        top += stride;
+    }
+    if (k1 < INFINITY) {
+        *top = c1;
+        top += stride;
+    }
     ref = c0;
 }
 
@@ -271,11 +288,11 @@ __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t*
     h.u = h.v = 0.0f;
     int32_t best_orig = INT_MAX;
     int32_t ref = 0;
-    int sp = 0;
+    int32_t* top = stack;
     while (ref != kDone) {
         if (ref >= 0) {
             if (COUNT) ++n_nodes;
-            node4_step(sc.nodes, ref, sp, stack, stride, r, h.t);
+            node4_step(sc.nodes, ref, top, stack, stride, r, h.t);
         } else {
             const int32_t lr = ~ref;
             const int32_t first = lr >> 3;
@@ -284,12 +301,7 @@ __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t*
                 if (COUNT) ++n_tris;
                 tri_test(sc.tris, first + i, o, d, h, best_orig);
             }
-            if (sp == 0) {
-                ref = kDone;
-            } else {
-                --sp;
-                ref = stack[sp * stride];
-            }
+            stack_pop(ref, top, stack, stride);
         }
     }
     return h;
