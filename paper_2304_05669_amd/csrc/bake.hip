@@ -287,9 +287,11 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
 
     while (true) {
         // ---- fold finished rays and refill free lanes ----------------------
+        // (once every sample is handed out, finished lanes keep their hits
+        // and are folded together when the last ray ends)
         const uint64_t tracing = dev::ballot(state == kTracing);
         const int n_free = 64 - __popcll(tracing);
-        if (n_free >= kRefillMin || tracing == 0) {
+        if ((n_free >= kRefillMin && next_q < S) || tracing == 0) {
             const bool done = state == kFinished;
             flush(done && cur_lobe >= 0 && cur_lobe != lobe);
             if (done) {
