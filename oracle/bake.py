@@ -39,6 +39,8 @@ def lib():
                                 _f32p, _f32p, C.c_double, C.c_double]
     L.orc_scene_free.argtypes = [C.c_void_p]
     L.orc_philox.argtypes = [_u32p, _u32p, _u32p, C.c_int64]
+    L.orc_lobe_uniforms.argtypes = [C.c_uint64, _i64p, _i32p, _i32p, _i32p, C.c_int64,
+                                    _f64p, _f64p]
     L.orc_frame.argtypes = [_f64p, _f64p, _f64p]
     L.orc_sample_cosine.argtypes = [C.c_double, C.c_double, _f64p]
     L.orc_sample_ggx.argtypes = [C.c_double, C.c_double, C.c_double, _f64p]
@@ -103,6 +105,25 @@ def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
     out = np.zeros_like(ctr)
     lib().orc_philox(ctr, key, out, len(ctr))
     return out
+
+
+def lobe_uniforms(seed: int, p, lobe, s, n):
+    """(xi1, xi2) of sample s of n for lobe `lobe` of point p (arrays,
+    broadcast): Philox4x32-10 on the counter (p low, p high, lobe, s) under
+    key `seed`, stratified along the Z-order curve (``sample_uniforms`` in
+    the C oracle)."""
+    p, lobe, s, n = np.broadcast_arrays(np.asarray(p, np.int64), np.asarray(lobe, np.int32),
+                                        np.asarray(s, np.int32), np.asarray(n, np.int32))
+    p = np.ascontiguousarray(p.ravel())
+    lobe = np.ascontiguousarray(lobe.ravel())
+    s = np.ascontiguousarray(s.ravel())
+    n = np.ascontiguousarray(n.ravel())
+    if np.any(n < 1) or np.any(s < 0) or np.any(s >= n):
+        raise ValueError("need 0 <= s < n")
+    xi1 = np.empty(len(p), np.float64)
+    xi2 = np.empty(len(p), np.float64)
+    lib().orc_lobe_uniforms(C.c_uint64(seed), p, lobe, s, n, len(p), xi1, xi2)
+    return xi1, xi2
 
 
 def frame(n):

@@ -80,8 +80,17 @@ void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t
     for (int64_t i = 0; i < n; ++i) philox(ctr + 4 * i, key + 2 * i, out + 4 * i);
 }
 
-/* Two uniforms in [0, 1) with 24 significant bits from a Philox block. */
-static void sample_uniforms(uint64_t seed, int64_t p, int lobe, int s,
+/* The two uniforms of sample s of a lobe's n samples, stratified along the
+ * Z-order (Morton) curve of the unit square.  The 32-bit line is cut into n
+ * segments of width W = floor(2^32 / n); sample s takes the point
+ * U = s W + floor(u0 W / 2^32) of its own segment (u the Philox block of the
+ * counter (p low, p high, lobe, s)).  Read as a Morton code, U names a cell
+ * of a 2^16 x 2^16 grid: its bit 2i is bit i of the column X, its bit 2i + 1
+ * bit i of the row Y.  A point inside the cell comes from the top bytes of
+ * u1 and u2: xi1 = (256 X + (u1 >> 24)) / 2^24, xi2 = (256 Y + (u2 >> 24)) /
+ * 2^24.  The segments tile [0, nW), all but less than n / 2^32 of the
+ * square, so the estimate is stratified and unbiased up to that sliver. */
+static void sample_uniforms(uint64_t seed, int64_t p, int lobe, int s, int n,
                             double* xi1, double* xi2)
 {
     uint32_t c[4] = {(uint32_t)(uint64_t)p, (uint32_t)((uint64_t)p >> 32),
@@ -89,8 +98,23 @@ static void sample_uniforms(uint64_t seed, int64_t p, int lobe, int s,
     uint32_t k[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t u[4];
     philox(c, k, u);
-    *xi1 = (double)(u[0] >> 8) * (1.0 / 16777216.0);
-    *xi2 = (double)(u[1] >> 8) * (1.0 / 16777216.0);
+    const uint64_t W = ((uint64_t)1 << 32) / (uint64_t)n;
+    const uint64_t U = (uint64_t)s * W + (((uint64_t)u[0] * W) >> 32);
+    uint32_t X = 0, Y = 0;
+    for (int i = 0; i < 16; ++i) {
+        X |= (uint32_t)((U >> (2 * i)) & 1u) << i;
+        Y |= (uint32_t)((U >> (2 * i + 1)) & 1u) << i;
+    }
+    *xi1 = ((double)X * 256.0 + (double)(u[1] >> 24)) / 16777216.0;
+    *xi2 = ((double)Y * 256.0 + (double)(u[2] >> 24)) / 16777216.0;
+}
+
+/* The uniforms of samples s[i] of n[i] for lobe lobe[i] of point p[i]. */
+void orc_lobe_uniforms(uint64_t seed, const int64_t* p, const int32_t* lobe, const int32_t* s,
+                       const int32_t* n, int64_t count, double* xi1, double* xi2)
+{
+    for (int64_t i = 0; i < count; ++i)
+        sample_uniforms(seed, p[i], lobe[i], s[i], n[i], xi1 + i, xi2 + i);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -589,7 +613,7 @@ int orc_bake(void* sp, const float* pts, const int32_t* ptri, int64_t stride,
                 /* diffuse lobe: cosine-weighted directions, weight 1 */
                 for (int s = 0; s < spp_d; ++s) {
                     double xi1, xi2, l[3], wi[3], R[3], Rl[3], Rh[3];
-                    sample_uniforms(seed, p, 0, s, &xi1, &xi2);
+                    sample_uniforms(seed, p, 0, s, spp_d, &xi1, &xi2);
                     orc_sample_cosine(xi1, xi2, l);
                     to_world(t, b, n, l, wi);
                     if (flags & ORC_WEAK_FURNACE) {
@@ -610,7 +634,7 @@ int orc_bake(void* sp, const float* pts, const int32_t* ptri, int64_t stride,
                     double alpha = sigma[k] * sigma[k];
                     for (int s = 0; s < spp_s; ++s) {
                         double xi1, xi2, l[3], m[3], wi[3], F1 = 0.0;
-                        sample_uniforms(seed, p, 1 + k, s, &xi1, &xi2);
+                        sample_uniforms(seed, p, 1 + k, s, spp_s, &xi1, &xi2);
                         orc_sample_ggx(alpha, xi1, xi2, l);
                         to_world(t, b, n, l, m);
                         double w = spec_weight(alpha, n, wo, cos_o, m, wi, &F1, flags);

@@ -132,6 +132,8 @@ BakeLaunch make_bake_launch(fipt_scene s, const fipt_points* pts, const fipt_bak
     b.out_stride = out->stride;
     b.spp_d = p->spp_d;
     b.spp_s = p->spp_s;
+    b.w_d = stratum_width(p->spp_d);
+    b.w_s = stratum_width(p->spp_s);
     b.K = p->n_levels;
     for (int k = 0; k < FIPT_MAX_LEVELS; ++k) b.sigma[k] = k < p->n_levels ? p->sigma[k] : 1.0f;
     b.seed = p->seed;

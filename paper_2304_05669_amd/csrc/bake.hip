@@ -93,7 +93,7 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sig
         if (active) {
             const int s = lobe == 0 ? q : (q - spp_d) - (lobe - 1) * spp_s;
             float xi1, xi2;
-            dev::lobe_uniforms(b.seed, rng_p, lobe, s, xi1, xi2);
+            dev::lobe_uniforms(b.seed, rng_p, lobe, s, lobe == 0 ? b.w_d : b.w_s, xi1, xi2);
             float sp_, cp_;
             sincospif(2.0f * xi2, &sp_, &cp_);
             if (lobe == 0) {
@@ -320,7 +320,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                         lobe = lobe_of(q, spp_d, spp_s);
                         const int s = lobe == 0 ? q : (q - spp_d) - (lobe - 1) * spp_s;
                         float xi1, xi2;
-                        dev::lobe_uniforms(b.seed, rng_p, lobe, s, xi1, xi2);
+                        dev::lobe_uniforms(b.seed, rng_p, lobe, s, lobe == 0 ? b.w_d : b.w_s, xi1, xi2);
                         float sp_, cp_;
                         sincospif(2.0f * xi2, &sp_, &cp_);
                         bool shoot = false;
@@ -499,6 +499,8 @@ __device__ __forceinline__ BakeLaunch uniform_job(const BakeLaunch& j) {
     b.out_stride = wave_uniform(j.out_stride);
     b.spp_d = u32(j.spp_d);
     b.spp_s = u32(j.spp_s);
+    b.w_d = (uint32_t)u32((int32_t)j.w_d);
+    b.w_s = (uint32_t)u32((int32_t)j.w_s);
     b.K = u32(j.K);
     b.seed = (uint64_t)wave_uniform((int64_t)j.seed);
     b.eps = __int_as_float(u32(__float_as_int(j.eps)));
@@ -556,11 +558,11 @@ __global__ __launch_bounds__(kBlock) void k_cast_rays(DeviceScene sc, const floa
 
 // xi1, xi2 of (point p0 + i / n_samples, lobe, sample i % n_samples).
 __global__ void k_lobe_uniforms(uint64_t seed, int64_t p0, int64_t total, int32_t lobe,
-                                int32_t n_samples, float* out) {
+                                int32_t n_samples, uint32_t w, float* out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     float xi1, xi2;
-    dev::lobe_uniforms(seed, p0 + i / n_samples, lobe, (int)(i % n_samples), xi1, xi2);
+    dev::lobe_uniforms(seed, p0 + i / n_samples, lobe, (int)(i % n_samples), w, xi1, xi2);
     out[i] = xi1;
     out[total + i] = xi2;
 }
@@ -706,7 +708,7 @@ int launch_lobe_uniforms(uint64_t seed, int64_t p0, int64_t n_points, int32_t lo
                          int32_t n_samples, float* out, void* stream) {
     const int64_t total = n_points * n_samples;
     hipLaunchKernelGGL(k_lobe_uniforms, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, seed, p0, total, lobe, n_samples, out);
+                       (hipStream_t)stream, seed, p0, total, lobe, n_samples, stratum_width(n_samples), out);
     return check_launch("lobe_uniforms");
 }
 

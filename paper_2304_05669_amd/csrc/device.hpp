@@ -44,14 +44,33 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// Two uniforms in [0, 1) with 24 significant bits (exact in float).
+// The even bits of x (bit 2i moved to bit i), packed into the low half.
+__device__ __forceinline__ uint32_t even_bits(uint32_t x) {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+
+// The uniforms (xi1, xi2) in [0, 1)^2 of sample s of a lobe's n samples,
+// stratified along the Z-order curve.  With the Philox block u of counter
+// (p low, p high, lobe, s) and w = floor(2^32 / n) (0 standing for 2^32,
+// n = 1), the position on the curve U = s w + floor(u0 w / 2^32) lies in
+// the s-th of n equal segments; the even and odd bits of U give the top 16
+// bits of the two coordinates and the top bytes of u1 and u2 their low 8
+// bits.  Samples with nearby indices get nearby directions, and the
+// estimate is stratified.  Both values have 24 significant bits (exact in
+// float).
 __device__ __forceinline__ void lobe_uniforms(uint64_t seed, int64_t p, int lobe, int s,
-                                              float& xi1, float& xi2) {
+                                              uint32_t w, float& xi1, float& xi2) {
     const uint4 c = make_uint4((uint32_t)(uint64_t)p, (uint32_t)((uint64_t)p >> 32),
                                (uint32_t)lobe, (uint32_t)s);
     const uint4 u = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    xi1 = (float)(u.x >> 8) * (1.0f / 16777216.0f);
-    xi2 = (float)(u.y >> 8) * (1.0f / 16777216.0f);
+    const uint32_t U = w == 0 ? u.x : (uint32_t)s * w + __umulhi(u.x, w);
+    xi1 = (float)((even_bits(U) << 8) | (u.y >> 24)) * (1.0f / 16777216.0f);
+    xi2 = (float)((even_bits(U >> 1) << 8) | (u.z >> 24)) * (1.0f / 16777216.0f);
 }
 
 // ---- shading frame (Duff et al., JCGT 2017), sign from n.z >= 0 ----------

@@ -111,6 +111,12 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
               HostBvh* out);
 
 // ---- kernels (launchers defined in the .hip files) -------------------------
+// Width of each of n equal segments of the 32-bit line, floor(2^32 / n);
+// 0 stands for 2^32 (n = 1).
+inline uint32_t stratum_width(int64_t n) {
+    return n <= 1 ? 0u : (uint32_t)((uint64_t(1) << 32) / (uint64_t)n);
+}
+
 struct DeviceScene {
     const Bvh4Node* nodes;
     const TriGeom* tris;
@@ -148,6 +154,7 @@ struct BakeLaunch {
     float* out;
     int64_t out_stride;
     int32_t spp_d, spp_s, K;
+    uint32_t w_d, w_s;    // stratum widths stratum_width(spp_d), stratum_width(spp_s)
     float sigma[FIPT_MAX_LEVELS];
     uint64_t seed;
     float eps;

@@ -266,8 +266,9 @@ def fipt_cast_rays(scene: Scene, rays: torch.Tensor, want_tuv: bool = True):
 
 def fipt_lobe_uniforms(seed: int, p0: int, n_points: int, lobe: int, n_samples: int,
                        device: int = 0) -> torch.Tensor:
-    """The bake's uniforms for lobe ``lobe``, samples 0..n_samples-1 of the
-    points p0..p0+n_points-1: float32 GPU tensor [2, n_points, n_samples]."""
+    """The bake's stratified uniforms for lobe ``lobe`` with n_samples
+    samples, samples 0..n_samples-1 of the points p0..p0+n_points-1: float32
+    GPU tensor [2, n_points, n_samples]."""
     out = torch.empty((2, n_points, n_samples), dtype=torch.float32, device=torch.device("cuda", device))
     _check(lib().fipt_lobe_uniforms(int(seed) & ((1 << 64) - 1), int(p0), int(n_points), int(lobe),
                                     int(n_samples), _dev(out, torch.float32, "out"), _stream()))

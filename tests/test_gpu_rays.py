@@ -1,7 +1,8 @@
 """The bake's random streams and its ray cast, each checked on its own
-through the C ABI against the oracle: the lobe uniforms bit for bit over
-2^20 counters per lobe (key and point index above 32 bits), and the closest
-hit of 2^16 random rays against brute force over every triangle."""
+through the C ABI against the oracle: the stratified lobe uniforms bit for
+bit over 2^20 counters per case (key and point index above 32 bits), and
+the closest hit of 2^16 random rays against brute force over every
+triangle."""
 import numpy as np
 import pytest
 import torch
@@ -15,21 +16,17 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
 
 
-@pytest.mark.parametrize("lobe", [0, 3, 16])
-def test_lobe_uniforms_bitwise(lobe):
+@pytest.mark.parametrize("lobe,n_s", [(0, 1024), (3, 100), (16, 1)])
+def test_lobe_uniforms_bitwise(lobe, n_s):
     seed = 0x0123456789ABCDEF
     p0 = (1 << 32) - 500                     # the point index crosses into the high word
-    n_pts, n_s = 1024, 1024
+    n_pts = (1 << 20) // n_s
     got = fipt.fipt_lobe_uniforms(seed, p0, n_pts, lobe, n_s).cpu().numpy()
     p = p0 + np.repeat(np.arange(n_pts, dtype=np.int64), n_s)
     s = np.tile(np.arange(n_s, dtype=np.int64), n_pts)
-    ctr = np.stack([p & 0xFFFFFFFF, p >> 32, np.full_like(p, lobe), s], axis=1).astype(np.uint32)
-    key = np.tile(np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint64), (len(p), 1)).astype(np.uint32)
-    u = ob.philox(ctr, key)
-    want1 = ((u[:, 0] >> 8).astype(np.float64) * 2.0 ** -24).astype(np.float32)
-    want2 = ((u[:, 1] >> 8).astype(np.float64) * 2.0 ** -24).astype(np.float32)
-    np.testing.assert_array_equal(got[0].reshape(-1), want1)
-    np.testing.assert_array_equal(got[1].reshape(-1), want2)
+    want1, want2 = ob.lobe_uniforms(seed, p, lobe, s, n_s)
+    np.testing.assert_array_equal(got[0].reshape(-1), want1.astype(np.float32))
+    np.testing.assert_array_equal(got[1].reshape(-1), want2.astype(np.float32))
 
 
 def _mesh():
