@@ -153,8 +153,13 @@ def test_quadrature_matches_monte_carlo(tiny, tiny_oracle, tiny_points):
             qs = ob.quadrature(tiny_oracle, x, n, wo, 0, sigma=s, n_theta=600, n_phi=600)
             for c in range(3):
                 j0, j1 = 3 + 3 * k + c, 3 + 3 * K + 3 * k + c
-                assert abs(qs[c] - r["mean"][j0, q]) < 4.5 * se[j0, q] + 3e-3 * abs(qs[c]) + 1e-9, (p, s, c)
-                assert abs(qs[3 + c] - r["mean"][j1, q]) < 4.5 * se[j1, q] + 3e-3 * abs(qs[3 + c]) + 1e-9, (p, s, c)
+                # the Fresnel part F1 = (1 - wi.m)^5 of a narrow lobe seen near
+                # the normal is carried by rare far-tail half vectors, where the
+                # sample variance understates the error: floor of 1e-6 of the
+                # lobe's total (Ls0 + Ls1) on both parts
+                floor = 1e-6 * (abs(qs[c]) + abs(qs[3 + c])) + 1e-9
+                assert abs(qs[c] - r["mean"][j0, q]) < 4.5 * se[j0, q] + 3e-3 * abs(qs[c]) + floor, (p, s, c)
+                assert abs(qs[3 + c] - r["mean"][j1, q]) < 4.5 * se[j1, q] + 3e-3 * abs(qs[3 + c]) + floor, (p, s, c)
 
 
 def test_deterministic_and_batch_independent(tiny_oracle, tiny_points):
