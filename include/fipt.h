@@ -225,7 +225,7 @@ int fipt_gen_points(fipt_scene s, const fipt_camera* cams, int32_t n_cams,
  * w = G(wi, wo) (wo.m) / ((n.wo)(n.m)) with separable Smith G, F1 =
  * (1 - wi.m)^5, F0 = 1 - F1, and samples with wo.m <= 0 or n.wi <= 0 count
  * as zero.  Each lobe's samples are stratified: the uniforms of sample s
- * come from the s-th of spp equal segments of a Z-order curve over the unit
+ * come from the s-th of spp equal segments of a curve through the unit
  * square (see fipt_lobe_uniforms).  Points with tri < 0 or n.wo = 0 get zeros.  `out` must hold
  * 3 + 6K planes of at least pts->n elements.  Asynchronous on `stream`;
  * allocates nothing: its work counters come from a ring of 16 slots held by
@@ -241,10 +241,12 @@ int fipt_bake(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
  * `seed`, when the lobe has n = n_samples samples.  With u the
  * Philox4x32-10 block of the counter (p low, p high, lobe, s) and
  * W = floor(2^32 / n), the point U = s W + floor(u0 W / 2^32) on the
- * 32-bit line lies in the s-th of n equal segments; read as a Morton code,
- * its even bits give the top 16 bits of xi1 and its odd bits those of xi2,
- * and the top bytes of u1 and u2 give their low 8 bits (each uniform a
- * 24-bit integer times 2^-24).
+ * 32-bit line lies in the s-th of n equal segments.  U's top four bits
+ * pick a cell of the 4 x 4 grid along a Hilbert curve from cell (0, 0) to
+ * cell (3, 0) (first step toward larger xi2); its other 28 bits, read as a
+ * Morton code (even bits to xi1, odd bits to xi2), give the next 14 bits of
+ * each coordinate, and the top bytes of u1 and u2 their low 8 bits (each
+ * uniform a 24-bit integer times 2^-24).
  * out: device float [2][n_points][n_samples] (xi1 block, then xi2 block).
  * For checking the random streams against other implementations;
  * n_points * n_samples must be in [1, 2^31).  Asynchronous on `stream`. */

@@ -80,16 +80,46 @@ void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t
     for (int64_t i = 0; i < n; ++i) philox(ctr + 4 * i, key + 2 * i, out + 4 * i);
 }
 
-/* The two uniforms of sample s of a lobe's n samples, stratified along the
- * Z-order (Morton) curve of the unit square.  The 32-bit line is cut into n
- * segments of width W = floor(2^32 / n); sample s takes the point
+/* Cell (x, y) of a 2^k x 2^k grid at distance d along the Hilbert curve that
+ * starts in cell (0, 0) and ends in cell (2^k - 1, 0): the quadrant of each
+ * level is read from two bits of d, finest level first, and the partial
+ * cell is reflected and transposed as the curve's orientation requires
+ * (the curve of Hilbert 1891, in its common iterative form). */
+static void hilbert_cell(int k, uint32_t d, uint32_t* x, uint32_t* y)
+{
+    uint32_t cx = 0, cy = 0;
+    for (uint32_t side = 1; side < (1u << k); side *= 2) {
+        const uint32_t qx = (d >> 1) & 1u;
+        const uint32_t qy = (d ^ qx) & 1u;
+        if (qy == 0) {
+            if (qx == 1) {
+                cx = side - 1 - cx;
+                cy = side - 1 - cy;
+            }
+            const uint32_t t = cx;
+            cx = cy;
+            cy = t;
+        }
+        cx += side * qx;
+        cy += side * qy;
+        d >>= 2;
+    }
+    *x = cx;
+    *y = cy;
+}
+
+/* The two uniforms of sample s of a lobe's n samples, stratified along a
+ * curve through the unit square.  The 32-bit line is cut into n segments
+ * of width W = floor(2^32 / n); sample s takes the point
  * U = s W + floor(u0 W / 2^32) of its own segment (u the Philox block of the
- * counter (p low, p high, lobe, s)).  Read as a Morton code, U names a cell
- * of a 2^16 x 2^16 grid: its bit 2i is bit i of the column X, its bit 2i + 1
- * bit i of the row Y.  A point inside the cell comes from the top bytes of
- * u1 and u2: xi1 = (256 X + (u1 >> 24)) / 2^24, xi2 = (256 Y + (u2 >> 24)) /
- * 2^24.  The segments tile [0, nW), all but less than n / 2^32 of the
- * square, so the estimate is stratified and unbiased up to that sliver. */
+ * counter (p low, p high, lobe, s)).  The top four bits of U pick a cell of
+ * the 4 x 4 grid along the Hilbert curve; the other 28 bits, read as a
+ * Morton code (bit 2i to the column, bit 2i + 1 to the row), place the
+ * point inside that cell on a 2^14 x 2^14 grid.  A point inside the finest
+ * cell comes from the top bytes of u1 and u2, so each coordinate has 24
+ * bits: xi1 = (2^8 X + (u1 >> 24)) / 2^24, xi2 = (2^8 Y + (u2 >> 24)) / 2^24.
+ * The segments tile [0, nW), all but less than n / 2^32 of the square, so
+ * the estimate is stratified and unbiased up to that sliver. */
 static void sample_uniforms(uint64_t seed, int64_t p, int lobe, int s, int n,
                             double* xi1, double* xi2)
 {
@@ -100,8 +130,10 @@ static void sample_uniforms(uint64_t seed, int64_t p, int lobe, int s, int n,
     philox(c, k, u);
     const uint64_t W = ((uint64_t)1 << 32) / (uint64_t)n;
     const uint64_t U = (uint64_t)s * W + (((uint64_t)u[0] * W) >> 32);
-    uint32_t X = 0, Y = 0;
-    for (int i = 0; i < 16; ++i) {
+    uint32_t cx, cy;
+    hilbert_cell(2, (uint32_t)(U >> 28), &cx, &cy);
+    uint32_t X = cx << 14, Y = cy << 14;
+    for (int i = 0; i < 14; ++i) {
         X |= (uint32_t)((U >> (2 * i)) & 1u) << i;
         Y |= (uint32_t)((U >> (2 * i + 1)) & 1u) << i;
     }

@@ -55,22 +55,29 @@ __device__ __forceinline__ uint32_t even_bits(uint32_t x) {
 }
 
 // The uniforms (xi1, xi2) in [0, 1)^2 of sample s of a lobe's n samples,
-// stratified along the Z-order curve.  With the Philox block u of counter
-// (p low, p high, lobe, s) and w = floor(2^32 / n) (0 standing for 2^32,
-// n = 1), the position on the curve U = s w + floor(u0 w / 2^32) lies in
-// the s-th of n equal segments; the even and odd bits of U give the top 16
-// bits of the two coordinates and the top bytes of u1 and u2 their low 8
-// bits.  Samples with nearby indices get nearby directions, and the
-// estimate is stratified.  Both values have 24 significant bits (exact in
-// float).
+// stratified along a curve over the unit square.  With the Philox block u
+// of counter (p low, p high, lobe, s) and w = floor(2^32 / n) (0 standing
+// for 2^32, n = 1), the position U = s w + floor(u0 w / 2^32) lies in the
+// s-th of n equal segments of the 32-bit line.  U's top four bits number
+// the cells of the 4 x 4 grid along a Hilbert curve (table: cell d is the
+// nibble d of 0x3267BFEA9DC84510, column in its low two bits, row in the
+// high two); the other 28 bits, read as a Morton code, place the point in
+// that cell (14 bits per axis); the top bytes of u1 and u2 give the low 8
+// bits of the two 24-bit results.  Samples with nearby indices get nearby
+// directions (the Hilbert order has no jump across the square), and the
+// estimate is stratified.  Both values are exact in float.
 __device__ __forceinline__ void lobe_uniforms(uint64_t seed, int64_t p, int lobe, int s,
                                               uint32_t w, float& xi1, float& xi2) {
     const uint4 c = make_uint4((uint32_t)(uint64_t)p, (uint32_t)((uint64_t)p >> 32),
                                (uint32_t)lobe, (uint32_t)s);
     const uint4 u = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     const uint32_t U = w == 0 ? u.x : (uint32_t)s * w + __umulhi(u.x, w);
-    xi1 = (float)((even_bits(U) << 8) | (u.y >> 24)) * (1.0f / 16777216.0f);
-    xi2 = (float)((even_bits(U >> 1) << 8) | (u.z >> 24)) * (1.0f / 16777216.0f);
+    const uint32_t d = U >> 28;
+    const uint32_t cell = ((d < 8 ? 0x9DC84510u : 0x3267BFEAu) >> ((d & 7u) * 4u)) & 15u;
+    const uint32_t X = ((cell & 3u) << 14) | even_bits(U & 0x0FFFFFFFu);
+    const uint32_t Y = ((cell >> 2) << 14) | even_bits((U >> 1) & 0x07FFFFFFu);
+    xi1 = (float)((X << 8) | (u.y >> 24)) * (1.0f / 16777216.0f);
+    xi2 = (float)((Y << 8) | (u.z >> 24)) * (1.0f / 16777216.0f);
 }
 
 // ---- shading frame (Duff et al., JCGT 2017), sign from n.z >= 0 ----------
