@@ -54,11 +54,23 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_lobe_uniforms(1, 0, 1 << 16, 0, 1 << 15, 1, None) == fipt.EINVAL
 
 
-@pytest.mark.parametrize("name", ["tiny", "room", "degenerate", "skewed"])
+# (scale, offset) applied to the room: the 4-wide nodes store bounds as
+# half-precision offsets in units of one power of two for the whole tree, so
+# the validator's enclosure check runs at extreme scales and far from the origin
+FRAMES = {"room_far": (1.0, 1.0e6), "room_huge": (1.0e30, 0.0), "room_micro": (1.0e-30, 0.0),
+          "room_far_small": (1.0e-3, 5.0e3)}
+
+
+@pytest.mark.parametrize("name", ["tiny", "room", "degenerate", "skewed"] + list(FRAMES))
 def test_bvh_builder_invariants(name):
     if name == "tiny":
         sc = synth.tiny_box()
         v, t = sc.verts, sc.tris
+    elif name in FRAMES:
+        scale, offset = FRAMES[name]
+        sc = synth.room(n_cams=1, width=2, height=2)
+        v = (sc.verts.astype(np.float64) * scale + offset).astype(np.float32)
+        t = sc.tris
     elif name == "room":
         sc = synth.room(n_cams=1, width=2, height=2)
         v, t = sc.verts, sc.tris

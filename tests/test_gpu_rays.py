@@ -40,8 +40,21 @@ def _mesh():
     return verts, tris
 
 
-def test_cast_rays_match_brute_force():
+# (scale, offset): the mesh and ray origins are mapped by x -> scale x + offset,
+# so the node bounds' single exponent and origins are exercised far from the
+# unit cube (large coordinates with small extents, and a sub-millimetre scene)
+TRANSFORMS = {
+    "unit": (1.0, (0.0, 0.0, 0.0)),
+    "far": (1000.0, (2.0e4, -3.0e4, 1.0e4)),
+    "small": (1.0e-4, (1.0e-4, 3.0e-4, -2.0e-4)),
+}
+
+
+@pytest.mark.parametrize("frame", list(TRANSFORMS))
+def test_cast_rays_match_brute_force(frame):
+    scale, offset = TRANSFORMS[frame]
     verts, tris = _mesh()
+    verts = (verts.astype(np.float64) * scale + np.array(offset)).astype(np.float32)
     rng = np.random.Generator(np.random.PCG64(77))
     n = 1 << 16
     o = rng.uniform(0.02, 0.98, size=(n, 3))
@@ -52,6 +65,7 @@ def test_cast_rays_match_brute_force():
     # a few rays from outside the box, pointing away from it: misses
     o[-256:] = rng.uniform(1.5, 2.0, size=(256, 3))
     d[-256:] = np.abs(d[-256:]) + 0.1
+    o = o * scale + np.array(offset)
     o32, d32 = o.astype(np.float32), d.astype(np.float32)
     scene = fipt.Scene(verts, tris, device=0)
     try:
@@ -65,17 +79,19 @@ def test_cast_rays_match_brute_force():
     sc = synth.Scene(name="rays", verts=verts, tris=tris, cache_kind="triangle",
                      cache=np.zeros((3, len(tris)), np.float32),
                      emission=np.zeros((3, len(tris)), np.float32))
-    osc = ob.OracleScene(sc)
+    # the oracle's ambiguity band tol_rel (1 + t) is sized for unit scenes:
+    # scale it with a smaller scene so it covers the same relative width
+    osc = ob.OracleScene(sc, tol_rel=1e-5 * min(scale, 1.0))
     w_tri, w_t, w_b, n_cand = ob.cast(osc, o32.astype(np.float64), d32.astype(np.float64))
     assert (tri[-256:] == -1).all() and (w_tri[-256:] == -1).all()
     clear = n_cand <= 1
     assert clear.mean() > 0.995
     np.testing.assert_array_equal(tri[clear], w_tri[clear])
     hit = clear & (w_tri >= 0)
-    np.testing.assert_allclose(tuv[0, hit], w_t[hit], rtol=2e-5, atol=1e-6)
+    np.testing.assert_allclose(tuv[0, hit], w_t[hit], rtol=2e-5, atol=1e-6 * scale)
     np.testing.assert_allclose(tuv[1, hit], w_b[hit, 0], atol=2e-4)
     np.testing.assert_allclose(tuv[2, hit], w_b[hit, 1], atol=2e-4)
     # inside the tie band the GPU still reports a hit of similar distance
     amb = ~clear
     assert (tri[amb] >= 0).all()
-    np.testing.assert_allclose(tuv[0, amb], w_t[amb], rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(tuv[0, amb], w_t[amb], rtol=1e-3, atol=1e-5 * scale)
