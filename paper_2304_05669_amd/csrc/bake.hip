@@ -29,8 +29,11 @@ using dev::v3;
 
 constexpr int kBlock = 64;              // one wavefront: a finished wave frees its LDS at once
 constexpr int kWaves = kBlock / 64;
-// persistent grids: two rounds of the 16 wavefronts a CU holds at once
-constexpr int kGridWavesPerCu = 32;
+// persistent grids: one round of the 20 wavefronts a CU holds at once (5
+// per SIMD at 96 VGPRs, 8 KB of LDS each); points are handed out
+// dynamically, so a larger grid only queues workgroups, and the server's
+// back-to-back launches on two streams then crowd each other
+constexpr int kGridWavesPerCu = 20;
 
 // Lobe of flattened sample q: 0 for the first spp_d (diffuse) samples, then
 // 1 + (q - spp_d) / spp_s.  The quotient is below 17 and r < 2^20 (spp <=
@@ -713,7 +716,7 @@ int launch_lobe_uniforms(uint64_t seed, int64_t p0, int64_t n_points, int32_t lo
 }
 
 int launch_bake(const BakeLaunch& b, int32_t* counters, uint64_t* stats, void* stream) {
-    // persistent grid: up to two rounds of resident workgroups, a multiple
+    // persistent grid: up to one round of resident workgroups, a multiple
     // of kXcdCount so every XCD gets the same number of workgroups
     const int64_t want = (b.n + kWaves - 1) / kWaves;
     int64_t blocks = std::min(want, (int64_t)device_cus() * kGridWavesPerCu / kWaves);
