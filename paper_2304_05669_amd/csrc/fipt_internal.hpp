@@ -197,17 +197,13 @@ struct GridPlanDev {
     int64_t n_seg;
     int32_t* cell_seg;      // [n_cell + 1] ranges of each occupied cell's segments
     int64_t n_cell;
-    int32_t* node_id;       // [n_act] active node linear index
-    int32_t* node_start;    // [n_act + 1] ranges into node_src
-    int32_t* node_src;      // [entries] (occupied cell index << 3) | corner
+    uint64_t* node_mask;    // [ceil(res^3 / 64)] bit v & 63 of word v >> 6: node v is active
+    int32_t* node_rank;     // [ceil(res^3 / 64)] active nodes before each mask word
+    int32_t* node_start;    // [n_act + 1] ranges into node_src, active nodes in index order
+    int32_t* node_src;      // [entries] (segment index << 3) | corner, 8 per segment
     int64_t n_act;
     float* pos;             // [3][n_points] positions in sorted (perm) order
-    double* seg_part;       // [n_seg][8][channels] scratch (room for 8 channels)
-    double* cell_part;      // [n_cell][8][channels] scratch
-    int32_t* seg_row;       // [n_seg] where a segment's partials go: row of cell_part if
-                            // its cell has one segment, else -1 - (its row of seg_part)
-    int32_t* multi_cell;    // [n_multi] occupied cells with two or more segments
-    int64_t n_multi;
+    double* seg_part;       // [8 corners][n_seg][channels] scratch (room for 8 channels)
     float* gp_rec;          // [n_points][8] scratch: per-point gradient records
 };
 int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_t gp_stride,

@@ -6,11 +6,12 @@
 // the per-point gradient planes are first copied into 32-byte records (so
 // the cell-ordered pass reads one line per point, not one per channel);
 // every segment sums weight * gradient of its points into the eight corners
-// of its cell (points in index order), straight into the cell's partials
-// when the cell has a single segment; every cell with several segments sums
-// them (in order); and every node next to an occupied cell sums the corner
-// partials of at most eight cells (in order).  The result is bitwise
-// reproducible.
+// of its cell (points in index order); and every grid node sums, for each
+// occupied cell it is a corner of (in cell order), that cell's segment
+// partials (in order), writing zero where no cell contributes.  The plan
+// lists each node's contributions as (segment, corner) pairs, and a node
+// finds its list through a bit mask of the active nodes with a prefix count
+// per 64 nodes.  The result is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,10 +34,9 @@ namespace {
 
 void plan_free(fipt_grid_plan p) {
     if (!p) return;
-    void* ptrs[] = {p->d.perm,      p->d.seg_start, p->d.seg_cell, p->d.cell_seg,
-                    p->d.node_id,   p->d.node_start, p->d.node_src, p->d.pos,
-                    p->d.seg_part,  p->d.cell_part, p->d.seg_row,  p->d.multi_cell,
-                    p->d.gp_rec};
+    void* ptrs[] = {p->d.perm,       p->d.seg_start, p->d.seg_cell, p->d.cell_seg,
+                    p->d.node_mask,  p->d.node_rank, p->d.node_start, p->d.node_src,
+                    p->d.pos,        p->d.seg_part,  p->d.gp_rec};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -111,17 +111,10 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     cell_seg.push_back((int32_t)seg_cell.size());
     const int64_t S = (int64_t)seg_cell.size();
     const int64_t M = (int64_t)cell_id.size();
-    // a cell with one segment takes its partials straight from pass 1
-    std::vector<int32_t> seg_row(S), multi_cell;
-    for (int64_t m = 0; m < M; ++m) {
-        const int32_t g0 = cell_seg[m], g1 = cell_seg[m + 1];
-        if (g1 - g0 == 1) {
-            seg_row[g0] = (int32_t)m;
-        } else {
-            multi_cell.push_back((int32_t)m);
-            for (int32_t g = g0; g < g1; ++g) seg_row[g] = -1 - g;
-        }
-    }
+    // node lists index their entries with 32 bits: eight per segment, each
+    // entry holding the segment index and the corner in 32 bits
+    if (8 * S >= (int64_t(1) << 31))
+        return fail(FIPT_EINVAL, "%lld segments: too many for one plan", (long long)S);
     std::vector<std::pair<int64_t, int32_t>> nk;
     nk.reserve(8 * M);
     for (int64_t m = 0; m < M; ++m) {
@@ -133,15 +126,24 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
         }
     }
     std::sort(nk.begin(), nk.end());
-    std::vector<int32_t> node_id, node_start, node_src(nk.size());
+    const int64_t n_nodes = (int64_t)res * res * res;
+    const int64_t n_words = (n_nodes + 63) / 64;
+    std::vector<uint64_t> node_mask(n_words, 0);
+    // each node's list: for every occupied cell it is a corner of (cell
+    // order), that cell's segments (segment order), as (segment << 3) | corner
+    std::vector<int32_t> node_rank(n_words, 0), node_start, node_src;
+    node_src.reserve(8 * S);
     for (size_t e = 0; e < nk.size(); ++e) {
-        node_src[e] = nk[e].second;
         if (e == 0 || nk[e].first != nk[e - 1].first) {
-            node_start.push_back((int32_t)e);
-            node_id.push_back((int32_t)nk[e].first);
+            node_start.push_back((int32_t)node_src.size());
+            node_mask[nk[e].first >> 6] |= uint64_t(1) << (nk[e].first & 63);
         }
+        const int32_t m = nk[e].second >> 3, corner = nk[e].second & 7;
+        for (int32_t g = cell_seg[m]; g < cell_seg[m + 1]; ++g) node_src.push_back((g << 3) | corner);
     }
-    node_start.push_back((int32_t)nk.size());
+    node_start.push_back((int32_t)node_src.size());
+    for (int64_t w = 1; w < n_words; ++w)
+        node_rank[w] = node_rank[w - 1] + __builtin_popcountll(node_mask[w - 1]);
     // positions stored in sorted order: the adjoint reads them contiguously
     std::vector<float> pcopy(3 * n);
     for (int k = 0; k < 3; ++k)
@@ -162,30 +164,26 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     }
     d.n_seg = S;
     d.n_cell = M;
-    d.n_multi = (int64_t)multi_cell.size();
-    d.n_act = (int64_t)node_id.size();
+    d.n_act = (int64_t)node_start.size() - 1;
     int rc;
     if ((rc = upload(&d.perm, perm, &p->bytes)) || (rc = upload(&d.seg_start, seg_start, &p->bytes)) ||
         (rc = upload(&d.seg_cell, seg_cell, &p->bytes)) || (rc = upload(&d.cell_seg, cell_seg, &p->bytes)) ||
-        (rc = upload(&d.node_id, node_id, &p->bytes)) ||
+        (rc = upload(&d.node_mask, node_mask, &p->bytes)) ||
+        (rc = upload(&d.node_rank, node_rank, &p->bytes)) ||
         (rc = upload(&d.node_start, node_start, &p->bytes)) ||
-        (rc = upload(&d.node_src, node_src, &p->bytes)) || (rc = upload(&d.pos, pcopy, &p->bytes)) ||
-        (rc = upload(&d.seg_row, seg_row, &p->bytes)) ||
-        (rc = upload(&d.multi_cell, multi_cell, &p->bytes))) {
+        (rc = upload(&d.node_src, node_src, &p->bytes)) || (rc = upload(&d.pos, pcopy, &p->bytes))) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return rc;
     }
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&d.seg_part), sizeof(double) * 64 * std::max<int64_t>(S, 1));
-    if (e == hipSuccess)
-        e = hipMalloc(reinterpret_cast<void**>(&d.cell_part), sizeof(double) * 64 * std::max<int64_t>(M, 1));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.gp_rec), sizeof(float) * 8 * n);
     if (e != hipSuccess) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return fail(FIPT_ENOMEM, "hipMalloc partials: %s", hipGetErrorString(e));
     }
-    p->bytes += (int64_t)(sizeof(double) * 64 * (S + M) + sizeof(float) * 8 * n);
+    p->bytes += (int64_t)(sizeof(double) * 64 * S + sizeof(float) * 8 * n);
     if (prev >= 0) (void)hipSetDevice(prev);
     *out = p;
     return FIPT_OK;

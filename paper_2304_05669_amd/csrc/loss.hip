@@ -238,9 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_segments(GridPlanDev plan, G
             }
         }
     }
-    const int32_t row = plan.seg_row[m];
-    double* dst = row >= 0 ? plan.cell_part + ((int64_t)row * 8 + corner) * C
-                           : plan.seg_part + ((int64_t)(-1 - row) * 8 + corner) * C;
+    double* dst = plan.seg_part + ((int64_t)corner * plan.n_seg + m) * C;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) dst[ch] = acc[ch];
 }
@@ -261,40 +259,44 @@ __global__ __launch_bounds__(kBlock) void k_scatter_records(const float* __restr
     r[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
-// Adjoint, pass 2: per occupied cell with several segments and corner, the
-// sum of its segments' partials in order.
-__global__ __launch_bounds__(kBlock) void k_scatter_combine(GridPlanDev plan, int C) {
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t i = tid >> 3;
-    const int corner = (int)(tid & 7);
-    if (i >= plan.n_multi) return;
-    const int64_t m = plan.multi_cell[i];
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t g = plan.cell_seg[m]; g < plan.cell_seg[m + 1]; ++g) {
-        const double* pp = plan.seg_part + ((int64_t)g * 8 + corner) * C;
-        for (int ch = 0; ch < C; ++ch) s[ch] += pp[ch];
-    }
-    double* dst = plan.cell_part + (m * 8 + corner) * C;
-    for (int ch = 0; ch < C; ++ch) dst[ch] = s[ch];
-}
-
-// Adjoint, pass 3: per active node, the sum of at most eight cell partials
-// in the plan's fixed order.
-__global__ __launch_bounds__(kBlock) void k_scatter_nodes(GridPlanDev plan, int C,
-                                                          const double* __restrict__ part,
-                                                          float* __restrict__ out) {
-    const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (a >= plan.n_act) return;
+// Adjoint, pass 2: per grid node, the partials of its (segment, corner)
+// list -- every occupied cell it is a corner of, in the plan's cell order,
+// and that cell's segments in order; nodes next to no occupied cell get
+// zero, so the whole gradient grid is written in one pass.  Four entries
+// and their partials are fetched together, then added in order.
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_scatter_grid(GridPlanDev plan, float* __restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t R = plan.res;
     const int64_t plane = R * R * R;
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t e = plan.node_start[a]; e < plan.node_start[a + 1]; ++e) {
-        const int32_t src = plan.node_src[e];
-        const double* pp = part + ((int64_t)(src >> 3) * 8 + (src & 7)) * C;
-        for (int ch = 0; ch < C; ++ch) s[ch] += pp[ch];
+    if (v >= plane) return;
+    double s[C];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) s[ch] = 0.0;
+    const uint64_t word = plan.node_mask[v >> 6];
+    const uint64_t bit = uint64_t(1) << (v & 63);
+    if (word & bit) {
+        const int64_t a = plan.node_rank[v >> 6] + __popcll(word & (bit - 1));
+        const int32_t e0 = plan.node_start[a], e1 = plan.node_start[a + 1];
+        for (int32_t e = e0; e < e1; e += 4) {
+            double pv[4][C];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t src = plan.node_src[min(e + u, e1 - 1)];
+                const double* pp = plan.seg_part + ((int64_t)(src & 7) * plan.n_seg + (src >> 3)) * C;
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) pv[u][ch] = pp[ch];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e + u < e1) {
+#pragma unroll
+                    for (int ch = 0; ch < C; ++ch) s[ch] += pv[u][ch];
+                }
+        }
     }
-    const int32_t node = plan.node_id[a];
-    for (int ch = 0; ch < C; ++ch) out[ch * plane + node] = (float)s[ch];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) out[ch * plane + v] = (float)s[ch];
 }
 
 __global__ void k_scale_by(const float* __restrict__ x, int64_t n, const double* __restrict__ f,
@@ -303,10 +305,6 @@ __global__ void k_scale_by(const float* __restrict__ x, int64_t n, const double*
     if (i < n) out[i] = (float)((double)x[i] * f[0]);
 }
 
-__global__ void k_fill_zero(float* p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) p[i] = 0.0f;
-}
 
 int check(const char* what) {
     hipError_t e = hipGetLastError();
@@ -388,37 +386,35 @@ int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_
                         float* grad_grid, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     const GridFrame g = make_frame(p.bmin, p.bmax, p.res);
-    const int64_t total = (int64_t)C * p.res * p.res * p.res;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, st, grad_grid, total);
-    int rc = check("grid_scatter fill");
-    if (rc) return rc;
-    if (p.n_seg == 0) return FIPT_OK;
-    const unsigned rb = (unsigned)((p.n_points + kBlock - 1) / kBlock);
-    const unsigned cb = (unsigned)((8 * p.n_seg + kBlock - 1) / kBlock);
-    switch (C) {
+    if (C < 1 || C > 8) return fail(FIPT_EINVAL, "channels must be in [1, 8]");
+    if (p.n_seg > 0) {
+        const unsigned rb = (unsigned)((p.n_points + kBlock - 1) / kBlock);
+        const unsigned cb = (unsigned)((8 * p.n_seg + kBlock - 1) / kBlock);
+        switch (C) {
 #define FIPT_SC(N)                                                                                \
     case N:                                                                                       \
         hipLaunchKernelGGL(k_scatter_records<N>, dim3(rb), dim3(kBlock), 0, st, gp, gs, p.n_points, \
                            p.gp_rec);                                                             \
         hipLaunchKernelGGL(k_scatter_segments<N>, dim3(cb), dim3(kBlock), 0, st, p, g);            \
         break
-        FIPT_SC(1); FIPT_SC(2); FIPT_SC(3); FIPT_SC(4);
-        FIPT_SC(5); FIPT_SC(6); FIPT_SC(7); FIPT_SC(8);
+            FIPT_SC(1); FIPT_SC(2); FIPT_SC(3); FIPT_SC(4);
+            FIPT_SC(5); FIPT_SC(6); FIPT_SC(7); FIPT_SC(8);
 #undef FIPT_SC
-        default: return fail(FIPT_EINVAL, "channels must be in [1, 8]");
-    }
-    rc = check("grid_scatter segments");
-    if (rc) return rc;
-    if (p.n_multi > 0) {
-        hipLaunchKernelGGL(k_scatter_combine, dim3((unsigned)((8 * p.n_multi + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, st, p, C);
-        rc = check("grid_scatter cells");
+        }
+        const int rc = check("grid_scatter segments");
         if (rc) return rc;
     }
-    if (p.n_act == 0) return FIPT_OK;
-    hipLaunchKernelGGL(k_scatter_nodes, dim3((unsigned)((p.n_act + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, st, p, C, (const double*)p.cell_part, grad_grid);
+    const int64_t nodes = (int64_t)p.res * p.res * p.res;
+    const dim3 nb((unsigned)((nodes + kBlock - 1) / kBlock));
+    switch (C) {
+#define FIPT_SG(N)                                                                           \
+    case N:                                                                                  \
+        hipLaunchKernelGGL(k_scatter_grid<N>, nb, dim3(kBlock), 0, st, p, grad_grid);        \
+        break
+        FIPT_SG(1); FIPT_SG(2); FIPT_SG(3); FIPT_SG(4);
+        FIPT_SG(5); FIPT_SG(6); FIPT_SG(7); FIPT_SG(8);
+#undef FIPT_SG
+    }
     return check("grid_scatter nodes");
 }
 

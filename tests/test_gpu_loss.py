@@ -131,6 +131,26 @@ def test_grid_scatter_parity_and_determinism():
     assert_close_rel(got.cpu().numpy().reshape(5, -1), want.reshape(5, -1), 1e-5, what="grid scatter")
 
 
+@pytest.mark.parametrize("n,C,R", [(1, 1, 2), (7, 3, 5), (4099, 8, 17), (60000, 2, 64)])
+def test_grid_scatter_writes_every_node(n, C, R):
+    """The adjoint writes the whole gradient grid (zero where no point
+    contributes), so an output buffer full of NaN comes back finite and equal
+    to the oracle's scatter, for any channel count."""
+    bmin = np.array([-1.0, 0.0, 2.0], np.float32)
+    bmax = np.array([1.0, 3.0, 2.5], np.float32)
+    rng = np.random.default_rng(n + C)
+    pos = (bmin[:, None] + rng.uniform(-0.1, 1.1, size=(3, n)) * (bmax - bmin)[:, None]).astype(np.float32)
+    gp = rng.standard_normal((C, n)).astype(np.float32)
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    out = torch.full((C, R, R, R), float("nan"), dtype=torch.float32, device=DEV)
+    got = plan.scatter(_t(gp), out=out)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().reshape(C, -1)
+    assert np.isfinite(got).all()
+    want = orr.grid_scatter(gp, pos, bmin, bmax, R)
+    assert_close_rel(got, want.reshape(C, -1), 1e-5, what="grid scatter")
+
+
 def test_grid_gather_autograd_end_to_end():
     """Loss of the factored render with the material read from a grid:
     d loss / d grid through GridGather + FactoredLoss equals the oracle's
