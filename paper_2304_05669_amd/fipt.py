@@ -152,6 +152,14 @@ def _dev(t: torch.Tensor, dtype, name: str) -> int:
     return t.data_ptr()
 
 
+def _need(t: torch.Tensor, shape, name: str):
+    """Reject a caller buffer whose shape differs from what the kernel writes
+    or reads (the C entry points take bare pointers)."""
+    if not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(shape):
+        got = tuple(t.shape) if isinstance(t, torch.Tensor) else type(t).__name__
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {got}")
+
+
 def _f32_array(v, n):
     a = (C.c_float * n)()
     for i, x in enumerate(v):
@@ -348,10 +356,15 @@ def fipt_render_loss(shading: torch.Tensor, material: torch.Tensor, observed: to
     dev = material.device
     if loss_buf is None:
         loss_buf = torch.empty((LOSS_SLOTS,), dtype=torch.float64, device=dev)
+    _need(loss_buf, (LOSS_SLOTS,), "loss_buf")
     if want_grad and grad is None:
         grad = torch.empty((5, n), dtype=torch.float32, device=dev)
+    if want_grad:
+        _need(grad, (5, n), "grad")
     if want_lr and lr is None:
         lr = torch.empty((3, n), dtype=torch.float32, device=dev)
+    if want_lr:
+        _need(lr, (3, n), "lr")
     sh = Shading(_dev(shading, torch.float32, "shading"), n)
     sig = _f32_array(sigma, K)
     _check(lib().fipt_render_loss(
@@ -367,6 +380,8 @@ def fipt_scale_by(x: torch.Tensor, factor: torch.Tensor, out: torch.Tensor = Non
     """out = x * factor[0] (factor: one float64 on the GPU) in a HIP kernel."""
     if out is None:
         out = torch.empty_like(x)
+    _need(out, x.shape, "out")
+    _need(factor, (1,), "factor")
     _check(lib().fipt_scale_by(_dev(x, torch.float32, "x"), x.numel(),
                                _dev(factor, torch.float64, "factor"),
                                _dev(out, torch.float32, "out"), _stream()))
@@ -396,10 +411,15 @@ class FactoredLoss(torch.autograd.Function):
 # --------------------------------------------------------------------------
 def fipt_grid_gather(grid: torch.Tensor, bmin, bmax, pos: torch.Tensor, out: torch.Tensor = None):
     """grid [C, R, R, R] float32 GPU (x fastest), pos [3, n] -> [C, n]."""
+    if grid.dim() != 4 or not (grid.shape[1] == grid.shape[2] == grid.shape[3]):
+        raise ValueError(f"grid must be [C, R, R, R], got {tuple(grid.shape)}")
+    if pos.dim() != 2 or pos.shape[0] != 3:
+        raise ValueError(f"pos must be [3, n], got {tuple(pos.shape)}")
     Cn, R = grid.shape[0], grid.shape[1]
     n = pos.shape[1]
     if out is None:
         out = torch.empty((Cn, n), dtype=torch.float32, device=grid.device)
+    _need(out, (Cn, n), "out")
     _check(lib().fipt_grid_gather(_dev(grid, torch.float32, "grid"), Cn, R, _f32_array(bmin, 3),
                                   _f32_array(bmax, 3), _dev(pos, torch.float32, "pos"), n, n,
                                   _dev(out, torch.float32, "out"), n, _stream()))
@@ -420,10 +440,13 @@ class GridPlan:
         self.handle = h
 
     def scatter(self, grad_points: torch.Tensor, out: torch.Tensor = None):
+        if grad_points.dim() != 2 or grad_points.shape[1] < self.n:
+            raise ValueError(f"grad_points must be [C, >= {self.n}], got {tuple(grad_points.shape)}")
         Cn = grad_points.shape[0]
         if out is None:
             out = torch.empty((Cn, self.res, self.res, self.res), dtype=torch.float32,
                               device=grad_points.device)
+        _need(out, (Cn, self.res, self.res, self.res), "out")
         _check(lib().fipt_grid_scatter(self.handle, _dev(grad_points, torch.float32, "grad_points"),
                                        Cn, grad_points.shape[1], _dev(out, torch.float32, "out"),
                                        _stream()))

@@ -107,3 +107,27 @@ def test_bvh_rejects_bad_meshes():
         fipt.fipt_bvh_validate(v2, np.array([[0, 1, 2]], np.int32))
     with pytest.raises(fipt.FiptError):
         fipt.fipt_bvh_validate(v, np.zeros((0, 3), np.int32))
+
+
+def test_binding_rejects_misshapen_buffers():
+    """The C entry points take bare pointers, so the binding checks the shape
+    of every caller buffer before anything reaches the device."""
+    import torch
+    z = torch.zeros
+    with pytest.raises(ValueError):
+        fipt.fipt_grid_gather(z(5, 4, 4, 3), [0, 0, 0], [1, 1, 1], z(3, 10))
+    with pytest.raises(ValueError):
+        fipt.fipt_grid_gather(z(5, 4, 4, 4), [0, 0, 0], [1, 1, 1], z(2, 10))
+    with pytest.raises(ValueError):
+        fipt.fipt_grid_gather(z(5, 4, 4, 4), [0, 0, 0], [1, 1, 1], z(3, 10), out=z(5, 9))
+    K = 6
+    sh, mat, obs = z(3 + 6 * K, 10), z(5, 10), z(3, 10)
+    sig = [0.02, 0.1, 0.25, 0.5, 0.75, 1.0]
+    with pytest.raises(ValueError):
+        fipt.fipt_render_loss(sh, mat, obs, sig, grad=z(5, 9))
+    with pytest.raises(ValueError):
+        fipt.fipt_render_loss(sh, mat, obs, sig, want_lr=True, lr=z(3, 11))
+    with pytest.raises(ValueError):
+        fipt.fipt_render_loss(sh, mat, obs, sig, loss_buf=torch.zeros(1, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        fipt.fipt_scale_by(z(10), torch.zeros(1, dtype=torch.float64), out=z(9))

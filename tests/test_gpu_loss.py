@@ -151,6 +151,16 @@ def test_grid_scatter_writes_every_node(n, C, R):
     assert_close_rel(got, want.reshape(C, -1), 1e-5, what="grid scatter")
 
 
+def test_grid_scatter_rejects_misshapen_buffers():
+    pos = np.random.default_rng(3).uniform(0, 1, size=(3, 100)).astype(np.float32)
+    plan = fipt.GridPlan(pos, 8, np.zeros(3, np.float32), np.ones(3, np.float32))
+    gp = torch.zeros((5, 100), dtype=torch.float32, device=DEV)
+    with pytest.raises(ValueError):
+        plan.scatter(gp, out=torch.zeros((5, 8, 8, 7), dtype=torch.float32, device=DEV))
+    with pytest.raises(ValueError):
+        plan.scatter(gp[:, :99].contiguous())
+
+
 def test_grid_gather_autograd_end_to_end():
     """Loss of the factored render with the material read from a grid:
     d loss / d grid through GridGather + FactoredLoss equals the oracle's
