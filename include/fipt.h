@@ -301,7 +301,9 @@ int fipt_grid_gather(const float* grid, int32_t channels, int32_t res,
 /* Adjoint of fipt_grid_gather for a fixed point set.  The plan sorts the
  * points by grid cell once (host positions pos_host[3][n]) so the adjoint
  * sums every node's contributions in a fixed order: results are bitwise
- * reproducible, with no atomics.  The plan owns device memory. */
+ * reproducible, with no atomics.  The plan owns device memory.
+ * 1 <= n < 2^31, 2 <= res <= 1024; FIPT_EINVAL also when the sorted points
+ * make 2^28 or more segments (runs of at most 48 points of one cell). */
 int fipt_grid_plan_create(const float* pos_host, int64_t n, int32_t res,
                           const float* bmin_host, const float* bmax_host,
                           int32_t device, fipt_grid_plan* out);
