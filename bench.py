@@ -105,8 +105,10 @@ def setup_room(sc, dev):
 
 def traversal_bytes(scene, planes, tri, sc, out):
     """Algorithmic bytes of one bake launch, from the instrumented kernel:
-    128 B per 4-wide BVH node fetched, 48 B per triangle tested, 48 B radiance
-    record per hit, 40 B per point read and 156 B per point written."""
+    80 B per 4-wide BVH node visited (the half-precision planes, origin and
+    child references the node step reads of its 128-byte line), 48 B per
+    triangle tested, 48 B radiance record per hit, 40 B per point read and
+    156 B per point written."""
     stats = torch.zeros(6, dtype=torch.int64, device=planes.device)
     fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out, stats=stats)
     torch.cuda.synchronize()
@@ -114,7 +116,7 @@ def traversal_bytes(scene, planes, tri, sc, out):
     n = planes.shape[1]
     P = 3 + 6 * len(sc.sigma)
     samples = n * sc.spp * (1 + len(sc.sigma))
-    total = nodes * 128 + tris * 48 + hits * 48 + n * 40 + n * P * 4
+    total = nodes * 80 + tris * 48 + hits * 48 + n * 40 + n * P * 4
     ops = nodes * OPS_PER_NODE + tris * OPS_PER_TRI + samples * OPS_PER_SAMPLE + hits * OPS_PER_HIT
     return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, bytes=total, ops=ops,
                 nodes_per_ray=nodes / max(rays, 1), tris_per_ray=tris / max(rays, 1),
