@@ -271,7 +271,12 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
 }
 
 // Triangle test (Moller-Trumbore) of leaf-order triangle `i`; updates the
-// closest hit, exact distance ties going to the lower original index.
+// closest hit, exact distance ties going to the lower original index.  A
+// triangle parallel to the ray (det = 0) needs no early exit: its
+// reciprocal is infinite, so u, v and t are infinite or NaN and the inside
+// test fails; without the branch all three loads issue together (the
+// branch let the compiler delay the vertex load behind it, a second memory
+// round trip per test).
 __device__ __forceinline__ void tri_test(const TriGeom* tris, int32_t i, V3 o, V3 d, Hit& h,
                                          int32_t& best_orig) {
     const float4* tp = reinterpret_cast<const float4*>(tris + i);
@@ -282,7 +287,6 @@ __device__ __forceinline__ void tri_test(const TriGeom* tris, int32_t i, V3 o, V
     const V3 e2 = v3(t2.x, t2.y, t2.z);
     const V3 pv = cross(d, e2);
     const float det = dot(e1, pv);
-    if (det == 0.0f) return;
     const float inv = __builtin_amdgcn_rcpf(det);
     const V3 s = o - v3(t0.x, t0.y, t0.z);
     const float u = dot(s, pv) * inv;
