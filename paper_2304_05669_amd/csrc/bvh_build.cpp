@@ -64,12 +64,15 @@ int ceil_log2(int64_t x) {
     return l;
 }
 
+// 2^-20 relative, plus the smallest normal float so a bound at exactly zero
+// still moves (an absolute floor any larger would inflate the boxes of a
+// scene whose coordinates are themselves that small)
 float widen_lo(float v) {
-    float e = std::fabs(v) * 9.5367431640625e-07f + 1e-30f;  // 2^-20 relative
+    float e = std::fabs(v) * 9.5367431640625e-07f + 1.17549435e-38f;
     return v - e;
 }
 float widen_hi(float v) {
-    float e = std::fabs(v) * 9.5367431640625e-07f + 1e-30f;
+    float e = std::fabs(v) * 9.5367431640625e-07f + 1.17549435e-38f;
     return v + e;
 }
 
@@ -619,7 +622,9 @@ double sah_cost4(const std::vector<Wide4>& nodes) {
             hi[k] = std::max(hi[k], r.hi[k][i]);
         }
     }
-    const double root = std::max(area(lo, hi), 1e-30);
+    // area ratios are scale-free: only a root of zero area needs a stand-in
+    const double root_area = area(lo, hi);
+    const double root = root_area > 0.0 ? root_area : 1.0;
     double c = OptimalCollapser::kNodeCost;
     for (const Wide4& n : nodes) {
         for (int i = 0; i < 4; ++i) {
@@ -825,7 +830,7 @@ int validate4(const fipt::HostBvh& b, const float* verts, const int32_t* tris, i
                 if (ch.child[j] == kEmptyChild) continue;
                 for (int k = 0; k < 3; ++k) {
                     const float tol = 4.0f * 9.5367431640625e-07f *
-                                          std::max(std::fabs(lo[k]), std::fabs(hi[k])) + 1e-30f;
+                                          std::max(std::fabs(lo[k]), std::fabs(hi[k])) + 1.17549435e-38f;
                     if (ch.lo[k][j] < lo[k] - tol || ch.hi[k][j] > hi[k] + tol)
                         return fail(FIPT_EINVAL, "4-wide node %d leaves its parent box", c);
                 }
@@ -871,7 +876,7 @@ int validate_subtree(const fipt::HostBvh& b, const float* verts, const int32_t* 
             if (l0[k] < lo[k] || h0[k] > hi[k] || l1[k] < lo[k] || h1[k] > hi[k]) {
                 // children are widened independently of the parent; allow
                 // their few-ulp margin
-                const float tol = 4.0f * 9.5367431640625e-07f * std::max(std::fabs(lo[k]), std::fabs(hi[k])) + 1e-30f;
+                const float tol = 4.0f * 9.5367431640625e-07f * std::max(std::fabs(lo[k]), std::fabs(hi[k])) + 1.17549435e-38f;
                 if (l0[k] < lo[k] - tol || h0[k] > hi[k] + tol || l1[k] < lo[k] - tol || h1[k] > hi[k] + tol)
                     return fail(FIPT_EINVAL, "child box of node %d leaves its parent box", ref);
             }

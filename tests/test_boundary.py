@@ -131,3 +131,13 @@ def test_binding_rejects_misshapen_buffers():
         fipt.fipt_render_loss(sh, mat, obs, sig, loss_buf=torch.zeros(1, dtype=torch.float64))
     with pytest.raises(ValueError):
         fipt.fipt_scale_by(z(10), torch.zeros(1, dtype=torch.float64), out=z(9))
+
+
+@pytest.mark.parametrize("e", [-100, 100])
+def test_bvh_is_scale_invariant(e):
+    """Scaling a scene by a power of two changes no rounding, so the builder
+    must make the same tree (no absolute constant may enter its choices)."""
+    sc = synth.room(n_cams=1, width=2, height=2)
+    base = fipt.fipt_bvh_validate(sc.verts, sc.tris)
+    scaled = np.ldexp(sc.verts.astype(np.float64), e).astype(np.float32)
+    assert fipt.fipt_bvh_validate(scaled, sc.tris) == base
