@@ -10,5 +10,7 @@ seeded inputs from ``synth``.
                      ``oracle.build``);
 * ``oracle.render``  factored re-render, photometric loss and its gradient
                      (Eq. 5, 8, 2/15), trilinear material grid and its
-                     adjoint, in numpy float64.
+                     adjoint, in numpy float64;
+* ``oracle.emission`` per-triangle emission re-estimation (Eq. 13 with
+                     f = 0: the median of the observed pixels), in numpy.
 """
