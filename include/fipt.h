@@ -59,6 +59,7 @@ extern "C" {
 
 typedef struct fipt_scene_s* fipt_scene;
 typedef struct fipt_grid_plan_s* fipt_grid_plan;
+typedef struct fipt_emission_plan_s* fipt_emission_plan;
 typedef struct fipt_server_s* fipt_server;
 
 /* Pinhole camera: rays leave `pos` through pixel centres; `fwd` is the view
@@ -315,6 +316,30 @@ int fipt_grid_plan_destroy(fipt_grid_plan plan);
  * with the same plan must not overlap (one stream, or ordered streams). */
 int fipt_grid_scatter(fipt_grid_plan plan, const float* grad_points, int32_t channels,
                       int64_t gp_stride, float* grad_grid, void* stream);
+
+/* ---- emission re-estimation (Sec. 4.4, Eq. 13) ------------------------- */
+
+/* Under the assumption that an emitter reflects no light (f = 0), the
+ * minimiser of Eq. 13 for a triangle classified as an emitter is, per
+ * channel, the median of the observed values of the pixels whose primary
+ * hit is that triangle.  The plan groups pixels by triangle once:
+ * tri_host[n] (host) is each pixel's primary-hit triangle, -1 for none (as
+ * written by fipt_gen_points), each in [-1, n_tris).  1 <= n < 2^31,
+ * 1 <= n_tris < 2^31.  The plan owns device memory. */
+int fipt_emission_plan_create(const int32_t* tri_host, int64_t n, int64_t n_tris, int32_t device,
+                              fipt_emission_plan* out);
+int fipt_emission_plan_destroy(fipt_emission_plan plan);
+
+/* le[c][t] (device float [3][le_stride]) := for every triangle t with
+ * emitter[t] != 0 (device uint8 [n_tris]), the median over the pixels p of
+ * t of observed[c][p] (device float [3][obs_stride]), the lower of the two
+ * middle values for an even count, so the result is one of the
+ * observations (negative zero is treated as zero); 0 for other triangles
+ * and for triangles no pixel sees.  Exact and bitwise reproducible;
+ * allocates nothing; asynchronous on `stream`.  obs_stride >= n,
+ * le_stride >= n_tris. */
+int fipt_emission_median(fipt_emission_plan plan, const float* observed, int64_t obs_stride,
+                         const uint8_t* emitter, float* le, int64_t le_stride, void* stream);
 
 /* ---- serving: continuous batching of bake requests --------------------- */
 

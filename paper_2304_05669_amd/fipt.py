@@ -31,6 +31,7 @@ EXPORTS = (
     "fipt_cast_rays", "fipt_gen_points",
     "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_render_loss", "fipt_scale_by",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
+    "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
     "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
     "fipt_server_result", "fipt_server_release", "fipt_server_cancel", "fipt_server_stats_get",
     "fipt_server_destroy",
@@ -110,6 +111,9 @@ def lib():
         "fipt_grid_plan_create": (C.c_int, [_vp, _i64, _i32, _f32p, _f32p, _i32, C.POINTER(_vp)]),
         "fipt_grid_plan_destroy": (C.c_int, [_vp]),
         "fipt_grid_scatter": (C.c_int, [_vp, _vp, _i32, _i64, _vp, _vp]),
+        "fipt_emission_plan_create": (C.c_int, [_vp, _i64, _i64, _i32, C.POINTER(_vp)]),
+        "fipt_emission_plan_destroy": (C.c_int, [_vp]),
+        "fipt_emission_median": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i64, _vp]),
         "fipt_server_create": (C.c_int, [_i32, _i64, _i32, _i64, C.POINTER(_vp)]),
         "fipt_server_submit": (C.c_int, [_vp, _vp, C.POINTER(Points), C.POINTER(BakeParams),
                                          C.POINTER(_u64)]),
@@ -456,6 +460,46 @@ class GridPlan:
         try:
             if getattr(self, "handle", None) and _lib is not None:
                 _lib.fipt_grid_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class EmissionPlan:
+    """Per-triangle emission re-estimation (Eq. 13 with f = 0): the pixels
+    grouped by their primary-hit triangle once (``tri_host`` [n], -1 for
+    none), then ``median`` of the observations per emitter triangle."""
+
+    def __init__(self, tri_host, n_tris: int, device: int = 0):
+        import numpy as np
+        t = np.ascontiguousarray(tri_host, dtype=np.int32)
+        if t.ndim != 1:
+            raise ValueError("tri_host must be [n]")
+        self.n = int(t.shape[0])
+        self.n_tris = int(n_tris)
+        h = C.c_void_p()
+        _check(lib().fipt_emission_plan_create(t.ctypes.data, self.n, self.n_tris, device, C.byref(h)))
+        self.handle = h
+
+    def median(self, observed: torch.Tensor, emitter: torch.Tensor, out: torch.Tensor = None):
+        """observed [3, n] float32 GPU, emitter [n_tris] uint8 (or bool) GPU
+        -> Le [3, n_tris] float32 GPU."""
+        if observed.dim() != 2 or observed.shape[0] != 3 or observed.shape[1] != self.n:
+            raise ValueError(f"observed must be [3, {self.n}], got {tuple(observed.shape)}")
+        if emitter.dtype == torch.bool:
+            emitter = emitter.to(torch.uint8)
+        _need(emitter, (self.n_tris,), "emitter")
+        if out is None:
+            out = torch.empty((3, self.n_tris), dtype=torch.float32, device=observed.device)
+        _need(out, (3, self.n_tris), "out")
+        _check(lib().fipt_emission_median(self.handle, _dev(observed, torch.float32, "observed"), self.n,
+                                          _dev(emitter, torch.uint8, "emitter"),
+                                          _dev(out, torch.float32, "out"), self.n_tris, _stream()))
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.fipt_emission_plan_destroy(self.handle)
         except Exception:
             pass
 

@@ -52,6 +52,8 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_lobe_uniforms(1, 0, 0, 0, 4, 1, None) == fipt.EINVAL
     assert L.fipt_lobe_uniforms(1, 0, 4, 17, 4, 1, None) == fipt.EINVAL
     assert L.fipt_lobe_uniforms(1, 0, 1 << 16, 0, 1 << 15, 1, None) == fipt.EINVAL
+    assert L.fipt_emission_plan_create(None, 10, 5, 0, None) == fipt.EINVAL
+    assert L.fipt_emission_median(None, None, 1, None, None, 1, None) == fipt.EINVAL
 
 
 # (scale, offset) applied to the room: the 4-wide nodes store bounds as
