@@ -18,7 +18,8 @@ from .scenes import (  # noqa: F401
     random_observations,
     observation_noise,
     serving_trace,
-    emission_schedule,
+    emitter_observations,
+    emitter_schedule,
     icosphere,
     SERVING_TRIANGLES,
     SIGMA_GRID,

@@ -468,17 +468,36 @@ def serving_trace(n_requests: int, rate: float, room_points, seed: int = 1104,
     return out
 
 
-def emission_schedule(emission: np.ndarray, n_iter: int, seed: int = 2105) -> list:
-    """Per-triangle emission for each of ``n_iter`` re-bakes of the emitter
-    loop: iteration i scales every emissive triangle's radiance by its own
-    factor drawn uniformly in [0.5, 1.5] (a stand-in for the re-estimated
-    emission); non-emissive triangles stay at zero.  float32 [3, T] each."""
+def emitter_schedule(emission: np.ndarray, n_iter: int, seed: int = 2105) -> list:
+    """Emitter classification for each of ``n_iter`` iterations of the
+    emitter loop: iteration i flags the first (i + 1) / n_iter of the
+    emissive triangles in a seeded random order (a stand-in for thresholding
+    an emission mask that sharpens over the iterations).  bool [T] each."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    lit = np.any(emission > 0, axis=0)
+    lit = np.flatnonzero(np.any(emission > 0, axis=0))
+    order = rng.permutation(lit)
     out = []
-    for _ in range(n_iter):
-        f = np.ones(emission.shape[1], dtype=np.float32)
-        f[lit] = rng.uniform(0.5, 1.5, size=int(lit.sum())).astype(np.float32)
-        out.append((emission * f[None, :]).astype(np.float32))
+    for i in range(n_iter):
+        flags = np.zeros(emission.shape[1], dtype=bool)
+        flags[order[: max(1, (len(order) * (i + 1)) // n_iter)]] = True
+        out.append(flags)
     return out
+
+
+def emitter_observations(emission: np.ndarray, tri: np.ndarray, seed: int = 2106) -> np.ndarray:
+    """Observed RGB of every pixel for the emission estimate: a pixel whose
+    primary hit is an emissive triangle sees its emission with 1 % Gaussian
+    multiplicative noise (an emitter reflects nothing); other pixels see
+    uniform values in [0, 1].  float32 [3, n]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tri = np.asarray(tri)
+    n = len(tri)
+    obs = rng.uniform(0.0, 1.0, size=(3, n)).astype(np.float32)
+    seen = tri >= 0
+    lit = np.any(emission > 0, axis=0)
+    on = seen.copy()
+    on[seen] = lit[tri[seen]]
+    obs[:, on] = (emission[:, tri[on]] * (1.0 + 0.01 * rng.standard_normal((3, int(on.sum()))))
+                  ).astype(np.float32)
+    return obs
 
