@@ -9,8 +9,9 @@ seeded inputs from ``synth``.
                      brute-force ray casting in double precision (C, built by
                      ``oracle.build``);
 * ``oracle.render``  factored re-render, photometric loss and its gradient
-                     (Eq. 5, 8, 2/15), trilinear material grid and its
-                     adjoint, in numpy float64;
+                     (Eq. 5, 8, 2/15), the emission-masked loss (Eq. 12/15)
+                     with the diffuse prior (Eq. 17), trilinear material
+                     grid and its adjoint, in numpy float64;
 * ``oracle.emission`` per-triangle emission re-estimation (Eq. 13 with
                      f = 0: the median of the observed pixels), in numpy.
 """

@@ -12,10 +12,17 @@ Definitions followed (Factorized Inverse Path Tracing, Sec. 3-4):
   (Gamma(Lr) - Gamma(Lgt))^2, Gamma the identity unless a tone map is
   asked for.
 
+* Sec. 4.4, Eq. 12 / Eq. 15: with an emission mask alpha per point the
+  rendered value compared with Lgt is (1 - alpha) Lr + alpha Lgt;
+* Sec. 4.5, Eq. 17: the diffuse prior
+  l_d = lambda_d * sum over points of (|1 - sigma| + |m|).
+
 Readings where the paper is silent: below the first level or above the last
 the interpolation clamps (zero roughness gradient); at an interior knot the
 right-hand segment is used; the optional tone map is
-Gamma(x) = sRGB-OETF(log(1 + max(x, 0))).
+Gamma(x) = sRGB-OETF(log(1 + max(x, 0))).  The prior's derivative takes
+sign(0) = 0 at the kinks of the absolute values (sigma = 1, m = 0), and its
+roughness term is not clamped by the interpolation bracket.
 """
 from __future__ import annotations
 
@@ -107,6 +114,39 @@ def loss_and_grad(shading, material, observed, sigma_grid, tone: int = 0):
     dsig = np.sum(g * (r["ks"] * r["dS0"] + r["dS1"]), axis=0) / r["dsig"]
     grad[3] = np.where(r["clamped"], 0.0, dsig)
     return loss, grad, r["Lr"]
+
+
+def masked_loss_and_grad(shading, material, observed, alpha, sigma_grid, tone: int = 0,
+                         lambda_d: float = 0.0):
+    """Emission-masked photometric loss (Eq. 12 / 15) plus the diffuse prior
+    (Eq. 17), with its gradients.
+
+    alpha [N] is the emission mask; the loss is
+      sum over points and channels of (Gamma((1 - alpha) Lr + alpha Lgt) - Gamma(Lgt))^2
+      + lambda_d * sum over points of (|1 - sigma| + |m|).
+    Returns (loss, grad [5, N] with respect to the material, grad_alpha [N],
+    Lr [3, N]); Lr is the unmasked reflected radiance."""
+    r = render(shading, material, sigma_grid)
+    Lgt = np.asarray(observed, dtype=np.float64)
+    al = np.asarray(alpha, dtype=np.float64)[None, :]
+    Lr = r["Lr"]
+    Lhat = (1.0 - al) * Lr + al * Lgt
+    res = tonemap(Lhat, tone) - tonemap(Lgt, tone)
+    mat = np.asarray(material, dtype=np.float64)
+    sig, met = mat[3], mat[4]
+    prior = lambda_d * np.sum(np.abs(1.0 - sig) + np.abs(met))
+    loss = float(np.sum(res * res) + prior)
+    gh = 2.0 * res * tonemap_d(Lhat, tone)                       # dl/dLhat [3, N]
+    g = gh * (1.0 - al)                                          # dl/dLr
+    grad = np.zeros((5, g.shape[1]))
+    grad[0:3] = g * ((1.0 - r["m"]) * r["Ld"] + r["m"] * r["L0"])
+    grad[4] = np.sum(g * (-r["a"] * r["Ld"] + (r["a"] - 0.04) * r["L0"]), axis=0)
+    dsig = np.sum(g * (r["ks"] * r["dS0"] + r["dS1"]), axis=0) / r["dsig"]
+    grad[3] = np.where(r["clamped"], 0.0, dsig)
+    grad[3] += -lambda_d * np.sign(1.0 - sig)
+    grad[4] += lambda_d * np.sign(met)
+    grad_alpha = np.sum(gh * (Lgt - Lr), axis=0)
+    return loss, grad, grad_alpha, Lr
 
 
 # -------------------------------------------------------------------------
