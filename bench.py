@@ -43,12 +43,16 @@ OPS_PER_HIT = 12       # radiance: barycentric blend of the corner cache + emiss
 # render-loss bytes per point: material 20 + Ld 12 + two bracketing levels
 # of Ls0/Ls1 48 + Lgt 12 + gradient 20
 LOSS_BYTES_PER_POINT = 112
+# the masked loss also reads alpha and writes d loss / d alpha
+MASKED_LOSS_BYTES_PER_POINT = 120
+LAMBDA_D = 5e-4        # weight of the diffuse prior, as in Eq. 17
 SHADING_PLANES = 39
 COUNTERS = os.path.join(ROOT, "profiles", "counters_room.json")
 # the sources each measured kernel is built from
 KERNEL_SOURCES = {
     "k_bake": ("bake.hip", "device.hpp", "fipt_internal.hpp", "bvh_build.cpp"),
     "k_render_loss": ("loss.hip", "fipt_internal.hpp"),
+    "k_render_loss_masked": ("loss.hip", "fipt_internal.hpp"),
 }
 
 
@@ -291,15 +295,26 @@ def copy_bandwidth(dev, n=1 << 28, reps=5):
     return 8 * n / (ms * 1e-3) / 1e9, ms
 
 
-def loss_timing(shading, mat, obs, sigma, reps=10, flush=None):
+def loss_timing(shading, mat, obs, sigma, reps=10, flush=None, alpha=None, lambda_d=0.0,
+                tonemap=0):
     """Mean fused render + loss + gradient time (ms) over ``reps`` launches;
     with ``flush`` (a >= 512 MB tensor) the caches are refilled by reading it
     before each launch (reads, so no dirty lines are left to write back), and
-    the kernel's inputs come from HBM."""
+    the kernel's inputs come from HBM.  With ``alpha`` the emission-masked
+    loss with the diffuse prior is timed (material and mask gradients)."""
     n = shading.shape[1]
     grad = torch.empty((5, n), dtype=torch.float32, device=shading.device)
     buf = torch.empty((fipt.LOSS_SLOTS,), dtype=torch.float64, device=shading.device)
-    fipt.fipt_render_loss(shading, mat, obs, sigma, loss_buf=buf, grad=grad)
+    galpha = torch.empty((n,), dtype=torch.float32, device=shading.device)
+
+    def launch():
+        if alpha is None:
+            fipt.fipt_render_loss(shading, mat, obs, sigma, tonemap, loss_buf=buf, grad=grad)
+        else:
+            fipt.fipt_render_loss_masked(shading, mat, obs, sigma, alpha, lambda_d, tonemap,
+                                         loss_buf=buf, grad=grad, grad_alpha=galpha)
+
+    launch()
     # a ~2 ms spin first, so the host has queued the launches before the GPU
     # reaches them and the events time the kernels, not the Python calls
     torch.cuda._sleep(5_000_000)
@@ -308,7 +323,7 @@ def loss_timing(shading, mat, obs, sigma, reps=10, flush=None):
         if flush is not None:
             flush.sum()
         tm.mark("a")
-        fipt.fipt_render_loss(shading, mat, obs, sigma, loss_buf=buf, grad=grad)
+        launch()
         tm.mark("b")
     torch.cuda.synchronize()
     return float(np.mean(tm.spans("a", "b")))
@@ -513,7 +528,23 @@ def main():
 
     flush = torch.ones((1 << 27,), dtype=torch.float32, device=dev)      # 512 MB
     t_loss_cold = loss_timing(shading, mat, obs, sc.sigma, flush=flush)
-    del flush
+    # the emission-masked loss with the diffuse prior (Eq. 15 + Eq. 17), with
+    # and without the tone map, on a mask shaped by the room's emitters
+    alpha = torch.from_numpy(synth.emission_mask(sc.emission, tri.cpu().numpy())).to(dev)
+    masked = {"bytes_per_point": MASKED_LOSS_BYTES_PER_POINT, "lambda_d": LAMBDA_D,
+              "traffic_log_srgb": traffic.get("k_render_loss_masked"),
+              "mask": "0.5-1 on pixels of emissive triangles, below 0.02 elsewhere"}
+    for tone, name in ((0, "identity"), (1, "log_srgb")):
+        warm = loss_timing(shading, mat, obs, sc.sigma, alpha=alpha, lambda_d=LAMBDA_D,
+                           tonemap=tone)
+        cold = loss_timing(shading, mat, obs, sc.sigma, flush=flush, alpha=alpha,
+                           lambda_d=LAMBDA_D, tonemap=tone)
+        masked[name] = {"warm_ms": warm, "cold_ms": cold,
+                        "warm_gbs": N * MASKED_LOSS_BYTES_PER_POINT / (warm * 1e-3) / 1e9,
+                        "cold_gbs": N * MASKED_LOSS_BYTES_PER_POINT / (cold * 1e-3) / 1e9,
+                        "points_per_s": N / (warm * 1e-3)}
+    log(f"masked loss: {masked}")
+    del flush, alpha
 
     large = None
     if args.large_rebakes > 0:
@@ -565,6 +596,7 @@ def main():
                      "ops_per_launch": trav["ops"] if trav else None,
                      "effective_traversal_gbs": bake_bytes / (t_bake * 1e-3) / 1e9 if trav else None,
                      "traversal_bytes_per_launch": bake_bytes},
+        "masked_loss": masked,
         "roofline_render_loss": {"bound": "hbm", "achieved": loss_gbs, "peak": PEAK_HBM_GBS,
                                  "unit": "GB/s", "frac": loss_gbs / PEAK_HBM_GBS,
                                  "traffic": traffic.get("k_render_loss"),

@@ -282,6 +282,27 @@ int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels,
                      double* loss_dev, float* grad_dev, int64_t grad_stride,
                      float* Lr_dev, int64_t lr_stride, void* stream);
 
+/* Emission-masked loss (Sec. 4.4, Eq. 12 and its tone-mapped form Eq. 15)
+ * plus the diffuse prior (Sec. 4.5, Eq. 17), over the same inputs as
+ * fipt_render_loss and an emission mask alpha[n] (device float, NULL for
+ * alpha = 0 everywhere):
+ *   Lhat = (1 - alpha) Lr + alpha Lgt,
+ *   loss = sum over points and channels of (Gamma(Lhat) - Gamma(Lgt))^2
+ *        + lambda_d * sum over points of (|1 - sigma| + |m|).
+ * lambda_d must be finite and >= 0 (the paper uses 5e-4).  If grad_dev is
+ * not NULL it receives d loss / d material [5][grad_stride] (the prior's
+ * terms use sign(0) = 0 and are added whether or not the roughness is
+ * clamped); if grad_alpha_dev is not NULL it receives d loss / d alpha [n];
+ * Lr_dev, if not NULL, receives the unmasked Lr.  With alpha NULL or zero
+ * and lambda_d = 0 the results equal fipt_render_loss's bit for bit.
+ * loss_dev as for fipt_render_loss. */
+int fipt_render_loss_masked(const fipt_shading* sh, int64_t n, int32_t n_levels,
+                            const float* sigma_host, const float* material, int64_t mat_stride,
+                            const float* observed, int64_t obs_stride, const float* alpha,
+                            int32_t tonemap, double lambda_d, double* loss_dev, float* grad_dev,
+                            int64_t grad_stride, float* grad_alpha_dev, float* Lr_dev,
+                            int64_t lr_stride, void* stream);
+
 /* out[i] = x[i] * factor_dev[0] for i < n (device float arrays, factor a
  * device double): the chain rule step of the loss's backward pass, which
  * scales the stored gradient by the incoming gradient without a host

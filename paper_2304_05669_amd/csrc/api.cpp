@@ -378,11 +378,12 @@ int fipt_bake_traversal_stats(fipt_scene s, const fipt_points* pts, const fipt_b
     return bake_common(s, pts, p, out, stats_dev, stream);
 }
 
-int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels, const float* sigma_host,
-                     const float* material, int64_t mat_stride, const float* observed,
-                     int64_t obs_stride, int32_t tonemap, double* loss_dev, float* grad_dev,
-                     int64_t grad_stride, float* Lr_dev, int64_t lr_stride, void* stream) {
-    clear_error();
+namespace {
+int check_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels, const float* sigma_host,
+                      const float* material, int64_t mat_stride, const float* observed,
+                      int64_t obs_stride, int32_t tonemap, const double* loss_dev,
+                      const float* grad_dev, int64_t grad_stride, const float* Lr_dev,
+                      int64_t lr_stride) {
     if (!sh || !sh->planes) return fail(FIPT_EINVAL, "shading is NULL");
     if (n < 1) return fail(FIPT_EINVAL, "n must be >= 1, got %lld", (long long)n);
     if (n_levels < 2 || n_levels > FIPT_MAX_LEVELS)
@@ -401,9 +402,41 @@ int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels, const 
     if (Lr_dev && lr_stride < n) return fail(FIPT_EINVAL, "lr_stride < n");
     if (tonemap != FIPT_TONEMAP_NONE && tonemap != FIPT_TONEMAP_LOG_SRGB)
         return fail(FIPT_EINVAL, "unknown tonemap %d", tonemap);
+    return FIPT_OK;
+}
+}  // namespace
+
+int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels, const float* sigma_host,
+                     const float* material, int64_t mat_stride, const float* observed,
+                     int64_t obs_stride, int32_t tonemap, double* loss_dev, float* grad_dev,
+                     int64_t grad_stride, float* Lr_dev, int64_t lr_stride, void* stream) {
+    clear_error();
+    int rc = check_render_loss(sh, n, n_levels, sigma_host, material, mat_stride, observed,
+                               obs_stride, tonemap, loss_dev, grad_dev, grad_stride, Lr_dev,
+                               lr_stride);
+    if (rc) return rc;
     return launch_render_loss(sh->planes, sh->stride, n, n_levels, sigma_host, material, mat_stride,
                               observed, obs_stride, tonemap, loss_dev, grad_dev, grad_stride,
-                              Lr_dev, lr_stride, stream);
+                              Lr_dev, lr_stride, nullptr, stream);
+}
+
+int fipt_render_loss_masked(const fipt_shading* sh, int64_t n, int32_t n_levels,
+                            const float* sigma_host, const float* material, int64_t mat_stride,
+                            const float* observed, int64_t obs_stride, const float* alpha,
+                            int32_t tonemap, double lambda_d, double* loss_dev, float* grad_dev,
+                            int64_t grad_stride, float* grad_alpha_dev, float* Lr_dev,
+                            int64_t lr_stride, void* stream) {
+    clear_error();
+    int rc = check_render_loss(sh, n, n_levels, sigma_host, material, mat_stride, observed,
+                               obs_stride, tonemap, loss_dev, grad_dev, grad_stride, Lr_dev,
+                               lr_stride);
+    if (rc) return rc;
+    if (!std::isfinite(lambda_d) || lambda_d < 0.0)
+        return fail(FIPT_EINVAL, "lambda_d must be finite and >= 0");
+    const RenderLossMask mask{alpha, grad_alpha_dev, lambda_d};
+    return launch_render_loss(sh->planes, sh->stride, n, n_levels, sigma_host, material, mat_stride,
+                              observed, obs_stride, tonemap, loss_dev, grad_dev, grad_stride,
+                              Lr_dev, lr_stride, &mask, stream);
 }
 
 int fipt_scale_by(const float* x, int64_t n, const double* factor_dev, float* out, void* stream) {

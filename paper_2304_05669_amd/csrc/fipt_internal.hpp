@@ -177,11 +177,18 @@ int launch_bake_tiles(const TileDesc* tiles_dev, int32_t n_tiles, int32_t* count
                       int32_t grid, void* stream);
 int bake_tiles_grid_hint();
 
+// Terms of the masked loss (Eq. 12 / 15 with the prior of Eq. 17); a NULL
+// RenderLossMask* selects the plain loss.
+struct RenderLossMask {
+    const float* alpha;  // [n] or NULL (zero)
+    float* grad_alpha;   // [n] or NULL
+    double lambda_d;
+};
 int launch_render_loss(const float* sh, int64_t sh_stride, int64_t n, int32_t K,
                        const float* sigma_host, const float* mat, int64_t mat_stride,
                        const float* obs, int64_t obs_stride, int32_t tone, double* loss,
                        float* grad, int64_t grad_stride, float* Lr, int64_t lr_stride,
-                       void* stream);
+                       const RenderLossMask* mask, void* stream);
 int launch_scale_by(const float* x, int64_t n, const double* f, float* out, void* stream);
 int launch_grid_gather(const float* grid, int32_t C, int32_t R, const float* bmin,
                        const float* bmax, const float* pos, int64_t pos_stride, int64_t n,

@@ -28,26 +28,34 @@ struct SigmaTable {
 };
 
 // Tone maps in double: the per-point arithmetic of this kernel runs in
-// float64, which costs nothing here (a few dozen operations per point
-// against ~200 bytes of traffic) and removes the float32 cancellation in
-// Lr - Lgt that would otherwise dominate the gradient of well-fit points.
-__device__ __forceinline__ double srgb_oetf(double x) {
-    return x <= 0.0031308 ? 12.92 * x : 1.055 * pow(x, 1.0 / 2.4) - 0.055;
+// float64, which removes the float32 cancellation in Lr - Lgt that would
+// otherwise dominate the gradient of well-fit points.  The log-sRGB map
+// Gamma(x) = sRGB-OETF(log(1 + x)) and its derivative share one log1p and
+// one power, the power taken as exp(log(u) / 2.4) (a few ulp in double,
+// and several times cheaper than a general pow).
+template <int TONE>
+__device__ __forceinline__ double tone_vd(double x, double& d) {
+    if (TONE == 0) {
+        d = 1.0;
+        return x;
+    }
+    if (!(x > 0.0)) {
+        d = 0.0;
+        return 0.0;
+    }
+    const double u = log1p(x);
+    if (u <= 0.0031308) {
+        d = 12.92 / (1.0 + x);
+        return 12.92 * u;
+    }
+    const double p = exp(log(u) * (1.0 / 2.4));
+    d = (1.055 / 2.4) * p / (u * (1.0 + x));
+    return 1.055 * p - 0.055;
 }
-__device__ __forceinline__ double srgb_oetf_d(double x) {
-    return x <= 0.0031308 ? 12.92 : (1.055 / 2.4) * pow(x, 1.0 / 2.4 - 1.0);
-}
-
 template <int TONE>
 __device__ __forceinline__ double tone(double x) {
-    if (TONE == 0) return x;
-    return srgb_oetf(log1p(fmax(x, 0.0)));
-}
-template <int TONE>
-__device__ __forceinline__ double tone_d(double x) {
-    if (TONE == 0) return 1.0;
-    if (!(x > 0.0)) return 0.0;
-    return srgb_oetf_d(log1p(x)) / (1.0 + x);
+    double d;
+    return tone_vd<TONE>(x, d);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -61,19 +69,52 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
-template <int TONE, bool GRAD, bool LR>
-__global__ __launch_bounds__(kBlock) void k_render_loss(
-    const float* __restrict__ sh, int64_t ss, int64_t n, int K, SigmaTable tab,
-    const float* __restrict__ mat, int64_t ms, const float* __restrict__ obs, int64_t os,
-    double* __restrict__ partials, float* __restrict__ grad, int64_t gs, float* __restrict__ Lr,
-    int64_t ls) {
+// Arguments of the render-loss kernel.  The masked form (Eq. 12 / 15 with
+// the diffuse prior of Eq. 17) additionally reads the emission mask alpha
+// (NULL: zero everywhere), writes d loss / d alpha when galpha is not NULL,
+// and lets grad be NULL.
+struct RLArgs {
+    const float* sh;
+    int64_t ss;
+    int64_t n;
+    int K;
+    const float* mat;
+    int64_t ms;
+    const float* obs;
+    int64_t os;
+    double* partials;
+    float* grad;
+    int64_t gs;
+    float* Lr;
+    int64_t ls;
+    const float* alpha;
+    float* galpha;
+    double lam;  // lambda_d of the diffuse prior
+};
+
+__device__ __forceinline__ double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
+
+// MASK selects the masked loss with the prior: the compared value is
+// (1 - alpha) Lr + alpha Lgt, whose derivative carries a factor (1 - alpha)
+// into the material gradient, and lambda_d (|1 - sigma| + |m|) is added per
+// point (derivative sign(0) = 0 at the kinks).  With alpha = 0 and
+// lambda_d = 0 every operation it adds is exact, so it reproduces the plain
+// loss bit for bit.
+template <int TONE, bool GRAD, bool LR, bool MASK>
+__global__ __launch_bounds__(kBlock) void k_render_loss(RLArgs g, SigmaTable tab) {
     __shared__ double s_red[kBlock / 64];
+    const float* __restrict__ sh = g.sh;
+    const float* __restrict__ mat = g.mat;
+    const float* __restrict__ obs = g.obs;
+    const int64_t ss = g.ss, ms = g.ms, os = g.os, n = g.n;
+    const int K = g.K;
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += stride) {
         const double a[3] = {mat[p], mat[ms + p], mat[2 * ms + p]};
         const float sg = mat[3 * ms + p];
         const double m = mat[4 * ms + p];
+        const double al = (MASK && g.alpha) ? (double)g.alpha[p] : 0.0;
         // bracket: largest j with s_j <= sigma, clamped to [0, K-2]
         int j = 0;
         for (int k = 1; k < K - 1; ++k) j = (tab.s[k] <= sg) ? k : j;
@@ -81,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_render_loss(
         const double t = fmin(fmax(((double)sg - (double)tab.s[j]) * tab.inv_gap[j], 0.0), 1.0);
         const float* s0j = sh + (3 + 3 * j) * ss + p;
         const float* s1j = sh + (3 + 3 * K + 3 * j) * ss + p;
-        double dsig = 0.0, dm = 0.0;
+        double dsig = 0.0, dm = 0.0, dal = 0.0;
         double da[3], lr[3];
         double l = 0.0;
 #pragma unroll
@@ -96,31 +137,44 @@ __global__ __launch_bounds__(kBlock) void k_render_loss(
             const double r = kd * ld + ks * L0 + L1;
             lr[c] = r;
             const double y = obs[c * os + p];
-            const double res = tone<TONE>(r) - tone<TONE>(y);
+            const double h = MASK ? (1.0 - al) * r + al * y : r;
+            double dh;
+            const double res = tone_vd<TONE>(h, dh) - tone<TONE>(y);
             l += res * res;
             if (GRAD) {
-                const double g = 2.0 * res * tone_d<TONE>(r);
-                da[c] = g * ((1.0 - m) * ld + m * L0);
-                dm += g * (-a[c] * ld + (a[c] - 0.04) * L0);
-                dsig += g * (ks * (B0 - A0) + (B1 - A1));
+                const double gh = 2.0 * res * dh;
+                const double gr = MASK ? gh * (1.0 - al) : gh;
+                da[c] = gr * ((1.0 - m) * ld + m * L0);
+                dm += gr * (-a[c] * ld + (a[c] - 0.04) * L0);
+                dsig += gr * (ks * (B0 - A0) + (B1 - A1));
+                if (MASK) dal += gh * (y - r);
             }
         }
+        if (MASK) l += g.lam * (fabs(1.0 - (double)sg) + fabs(m));
         acc += l;
-        if (GRAD) {
+        if (GRAD && (!MASK || g.grad)) {
+            float* __restrict__ grad = g.grad;
+            const int64_t gs = g.gs;
+            double gsig = clamped ? 0.0 : dsig * tab.inv_gap[j];
+            if (MASK) {
+                gsig += -g.lam * sgn(1.0 - (double)sg);
+                dm += g.lam * sgn(m);
+            }
             grad[p] = (float)da[0];
             grad[gs + p] = (float)da[1];
             grad[2 * gs + p] = (float)da[2];
-            grad[3 * gs + p] = clamped ? 0.0f : (float)(dsig * tab.inv_gap[j]);
+            grad[3 * gs + p] = (float)gsig;
             grad[4 * gs + p] = (float)dm;
         }
+        if (GRAD && MASK && g.galpha) g.galpha[p] = (float)dal;
         if (LR) {
-            Lr[p] = (float)lr[0];
-            Lr[ls + p] = (float)lr[1];
-            Lr[2 * ls + p] = (float)lr[2];
+            g.Lr[p] = (float)lr[0];
+            g.Lr[g.ls + p] = (float)lr[1];
+            g.Lr[2 * g.ls + p] = (float)lr[2];
         }
     }
     const double tot = block_sum(acc, s_red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (threadIdx.x == 0) g.partials[blockIdx.x] = tot;
 }
 
 // Sum the per-workgroup partials in index order (one workgroup).
@@ -312,12 +366,24 @@ int check(const char* what) {
     return FIPT_OK;
 }
 
+template <int TONE, bool GRAD, bool LR, bool MASK>
+void launch_rl(dim3 grid, hipStream_t st, const RLArgs& a, const SigmaTable& tab) {
+    hipLaunchKernelGGL((k_render_loss<TONE, GRAD, LR, MASK>), grid, dim3(kBlock), 0, st, a, tab);
+}
+
 template <int TONE, bool GRAD, bool LR>
-void launch_rl(dim3 grid, hipStream_t st, const float* sh, int64_t ss, int64_t n, int K,
-               const SigmaTable& tab, const float* mat, int64_t ms, const float* obs, int64_t os,
-               double* partials, float* grad, int64_t gs, float* Lr, int64_t ls) {
-    hipLaunchKernelGGL((k_render_loss<TONE, GRAD, LR>), grid, dim3(kBlock), 0, st, sh, ss, n, K,
-                       tab, mat, ms, obs, os, partials, grad, gs, Lr, ls);
+void launch_rl_mask(bool mask, dim3 grid, hipStream_t st, const RLArgs& a, const SigmaTable& tab) {
+    if (mask) launch_rl<TONE, GRAD, LR, true>(grid, st, a, tab);
+    else launch_rl<TONE, GRAD, LR, false>(grid, st, a, tab);
+}
+
+template <int TONE>
+void launch_rl_tone(bool g, bool l, bool mask, dim3 grid, hipStream_t st, const RLArgs& a,
+                    const SigmaTable& tab) {
+    if (g && l) launch_rl_mask<TONE, true, true>(mask, grid, st, a, tab);
+    else if (g) launch_rl_mask<TONE, true, false>(mask, grid, st, a, tab);
+    else if (l) launch_rl_mask<TONE, false, true>(mask, grid, st, a, tab);
+    else launch_rl_mask<TONE, false, false>(mask, grid, st, a, tab);
 }
 
 }  // namespace
@@ -325,7 +391,7 @@ void launch_rl(dim3 grid, hipStream_t st, const float* sh, int64_t ss, int64_t n
 int launch_render_loss(const float* sh, int64_t ss, int64_t n, int32_t K, const float* sigma,
                        const float* mat, int64_t ms, const float* obs, int64_t os, int32_t tone,
                        double* loss, float* grad, int64_t gs, float* Lr, int64_t ls,
-                       void* stream) {
+                       const RenderLossMask* mask, void* stream) {
     SigmaTable tab;
     for (int k = 0; k < FIPT_MAX_LEVELS; ++k) {
         tab.s[k] = k < K ? sigma[k] : 0.0f;
@@ -336,20 +402,12 @@ int launch_render_loss(const float* sh, int64_t ss, int64_t n, int32_t K, const 
     hipStream_t st = (hipStream_t)stream;
     double* partials = loss + 1;
     const dim3 grid(blocks);
-    const bool g = grad != nullptr, l = Lr != nullptr;
-#define FIPT_RL(T, G, L) launch_rl<T, G, L>(grid, st, sh, ss, n, K, tab, mat, ms, obs, os, partials, grad, gs, Lr, ls)
-    if (tone == 0) {
-        if (g && l) FIPT_RL(0, true, true);
-        else if (g) FIPT_RL(0, true, false);
-        else if (l) FIPT_RL(0, false, true);
-        else FIPT_RL(0, false, false);
-    } else {
-        if (g && l) FIPT_RL(1, true, true);
-        else if (g) FIPT_RL(1, true, false);
-        else if (l) FIPT_RL(1, false, true);
-        else FIPT_RL(1, false, false);
-    }
-#undef FIPT_RL
+    RLArgs a{sh, ss, n, K, mat, ms, obs, os, partials, grad, gs, Lr, ls,
+             mask ? mask->alpha : nullptr, mask ? mask->grad_alpha : nullptr,
+             mask ? mask->lambda_d : 0.0};
+    const bool g = grad != nullptr || (mask && mask->grad_alpha), l = Lr != nullptr;
+    if (tone == 0) launch_rl_tone<0>(g, l, mask != nullptr, grid, st, a, tab);
+    else launch_rl_tone<1>(g, l, mask != nullptr, grid, st, a, tab);
     int rc = check("render_loss");
     if (rc) return rc;
     hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, st, partials, blocks, loss);

@@ -29,7 +29,8 @@ EXPORTS = (
     "fipt_last_error", "fipt_version", "fipt_scene_create", "fipt_scene_set_radiance",
     "fipt_scene_set_emission", "fipt_scene_info_get", "fipt_bvh_validate", "fipt_scene_destroy",
     "fipt_cast_rays", "fipt_gen_points",
-    "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_render_loss", "fipt_scale_by",
+    "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_render_loss",
+    "fipt_render_loss_masked", "fipt_scale_by",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
     "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
@@ -106,6 +107,9 @@ def lib():
                                                 C.POINTER(Shading), _vp, _vp]),
         "fipt_render_loss": (C.c_int, [C.POINTER(Shading), _i64, _i32, _f32p, _vp, _i64, _vp, _i64,
                                        _i32, _vp, _vp, _i64, _vp, _i64, _vp]),
+        "fipt_render_loss_masked": (C.c_int, [C.POINTER(Shading), _i64, _i32, _f32p, _vp, _i64, _vp,
+                                              _i64, _vp, _i32, C.c_double, _vp, _vp, _i64, _vp, _vp,
+                                              _i64, _vp]),
         "fipt_scale_by": (C.c_int, [_vp, _i64, _vp, _vp, _vp]),
         "fipt_grid_gather": (C.c_int, [_vp, _i32, _i32, _f32p, _f32p, _vp, _i64, _i64, _vp, _i64, _vp]),
         "fipt_grid_plan_create": (C.c_int, [_vp, _i64, _i32, _f32p, _f32p, _i32, C.POINTER(_vp)]),
@@ -380,6 +384,53 @@ def fipt_render_loss(shading: torch.Tensor, material: torch.Tensor, observed: to
     return loss_buf, (grad if want_grad else None), (lr if want_lr else None)
 
 
+def fipt_render_loss_masked(shading: torch.Tensor, material: torch.Tensor, observed: torch.Tensor,
+                            sigma, alpha: torch.Tensor = None, lambda_d: float = 0.0,
+                            tonemap: int = TONEMAP_NONE, want_grad: bool = True,
+                            want_grad_alpha: bool = True, want_lr: bool = False,
+                            loss_buf: torch.Tensor = None, grad: torch.Tensor = None,
+                            grad_alpha: torch.Tensor = None, lr: torch.Tensor = None):
+    """Emission-masked loss plus the diffuse prior.  Returns (loss_buf,
+    grad [5, n], grad_alpha [n], Lr [3, n]) with None for what was not asked
+    for; alpha [n] float32 GPU or None (zero)."""
+    K = len(sigma)
+    n = material.shape[1]
+    if shading.shape[0] != 3 + 6 * K or shading.shape[1] != n:
+        raise ValueError("shading must be [3 + 6K, n]")
+    if material.shape[0] != 5 or observed.shape != (3, n):
+        raise ValueError("material must be [5, n] and observed [3, n]")
+    if alpha is not None:
+        _need(alpha, (n,), "alpha")
+    dev = material.device
+    if loss_buf is None:
+        loss_buf = torch.empty((LOSS_SLOTS,), dtype=torch.float64, device=dev)
+    _need(loss_buf, (LOSS_SLOTS,), "loss_buf")
+    if want_grad and grad is None:
+        grad = torch.empty((5, n), dtype=torch.float32, device=dev)
+    if want_grad:
+        _need(grad, (5, n), "grad")
+    if want_grad_alpha and grad_alpha is None:
+        grad_alpha = torch.empty((n,), dtype=torch.float32, device=dev)
+    if want_grad_alpha:
+        _need(grad_alpha, (n,), "grad_alpha")
+    if want_lr and lr is None:
+        lr = torch.empty((3, n), dtype=torch.float32, device=dev)
+    if want_lr:
+        _need(lr, (3, n), "lr")
+    sh = Shading(_dev(shading, torch.float32, "shading"), n)
+    sig = _f32_array(sigma, K)
+    _check(lib().fipt_render_loss_masked(
+        C.byref(sh), n, K, sig, _dev(material, torch.float32, "material"), n,
+        _dev(observed, torch.float32, "observed"), n,
+        _dev(alpha, torch.float32, "alpha") if alpha is not None else None, int(tonemap),
+        float(lambda_d), _dev(loss_buf, torch.float64, "loss_buf"),
+        _dev(grad, torch.float32, "grad") if want_grad else None, n,
+        _dev(grad_alpha, torch.float32, "grad_alpha") if want_grad_alpha else None,
+        _dev(lr, torch.float32, "lr") if want_lr else None, n, _stream()))
+    return (loss_buf, grad if want_grad else None, grad_alpha if want_grad_alpha else None,
+            lr if want_lr else None)
+
+
 def fipt_scale_by(x: torch.Tensor, factor: torch.Tensor, out: torch.Tensor = None):
     """out = x * factor[0] (factor: one float64 on the GPU) in a HIP kernel."""
     if out is None:
@@ -408,6 +459,29 @@ class FactoredLoss(torch.autograd.Function):
         (grad,) = ctx.saved_tensors
         g = fipt_scale_by(grad, go.reshape(1).to(torch.float64).contiguous())
         return g, None, None, None, None
+
+
+class MaskedFactoredLoss(torch.autograd.Function):
+    """Emission-masked loss plus diffuse prior (library gradients);
+    differentiable in ``material`` [5, n] and ``alpha`` [n]."""
+
+    @staticmethod
+    def forward(ctx, material, alpha, shading, observed, sigma, tonemap=TONEMAP_NONE, lambda_d=0.0):
+        buf, grad, galpha, _ = fipt_render_loss_masked(
+            shading, material.detach(), observed, sigma, alpha.detach(), lambda_d, tonemap,
+            want_grad=material.requires_grad, want_grad_alpha=alpha.requires_grad)
+        empty = material.new_empty(0)
+        ctx.save_for_backward(grad if grad is not None else empty,
+                              galpha if galpha is not None else empty)
+        return buf[0]
+
+    @staticmethod
+    def backward(ctx, go):
+        grad, galpha = ctx.saved_tensors
+        f = go.reshape(1).to(torch.float64).contiguous()
+        gm = fipt_scale_by(grad, f) if grad.numel() else None
+        ga = fipt_scale_by(galpha, f) if galpha.numel() else None
+        return gm, ga, None, None, None, None, None
 
 
 # --------------------------------------------------------------------------

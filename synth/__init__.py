@@ -19,6 +19,7 @@ from .scenes import (  # noqa: F401
     observation_noise,
     serving_trace,
     emitter_observations,
+    emission_mask,
     emitter_schedule,
     icosphere,
     SERVING_TRIANGLES,

@@ -501,3 +501,20 @@ def emitter_observations(emission: np.ndarray, tri: np.ndarray, seed: int = 2106
                   ).astype(np.float32)
     return obs
 
+
+
+def emission_mask(emission: np.ndarray, tri: np.ndarray, seed: int = 2107) -> np.ndarray:
+    """Emission mask alpha per pixel for the masked loss, shaped like a mask
+    part-way through its optimisation: pixels whose primary hit is an
+    emissive triangle get values in [0.5, 1], all others small values in
+    [0, 0.02) (most of them below the 0.01 emitter threshold).  float32 [n]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tri = np.asarray(tri)
+    n = len(tri)
+    alpha = (0.02 * rng.random(n) ** 2).astype(np.float32)
+    seen = tri >= 0
+    lit = np.any(emission > 0, axis=0)
+    on = seen.copy()
+    on[seen] = lit[tri[seen]]
+    alpha[on] = rng.uniform(0.5, 1.0, int(on.sum())).astype(np.float32)
+    return alpha

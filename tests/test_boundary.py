@@ -43,6 +43,13 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_render_loss(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, 0, 1, None, 10, None, 10,
                               None) == fipt.EINVAL
     assert b"increasing" in L.fipt_last_error()
+    sig = (C.c_float * 2)(0.2, 0.5)
+    for lam in (-1e-3, float("nan"), float("inf")):
+        assert L.fipt_render_loss_masked(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, None, 0, lam, 1,
+                                         None, 10, None, None, 10, None) == fipt.EINVAL
+        assert b"lambda_d" in L.fipt_last_error()
+    assert L.fipt_render_loss_masked(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, None, 2, 0.0, 1,
+                                     None, 10, None, None, 10, None) == fipt.EINVAL
     assert L.fipt_server_create(0, 1024, 4, 1 << 20, C.byref(out)) == fipt.EINVAL
     assert L.fipt_grid_gather(None, 5, 128, None, None, None, 1, 1, None, 1, None) == fipt.EINVAL
     assert L.fipt_scale_by(None, 1, None, None, None) == fipt.EINVAL
@@ -133,6 +140,10 @@ def test_binding_rejects_misshapen_buffers():
         fipt.fipt_render_loss(sh, mat, obs, sig, loss_buf=torch.zeros(1, dtype=torch.float64))
     with pytest.raises(ValueError):
         fipt.fipt_scale_by(z(10), torch.zeros(1, dtype=torch.float64), out=z(9))
+    with pytest.raises(ValueError):
+        fipt.fipt_render_loss_masked(sh, mat, obs, sig, alpha=z(9))
+    with pytest.raises(ValueError):
+        fipt.fipt_render_loss_masked(sh, mat, obs, sig, grad_alpha=z(11))
 
 
 @pytest.mark.parametrize("e", [-100, 100])

@@ -1,5 +1,6 @@
-"""GPU parity of the factored re-render, loss and gradient and of the
-trilinear material grid and its adjoint, through the C ABI.
+"""GPU parity of the factored re-render, loss and gradient, of the
+emission-masked loss with the diffuse prior, and of the trilinear material
+grid and its adjoint, through the C ABI.
 
 Sizes: 100,003 points (many workgroups and a ragged tail) and the full
 differentiation workload of 1,843,200 points; a 128^3 grid."""
@@ -92,6 +93,107 @@ def test_autograd_function_and_finite_differences():
             lm = float(fipt.fipt_render_loss(sh, _t(mm), obs, SIG, want_grad=False)[0][0].item())
             fd = (lp - lm) / (2 * eps)
             assert abs(fd - g[c, p] / 3.0) <= 2e-3 * max(1.0, abs(fd)), (p, c, fd, g[c, p] / 3.0)
+
+
+def _mask_inputs(n, seed):
+    """Random mask in [0, 1] with exact zeros and ones, and materials that
+    hit the prior's kinks (sigma = 1, m = 0) on a few points."""
+    rng = np.random.default_rng(seed)
+    alpha = rng.uniform(0, 1, n).astype(np.float32)
+    alpha[rng.random(n) < 0.1] = 0.0
+    alpha[rng.random(n) < 0.05] = 1.0
+    mat = synth.random_materials(n, seed=seed + 1)
+    mat[3, rng.random(n) < 0.02] = 1.0
+    mat[4, rng.random(n) < 0.02] = 0.0
+    return alpha, mat
+
+
+@pytest.mark.parametrize("n", [1, 63, 100003, 1843200])
+@pytest.mark.parametrize("tone", [0, 1])
+def test_masked_loss_parity(n, tone):
+    """Emission-masked loss with the diffuse prior (Eq. 12 / 15, 17) against
+    the oracle: loss, material and mask gradients, Lr."""
+    sh = synth.random_shading(n, 6, seed=n % 79 + 5)
+    alpha, mat = _mask_inputs(n, n % 73 + 6)
+    obs = synth.random_observations(n, seed=n % 71 + 7)
+    lam = 5e-4
+    loss_o, grad_o, ga_o, lr_o = orr.masked_loss_and_grad(sh, mat, obs, alpha, SIG, tone, lam)
+    buf, grad, ga, lr = fipt.fipt_render_loss_masked(_t(sh), _t(mat), _t(obs), SIG, _t(alpha), lam,
+                                                     tone, want_lr=True)
+    torch.cuda.synchronize()
+    loss_g = float(buf[0].item())
+    assert abs(loss_g - loss_o) <= 1e-6 * abs(loss_o), (loss_g, loss_o)
+    assert_close_rel(grad.cpu().numpy(), grad_o, 1e-4, what="material gradient")
+    assert_close_rel(ga.cpu().numpy()[None, :], ga_o[None, :], 1e-4, what="mask gradient")
+    assert_close_rel(lr.cpu().numpy(), lr_o, 1e-5, what="Lr")
+    buf2, grad2, ga2, _ = fipt.fipt_render_loss_masked(_t(sh), _t(mat), _t(obs), SIG, _t(alpha),
+                                                       lam, tone)
+    torch.cuda.synchronize()
+    assert float(buf2[0].item()) == loss_g
+    assert torch.equal(grad2, grad) and torch.equal(ga2, ga)
+
+
+@pytest.mark.parametrize("tone", [0, 1])
+def test_masked_without_mask_or_prior_is_the_plain_loss_bitwise(tone):
+    n = 100003
+    sh = _t(synth.random_shading(n, 6, seed=21))
+    mat = _t(synth.random_materials(n, seed=22))
+    obs = _t(synth.random_observations(n, seed=23))
+    buf, grad, lr = fipt.fipt_render_loss(sh, mat, obs, SIG, tone, want_lr=True)
+    for alpha in (None, torch.zeros(n, dtype=torch.float32, device=DEV)):
+        b2, g2, _, l2 = fipt.fipt_render_loss_masked(sh, mat, obs, SIG, alpha, 0.0, tone,
+                                                     want_grad_alpha=False, want_lr=True)
+        torch.cuda.synchronize()
+        assert float(b2[0].item()) == float(buf[0].item())
+        assert torch.equal(g2, grad) and torch.equal(l2, lr)
+
+
+def test_masked_outputs_are_independent():
+    """Each output can be asked for alone: the mask gradient without the
+    material gradient and the loss alone give the same values."""
+    n = 4099
+    sh = synth.random_shading(n, 6, seed=24)
+    alpha, mat = _mask_inputs(n, 25)
+    obs = synth.random_observations(n, seed=26)
+    args = (_t(sh), _t(mat), _t(obs), SIG, _t(alpha), 0.01, 1)
+    full = fipt.fipt_render_loss_masked(*args)
+    only_a = fipt.fipt_render_loss_masked(*args, want_grad=False)
+    only_l = fipt.fipt_render_loss_masked(*args, want_grad=False, want_grad_alpha=False)
+    torch.cuda.synchronize()
+    assert only_a[1] is None and only_l[1] is None and only_l[2] is None
+    assert torch.equal(only_a[2], full[2])
+    assert float(only_a[0][0].item()) == float(full[0][0].item()) == float(only_l[0][0].item())
+
+
+def test_masked_autograd_function():
+    n = 3000
+    sh = _t(synth.random_shading(n, 6, seed=27))
+    alpha_n, mat_n = _mask_inputs(n, 28)
+    obs = _t(synth.random_observations(n, seed=29))
+    mat = _t(mat_n).requires_grad_(True)
+    alpha = _t(alpha_n).requires_grad_(True)
+    loss = fipt.MaskedFactoredLoss.apply(mat, alpha, sh, obs, SIG, 1, 5e-4)
+    (2.5 * loss).backward()
+    _, grad_o, ga_o, _ = orr.masked_loss_and_grad(sh.cpu().numpy(), mat_n, obs.cpu().numpy(),
+                                                  alpha_n, SIG, 1, 5e-4)
+    assert_close_rel(mat.grad.cpu().numpy(), 2.5 * grad_o, 1e-4, what="autograd material")
+    assert_close_rel(alpha.grad.cpu().numpy()[None, :], 2.5 * ga_o[None, :], 1e-4,
+                     what="autograd mask")
+
+
+def test_masked_rejects_bad_arguments():
+    n = 64
+    sh = _t(synth.random_shading(n, 6, seed=30))
+    mat = _t(synth.random_materials(n, seed=31))
+    obs = _t(synth.random_observations(n, seed=32))
+    for lam in (-1e-3, float("nan"), float("inf")):
+        with pytest.raises(fipt.FiptError):
+            fipt.fipt_render_loss_masked(sh, mat, obs, SIG, None, lam)
+    with pytest.raises(ValueError):
+        fipt.fipt_render_loss_masked(sh, mat, obs, SIG, torch.zeros(n - 1, device=DEV), 0.0)
+    with pytest.raises(ValueError):
+        fipt.fipt_render_loss_masked(sh, mat, obs, SIG, None, 0.0,
+                                     grad_alpha=torch.zeros(n + 1, device=DEV))
 
 
 def test_grid_gather_parity():
