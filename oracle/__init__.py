@@ -12,6 +12,8 @@ seeded inputs from ``synth``.
                      (Eq. 5, 8, 2/15), the emission-masked loss (Eq. 12/15)
                      with the diffuse prior (Eq. 17), trilinear material
                      grid and its adjoint, in numpy float64;
+* ``oracle.cache``   the voxel radiance cache: average pooling of observed
+                     pixels onto a grid and the nearest-voxel index (Sec. 4.2);
 * ``oracle.emission`` per-triangle emission re-estimation (Eq. 13 with
                      f = 0: the median of the observed pixels), in numpy.
 """

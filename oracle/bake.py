@@ -38,6 +38,8 @@ def lib():
     L.orc_scene_new.argtypes = [_f32p, C.c_int64, _i32p, C.c_int64, C.c_int,
                                 _f32p, _f32p, C.c_double, C.c_double]
     L.orc_scene_free.argtypes = [C.c_void_p]
+    L.orc_scene_set_voxel.restype = C.c_int
+    L.orc_scene_set_voxel.argtypes = [C.c_void_p, _f32p, C.c_int, _f64p, _f64p]
     L.orc_philox.argtypes = [_u32p, _u32p, _u32p, C.c_int64]
     L.orc_lobe_uniforms.argtypes = [C.c_uint64, _i64p, _i32p, _i32p, _i32p, C.c_int64,
                                     _f64p, _f64p]
@@ -89,6 +91,18 @@ class OracleScene:
         self._keep = (verts, tris, cache, emission)
         self.handle = lib().orc_scene_new(verts, len(verts), tris, len(tris), kind,
                                           cache, emission, tol_rel, max_t)
+
+    def set_voxel_cache(self, cache, res: int, lo, hi):
+        """Use a voxel grid cache [3, res^3] (x fastest) over the box
+        [lo, hi] instead of the scene's own cache: a hit reads the voxel
+        that contains it (Sec. 4.2, nearest-voxel query)."""
+        c = np.ascontiguousarray(cache, dtype=np.float32).reshape(3, -1)
+        if c.shape[1] != res ** 3:
+            raise ValueError("cache must be [3, res^3]")
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        if lib().orc_scene_set_voxel(self.handle, c, int(res), lo, hi) != 0:
+            raise ValueError("bad voxel grid")
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

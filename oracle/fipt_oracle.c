@@ -18,7 +18,11 @@
  *   - the shading integrals of Eq. 6 with the Fresnel split of Eq. 7,
  *     estimated by importance-sampled Monte Carlo with the stage-1 radiance
  *     query of Eq. 9 (incident radiance = radiance cache + per-triangle
- *     emission at the first hit, zero on a miss):
+ *     emission at the first hit, zero on a miss); the cache is per
+ *     triangle, per vertex (barycentric blend), or, as Sec. 4.2 builds it,
+ *     a voxel grid read at the voxel that contains the hit point (nearest
+ *     voxel; voxel (i, j, k) of an R^3 grid over [lo, hi] holds the points
+ *     with floor((x - lo) R / (hi - lo)) = (i, j, k), clamped to the grid):
  *       Ld       = mean over cosine-distributed wi of R
  *       Ls0_k    = mean over GGX-sampled half vectors of R * F0 * w
  *       Ls1_k    = mean over GGX-sampled half vectors of R * F1 * w
@@ -239,8 +243,11 @@ typedef struct {
     double* slack; /* [T] barycentric slack covering the largest tolerance */
     double* emin;  /* [T] 1e-14 * |e1| |e2| (parallel-ray threshold) */
     int32_t* tri;  /* [T][3] */
-    int cache_kind;            /* 0: per triangle [3][T], 1: per vertex [3][V] */
+    int cache_kind;            /* 0: per triangle [3][T], 1: per vertex [3][V],
+                                  2: voxel grid [3][R^3], x fastest */
     double* cache;             /* [3][n] */
+    int vox_res;               /* R */
+    double vox_lo[3], vox_hi[3];
     double* emission;          /* [3][T] */
     double tol_rel;            /* ambiguity tolerance, relative to 1 + t */
 } scene_t;
@@ -293,6 +300,29 @@ void* orc_scene_new(const float* verts, int64_t V, const int32_t* tris, int64_t 
         S->emin[f] = 1e-14 * l_e1 * l_e2;
     }
     return S;
+}
+
+/* Switch the scene's cache to a voxel grid: cache [3][res^3] (x fastest)
+ * over the box [lo, hi]. */
+int orc_scene_set_voxel(void* sp, const float* cache, int res, const double* lo, const double* hi)
+{
+    scene_t* S = (scene_t*)sp;
+    if (res < 1) return -1;
+    for (int a = 0; a < 3; ++a)
+        if (!(hi[a] > lo[a])) return -1;
+    int64_t nv = (int64_t)res * res * res;
+    double* c = (double*)malloc(sizeof(double) * 3 * nv);
+    if (!c) return -1;
+    for (int64_t i = 0; i < 3 * nv; ++i) c[i] = (double)cache[i];
+    free(S->cache);
+    S->cache = c;
+    S->cache_kind = 2;
+    S->vox_res = res;
+    for (int a = 0; a < 3; ++a) {
+        S->vox_lo[a] = lo[a];
+        S->vox_hi[a] = hi[a];
+    }
+    return 0;
 }
 
 void orc_scene_free(void* p)
@@ -406,9 +436,37 @@ static void cast(const scene_t* S, const double o[3], const double d[3], cast_t*
     out->n_cand = n;
 }
 
+/* Hit point of a hit: v0 + b1 e1 + b2 e2. */
+static void hit_point(const scene_t* S, const hit_t* h, double x[3])
+{
+    int64_t f = h->tri;
+    for (int a = 0; a < 3; ++a)
+        x[a] = S->v0[3 * f + a] + h->b1 * S->e1[3 * f + a] + h->b2 * S->e2[3 * f + a];
+}
+
+/* Voxel coordinate of x along axis a (before flooring). */
+static double voxel_coord(const scene_t* S, const double x[3], int a)
+{
+    return (x[a] - S->vox_lo[a]) * S->vox_res / (S->vox_hi[a] - S->vox_lo[a]);
+}
+
+static int voxel_clamp(const scene_t* S, double u)
+{
+    double i = floor(u);
+    if (i < 0.0) return 0;
+    if (i > S->vox_res - 1) return S->vox_res - 1;
+    return (int)i;
+}
+
+static int64_t voxel_linear(const scene_t* S, int i, int j, int k)
+{
+    return ((int64_t)k * S->vox_res + j) * S->vox_res + i;
+}
+
 /* Radiance leaving the hit toward the ray origin: radiance cache (per
- * triangle, or per vertex interpolated with barycentric weights) plus the
- * triangle's emission; zero on a miss (Eq. 9 with per-triangle emission). */
+ * triangle, per vertex interpolated with barycentric weights, or the voxel
+ * that contains the hit point) plus the triangle's emission; zero on a miss
+ * (Eq. 9 with per-triangle emission). */
 static void radiance(const scene_t* S, const hit_t* h, int clamp, double R[3])
 {
     if (h->tri < 0) {
@@ -417,7 +475,15 @@ static void radiance(const scene_t* S, const hit_t* h, int clamp, double R[3])
     }
     int64_t f = h->tri;
     for (int c = 0; c < 3; ++c) R[c] = S->emission[c * S->T + f];
-    if (S->cache_kind == 0) {
+    if (S->cache_kind == 2) {
+        double x[3];
+        hit_point(S, h, x);
+        int64_t v = voxel_linear(S, voxel_clamp(S, voxel_coord(S, x, 0)),
+                                 voxel_clamp(S, voxel_coord(S, x, 1)),
+                                 voxel_clamp(S, voxel_coord(S, x, 2)));
+        int64_t nv = (int64_t)S->vox_res * S->vox_res * S->vox_res;
+        for (int c = 0; c < 3; ++c) R[c] += S->cache[c * nv + v];
+    } else if (S->cache_kind == 0) {
         for (int c = 0; c < 3; ++c) R[c] += S->cache[c * S->T + f];
     } else {
         double w1 = h->b1, w2 = h->b2, w0 = 1.0 - w1 - w2;
@@ -433,6 +499,39 @@ static void radiance(const scene_t* S, const hit_t* h, int clamp, double R[3])
     }
 }
 
+/* With a voxel cache: widen [Rmin, Rmax] by the radiance of every voxel
+ * whose face lies within the rounding band of the hit point (single
+ * precision may place the point in either voxel).  Returns 1 if it did. */
+static int voxel_ties(const scene_t* S, const hit_t* h, double Rmin[3], double Rmax[3])
+{
+    if (S->cache_kind != 2 || h->tri < 0) return 0;
+    double x[3];
+    hit_point(S, h, x);
+    double mag = fmax(fabs(x[0]), fmax(fabs(x[1]), fabs(x[2])));
+    int lo_i[3], hi_i[3], wide = 0;
+    for (int a = 0; a < 3; ++a) {
+        double band = S->tol_rel * (1.0 + h->t + mag) * S->vox_res / (S->vox_hi[a] - S->vox_lo[a]);
+        double u = voxel_coord(S, x, a);
+        lo_i[a] = voxel_clamp(S, u - band);
+        hi_i[a] = voxel_clamp(S, u + band);
+        if (hi_i[a] != lo_i[a]) wide = 1;
+    }
+    if (!wide) return 0;
+    int64_t nv = (int64_t)S->vox_res * S->vox_res * S->vox_res;
+    int64_t f = h->tri;
+    for (int k = lo_i[2]; k <= hi_i[2]; ++k)
+        for (int j = lo_i[1]; j <= hi_i[1]; ++j)
+            for (int i = lo_i[0]; i <= hi_i[0]; ++i) {
+                int64_t v = voxel_linear(S, i, j, k);
+                for (int c = 0; c < 3; ++c) {
+                    double r = S->emission[c * S->T + f] + S->cache[c * nv + v];
+                    Rmin[c] = fmin(Rmin[c], r);
+                    Rmax[c] = fmax(Rmax[c], r);
+                }
+            }
+    return 1;
+}
+
 /* Nominal radiance plus its per-channel minimum and maximum over every
  * outcome single precision may produce. */
 static int radiance_envelope(const scene_t* S, const cast_t* h, double R[3],
@@ -440,7 +539,7 @@ static int radiance_envelope(const scene_t* S, const cast_t* h, double R[3],
 {
     radiance(S, &h->nominal, 0, R);
     for (int c = 0; c < 3; ++c) Rmin[c] = Rmax[c] = R[c];
-    int ambiguous = 0;
+    int ambiguous = voxel_ties(S, &h->nominal, Rmin, Rmax);
     for (int i = 0; i < h->n_cand; ++i) {
         double r[3];
         radiance(S, &h->cand[i], 1, r);
@@ -448,6 +547,7 @@ static int radiance_envelope(const scene_t* S, const cast_t* h, double R[3],
             Rmin[c] = fmin(Rmin[c], r[c]);
             Rmax[c] = fmax(Rmax[c], r[c]);
         }
+        ambiguous |= voxel_ties(S, &h->cand[i], Rmin, Rmax);
     }
     if (h->n_cand > 1 || (h->n_cand == 1 && h->cand[0].tri != h->nominal.tri)) ambiguous = 1;
     return ambiguous;
