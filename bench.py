@@ -46,6 +46,7 @@ LOSS_BYTES_PER_POINT = 112
 # the masked loss also reads alpha and writes d loss / d alpha
 MASKED_LOSS_BYTES_PER_POINT = 120
 LAMBDA_D = 5e-4        # weight of the diffuse prior, as in Eq. 17
+VOXEL_RES = 256        # the radiance cache grid of Sec. 4.2
 SHADING_PLANES = 39
 COUNTERS = os.path.join(ROOT, "profiles", "counters_room.json")
 # the sources each measured kernel is built from
@@ -53,6 +54,7 @@ KERNEL_SOURCES = {
     "k_bake": ("bake.hip", "device.hpp", "fipt_internal.hpp", "bvh_build.cpp"),
     "k_render_loss": ("loss.hip", "fipt_internal.hpp"),
     "k_render_loss_masked": ("loss.hip", "fipt_internal.hpp"),
+    "k_bake_voxel": ("bake.hip", "device.hpp", "fipt_internal.hpp", "bvh_build.cpp"),
 }
 
 
@@ -329,6 +331,53 @@ def loss_timing(shading, mat, obs, sigma, reps=10, flush=None, alpha=None, lambd
     return float(np.mean(tm.spans("a", "b")))
 
 
+def run_voxel(scene, sc, planes, tri, obs, out, reps=3):
+    """The radiance cache as Sec. 4.2 builds it, on the room: the
+    observations pooled onto a 256^3 voxel grid over the room's box, then
+    bakes whose radiance query reads the voxel of each hit (plus the
+    triangles' emission).  The scene's own cache is restored afterwards."""
+    R = VOXEL_RES
+    N = planes.shape[1]
+    S = sc.spp * (1 + len(sc.sigma))
+    bmin, bmax = sc.bmin.tolist(), sc.bmax.tolist()
+    t0 = time.perf_counter()
+    plan = fipt.VoxelPlan(planes[0:3].cpu().numpy(), R, bmin, bmax)
+    plan_s = time.perf_counter() - t0
+    cache = plan.pool(obs)
+    torch.cuda.synchronize()
+    torch.cuda._sleep(5_000_000)
+    tm = Timer()
+    for _ in range(reps):
+        tm.mark("a")
+        plan.pool(obs, out=cache)
+        tm.mark("b")
+    torch.cuda.synchronize()
+    t_pool = float(np.mean(tm.spans("a", "b")))
+    occupied = int((cache.abs().sum(0) > 0).sum().item())
+    em = torch.from_numpy(sc.emission).to(obs.device)
+    scene.set_voxel_radiance(cache, R, bmin, bmax, em)
+    fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out)
+    torch.cuda.synchronize()
+    tb = Timer()
+    for _ in range(reps):
+        tb.mark("a")
+        fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out)
+        tb.mark("b")
+    torch.cuda.synchronize()
+    t_bake = float(np.mean(tb.spans("a", "b")))
+    kind = fipt.CACHE_VERTEX if sc.cache_kind == "vertex" else fipt.CACHE_TRIANGLE
+    scene.set_radiance(torch.from_numpy(sc.cache).to(obs.device), kind, em)
+    torch.cuda.synchronize()
+    pool_bytes = 16 * (R ** 3 + N)
+    del plan, cache
+    return {"res": R, "kernel": "k_bake<false, true, true>",
+            "traffic": measured_traffic().get("k_bake_voxel"), "plan_build_s": plan_s, "pool_ms": t_pool, "pool_bytes": pool_bytes,
+            "pool_gbs": pool_bytes / (t_pool * 1e-3) / 1e9, "occupied_voxels": occupied,
+            "bake_ms": t_bake, "gsamples_per_s": N * S / (t_bake * 1e-3) / 1e9,
+            "note": "pool bytes: start index and output per voxel (4 + 12 B), order index and "
+                    "observation per pixel (4 + 12 B)"}
+
+
 def run_large(dev, rebakes, copy_gbs):
     """The emitter loop on the ~2M-triangle room: ``rebakes`` iterations,
     each re-estimating the per-triangle emission of that iteration's emitter
@@ -545,6 +594,8 @@ def main():
                         "points_per_s": N / (warm * 1e-3)}
     log(f"masked loss: {masked}")
     del flush, alpha
+    voxel = run_voxel(scene, sc, planes, tri, obs, shading)
+    log(f"voxel cache: {voxel}")
 
     large = None
     if args.large_rebakes > 0:
@@ -597,6 +648,7 @@ def main():
                      "effective_traversal_gbs": bake_bytes / (t_bake * 1e-3) / 1e9 if trav else None,
                      "traversal_bytes_per_launch": bake_bytes},
         "masked_loss": masked,
+        "voxel_cache": voxel,
         "roofline_render_loss": {"bound": "hbm", "achieved": loss_gbs, "peak": PEAK_HBM_GBS,
                                  "unit": "GB/s", "frac": loss_gbs / PEAK_HBM_GBS,
                                  "traffic": traffic.get("k_render_loss"),

@@ -25,7 +25,9 @@
  *   - Layout: per-point data are structure-of-arrays float planes; plane k of
  *     a buffer starts at base + k * stride elements.
  *   - No call allocates device memory except fipt_scene_create,
- *     fipt_grid_plan_create and fipt_server_create (and their set-up calls).
+ *     fipt_scene_set_voxel_radiance, the plan constructors
+ *     (fipt_grid_plan_create, fipt_emission_plan_create,
+ *     fipt_voxel_plan_create) and fipt_server_create.
  */
 #ifndef FIPT_H
 #define FIPT_H
@@ -52,6 +54,8 @@ extern "C" {
 #define FIPT_CACHE_TRIANGLE 0   /* one RGB value per triangle, [3][T]          */
 #define FIPT_CACHE_VERTEX 1     /* one RGB value per vertex, [3][V], linear
                                    (barycentric) interpolation over triangles */
+#define FIPT_CACHE_VOXEL 2      /* voxel grid, nearest voxel of the hit point
+                                   (fipt_scene_set_voxel_radiance)            */
 
 /* Tone maps of the loss (fipt_render_loss). */
 #define FIPT_TONEMAP_NONE 0     /* Gamma(x) = x                                */
@@ -60,6 +64,7 @@ extern "C" {
 typedef struct fipt_scene_s* fipt_scene;
 typedef struct fipt_grid_plan_s* fipt_grid_plan;
 typedef struct fipt_emission_plan_s* fipt_emission_plan;
+typedef struct fipt_voxel_plan_s* fipt_voxel_plan;
 typedef struct fipt_server_s* fipt_server;
 
 /* Pinhole camera: rays leave `pos` through pixel centres; `fwd` is the view
@@ -170,6 +175,25 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris,
  * float planes; read on `stream`, not retained. */
 int fipt_scene_set_radiance(fipt_scene s, int32_t cache_kind, const float* cache,
                             int64_t n_cache, const float* emission, void* stream);
+
+/* Set a voxel-grid radiance cache, the form Sec. 4.2 gives L' (average of
+ * the observed pixels per voxel, queried at the nearest voxel): a hit at x
+ * reads voxel (i, j, k) = floor((x - bmin) res / (bmax - bmin)) per axis,
+ * clamped to [0, res - 1], whose value is cache[c][(k res + j) res + i]
+ * (device float [3][cache_stride], cache_stride >= res^3, as written by
+ * fipt_voxel_pool), and adds the triangle's emission Le ([3][n_tris],
+ * NULL = zero).  1 <= res <= 512; bmin_host < bmax_host (host float [3]),
+ * finite.  The scene keeps its own sparse copy (a voxel whose three values
+ * are all zero is empty: 16 bytes per 64 voxels plus 16 bytes per occupied
+ * voxel, kept until the scene is destroyed or a larger grid is set); the
+ * bake reads it until fipt_scene_set_radiance selects another cache.  The
+ * call waits for the device to finish earlier work and reads the occupied
+ * count back, so it is a set-up call, not one to capture.  On an error the
+ * scene is left with no cache (emission only).  Serving
+ * (fipt_server_submit) rejects scenes with a voxel cache. */
+int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cache_stride,
+                                  int32_t res, const float* bmin_host, const float* bmax_host,
+                                  const float* emission, void* stream);
 
 /* Replace the per-triangle emission only (device [3][n_tris]); the cache set
  * last is kept.  Used between re-bakes when emitters are re-estimated. */
@@ -337,6 +361,27 @@ int fipt_grid_plan_destroy(fipt_grid_plan plan);
  * with the same plan must not overlap (one stream, or ordered streams). */
 int fipt_grid_scatter(fipt_grid_plan plan, const float* grad_points, int32_t channels,
                       int64_t gp_stride, float* grad_grid, void* stream);
+
+/* ---- voxel radiance cache (Sec. 4.2) ------------------------------------ */
+
+/* Average pooling of observed pixels onto a voxel grid, the radiance cache
+ * L' that Sec. 4.2 queries in Eq. 9.  The plan sorts the pixels by voxel
+ * once: pos_host[3][n] (host float) are the pixels' surface points, each in
+ * voxel floor((x - bmin) res / (bmax - bmin)) per axis, clamped to
+ * [0, res - 1] (computed in double).  1 <= n < 2^31, 1 <= res <= 512,
+ * bmin_host < bmax_host (host float [3]), finite.  The plan owns device
+ * memory (4 (res^3 + 1 + n) bytes). */
+int fipt_voxel_plan_create(const float* pos_host, int64_t n, int32_t res, const float* bmin_host,
+                           const float* bmax_host, int32_t device, fipt_voxel_plan* out);
+int fipt_voxel_plan_destroy(fipt_voxel_plan plan);
+
+/* cache[c][v] (device float [3][cache_stride], cache_stride >= res^3) :=
+ * the mean of observed[c][p] (device float [3][obs_stride], obs_stride >=
+ * n) over the plan's pixels p in voxel v, summed in double in pixel order,
+ * or 0 for a voxel no pixel falls in.  Every voxel is written, so results
+ * are bitwise reproducible.  Asynchronous on `stream`. */
+int fipt_voxel_pool(fipt_voxel_plan plan, const float* observed, int64_t obs_stride, float* cache,
+                    int64_t cache_stride, void* stream);
 
 /* ---- emission re-estimation (Sec. 4.4, Eq. 13) ------------------------- */
 

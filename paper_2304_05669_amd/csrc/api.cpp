@@ -75,6 +75,9 @@ void scene_free(fipt_scene s) {
     if (s->d_nodes) (void)hipFree(s->d_nodes);
     if (s->d_tris) (void)hipFree(s->d_tris);
     if (s->d_rad) (void)hipFree(s->d_rad);
+    if (s->d_vox) (void)hipFree(s->d_vox);
+    if (s->d_vox_words) (void)hipFree(s->d_vox_words);
+    if (s->d_vox_total) (void)hipFree(s->d_vox_total);
     if (s->d_order) (void)hipFree(s->d_order);
     if (s->d_tri_idx) (void)hipFree(s->d_tri_idx);
     if (s->d_counters) (void)hipFree(s->d_counters);
@@ -237,6 +240,80 @@ int fipt_scene_set_radiance(fipt_scene s, int32_t cache_kind, const float* cache
                                  n_cache, emission, stream);
     if (rc == FIPT_OK) s->cache_kind = cache_kind;
     return rc;
+}
+
+int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cache_stride,
+                                  int32_t res, const float* bmin_host, const float* bmax_host,
+                                  const float* emission, void* stream) {
+    clear_error();
+    if (!s) return fail(FIPT_EINVAL, "scene is NULL");
+    if (!cache || !bmin_host || !bmax_host) return fail(FIPT_EINVAL, "cache/bmin/bmax is NULL");
+    if (res < 1 || res > kMaxVoxelRes)
+        return fail(FIPT_EINVAL, "res must be in [1, %d], got %d", kMaxVoxelRes, res);
+    const int64_t n_vox = (int64_t)res * res * res;
+    if (cache_stride < n_vox) return fail(FIPT_EINVAL, "cache_stride < res^3");
+    float scale[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(bmin_host[a]) || !std::isfinite(bmax_host[a]) ||
+            !(bmax_host[a] > bmin_host[a]))
+            return fail(FIPT_EINVAL, "the box must be finite with bmin < bmax on every axis");
+        scale[a] = (float)((double)res / ((double)bmax_host[a] - (double)bmin_host[a]));
+        if (!std::isfinite(scale[a]) || !(scale[a] > 0.0f))
+            return fail(FIPT_EINVAL, "the box is too thin for single precision");
+    }
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n_words = (n_vox + 63) >> 6;
+    // the bake may still be reading the old grid: wait before replacing it;
+    // until the new grid is complete the scene reads no voxel cache
+    HIP_TRY(hipDeviceSynchronize());
+    s->cache_kind = -1;
+    if (!s->d_vox_total) {
+        int rc = dev_alloc(&s->d_vox_total, 1, &s->bytes);
+        if (rc) return rc;
+    }
+    if (s->vox_word_capacity < n_words) {
+        if (s->d_vox_words) {
+            (void)hipFree(s->d_vox_words);
+            s->bytes -= 16 * s->vox_word_capacity;
+            s->d_vox_words = nullptr;
+            s->vox_word_capacity = 0;
+        }
+        int rc = dev_alloc(&s->d_vox_words, (size_t)n_words, &s->bytes);
+        if (rc) return rc;
+        s->vox_word_capacity = n_words;
+    }
+    int rc = launch_voxel_words(s->d_vox_words, cache, cache_stride, n_vox, s->d_vox_total, stream);
+    if (rc) return rc;
+    int64_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, s->d_vox_total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (s->vox_capacity < std::max<int64_t>(total, 1)) {
+        if (s->d_vox) {
+            (void)hipFree(s->d_vox);
+            s->bytes -= 16 * s->vox_capacity;
+            s->d_vox = nullptr;
+            s->vox_capacity = 0;
+        }
+        const int64_t cap = std::max<int64_t>(total, 1);
+        rc = dev_alloc(&s->d_vox, (size_t)cap, &s->bytes);
+        if (rc) return rc;
+        s->vox_capacity = cap;
+    }
+    rc = launch_voxel_compact(s->d_vox, s->d_vox_words, cache, cache_stride, n_vox, stream);
+    if (rc) return rc;
+    // corner values zero, emission as given
+    rc = launch_set_radiance(s->d_rad, s->d_order, s->d_tri_idx, s->n_tris, FIPT_CACHE_TRIANGLE,
+                             nullptr, s->n_tris, emission, stream);
+    if (rc) return rc;
+    s->vox_res = res;
+    for (int a = 0; a < 3; ++a) {
+        s->vox_lo[a] = bmin_host[a];
+        s->vox_scale[a] = scale[a];
+    }
+    s->cache_kind = FIPT_CACHE_VOXEL;
+    return FIPT_OK;
 }
 
 int fipt_scene_set_emission(fipt_scene s, const float* emission, void* stream) {

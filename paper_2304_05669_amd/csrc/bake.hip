@@ -57,7 +57,7 @@ __device__ __forceinline__ int slot_plane(int j, int K) {
 }
 
 // Bake point p of job b with the calling wavefront.
-template <bool COUNT>
+template <bool COUNT, bool VOXEL>
 __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sigma, int64_t p, int lane,
                                            int32_t* stack, uint32_t& n_rays, uint32_t& n_nodes,
                                            uint32_t& n_tris, uint32_t& n_hits) {
@@ -136,7 +136,7 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sig
             if (COUNT) ++n_rays;
             h = dev::trace<COUNT>(b.sc, o, wi, stack, kBlock, n_nodes, n_tris);
             if (COUNT && h.leaf >= 0) ++n_hits;
-            const V3 R = dev::radiance(b.sc, h);
+            const V3 R = VOXEL ? dev::radiance_voxel(b.sc, h, o, wi) : dev::radiance(b.sc, h);
             if (lobe == 0) {
                 c0 = R.x;
                 c1 = R.y;
@@ -210,7 +210,7 @@ __device__ __forceinline__ bool is_leaf(int32_t ref) {
     return (uint32_t)ref > (uint32_t)kDone;
 }
 
-template <bool COUNT>
+template <bool COUNT, bool VOXEL>
 __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const float* sigma, int64_t p,
                                                   int lane,
                                                   int32_t* stack, uint32_t& n_rays,
@@ -298,7 +298,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
             const bool done = state == kFinished;
             flush(done && cur_lobe >= 0 && cur_lobe != lobe);
             if (done) {
-                const V3 R = dev::radiance(sc, h);
+                const V3 R = VOXEL ? dev::radiance_voxel(sc, h, o, d) : dev::radiance(sc, h);
                 if (COUNT && h.leaf >= 0) ++n_hits;
                 if (cur_lobe != lobe) {
                     cur0 = cur1 = cur2 = cur3 = cur4 = cur5 = 0.0f;
@@ -453,7 +453,7 @@ __device__ __forceinline__ int64_t next_point(int32_t* counters, int home, int& 
 // workgroups fit a CU's 160 KB) measured ~3 % faster than four.
 #define FIPT_BAKE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(5, 8)))
 
-template <bool COUNT, bool REFILL>
+template <bool COUNT, bool REFILL, bool VOXEL>
 __global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake(BakeLaunch b, int32_t* counters,
                                                                      uint64_t* stats) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
@@ -464,10 +464,10 @@ __global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake(BakeLaunch 
     int tried = 0;
     for (int64_t p; (p = next_point(counters, home, tried, b.n, lane)) >= 0;) {
         if (REFILL)
-            bake_point_refill<COUNT>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits,
+            bake_point_refill<COUNT, VOXEL>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits,
                                      n_node_steps, n_tri_steps);
         else
-            bake_point<COUNT>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
+            bake_point<COUNT, VOXEL>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
     }
     if (COUNT) {
         // lane counters -> wave totals -> one 64-bit atomic per wave
@@ -493,6 +493,8 @@ __device__ __forceinline__ BakeLaunch uniform_job(const BakeLaunch& j) {
     b.sc.rad = static_cast<const TriRad*>(up(j.sc.rad));
     b.sc.n_tris = wave_uniform(j.sc.n_tris);
     b.sc.box_scale = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(j.sc.box_scale)));
+    b.sc.vox = nullptr;   // serving scenes have no voxel cache
+    b.sc.vox_res = 0;
     b.pts = static_cast<const float*>(up(j.pts));
     b.ptri = static_cast<const int32_t*>(up(j.ptri));
     b.pts_stride = wave_uniform(j.pts_stride);
@@ -534,9 +536,9 @@ __global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake_tiles(const
         const float* sigma = tiles[lo].job.sigma;
         const int64_t q = p - tiles[lo].first;
         if (job.K <= kRefillMaxK)
-            bake_point_refill<false>(job, sigma, q, lane, stack, a, bb, c, d, e, f);
+            bake_point_refill<false, false>(job, sigma, q, lane, stack, a, bb, c, d, e, f);
         else
-            bake_point<false>(job, sigma, q, lane, stack, a, bb, c, d);
+            bake_point<false, false>(job, sigma, q, lane, stack, a, bb, c, d);
     }
 }
 
@@ -726,14 +728,24 @@ int launch_bake(const BakeLaunch& b, int32_t* counters, uint64_t* stats, void* s
     // zeroed by a kernel, not a memset node, so a caller may capture the call
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, counters);
     const bool refill = b.K <= kRefillMaxK;
-    if (stats && refill)
-        hipLaunchKernelGGL((k_bake<true, true>), grid, block, 0, st, b, counters, stats);
+    if (b.sc.vox) {
+        // radiance from the voxel cache (Sec. 4.2)
+        if (stats && refill)
+            hipLaunchKernelGGL((k_bake<true, true, true>), grid, block, 0, st, b, counters, stats);
+        else if (stats)
+            hipLaunchKernelGGL((k_bake<true, false, true>), grid, block, 0, st, b, counters, stats);
+        else if (refill)
+            hipLaunchKernelGGL((k_bake<false, true, true>), grid, block, 0, st, b, counters, stats);
+        else
+            hipLaunchKernelGGL((k_bake<false, false, true>), grid, block, 0, st, b, counters, stats);
+    } else if (stats && refill)
+        hipLaunchKernelGGL((k_bake<true, true, false>), grid, block, 0, st, b, counters, stats);
     else if (stats)
-        hipLaunchKernelGGL((k_bake<true, false>), grid, block, 0, st, b, counters, stats);
+        hipLaunchKernelGGL((k_bake<true, false, false>), grid, block, 0, st, b, counters, stats);
     else if (refill)
-        hipLaunchKernelGGL((k_bake<false, true>), grid, block, 0, st, b, counters, stats);
+        hipLaunchKernelGGL((k_bake<false, true, false>), grid, block, 0, st, b, counters, stats);
     else
-        hipLaunchKernelGGL((k_bake<false, false>), grid, block, 0, st, b, counters, stats);
+        hipLaunchKernelGGL((k_bake<false, false, false>), grid, block, 0, st, b, counters, stats);
     return check_launch("bake");
 }
 

@@ -351,6 +351,36 @@ __device__ __forceinline__ V3 radiance(const DeviceScene& sc, const Hit& h) {
               w0 * r0.z + h.u * r1.y + h.v * r2.x + r2.w);
 }
 
+// Radiance at a hit with the voxel cache of Sec. 4.2: the value of the voxel
+// that contains the hit point o + t d (nearest-voxel query), plus the
+// triangle's emission (the last 16 bytes of its radiance record).  The
+// voxel coordinate is clamped in float before the conversion, so points
+// outside the grid read its border voxels and the conversion is exact.  The
+// grid is sparse: an occupancy word (bit mask of 64 voxels and the count of
+// occupied voxels before them) locates the value, and empty voxels read
+// zero without a second load.
+__device__ __forceinline__ V3 radiance_voxel(const DeviceScene& sc, const Hit& h, const V3& o,
+                                             const V3& d) {
+    if (h.leaf < 0) return v3(0.0f, 0.0f, 0.0f);
+    const float4 e = load_global(reinterpret_cast<const float4*>(sc.rad + h.leaf) + 2);
+    const float top = (float)(sc.vox_res - 1);
+    const float ux = fminf(fmaxf((fmaf(h.t, d.x, o.x) - sc.vox_lo[0]) * sc.vox_scale[0], 0.0f), top);
+    const float uy = fminf(fmaxf((fmaf(h.t, d.y, o.y) - sc.vox_lo[1]) * sc.vox_scale[1], 0.0f), top);
+    const float uz = fminf(fmaxf((fmaf(h.t, d.z, o.z) - sc.vox_lo[2]) * sc.vox_scale[2], 0.0f), top);
+    const int64_t r = sc.vox_res;
+    const int64_t v = ((int64_t)(int)uz * r + (int)uy) * r + (int)ux;
+    const int4 w = load_global(reinterpret_cast<const int4*>(sc.vox_words) + (v >> 6));
+    const uint64_t m = ((uint64_t)(uint32_t)w.y << 32) | (uint32_t)w.x;
+    const int b = (int)(v & 63);
+    V3 c = v3(e.y, e.z, e.w);
+    if ((m >> b) & 1ull) {
+        const uint32_t idx = (uint32_t)w.z + (uint32_t)__popcll(m & ((1ull << b) - 1ull));
+        const float4 q = load_global(sc.vox + idx);
+        c = v3(c.x + q.x, c.y + q.y, c.z + q.z);
+    }
+    return c;
+}
+
 // Lanes of the wave where p holds (the wave64 ballot on a boolean; HIP's
 // int-valued __ballot costs two extra instructions per call).
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }

@@ -123,6 +123,17 @@ struct DeviceScene {
     const TriRad* rad;
     int64_t n_tris;
     float box_scale;   // 2^E: the unit of the node bounds
+    // Voxel radiance cache (NULL unless the scene uses one), stored sparse:
+    // voxel v = (k R + j) R + i is occupied if bit v % 64 of word v / 64 is
+    // set (word = {mask low, mask high, occupied voxels before the word, 0});
+    // an occupied voxel's value (rgb, w unused) is vox[rank + occupied
+    // voxels before it in its word], an empty one is zero.  A point x lies
+    // in voxel floor((x - vox_lo) * vox_scale), clamped to [0, R - 1].
+    const uint4* vox_words;
+    const float4* vox;
+    int32_t vox_res;
+    float vox_lo[3];
+    float vox_scale[3];   // R / (hi - lo) per axis
 };
 
 int launch_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_idx,
@@ -130,6 +141,13 @@ int launch_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_id
                         const float* emission, void* stream);
 int launch_set_emission(TriRad* rad, const int32_t* order, int64_t n_tris,
                         const float* emission, void* stream);
+// Voxel cache planes [3][stride] -> the scene's sparse form: occupancy words
+// with ranks (and the occupied count in *total), then the occupied values.
+int launch_voxel_words(uint4* words, const float* cache, int64_t stride, int64_t n_vox,
+                       int64_t* total, void* stream);
+int launch_voxel_compact(float4* dst, const uint4* words, const float* cache, int64_t stride,
+                         int64_t n_vox, void* stream);
+constexpr int32_t kMaxVoxelRes = 512;
 // Cameras travel by value in the kernel arguments (no staging allocation).
 constexpr int kMaxCameras = 48;
 struct CameraTable {
@@ -233,6 +251,13 @@ struct fipt_scene_s {
     fipt::Bvh4Node* d_nodes = nullptr;   // 4-wide nodes
     fipt::TriGeom* d_tris = nullptr;
     fipt::TriRad* d_rad = nullptr;
+    uint4* d_vox_words = nullptr;  // voxel occupancy words, when cache_kind is FIPT_CACHE_VOXEL
+    int64_t vox_word_capacity = 0;
+    float4* d_vox = nullptr;       // occupied voxels' values
+    int64_t vox_capacity = 0;      // values allocated
+    int64_t* d_vox_total = nullptr;  // occupied count, read back by the set-up call
+    int32_t vox_res = 0;
+    float vox_lo[3] = {0, 0, 0}, vox_scale[3] = {0, 0, 0};
     int32_t* d_order = nullptr;    // leaf position -> original triangle
     int32_t* d_tri_idx = nullptr;  // original [T][3] vertex indices
     int32_t* d_counters = nullptr;  // [kBakeSlots][kXcdCount]
@@ -241,5 +266,10 @@ struct fipt_scene_s {
     std::mutex slot_mu;
     int64_t bytes = 0;
     std::atomic<int> refs{0};      // serving requests referencing the scene
-    fipt::DeviceScene view() const { return {d_nodes, d_tris, d_rad, n_tris, box_scale}; }
+    fipt::DeviceScene view() const {
+        const bool vox = cache_kind == FIPT_CACHE_VOXEL;
+        return {d_nodes, d_tris, d_rad, n_tris, box_scale, vox ? d_vox_words : nullptr,
+                vox ? d_vox : nullptr, vox ? vox_res : 0,
+                {vox_lo[0], vox_lo[1], vox_lo[2]}, {vox_scale[0], vox_scale[1], vox_scale[2]}};
+    }
 };

@@ -374,6 +374,8 @@ int fipt_server_submit(fipt_server srv, fipt_scene sc, const fipt_points* pts,
     int rc = check_bake_params(p);
     if (rc) return rc;
     if (sc->device != srv->device) return fail(FIPT_EINVAL, "scene and server are on different devices");
+    if (sc->cache_kind == FIPT_CACHE_VOXEL)
+        return fail(FIPT_EINVAL, "serving bakes scenes with a per-triangle or per-vertex cache");
     Request r;
     r.scene = sc;
     r.pts = *pts;

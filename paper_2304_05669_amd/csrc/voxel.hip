@@ -1,0 +1,295 @@
+// The voxel radiance cache of Sec. 4.2 for gfx950: average pooling of the
+// observed pixels onto a grid over the scene (the L' that the query of Eq. 9
+// reads), and the conversion of a grid into the scene's sparse form.
+//
+// The pixel-to-voxel map is fixed by the cameras, so a plan sorts the pixels
+// by voxel once (host counting sort, pixels of a voxel in index order) and
+// keeps a dense start array over all voxels.  The pooling kernel then runs
+// one thread per voxel over the whole grid: it sums its pixels' observations
+// in double, in pixel order, and writes the mean, or zero for an empty voxel,
+// so every voxel is written in one coalesced pass and the result does not
+// depend on scheduling.  The grid is ~4 (R^3 + n) bytes of plan and
+// 12 R^3 bytes of output: 268 MB in all at R = 256 for a million pixels,
+// which HBM holds with room to spare.
+//
+// The bake reads the grid at random surface points, so the scene keeps it
+// sparse: pixels only ever land on surfaces, and of the 16.8 M voxels of a
+// 256^3 grid over a room a few per cent are occupied.  One 16-byte word per
+// 64 voxels (occupancy bits and the number of occupied voxels before the
+// word) and the occupied values in voxel order take ~8 MB instead of 268 MB,
+// small enough to stay in the caches while the bake runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "fipt_internal.hpp"
+
+struct fipt_voxel_plan_s {
+    int32_t device = 0;
+    int64_t n = 0;           // pixels
+    int32_t res = 0;
+    int64_t n_vox = 0;       // res^3
+    int32_t* start = nullptr;  // [n_vox + 1] ranges into order
+    int32_t* order = nullptr;  // [n] pixels grouped by voxel, index order within one
+    int64_t bytes = 0;
+};
+
+namespace fipt {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void k_voxel_pool(const int32_t* __restrict__ start,
+                                                       const int32_t* __restrict__ order,
+                                                       int64_t n_vox,
+                                                       const float* __restrict__ obs, int64_t os,
+                                                       float* __restrict__ out, int64_t cs) {
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n_vox; v += step) {
+        const int32_t s = start[v], e = start[v + 1];
+        double r = 0.0, g = 0.0, b = 0.0;
+        int32_t i = s;
+        // four pixels' loads in flight at once; the additions keep pixel order
+        for (; i + 4 <= e; i += 4) {
+            int64_t p[4];
+            float q[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] = order[i + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                q[u][0] = obs[p[u]];
+                q[u][1] = obs[os + p[u]];
+                q[u][2] = obs[2 * os + p[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                r += q[u][0];
+                g += q[u][1];
+                b += q[u][2];
+            }
+        }
+        for (; i < e; ++i) {
+            const int64_t p = order[i];
+            r += obs[p];
+            g += obs[os + p];
+            b += obs[2 * os + p];
+        }
+        const int32_t k = e - s;
+        float mr = 0.0f, mg = 0.0f, mb = 0.0f;
+        if (k > 0) {
+            mr = (float)(r / (double)k);
+            mg = (float)(g / (double)k);
+            mb = (float)(b / (double)k);
+        }
+        out[v] = mr;
+        out[cs + v] = mg;
+        out[2 * cs + v] = mb;
+    }
+}
+
+// Occupancy of a grid given as planes [3][cs]: one wavefront per 64 voxels
+// (word), a voxel occupied when any channel is non-zero; .z holds the
+// word's occupied count until the scan turns it into a rank.
+__global__ __launch_bounds__(kBlock) void k_voxel_words(uint4* __restrict__ words,
+                                                        const float* __restrict__ cache,
+                                                        int64_t cs, int64_t n_vox) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_words = (n_vox + 63) >> 6;
+    const int64_t wave0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int64_t step = ((int64_t)gridDim.x * kBlock) >> 6;
+    for (int64_t w = wave0; w < n_words; w += step) {
+        const int64_t v = (w << 6) + lane;
+        bool occ = false;
+        if (v < n_vox) occ = (cache[v] != 0.0f) | (cache[cs + v] != 0.0f) | (cache[2 * cs + v] != 0.0f);
+        const uint64_t m = __builtin_amdgcn_ballot_w64(occ);
+        if (lane == 0)
+            words[w] = make_uint4((uint32_t)m, (uint32_t)(m >> 32), (uint32_t)__popcll(m), 0u);
+    }
+}
+
+// Exclusive scan of the words' counts into ranks, by one workgroup: each
+// thread sums a contiguous run of words, one thread scans the run totals,
+// then each thread rewrites its run.  The total goes to *total.
+__global__ __launch_bounds__(1024) void k_voxel_scan(uint4* __restrict__ words, int64_t n_words,
+                                                     int64_t* __restrict__ total) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n_words + 1023) / 1024;
+    const int64_t b = t * per, e = b + per < n_words ? b + per : n_words;
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += words[i].z;
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const uint32_t x = part[k];
+            part[k] = run;
+            run += x;
+        }
+        *total = run;
+    }
+    __syncthreads();
+    uint32_t run = part[t];
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t x = words[i].z;
+        words[i].z = run;
+        run += x;
+    }
+}
+
+// Occupied voxels' values in voxel order.
+__global__ __launch_bounds__(kBlock) void k_voxel_compact(float4* __restrict__ dst,
+                                                          const uint4* __restrict__ words,
+                                                          const float* __restrict__ cache,
+                                                          int64_t cs, int64_t n_vox) {
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n_vox; v += step) {
+        const uint4 w = words[v >> 6];
+        const uint64_t m = ((uint64_t)w.y << 32) | w.x;
+        const int b = (int)(v & 63);
+        if ((m >> b) & 1ull) {
+            const uint32_t idx = w.z + (uint32_t)__popcll(m & ((1ull << b) - 1ull));
+            dst[idx] = make_float4(cache[v], cache[cs + v], cache[2 * cs + v], 0.0f);
+        }
+    }
+}
+
+int grid_for(int64_t n) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)cus * 32));
+}
+
+int check_voxel(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FIPT_EHIP, "%s launch failed: %s", what, hipGetErrorString(e));
+    return FIPT_OK;
+}
+
+}  // namespace
+
+int launch_voxel_words(uint4* words, const float* cache, int64_t stride, int64_t n_vox,
+                       int64_t* total, void* stream) {
+    const int64_t n_words = (n_vox + 63) >> 6;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_voxel_words, dim3(grid_for(n_words * 64)), dim3(kBlock), 0, st, words,
+                       cache, stride, n_vox);
+    int rc = check_voxel("voxel_words");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_voxel_scan, dim3(1), dim3(1024), 0, st, words, n_words, total);
+    return check_voxel("voxel_scan");
+}
+
+int launch_voxel_compact(float4* dst, const uint4* words, const float* cache, int64_t stride,
+                         int64_t n_vox, void* stream) {
+    hipLaunchKernelGGL(k_voxel_compact, dim3(grid_for(n_vox)), dim3(kBlock), 0,
+                       (hipStream_t)stream, dst, words, cache, stride, n_vox);
+    return check_voxel("voxel_compact");
+}
+
+}  // namespace fipt
+
+using namespace fipt;
+
+extern "C" {
+
+int fipt_voxel_plan_create(const float* pos_host, int64_t n, int32_t res, const float* bmin_host,
+                           const float* bmax_host, int32_t device, fipt_voxel_plan* out) {
+    clear_error();
+    if (!out) return fail(FIPT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!pos_host || !bmin_host || !bmax_host) return fail(FIPT_EINVAL, "NULL argument");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(FIPT_EINVAL, "n must be in [1, 2^31)");
+    if (res < 1 || res > kMaxVoxelRes)
+        return fail(FIPT_EINVAL, "res must be in [1, %d], got %d", kMaxVoxelRes, res);
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(bmin_host[a]) || !std::isfinite(bmax_host[a]) ||
+            !(bmax_host[a] > bmin_host[a]))
+            return fail(FIPT_EINVAL, "the box must be finite with bmin < bmax on every axis");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(FIPT_EINVAL, "device %d not available", device);
+    const int64_t n_vox = (int64_t)res * res * res;
+    // voxel of every pixel (double arithmetic on the float inputs), then a
+    // stable counting sort
+    std::vector<int32_t> vox(n);
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t ijk[3];
+        for (int a = 0; a < 3; ++a) {
+            const double lo = bmin_host[a], hi = bmax_host[a];
+            const double u = ((double)pos_host[a * n + p] - lo) * res / (hi - lo);
+            double f = std::floor(u);
+            if (!(f >= 0.0)) f = 0.0;   // also NaN
+            if (f > res - 1) f = res - 1;
+            ijk[a] = (int64_t)f;
+        }
+        vox[p] = (int32_t)((ijk[2] * res + ijk[1]) * res + ijk[0]);
+    }
+    std::vector<int32_t> start(n_vox + 1, 0);
+    for (int64_t p = 0; p < n; ++p) ++start[vox[p] + 1];
+    for (int64_t v = 0; v < n_vox; ++v) start[v + 1] += start[v];
+    std::vector<int32_t> order(n);
+    {
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (int64_t p = 0; p < n; ++p) order[fill[vox[p]]++] = (int32_t)p;
+    }
+
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(device) != hipSuccess) return fail(FIPT_EHIP, "hipSetDevice(%d) failed", device);
+    fipt_voxel_plan pl = new fipt_voxel_plan_s();
+    pl->device = device;
+    pl->n = n;
+    pl->res = res;
+    pl->n_vox = n_vox;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->start), sizeof(int32_t) * start.size());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->order), sizeof(int32_t) * order.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(pl->start, start.data(), sizeof(int32_t) * start.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(pl->order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (pl->start) (void)hipFree(pl->start);
+        if (pl->order) (void)hipFree(pl->order);
+        delete pl;
+        if (prev >= 0) (void)hipSetDevice(prev);
+        return fail(e == hipErrorOutOfMemory ? FIPT_ENOMEM : FIPT_EHIP, "voxel plan upload: %s",
+                    hipGetErrorString(e));
+    }
+    pl->bytes = (int64_t)(sizeof(int32_t) * (start.size() + order.size()));
+    if (prev >= 0) (void)hipSetDevice(prev);
+    *out = pl;
+    return FIPT_OK;
+}
+
+int fipt_voxel_plan_destroy(fipt_voxel_plan pl) {
+    clear_error();
+    if (!pl) return FIPT_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(pl->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(pl->start);
+    (void)hipFree(pl->order);
+    delete pl;
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return FIPT_OK;
+}
+
+int fipt_voxel_pool(fipt_voxel_plan pl, const float* observed, int64_t obs_stride, float* cache,
+                    int64_t cache_stride, void* stream) {
+    clear_error();
+    if (!pl || !observed || !cache) return fail(FIPT_EINVAL, "NULL argument");
+    if (obs_stride < pl->n) return fail(FIPT_EINVAL, "obs_stride < the plan's pixel count");
+    if (cache_stride < pl->n_vox) return fail(FIPT_EINVAL, "cache_stride < res^3");
+    hipLaunchKernelGGL(k_voxel_pool, dim3(grid_for(pl->n_vox)), dim3(kBlock), 0,
+                       (hipStream_t)stream, pl->start, pl->order, pl->n_vox, observed, obs_stride,
+                       cache, cache_stride);
+    return check_voxel("voxel_pool");
+}
+
+}  // extern "C"

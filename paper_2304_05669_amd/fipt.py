@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("FIPT_LIBRARY", os.path.join(HERE, "libfipt.so"))
 OK, EINVAL, ENOMEM, EHIP, EBUSY, EAGAIN, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 MAX_LEVELS = 16
 LOSS_SLOTS = 2049
-CACHE_TRIANGLE, CACHE_VERTEX = 0, 1
+CACHE_TRIANGLE, CACHE_VERTEX, CACHE_VOXEL = 0, 1, 2
 TONEMAP_NONE, TONEMAP_LOG_SRGB = 0, 1
 
 # every entry point declared in include/fipt.h
@@ -33,6 +33,8 @@ EXPORTS = (
     "fipt_render_loss_masked", "fipt_scale_by",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
+    "fipt_scene_set_voxel_radiance", "fipt_voxel_plan_create", "fipt_voxel_plan_destroy",
+    "fipt_voxel_pool",
     "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
     "fipt_server_result", "fipt_server_release", "fipt_server_cancel", "fipt_server_stats_get",
     "fipt_server_destroy",
@@ -95,6 +97,10 @@ def lib():
         "fipt_version": (_i32, []),
         "fipt_scene_create": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _vp, C.POINTER(_vp)]),
         "fipt_scene_set_radiance": (C.c_int, [_vp, _i32, _vp, _i64, _vp, _vp]),
+        "fipt_scene_set_voxel_radiance": (C.c_int, [_vp, _vp, _i64, _i32, _f32p, _f32p, _vp, _vp]),
+        "fipt_voxel_plan_create": (C.c_int, [_vp, _i64, _i32, _f32p, _f32p, _i32, C.POINTER(_vp)]),
+        "fipt_voxel_plan_destroy": (C.c_int, [_vp]),
+        "fipt_voxel_pool": (C.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
         "fipt_scene_set_emission": (C.c_int, [_vp, _vp, _vp]),
         "fipt_scene_info_get": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
         "fipt_scene_destroy": (C.c_int, [_vp]),
@@ -206,6 +212,19 @@ class Scene:
             raise ValueError("emission must be [3, n_tris]")
         _check(lib().fipt_scene_set_radiance(self.handle, kind, _dev(cache, torch.float32, "cache"),
                                              cache.shape[1], ep, _stream()))
+
+    def set_voxel_radiance(self, cache: torch.Tensor, res: int, bmin, bmax,
+                           emission: torch.Tensor = None):
+        """Voxel-grid radiance cache (Sec. 4.2): cache [3, res^3] float32 GPU
+        (x fastest) over the box [bmin, bmax]; emission [3, n_tris] or None."""
+        if cache.dim() != 2 or cache.shape[0] != 3 or cache.shape[1] != res ** 3:
+            raise ValueError(f"cache must be [3, {res ** 3}], got {tuple(cache.shape)}")
+        if emission is not None and tuple(emission.shape) != (3, self.n_tris):
+            raise ValueError("emission must be [3, n_tris]")
+        ep = _dev(emission, torch.float32, "emission") if emission is not None else None
+        _check(lib().fipt_scene_set_voxel_radiance(
+            self.handle, _dev(cache, torch.float32, "cache"), cache.shape[1], int(res),
+            _f32_array(bmin, 3), _f32_array(bmax, 3), ep, _stream()))
 
     def set_emission(self, emission: torch.Tensor):
         if tuple(emission.shape) != (3, self.n_tris):
@@ -574,6 +593,47 @@ class EmissionPlan:
         try:
             if getattr(self, "handle", None) and _lib is not None:
                 _lib.fipt_emission_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class VoxelPlan:
+    """Average pooling of observed pixels onto a voxel grid (the radiance
+    cache of Sec. 4.2): the pixels' surface points ``pos_host`` [3, n] are
+    sorted by voxel of a res^3 grid over [bmin, bmax] once; ``pool`` then
+    averages observations per voxel."""
+
+    def __init__(self, pos_host, res: int, bmin, bmax, device: int = 0):
+        import numpy as np
+        pos = np.ascontiguousarray(pos_host, dtype=np.float32)
+        if pos.ndim != 2 or pos.shape[0] != 3:
+            raise ValueError("pos_host must be [3, n]")
+        self.n = int(pos.shape[1])
+        self.res = int(res)
+        self.bmin = [float(v) for v in bmin]
+        self.bmax = [float(v) for v in bmax]
+        h = C.c_void_p()
+        _check(lib().fipt_voxel_plan_create(pos.ctypes.data, self.n, self.res,
+                                            _f32_array(self.bmin, 3), _f32_array(self.bmax, 3),
+                                            device, C.byref(h)))
+        self.handle = h
+
+    def pool(self, observed: torch.Tensor, out: torch.Tensor = None):
+        """observed [3, n] float32 GPU -> cache [3, res^3] float32 GPU."""
+        if observed.dim() != 2 or observed.shape[0] != 3 or observed.shape[1] != self.n:
+            raise ValueError(f"observed must be [3, {self.n}], got {tuple(observed.shape)}")
+        nv = self.res ** 3
+        if out is None:
+            out = torch.empty((3, nv), dtype=torch.float32, device=observed.device)
+        _need(out, (3, nv), "out")
+        _check(lib().fipt_voxel_pool(self.handle, _dev(observed, torch.float32, "observed"), self.n,
+                                     _dev(out, torch.float32, "out"), nv, _stream()))
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.fipt_voxel_plan_destroy(self.handle)
         except Exception:
             pass
 

@@ -61,6 +61,16 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_lobe_uniforms(1, 0, 1 << 16, 0, 1 << 15, 1, None) == fipt.EINVAL
     assert L.fipt_emission_plan_create(None, 10, 5, 0, None) == fipt.EINVAL
     assert L.fipt_emission_median(None, None, 1, None, None, 1, None) == fipt.EINVAL
+    box0 = (C.c_float * 3)(0, 0, 0)
+    box1 = (C.c_float * 3)(1, 1, 1)
+    pos = (C.c_float * 3)(0.5, 0.5, 0.5)
+    assert L.fipt_voxel_plan_create(pos, 1, 0, box0, box1, 0, C.byref(out)) == fipt.EINVAL
+    assert L.fipt_voxel_plan_create(pos, 1, 513, box0, box1, 0, C.byref(out)) == fipt.EINVAL
+    assert L.fipt_voxel_plan_create(pos, 1, 4, box1, box0, 0, C.byref(out)) == fipt.EINVAL
+    assert b"bmin < bmax" in L.fipt_last_error()
+    assert L.fipt_voxel_plan_create(pos, 0, 4, box0, box1, 0, C.byref(out)) == fipt.EINVAL
+    assert L.fipt_voxel_pool(None, None, 1, None, 1, None) == fipt.EINVAL
+    assert L.fipt_scene_set_voxel_radiance(None, None, 8, 2, box0, box1, None, None) == fipt.EINVAL
 
 
 # (scale, offset) applied to the room: the 4-wide nodes store bounds as
