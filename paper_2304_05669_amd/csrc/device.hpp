@@ -367,11 +367,12 @@ __device__ __forceinline__ V3 radiance_voxel(const DeviceScene& sc, const Hit& h
     const float ux = fminf(fmaxf((fmaf(h.t, d.x, o.x) - sc.vox_lo[0]) * sc.vox_scale[0], 0.0f), top);
     const float uy = fminf(fmaxf((fmaf(h.t, d.y, o.y) - sc.vox_lo[1]) * sc.vox_scale[1], 0.0f), top);
     const float uz = fminf(fmaxf((fmaf(h.t, d.z, o.z) - sc.vox_lo[2]) * sc.vox_scale[2], 0.0f), top);
-    const int64_t r = sc.vox_res;
-    const int64_t v = ((int64_t)(int)uz * r + (int)uy) * r + (int)ux;
+    // res <= 512, so the voxel index fits 32 bits
+    const uint32_t r = (uint32_t)sc.vox_res;
+    const uint32_t v = ((uint32_t)uz * r + (uint32_t)uy) * r + (uint32_t)ux;
     const int4 w = load_global(reinterpret_cast<const int4*>(sc.vox_words) + (v >> 6));
     const uint64_t m = ((uint64_t)(uint32_t)w.y << 32) | (uint32_t)w.x;
-    const int b = (int)(v & 63);
+    const int b = (int)(v & 63u);
     V3 c = v3(e.y, e.z, e.w);
     if ((m >> b) & 1ull) {
         const uint32_t idx = (uint32_t)w.z + (uint32_t)__popcll(m & ((1ull << b) - 1ull));
