@@ -264,7 +264,8 @@ int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cach
     DeviceGuard g(s->device);
     if (g.rc) return g.rc;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t n_words = (n_vox + 63) >> 6;
+    const int64_t n_bricks_axis = (res + 3) / 4;
+    const int64_t n_words = n_bricks_axis * n_bricks_axis * n_bricks_axis;
     // the bake may still be reading the old grid: wait before replacing it;
     // until the new grid is complete the scene reads no voxel cache
     HIP_TRY(hipDeviceSynchronize());
@@ -284,7 +285,7 @@ int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cach
         if (rc) return rc;
         s->vox_word_capacity = n_words;
     }
-    int rc = launch_voxel_words(s->d_vox_words, cache, cache_stride, n_vox, s->d_vox_total, stream);
+    int rc = launch_voxel_words(s->d_vox_words, cache, cache_stride, res, s->d_vox_total, stream);
     if (rc) return rc;
     int64_t total = 0;
     HIP_TRY(hipMemcpyAsync(&total, s->d_vox_total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -301,7 +302,7 @@ int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cach
         if (rc) return rc;
         s->vox_capacity = cap;
     }
-    rc = launch_voxel_compact(s->d_vox, s->d_vox_words, cache, cache_stride, n_vox, stream);
+    rc = launch_voxel_compact(s->d_vox, s->d_vox_words, cache, cache_stride, res, stream);
     if (rc) return rc;
     // corner values zero, emission as given
     rc = launch_set_radiance(s->d_rad, s->d_order, s->d_tri_idx, s->n_tris, FIPT_CACHE_TRIANGLE,

@@ -356,9 +356,11 @@ __device__ __forceinline__ V3 radiance(const DeviceScene& sc, const Hit& h) {
 // triangle's emission (the last 16 bytes of its radiance record).  The
 // voxel coordinate is clamped in float before the conversion, so points
 // outside the grid read its border voxels and the conversion is exact.  The
-// grid is sparse: an occupancy word (bit mask of 64 voxels and the count of
-// occupied voxels before them) locates the value, and empty voxels read
-// zero without a second load.
+// grid is sparse, in bricks of 4 x 4 x 4 voxels: the brick's occupancy word
+// (bit mask of its 64 voxels and the count of occupied voxels in earlier
+// bricks) locates the value, and empty voxels read zero without a second
+// load.  Hits near each other on a surface fall in the same or adjacent
+// bricks, so their words and values share cache lines.
 __device__ __forceinline__ V3 radiance_voxel(const DeviceScene& sc, const Hit& h, const V3& o,
                                              const V3& d) {
     if (h.leaf < 0) return v3(0.0f, 0.0f, 0.0f);
@@ -367,12 +369,14 @@ __device__ __forceinline__ V3 radiance_voxel(const DeviceScene& sc, const Hit& h
     const float ux = fminf(fmaxf((fmaf(h.t, d.x, o.x) - sc.vox_lo[0]) * sc.vox_scale[0], 0.0f), top);
     const float uy = fminf(fmaxf((fmaf(h.t, d.y, o.y) - sc.vox_lo[1]) * sc.vox_scale[1], 0.0f), top);
     const float uz = fminf(fmaxf((fmaf(h.t, d.z, o.z) - sc.vox_lo[2]) * sc.vox_scale[2], 0.0f), top);
-    // res <= 512, so the voxel index fits 32 bits
-    const uint32_t r = (uint32_t)sc.vox_res;
-    const uint32_t v = ((uint32_t)uz * r + (uint32_t)uy) * r + (uint32_t)ux;
-    const int4 w = load_global(reinterpret_cast<const int4*>(sc.vox_words) + (v >> 6));
+    // brick of 4 x 4 x 4 voxels and the voxel's bit in it (res <= 512, so
+    // 32-bit indices)
+    const uint32_t ix = (uint32_t)ux, iy = (uint32_t)uy, iz = (uint32_t)uz;
+    const uint32_t nb = (uint32_t)sc.vox_bricks;
+    const uint32_t brick = ((iz >> 2) * nb + (iy >> 2)) * nb + (ix >> 2);
+    const int4 w = load_global(reinterpret_cast<const int4*>(sc.vox_words) + brick);
     const uint64_t m = ((uint64_t)(uint32_t)w.y << 32) | (uint32_t)w.x;
-    const int b = (int)(v & 63u);
+    const int b = (int)((((iz & 3u) << 2 | (iy & 3u)) << 2) | (ix & 3u));
     V3 c = v3(e.y, e.z, e.w);
     if ((m >> b) & 1ull) {
         const uint32_t idx = (uint32_t)w.z + (uint32_t)__popcll(m & ((1ull << b) - 1ull));

@@ -123,15 +123,18 @@ struct DeviceScene {
     const TriRad* rad;
     int64_t n_tris;
     float box_scale;   // 2^E: the unit of the node bounds
-    // Voxel radiance cache (NULL unless the scene uses one), stored sparse:
-    // voxel v = (k R + j) R + i is occupied if bit v % 64 of word v / 64 is
-    // set (word = {mask low, mask high, occupied voxels before the word, 0});
-    // an occupied voxel's value (rgb, w unused) is vox[rank + occupied
-    // voxels before it in its word], an empty one is zero.  A point x lies
-    // in voxel floor((x - vox_lo) * vox_scale), clamped to [0, R - 1].
+    // Voxel radiance cache (NULL unless the scene uses one), stored sparse in
+    // bricks of 4 x 4 x 4 voxels: voxel (i, j, k) belongs to brick
+    // (i / 4, j / 4, k / 4), numbered (bz B + by) B + bx with B = ceil(R / 4),
+    // as bit ((k % 4) * 4 + j % 4) * 4 + i % 4 of that brick's word
+    // {mask low, mask high, occupied voxels in earlier bricks, 0}; an
+    // occupied voxel's value (rgb, w unused) is vox[rank + occupied voxels
+    // before it in its brick], an empty one is zero.  A point x lies in
+    // voxel floor((x - vox_lo) * vox_scale), clamped to [0, R - 1].
     const uint4* vox_words;
     const float4* vox;
     int32_t vox_res;
+    int32_t vox_bricks;   // B
     float vox_lo[3];
     float vox_scale[3];   // R / (hi - lo) per axis
 };
@@ -141,12 +144,13 @@ int launch_set_radiance(TriRad* rad, const int32_t* order, const int32_t* tri_id
                         const float* emission, void* stream);
 int launch_set_emission(TriRad* rad, const int32_t* order, int64_t n_tris,
                         const float* emission, void* stream);
-// Voxel cache planes [3][stride] -> the scene's sparse form: occupancy words
-// with ranks (and the occupied count in *total), then the occupied values.
-int launch_voxel_words(uint4* words, const float* cache, int64_t stride, int64_t n_vox,
+// Voxel cache planes [3][stride] of an R^3 grid -> the scene's sparse brick
+// form: occupancy words with ranks (and the occupied count in *total), then
+// the occupied values.
+int launch_voxel_words(uint4* words, const float* cache, int64_t stride, int32_t res,
                        int64_t* total, void* stream);
 int launch_voxel_compact(float4* dst, const uint4* words, const float* cache, int64_t stride,
-                         int64_t n_vox, void* stream);
+                         int32_t res, void* stream);
 constexpr int32_t kMaxVoxelRes = 512;
 // Cameras travel by value in the kernel arguments (no staging allocation).
 constexpr int kMaxCameras = 48;
@@ -269,7 +273,7 @@ struct fipt_scene_s {
     fipt::DeviceScene view() const {
         const bool vox = cache_kind == FIPT_CACHE_VOXEL;
         return {d_nodes, d_tris, d_rad, n_tris, box_scale, vox ? d_vox_words : nullptr,
-                vox ? d_vox : nullptr, vox ? vox_res : 0,
+                vox ? d_vox : nullptr, vox ? vox_res : 0, vox ? (vox_res + 3) / 4 : 0,
                 {vox_lo[0], vox_lo[1], vox_lo[2]}, {vox_scale[0], vox_scale[1], vox_scale[2]}};
     }
 };

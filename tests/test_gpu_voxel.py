@@ -39,7 +39,7 @@ def _smooth_cache(R):
     return c.reshape(3, -1).astype(np.float32)
 
 
-@pytest.mark.parametrize("n,R", [(1, 1), (1000, 7), (100003, 64), (250000, 256)])
+@pytest.mark.parametrize("n,R", [(1, 1), (1000, 7), (100003, 64), (250000, 256), (50000, 512)])
 def test_voxel_pool_bitwise(n, R):
     rng = np.random.default_rng(n + R)
     lo = np.array([-1.0, 0.5, 2.0], np.float32)
@@ -86,9 +86,11 @@ def _voxel_scene(sc, cache, R, lo, hi, emission=True):
     return s
 
 
-def test_voxel_bake_parity_tiny(tiny, tiny_points):
+@pytest.mark.parametrize("R", [32, 30, 1])
+def test_voxel_bake_parity_tiny(tiny, tiny_points, R):
+    """R = 30 leaves the last brick of each axis partly outside the grid;
+    R = 1 is a single voxel."""
     pts, tri, _ = tiny_points
-    R = 32
     cache = _smooth_cache(R)
     s = _voxel_scene(tiny, cache, R, tiny.bmin, tiny.bmax)
     assert s.info().cache_kind == fipt.CACHE_VOXEL
@@ -99,7 +101,7 @@ def test_voxel_bake_parity_tiny(tiny, tiny_points):
     osc.set_voxel_cache(cache, R, tiny.bmin, tiny.bmax)
     want = ob.bake(osc, pts, tri, spp_d=tiny.spp, spp_s=tiny.spp, seed=tiny.seed)
     r = assert_bake_parity(got.cpu().numpy(), want)
-    print("tiny box voxel parity:", r)
+    print(f"tiny box voxel parity (R = {R}):", r)
     s.destroy()
 
 
