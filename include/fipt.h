@@ -391,7 +391,8 @@ int fipt_voxel_pool(fipt_voxel_plan plan, const float* observed, int64_t obs_str
  * hit is that triangle.  The plan groups pixels by triangle once:
  * tri_host[n] (host) is each pixel's primary-hit triangle, -1 for none (as
  * written by fipt_gen_points), each in [-1, n_tris).  1 <= n < 2^31,
- * 1 <= n_tris < 2^31.  The plan owns device memory. */
+ * 1 <= n_tris < 2^31.  The plan owns device memory (4 (n + 2 n_tris + 2)
+ * bytes). */
 int fipt_emission_plan_create(const int32_t* tri_host, int64_t n, int64_t n_tris, int32_t device,
                               fipt_emission_plan* out);
 int fipt_emission_plan_destroy(fipt_emission_plan plan);
@@ -403,7 +404,9 @@ int fipt_emission_plan_destroy(fipt_emission_plan plan);
  * observations (negative zero is treated as zero); 0 for other triangles
  * and for triangles no pixel sees.  Exact and bitwise reproducible;
  * allocates nothing; asynchronous on `stream`.  obs_stride >= n,
- * le_stride >= n_tris. */
+ * le_stride >= n_tris.  The call lists the emitters in the plan's memory,
+ * so calls with the same plan must not overlap (one stream, or ordered
+ * streams). */
 int fipt_emission_median(fipt_emission_plan plan, const float* observed, int64_t obs_stride,
                          const uint8_t* emitter, float* le, int64_t le_stride, void* stream);
 

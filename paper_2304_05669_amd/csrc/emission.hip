@@ -9,10 +9,13 @@
 //
 // The pixel-to-triangle map is fixed by the cameras, so a plan groups the
 // pixels by triangle once (host counting sort, pixels of a triangle in
-// index order).  The kernel runs persistent one-wave workgroups over blocks
-// of 64 triangles: each lane writes zeros for its triangle unless it is an
-// emitter, then the wave selects the median of every emitter of the block
-// in turn.  A segment of at most 64 pixels is ranked directly (each lane
+// index order).  A first kernel runs one wavefront per block of 64
+// triangles: each lane writes zeros for its triangle unless it is an
+// emitter, and the wave appends the block's emitters to a list (one atomic
+// per wave).  Emitters come in runs of consecutive triangles (a lamp's
+// faces), so the second kernel spreads the work by (emitter, channel) pair,
+// one wavefront each, instead of leaving a block's emitters to one wave.
+// A segment of at most 64 pixels is ranked directly (each lane
 // counts the values below its own, ties broken by position); a longer one
 // is searched by an exact radix selection over order-preserving 32-bit
 // keys, eight bits per pass, with a 256-bin histogram in LDS.  Integer
@@ -30,6 +33,7 @@ struct fipt_emission_plan_s {
     int64_t n_tris = 0;
     int32_t* order = nullptr;     // [n_seen] pixels grouped by triangle, index order within one
     int32_t* seg_start = nullptr; // [n_tris + 1] ranges into order
+    int32_t* emitters = nullptr;  // [n_tris + 1]: the call's emitter list, its length last
     int64_t bytes = 0;
 };
 
@@ -102,12 +106,12 @@ __device__ float segment_median(const float* __restrict__ obs, const int32_t* __
     return key_float(prefix);
 }
 
-__global__ __launch_bounds__(kWave) void k_emission_median(
-    const int32_t* __restrict__ order, const int32_t* __restrict__ seg_start, int64_t n_tris,
-    const float* __restrict__ obs, int64_t os, const uint8_t* __restrict__ emitter,
-    float* __restrict__ le, int64_t ls) {
-    __shared__ int32_t hist[256];
-    __shared__ int32_t pick[2];
+// Zero the non-emitters' outputs and list the emitters (list length in
+// list[n_tris], zeroed beforehand).  The list's order depends on
+// scheduling; each emitter's result does not.
+__global__ __launch_bounds__(kWave) void k_emission_list(const uint8_t* __restrict__ emitter,
+                                                          int64_t n_tris, float* __restrict__ le,
+                                                          int64_t ls, int32_t* __restrict__ list) {
     const int lane = threadIdx.x;
     for (int64_t b0 = (int64_t)blockIdx.x * kWave; b0 < n_tris; b0 += (int64_t)gridDim.x * kWave) {
         const int64_t t = b0 + lane;
@@ -117,19 +121,35 @@ __global__ __launch_bounds__(kWave) void k_emission_median(
             le[ls + t] = 0.0f;
             le[2 * ls + t] = 0.0f;
         }
-        uint64_t todo = __builtin_amdgcn_ballot_w64(em);
-        while (todo) {
-            const int j = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1;
-            const int64_t tt = b0 + j;
-            const int32_t s0 = seg_start[tt], k = seg_start[tt + 1] - s0;
-            for (int c = 0; c < 3; ++c) {
-                const float m = k > 0 ? segment_median(obs + c * os, order, s0, k, lane, hist, pick)
-                                      : 0.0f;
-                if (lane == 0) le[c * ls + tt] = m;
-            }
-        }
+        const uint64_t m = __builtin_amdgcn_ballot_w64(em);
+        if (m == 0) continue;
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(list + n_tris, (int32_t)__popcll(m));
+        base = __shfl(base, 0, kWave);
+        if (em) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)t;
     }
+}
+
+// One wavefront per (emitter, channel) pair of the list.
+__global__ __launch_bounds__(kWave) void k_emission_median(
+    const int32_t* __restrict__ order, const int32_t* __restrict__ seg_start, int64_t n_tris,
+    const float* __restrict__ obs, int64_t os, const int32_t* __restrict__ list,
+    float* __restrict__ le, int64_t ls) {
+    __shared__ int32_t hist[256];
+    __shared__ int32_t pick[2];
+    const int lane = threadIdx.x;
+    const int64_t items = 3 * (int64_t)list[n_tris];
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t tt = list[it / 3];
+        const int c = (int)(it % 3);
+        const int32_t s0 = seg_start[tt], k = seg_start[tt + 1] - s0;
+        const float m = k > 0 ? segment_median(obs + c * os, order, s0, k, lane, hist, pick) : 0.0f;
+        if (lane == 0) le[c * ls + tt] = m;
+    }
+}
+
+__global__ void k_emission_zero_count(int32_t* count) {
+    if (threadIdx.x == 0) *count = 0;
 }
 
 int check_emission(const char* what) {
@@ -181,6 +201,7 @@ int fipt_emission_plan_create(const int32_t* tri_host, int64_t n, int64_t n_tris
     p->n_tris = n_tris;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->order), sizeof(int32_t) * order.size());
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->seg_start), sizeof(int32_t) * seg.size());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->emitters), sizeof(int32_t) * (n_tris + 1));
     if (e == hipSuccess)
         e = hipMemcpy(p->order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -188,12 +209,13 @@ int fipt_emission_plan_create(const int32_t* tri_host, int64_t n, int64_t n_tris
     if (e != hipSuccess) {
         if (p->order) (void)hipFree(p->order);
         if (p->seg_start) (void)hipFree(p->seg_start);
+        if (p->emitters) (void)hipFree(p->emitters);
         delete p;
         if (prev >= 0) (void)hipSetDevice(prev);
         return fail(e == hipErrorOutOfMemory ? FIPT_ENOMEM : FIPT_EHIP, "emission plan upload: %s",
                     hipGetErrorString(e));
     }
-    p->bytes = (int64_t)(sizeof(int32_t) * (order.size() + seg.size()));
+    p->bytes = (int64_t)(sizeof(int32_t) * (order.size() + seg.size() + n_tris + 1));
     if (prev >= 0) (void)hipSetDevice(prev);
     *out = p;
     return FIPT_OK;
@@ -208,6 +230,7 @@ int fipt_emission_plan_destroy(fipt_emission_plan p) {
     (void)hipDeviceSynchronize();
     (void)hipFree(p->order);
     (void)hipFree(p->seg_start);
+    (void)hipFree(p->emitters);
     delete p;
     if (prev >= 0) (void)hipSetDevice(prev);
     return FIPT_OK;
@@ -223,9 +246,21 @@ int fipt_emission_median(fipt_emission_plan p, const float* observed, int64_t ob
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)cus * 16));
-    hipLaunchKernelGGL(k_emission_median, dim3((unsigned)blocks), dim3(kWave), 0, (hipStream_t)stream,
-                       p->order, p->seg_start, p->n_tris, observed, obs_stride, emitter, le, le_stride);
+    const int64_t waves = (int64_t)cus * 16;
+    hipStream_t st = (hipStream_t)stream;
+    // the list length is cleared by a kernel, not a memset node, so a caller
+    // may capture the call
+    hipLaunchKernelGGL(k_emission_zero_count, dim3(1), dim3(kWave), 0, st, p->emitters + p->n_tris);
+    int rc = check_emission("emission_zero_count");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_emission_list, dim3((unsigned)std::max<int64_t>(1, std::min(blocks_needed, waves))),
+                       dim3(kWave), 0, st, emitter, p->n_tris, le, le_stride, p->emitters);
+    rc = check_emission("emission_list");
+    if (rc) return rc;
+    // at most 3 n_tris items; the kernel reads the actual count
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(3 * p->n_tris, waves));
+    hipLaunchKernelGGL(k_emission_median, dim3((unsigned)grid), dim3(kWave), 0, st, p->order,
+                       p->seg_start, p->n_tris, observed, obs_stride, p->emitters, le, le_stride);
     return check_emission("emission_median");
 }
 
