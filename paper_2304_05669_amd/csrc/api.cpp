@@ -78,6 +78,7 @@ void scene_free(fipt_scene s) {
     if (s->d_vox) (void)hipFree(s->d_vox);
     if (s->d_vox_words) (void)hipFree(s->d_vox_words);
     if (s->d_vox_total) (void)hipFree(s->d_vox_total);
+    if (s->d_vox_tiles) (void)hipFree(s->d_vox_tiles);
     if (s->d_order) (void)hipFree(s->d_order);
     if (s->d_tri_idx) (void)hipFree(s->d_tri_idx);
     if (s->d_counters) (void)hipFree(s->d_counters);
@@ -275,17 +276,29 @@ int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cach
         if (rc) return rc;
     }
     if (s->vox_word_capacity < n_words) {
+        const int64_t old_tiles = (s->vox_word_capacity + kVoxelScanTile - 1) / kVoxelScanTile;
         if (s->d_vox_words) {
             (void)hipFree(s->d_vox_words);
-            s->bytes -= 16 * s->vox_word_capacity;
+            (void)hipFree(s->d_vox_tiles);
+            s->bytes -= 16 * s->vox_word_capacity + 4 * old_tiles;
             s->d_vox_words = nullptr;
+            s->d_vox_tiles = nullptr;
             s->vox_word_capacity = 0;
         }
         int rc = dev_alloc(&s->d_vox_words, (size_t)n_words, &s->bytes);
         if (rc) return rc;
+        rc = dev_alloc(&s->d_vox_tiles, (size_t)((n_words + kVoxelScanTile - 1) / kVoxelScanTile),
+                       &s->bytes);
+        if (rc) {
+            (void)hipFree(s->d_vox_words);
+            s->bytes -= 16 * n_words;
+            s->d_vox_words = nullptr;
+            return rc;
+        }
         s->vox_word_capacity = n_words;
     }
-    int rc = launch_voxel_words(s->d_vox_words, cache, cache_stride, res, s->d_vox_total, stream);
+    int rc = launch_voxel_words(s->d_vox_words, cache, cache_stride, res, s->d_vox_tiles,
+                                s->d_vox_total, stream);
     if (rc) return rc;
     int64_t total = 0;
     HIP_TRY(hipMemcpyAsync(&total, s->d_vox_total, sizeof(int64_t), hipMemcpyDeviceToHost, st));

@@ -148,7 +148,8 @@ int launch_set_emission(TriRad* rad, const int32_t* order, int64_t n_tris,
 // form: occupancy words with ranks (and the occupied count in *total), then
 // the occupied values.
 int launch_voxel_words(uint4* words, const float* cache, int64_t stride, int32_t res,
-                       int64_t* total, void* stream);
+                       uint32_t* tile_sum, int64_t* total, void* stream);
+constexpr int64_t kVoxelScanTile = 1024;   // words per scan tile
 int launch_voxel_compact(float4* dst, const uint4* words, const float* cache, int64_t stride,
                          int32_t res, void* stream);
 constexpr int32_t kMaxVoxelRes = 512;
@@ -260,6 +261,7 @@ struct fipt_scene_s {
     float4* d_vox = nullptr;       // occupied voxels' values
     int64_t vox_capacity = 0;      // values allocated
     int64_t* d_vox_total = nullptr;  // occupied count, read back by the set-up call
+    uint32_t* d_vox_tiles = nullptr; // per scan tile of words: its total, then its offset
     int32_t vox_res = 0;
     float vox_lo[3] = {0, 0, 0}, vox_scale[3] = {0, 0, 0};
     int32_t* d_order = nullptr;    // leaf position -> original triangle

@@ -126,35 +126,70 @@ __global__ __launch_bounds__(kBlock) void k_voxel_words(uint4* __restrict__ word
     }
 }
 
-// Exclusive scan of the words' counts into ranks, by one workgroup: each
-// thread sums a contiguous run of words, one thread scans the run totals,
-// then each thread rewrites its run.  The total goes to *total.
-__global__ __launch_bounds__(1024) void k_voxel_scan(uint4* __restrict__ words, int64_t n_words,
-                                                     int64_t* __restrict__ total) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (n_words + 1023) / 1024;
-    const int64_t b = t * per, e = b + per < n_words ? b + per : n_words;
-    uint32_t sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += words[i].z;
-    part[t] = sum;
+// Exclusive scan of the words' counts (.z) into ranks, in three passes over
+// tiles of 1024 words: each tile scanned by one workgroup (its total kept),
+// the tile totals scanned by one workgroup (the grand total to *total), the
+// tile offsets added.
+constexpr int kScanTile = (int)kVoxelScanTile;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* lds, uint32_t& sum) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t incl = x;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t up = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += up;
+    }
+    if (lane == 63) lds[wave] = incl;
     __syncthreads();
     if (t == 0) {
         uint32_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const uint32_t x = part[k];
-            part[k] = run;
-            run += x;
+        for (int w = 0; w < kScanTile / 64; ++w) {
+            const uint32_t v = lds[w];
+            lds[w] = run;
+            run += v;
         }
-        *total = run;
+        lds[kScanTile / 64] = run;
     }
     __syncthreads();
-    uint32_t run = part[t];
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t x = words[i].z;
-        words[i].z = run;
-        run += x;
+    sum = lds[kScanTile / 64];
+    const uint32_t r = lds[wave] + incl - x;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kScanTile) void k_voxel_scan_tiles(uint4* __restrict__ words,
+                                                                int64_t n_words,
+                                                                uint32_t* __restrict__ tile_sum) {
+    __shared__ uint32_t lds[kScanTile / 64 + 1];
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+    const uint32_t x = i < n_words ? words[i].z : 0u;
+    uint32_t sum;
+    const uint32_t r = block_exclusive_scan(x, lds, sum);
+    if (i < n_words) words[i].z = r;
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kScanTile) void k_voxel_scan_totals(uint32_t* __restrict__ tile_sum,
+                                                                 int64_t n_tiles,
+                                                                 int64_t* __restrict__ total) {
+    __shared__ uint32_t lds[kScanTile / 64 + 1];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < n_tiles; base += kScanTile) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t x = i < n_tiles ? tile_sum[i] : 0u;
+        uint32_t sum;
+        const uint32_t r = block_exclusive_scan(x, lds, sum);
+        if (i < n_tiles) tile_sum[i] = carry + r;
+        carry += sum;
     }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanTile) void k_voxel_scan_add(uint4* __restrict__ words,
+                                                              int64_t n_words,
+                                                              const uint32_t* __restrict__ tile_sum) {
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+    if (i < n_words) words[i].z += tile_sum[blockIdx.x];
 }
 
 // Occupied voxels' values in brick order, one wavefront per brick.
@@ -196,16 +231,25 @@ int check_voxel(const char* what) {
 }  // namespace
 
 int launch_voxel_words(uint4* words, const float* cache, int64_t stride, int32_t res,
-                       int64_t* total, void* stream) {
+                       uint32_t* tile_sum, int64_t* total, void* stream) {
     const int64_t nb = (res + 3) / 4;
     const int64_t n_words = nb * nb * nb;
+    const int64_t n_tiles = (n_words + kScanTile - 1) / kScanTile;
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_voxel_words, dim3(grid_for(n_words * 64)), dim3(kBlock), 0, st, words,
                        cache, stride, res);
     int rc = check_voxel("voxel_words");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_voxel_scan, dim3(1), dim3(1024), 0, st, words, n_words, total);
-    return check_voxel("voxel_scan");
+    hipLaunchKernelGGL(k_voxel_scan_tiles, dim3((unsigned)n_tiles), dim3(kScanTile), 0, st, words,
+                       n_words, tile_sum);
+    rc = check_voxel("voxel_scan_tiles");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_voxel_scan_totals, dim3(1), dim3(kScanTile), 0, st, tile_sum, n_tiles, total);
+    rc = check_voxel("voxel_scan_totals");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_voxel_scan_add, dim3((unsigned)n_tiles), dim3(kScanTile), 0, st, words,
+                       n_words, tile_sum);
+    return check_voxel("voxel_scan_add");
 }
 
 int launch_voxel_compact(float4* dst, const uint4* words, const float* cache, int64_t stride,
