@@ -190,7 +190,8 @@ int fipt_scene_set_radiance(fipt_scene s, int32_t cache_kind, const float* cache
  * call waits for the device to finish earlier work and reads the occupied
  * count back, so it is a set-up call, not one to capture.  On an error the
  * scene is left with no cache (emission only).  Serving
- * (fipt_server_submit) rejects scenes with a voxel cache. */
+ * (fipt_server_submit) rejects scenes with a voxel cache, and this call
+ * returns FIPT_EBUSY while serving requests reference the scene. */
 int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cache_stride,
                                   int32_t res, const float* bmin_host, const float* bmax_host,
                                   const float* emission, void* stream);

@@ -262,6 +262,10 @@ int fipt_scene_set_voxel_radiance(fipt_scene s, const float* cache, int64_t cach
         if (!std::isfinite(scale[a]) || !(scale[a] > 0.0f))
             return fail(FIPT_EINVAL, "the box is too thin for single precision");
     }
+    // serving launches read the scene's radiance records, which this call
+    // rewrites
+    if (s->refs.load() > 0)
+        return fail(FIPT_EBUSY, "scene referenced by %d serving requests", s->refs.load());
     DeviceGuard g(s->device);
     if (g.rc) return g.rc;
     hipStream_t st = (hipStream_t)stream;

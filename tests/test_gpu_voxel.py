@@ -208,11 +208,19 @@ def test_voxel_arguments_rejected(tiny, tiny_points):
         plan.pool(torch.zeros((3, pts.shape[1] - 1), device=DEV))
     with pytest.raises(ValueError):
         plan.pool(torch.zeros((3, pts.shape[1]), device=DEV), out=torch.zeros((3, 63), device=DEV))
+    srv = fipt.Server(device=0, pool_bytes=64 << 20, max_inflight=4, samples_per_launch=1 << 20)
+    # a scene that serving requests reference cannot change to a voxel cache
+    s.set_radiance(_t(tiny.cache), fipt.CACHE_TRIANGLE, _t(tiny.emission))
+    P, T = _t(pts), _t(tri, torch.int32)
+    t = srv.submit(s, P, T, 8, 8, tiny.sigma, 1)
+    assert srv.wait(t, timeout_s=60.0)
+    with pytest.raises(fipt.FiptError):
+        s.set_voxel_radiance(c, 4, tiny.bmin, tiny.bmax)
+    srv.release(t)
     # serving bakes per-triangle and per-vertex caches only
     s.set_voxel_radiance(c, 4, tiny.bmin, tiny.bmax)
-    srv = fipt.Server(device=0, pool_bytes=64 << 20, max_inflight=4, samples_per_launch=1 << 20)
     with pytest.raises(fipt.FiptError):
-        srv.submit(s, _t(pts), _t(tri, torch.int32), 8, 8, tiny.sigma, 1)
+        srv.submit(s, P, T, 8, 8, tiny.sigma, 1)
     srv.destroy()
     s.destroy()
 
