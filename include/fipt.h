@@ -172,7 +172,9 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris,
 /* Set the radiance the bake returns at a hit: radiance cache L' (Eq. 9) of
  * kind FIPT_CACHE_TRIANGLE ([3][n_tris]) or FIPT_CACHE_VERTEX ([3][n_verts]),
  * plus per-triangle emission Le ([3][n_tris], NULL = zero).  Both device
- * float planes; read on `stream`, not retained. */
+ * float planes; read on `stream`, not retained.  FIPT_EBUSY while serving
+ * requests reference the scene (their launches read the radiance records
+ * this call rewrites); the same holds for fipt_scene_set_emission. */
 int fipt_scene_set_radiance(fipt_scene s, int32_t cache_kind, const float* cache,
                             int64_t n_cache, const float* emission, void* stream);
 

@@ -235,6 +235,8 @@ int fipt_scene_set_radiance(fipt_scene s, int32_t cache_kind, const float* cache
     if (n_cache != want)
         return fail(FIPT_EINVAL, "cache has %lld entries, scene needs %lld", (long long)n_cache,
                     (long long)want);
+    if (s->refs.load() > 0)
+        return fail(FIPT_EBUSY, "scene referenced by %d serving requests", s->refs.load());
     DeviceGuard g(s->device);
     if (g.rc) return g.rc;
     int rc = launch_set_radiance(s->d_rad, s->d_order, s->d_tri_idx, s->n_tris, cache_kind, cache,
@@ -338,6 +340,8 @@ int fipt_scene_set_emission(fipt_scene s, const float* emission, void* stream) {
     clear_error();
     if (!s) return fail(FIPT_EINVAL, "scene is NULL");
     if (!emission) return fail(FIPT_EINVAL, "emission is NULL");
+    if (s->refs.load() > 0)
+        return fail(FIPT_EBUSY, "scene referenced by %d serving requests", s->refs.load());
     DeviceGuard g(s->device);
     if (g.rc) return g.rc;
     return launch_set_emission(s->d_rad, s->d_order, s->n_tris, emission, stream);

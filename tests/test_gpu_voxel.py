@@ -216,6 +216,10 @@ def test_voxel_arguments_rejected(tiny, tiny_points):
     assert srv.wait(t, timeout_s=60.0)
     with pytest.raises(fipt.FiptError):
         s.set_voxel_radiance(c, 4, tiny.bmin, tiny.bmax)
+    with pytest.raises(fipt.FiptError):
+        s.set_radiance(_t(tiny.cache), fipt.CACHE_TRIANGLE, _t(tiny.emission))
+    with pytest.raises(fipt.FiptError):
+        s.set_emission(_t(tiny.emission))
     srv.release(t)
     # serving bakes per-triangle and per-vertex caches only
     s.set_voxel_radiance(c, 4, tiny.bmin, tiny.bmax)
