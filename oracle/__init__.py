@@ -14,6 +14,8 @@ seeded inputs from ``synth``.
                      grid and its adjoint, in numpy float64;
 * ``oracle.cache``   the voxel radiance cache: average pooling of observed
                      pixels onto a grid and the nearest-voxel index (Sec. 4.2);
+* ``oracle.hashgrid`` the hash-grid material network of Eq. 14 (hash encoding
+                     and MLP), forward and backward, in numpy float64;
 * ``oracle.emission`` per-triangle emission re-estimation (Eq. 13 with
                      f = 0: the median of the observed pixels), in numpy.
 """
