@@ -386,6 +386,49 @@ int fipt_voxel_plan_destroy(fipt_voxel_plan plan);
 int fipt_voxel_pool(fipt_voxel_plan plan, const float* observed, int64_t obs_stride, float* cache,
                     int64_t cache_stride, void* stream);
 
+/* ---- hash-grid material network (Eq. 14) -------------------------------- */
+
+/* The paper's material network: (a, sigma, m) = Sigmoid(MLP(enc(x))), with
+ * enc a multiresolution hash encoding of FIPT_HG_LEVELS levels, 2^19
+ * entries of 2 features per level, and an MLP of two hidden layers of 64
+ * with ReLU and no biases.  Level l has 16 * 2^l cells per axis over the
+ * box [bmin, bmax]; a point is mapped to p = clamp((x - bmin) * inv, 0, 1)
+ * with inv = 1 / (bmax - bmin) in single precision, its cell at level l is
+ * c = min(floor(p N), N - 1) per axis (single precision, exact for these
+ * power-of-two N), and the 8 vertices of the cell are blended trilinearly.
+ * Levels 0-2 index their (N + 1)^3 vertices densely (x + y (N + 1) +
+ * z (N + 1)^2); the others hash the vertex as (x ^ 2654435761 y ^
+ * 805459861 z) mod 2^19 in 32-bit arithmetic.
+ * params: device float [FIPT_HG_PARAMS]: tables [32][2^19][2], then W1
+ * [64][64], W2 [64][64], W3 [5][64] (row = output unit).  Outputs are the
+ * material planes (a_r, a_g, a_b, sigma, m), as fipt_render_loss reads them. */
+#define FIPT_HG_LEVELS 32
+#define FIPT_HG_LOG2_TABLE 19
+#define FIPT_HG_PARAMS (32LL * (1LL << 19) * 2 + 64 * 64 + 64 * 64 + 5 * 64)
+
+/* material[5][mat_stride] (device) for the n points pos[3][pos_stride]
+ * (device).  1 <= n < 2^31; bmin_host < bmax_host (host float [3]).
+ * Asynchronous on `stream`. */
+int fipt_hashgrid_forward(const float* params, const float* pos, int64_t pos_stride, int64_t n,
+                          const float* bmin_host, const float* bmax_host, float* material,
+                          int64_t mat_stride, void* stream);
+
+/* Floats of workspace fipt_hashgrid_backward needs for n points. */
+int64_t fipt_hashgrid_workspace_floats(int64_t n);
+
+/* Adds d(sum over points and outputs of grad_material * material) /
+ * d params into grad_params (device float [FIPT_HG_PARAMS]; the caller
+ * zeroes it first for a plain gradient).  grad_material: device
+ * [5][gm_stride].  workspace: device, at least
+ * fipt_hashgrid_workspace_floats(n) floats, overwritten.  The table
+ * gradient is summed with float atomics (its last bits depend on
+ * scheduling); the weight gradients are summed in a fixed order.  Calls
+ * that share a workspace must not overlap.  Asynchronous on `stream`. */
+int fipt_hashgrid_backward(const float* params, const float* pos, int64_t pos_stride, int64_t n,
+                           const float* bmin_host, const float* bmax_host,
+                           const float* grad_material, int64_t gm_stride, float* grad_params,
+                           float* workspace, int64_t workspace_floats, void* stream);
+
 /* ---- emission re-estimation (Sec. 4.4, Eq. 13) ------------------------- */
 
 /* Under the assumption that an emitter reflects no light (f = 0), the

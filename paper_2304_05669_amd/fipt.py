@@ -34,7 +34,8 @@ EXPORTS = (
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
     "fipt_scene_set_voxel_radiance", "fipt_voxel_plan_create", "fipt_voxel_plan_destroy",
-    "fipt_voxel_pool",
+    "fipt_voxel_pool", "fipt_hashgrid_forward", "fipt_hashgrid_workspace_floats",
+    "fipt_hashgrid_backward",
     "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
     "fipt_server_result", "fipt_server_release", "fipt_server_cancel", "fipt_server_stats_get",
     "fipt_server_destroy",
@@ -101,6 +102,10 @@ def lib():
         "fipt_voxel_plan_create": (C.c_int, [_vp, _i64, _i32, _f32p, _f32p, _i32, C.POINTER(_vp)]),
         "fipt_voxel_plan_destroy": (C.c_int, [_vp]),
         "fipt_voxel_pool": (C.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
+        "fipt_hashgrid_forward": (C.c_int, [_vp, _vp, _i64, _i64, _f32p, _f32p, _vp, _i64, _vp]),
+        "fipt_hashgrid_workspace_floats": (_i64, [_i64]),
+        "fipt_hashgrid_backward": (C.c_int, [_vp, _vp, _i64, _i64, _f32p, _f32p, _vp, _i64, _vp,
+                                             _vp, _i64, _vp]),
         "fipt_scene_set_emission": (C.c_int, [_vp, _vp, _vp]),
         "fipt_scene_info_get": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
         "fipt_scene_destroy": (C.c_int, [_vp]),
@@ -636,6 +641,72 @@ class VoxelPlan:
                 _lib.fipt_voxel_plan_destroy(self.handle)
         except Exception:
             pass
+
+
+# hash-grid material network (Eq. 14): tables [32][2^19][2], W1, W2 [64][64], W3 [5][64]
+HG_PARAMS = 32 * (1 << 19) * 2 + 64 * 64 + 64 * 64 + 5 * 64
+
+
+def fipt_hashgrid_forward(params: torch.Tensor, pos: torch.Tensor, bmin, bmax,
+                          out: torch.Tensor = None):
+    """params [HG_PARAMS] float32 GPU, pos [3, n] -> material [5, n]."""
+    _need(params, (HG_PARAMS,), "params")
+    if pos.dim() != 2 or pos.shape[0] != 3:
+        raise ValueError(f"pos must be [3, n], got {tuple(pos.shape)}")
+    n = pos.shape[1]
+    if out is None:
+        out = torch.empty((5, n), dtype=torch.float32, device=pos.device)
+    _need(out, (5, n), "out")
+    _check(lib().fipt_hashgrid_forward(_dev(params, torch.float32, "params"),
+                                       _dev(pos, torch.float32, "pos"), n, n, _f32_array(bmin, 3),
+                                       _f32_array(bmax, 3), _dev(out, torch.float32, "out"), n,
+                                       _stream()))
+    return out
+
+
+def fipt_hashgrid_backward(params: torch.Tensor, pos: torch.Tensor, bmin, bmax,
+                           grad_material: torch.Tensor, grad_params: torch.Tensor = None,
+                           workspace: torch.Tensor = None):
+    """Adds d(sum grad_material * material) / d params into grad_params
+    (zeros if None) and returns it."""
+    _need(params, (HG_PARAMS,), "params")
+    n = pos.shape[1]
+    _need(pos, (3, n), "pos")
+    _need(grad_material, (5, n), "grad_material")
+    if grad_params is None:
+        grad_params = torch.zeros((HG_PARAMS,), dtype=torch.float32, device=pos.device)
+    _need(grad_params, (HG_PARAMS,), "grad_params")
+    need = int(lib().fipt_hashgrid_workspace_floats(n))
+    if workspace is None:
+        workspace = torch.empty((need,), dtype=torch.float32, device=pos.device)
+    if workspace.dim() != 1 or workspace.shape[0] < need:
+        raise ValueError(f"workspace must hold at least {need} floats")
+    _check(lib().fipt_hashgrid_backward(_dev(params, torch.float32, "params"),
+                                        _dev(pos, torch.float32, "pos"), n, n, _f32_array(bmin, 3),
+                                        _f32_array(bmax, 3),
+                                        _dev(grad_material, torch.float32, "grad_material"), n,
+                                        _dev(grad_params, torch.float32, "grad_params"),
+                                        _dev(workspace, torch.float32, "workspace"),
+                                        workspace.shape[0], _stream()))
+    return grad_params
+
+
+class HashGridMaterial(torch.autograd.Function):
+    """material [5, n] = Sigmoid(MLP(hash encoding(pos))); differentiable in
+    ``params`` through the library's backward pass."""
+
+    @staticmethod
+    def forward(ctx, params, pos, bmin, bmax):
+        ctx.save_for_backward(params, pos)
+        ctx.box = (list(bmin), list(bmax))
+        return fipt_hashgrid_forward(params.detach(), pos, bmin, bmax)
+
+    @staticmethod
+    def backward(ctx, g):
+        params, pos = ctx.saved_tensors
+        bmin, bmax = ctx.box
+        gp = fipt_hashgrid_backward(params.detach(), pos, bmin, bmax, g.contiguous())
+        return gp, None, None, None
 
 
 class GridGather(torch.autograd.Function):

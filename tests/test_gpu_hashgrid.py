@@ -1,0 +1,147 @@
+"""GPU parity of the hash-grid material network (Eq. 14) against the
+oracle, through the C ABI: forward outputs, the table and weight
+gradients of the backward pass, and the chain into the factored loss.
+
+Sizes: 1 to 100,003 points for the forward pass (and sampled points of the
+room's 1,843,200 shading points), 20,000 points for the backward pass, with
+points outside the box and on its faces.  The kernels compute in single
+precision against the float64 oracle; cell indices are the same integers
+on both sides by construction (single-precision positions, power-of-two
+resolutions)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import hashgrid as hg
+from oracle import render as orr
+from paper_2304_05669_amd import fipt
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+LO = np.array([-1.0, 0.0, 2.0], np.float32)
+HI = np.array([3.0, 2.0, 3.0], np.float32)
+SIG = tuple(float(s) for s in np.asarray(synth.SIGMA_GRID, np.float32))
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def _params(seed):
+    """Tables U(-1, 1) (so every level matters), weights N(0, 1/4^2)."""
+    rng = np.random.default_rng(seed)
+    p = np.empty(hg.N_PARAMS, np.float32)
+    p[:hg.N_TABLE] = rng.uniform(-1, 1, hg.N_TABLE)
+    p[hg.N_TABLE:] = rng.standard_normal(hg.N_PARAMS - hg.N_TABLE) / 4.0
+    return p
+
+
+def _points(n, seed):
+    rng = np.random.default_rng(seed)
+    x = LO[:, None] + rng.uniform(-0.05, 1.05, (3, n)) * (HI - LO)[:, None]
+    x[0, : n // 10] = HI[0]          # on the far face
+    x[2, n // 10: n // 5] = LO[2]    # on the near face
+    return x.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 1000, 100003])
+def test_forward_parity(n):
+    params = _params(n % 7)
+    x = _points(n, n % 11)
+    got = fipt.fipt_hashgrid_forward(_t(params), _t(x), LO, HI)
+    torch.cuda.synchronize()
+    want, _ = hg.forward(params, x, LO, HI)
+    err = np.abs(got.cpu().numpy().astype(np.float64) - want)
+    assert err.max() <= 2e-5, err.max()
+
+
+def test_forward_room_points_sampled():
+    """The room's shading points (the differentiation workload's size):
+    every output on the GPU, 4096 of them checked against the oracle."""
+    sc = synth.room()
+    scene = fipt.Scene(sc.verts, sc.tris, device=0)
+    planes, _ = fipt.fipt_gen_points(scene, sc.cameras)
+    pos = planes[0:3].contiguous()
+    params = _params(3)
+    got = fipt.fipt_hashgrid_forward(_t(params), pos, sc.bmin, sc.bmax)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(4).choice(sc.n_points, 4096, replace=False))
+    xs = pos.cpu().numpy()[:, idx]
+    want, _ = hg.forward(params, xs, sc.bmin, sc.bmax)
+    err = np.abs(got.cpu().numpy()[:, idx].astype(np.float64) - want)
+    assert err.max() <= 2e-5, err.max()
+    scene.destroy()
+
+
+def _close(got, want, tol, what):
+    """|got - want| <= tol (|want| + 1e-3 max|want|) elementwise."""
+    g = np.asarray(got, np.float64)
+    scale = np.abs(want) + 1e-3 * np.abs(want).max()
+    bad = np.abs(g - want) > tol * scale
+    assert not bad.any(), f"{what}: {bad.sum()} entries off, worst {np.max(np.abs(g - want) / scale):.3e}"
+
+
+def test_backward_parity_and_weight_determinism():
+    n = 20000
+    params = _params(5)
+    x = _points(n, 6)
+    gy = np.random.default_rng(7).standard_normal((5, n)).astype(np.float32)
+    P, X, G = _t(params), _t(x), _t(gy)
+    g1 = fipt.fipt_hashgrid_backward(P, X, LO, HI, G)
+    g2 = fipt.fipt_hashgrid_backward(P, X, LO, HI, G)
+    torch.cuda.synchronize()
+    want = hg.backward(params, x, LO, HI, gy)
+    a = g1.cpu().numpy()
+    # weight gradients: summed in a fixed order
+    assert torch.equal(g1[hg.N_TABLE:], g2[hg.N_TABLE:])
+    _close(a[hg.N_TABLE:hg.N_TABLE + hg.N_W1], want[hg.N_TABLE:hg.N_TABLE + hg.N_W1], 1e-3, "W1 grad")
+    _close(a[hg.N_TABLE + hg.N_W1:hg.N_TABLE + hg.N_W1 + hg.N_W2],
+           want[hg.N_TABLE + hg.N_W1:hg.N_TABLE + hg.N_W1 + hg.N_W2], 1e-3, "W2 grad")
+    _close(a[-hg.N_W3:], want[-hg.N_W3:], 1e-3, "W3 grad")
+    # table gradients: per level
+    for l in (0, 1, 2, 3, 10, 31):
+        sl = slice(l * hg.T * hg.FEATURES, (l + 1) * hg.T * hg.FEATURES)
+        _close(a[sl], want[sl], 1e-3, f"table grad level {l}")
+    # untouched entries stay exactly zero
+    touched = want[:hg.N_TABLE] != 0
+    assert np.all(a[:hg.N_TABLE][~touched] == 0.0)
+
+
+def test_backward_accumulates_and_rejects_small_workspace():
+    n = 500
+    params = _params(8)
+    x = _points(n, 9)
+    gy = np.random.default_rng(10).standard_normal((5, n)).astype(np.float32)
+    P, X, G = _t(params), _t(x), _t(gy)
+    once = fipt.fipt_hashgrid_backward(P, X, LO, HI, G)
+    twice = fipt.fipt_hashgrid_backward(P, X, LO, HI, G, grad_params=once.clone())
+    torch.cuda.synchronize()
+    w = slice(hg.N_TABLE, None)
+    torch.testing.assert_close(twice[w], 2 * once[w], rtol=1e-6, atol=0)
+    with pytest.raises(ValueError):
+        fipt.fipt_hashgrid_backward(P, X, LO, HI, G, workspace=torch.empty(10, device=DEV))
+    with pytest.raises(fipt.FiptError):
+        fipt.fipt_hashgrid_forward(P, X, HI, LO)
+
+
+def test_chain_into_factored_loss():
+    """material = network(x); loss = factored render loss; d loss / d params
+    through HashGridMaterial and FactoredLoss equals the oracle's chain."""
+    n = 5000
+    params = _params(11)
+    x = _points(n, 12)
+    sh = synth.random_shading(n, 6, seed=13)
+    obs = synth.random_observations(n, seed=14)
+    P = _t(params).requires_grad_(True)
+    mat = fipt.HashGridMaterial.apply(P, _t(x), LO, HI)
+    loss = fipt.FactoredLoss.apply(mat, _t(sh), _t(obs), SIG, 0)
+    loss.backward()
+    mat_o, _ = hg.forward(params, x, LO, HI)
+    loss_o, grad_mat_o, _ = orr.loss_and_grad(sh, mat_o, obs, SIG)
+    want = hg.backward(params, x, LO, HI, grad_mat_o)
+    assert abs(float(loss.item()) - loss_o) <= 1e-4 * loss_o
+    g = P.grad.cpu().numpy()
+    _close(g[hg.N_TABLE:], want[hg.N_TABLE:], 2e-3, "weight grads through the loss")
+    _close(g[:hg.T * hg.FEATURES], want[:hg.T * hg.FEATURES], 2e-3, "level 0 grads through the loss")
