@@ -47,6 +47,11 @@ LOSS_BYTES_PER_POINT = 112
 MASKED_LOSS_BYTES_PER_POINT = 120
 LAMBDA_D = 5e-4        # weight of the diffuse prior, as in Eq. 17
 VOXEL_RES = 256        # the radiance cache grid of Sec. 4.2
+# hash-grid network forward, per point: 32 levels x 8 vertices x 8 B of
+# table reads, 12 B position in, 20 B material out; 2 (64*64 + 64*64 + 5*64)
+# multiply-adds as flops
+HG_FWD_BYTES_PER_POINT = 32 * 8 * 8 + 12 + 20
+HG_FWD_FLOPS_PER_POINT = 2 * (64 * 64 + 64 * 64 + 5 * 64)
 SHADING_PLANES = 39
 COUNTERS = os.path.join(ROOT, "profiles", "counters_room.json")
 # the sources each measured kernel is built from
@@ -55,6 +60,7 @@ KERNEL_SOURCES = {
     "k_render_loss": ("loss.hip", "fipt_internal.hpp"),
     "k_render_loss_masked": ("loss.hip", "fipt_internal.hpp"),
     "k_bake_voxel": ("bake.hip", "device.hpp", "fipt_internal.hpp", "bvh_build.cpp"),
+    "k_hg_forward": ("hashgrid.hip", "fipt_internal.hpp"),
 }
 
 
@@ -378,6 +384,61 @@ def run_voxel(scene, sc, planes, tri, obs, out, reps=3):
                     "observation per pixel (4 + 12 B)"}
 
 
+def run_hashgrid(sc, planes, shading, obs, reps=5):
+    """The paper's material network (Eq. 14) on the room's points: forward
+    (hash encoding + MLP), the factored loss with its material gradient,
+    and the backward pass into table and weight gradients."""
+    N = planes.shape[1]
+    dev = planes.device
+    bmin, bmax = sc.bmin.tolist(), sc.bmax.tolist()
+    params = torch.from_numpy(synth.hashgrid_params()).to(dev)
+    pos = planes[0:3].contiguous()
+    mat = torch.empty((5, N), dtype=torch.float32, device=dev)
+    gmat = torch.empty((5, N), dtype=torch.float32, device=dev)
+    gpar = torch.zeros_like(params)
+    ws = torch.empty((int(fipt.lib().fipt_hashgrid_workspace_floats(N)),), dtype=torch.float32,
+                     device=dev)
+    buf = torch.empty((fipt.LOSS_SLOTS,), dtype=torch.float64, device=dev)
+
+    def once(tm=None):
+        if tm:
+            tm.mark("a")
+        fipt.fipt_hashgrid_forward(params, pos, bmin, bmax, out=mat)
+        if tm:
+            tm.mark("b")
+        fipt.fipt_render_loss(shading, mat, obs, sc.sigma, loss_buf=buf, grad=gmat)
+        if tm:
+            tm.mark("c")
+        gpar.zero_()
+        if tm:
+            tm.mark("d")
+        fipt.fipt_hashgrid_backward(params, pos, bmin, bmax, gmat, grad_params=gpar, workspace=ws)
+        if tm:
+            tm.mark("e")
+
+    once()
+    torch.cuda.synchronize()
+    torch.cuda._sleep(5_000_000)
+    tm = Timer()
+    for _ in range(reps):
+        once(tm)
+    torch.cuda.synchronize()
+    t_fwd = float(np.mean(tm.spans("a", "b")))
+    t_loss = float(np.mean(tm.spans("b", "c")))
+    t_zero = float(np.mean(tm.spans("c", "d")))
+    t_bwd = float(np.mean(tm.spans("d", "e")))
+    fwd_bytes = HG_FWD_BYTES_PER_POINT * N
+    return {"points": N, "params": int(params.numel()), "forward_ms": t_fwd,
+            "loss_ms": t_loss, "zero_grad_ms": t_zero, "backward_ms": t_bwd,
+            "step_points_per_s": N / ((t_fwd + t_loss + t_zero + t_bwd) * 1e-3),
+            "forward_bytes_per_point": HG_FWD_BYTES_PER_POINT,
+            "forward_gbs": fwd_bytes / (t_fwd * 1e-3) / 1e9,
+            "forward_flops_per_point": HG_FWD_FLOPS_PER_POINT,
+            "forward_tflops": HG_FWD_FLOPS_PER_POINT * N / (t_fwd * 1e-3) / 1e12,
+            "traffic_forward": measured_traffic().get("k_hg_forward"),
+            "kernel": "k_hg_forward"}
+
+
 def run_large(dev, rebakes, copy_gbs):
     """The emitter loop on the ~2M-triangle room: ``rebakes`` iterations,
     each re-estimating the per-triangle emission of that iteration's emitter
@@ -596,6 +657,8 @@ def main():
     del flush, alpha
     voxel = run_voxel(scene, sc, planes, tri, obs, shading)
     log(f"voxel cache: {voxel}")
+    hashgrid = run_hashgrid(sc, planes, shading, obs)
+    log(f"hash-grid network: {hashgrid}")
 
     large = None
     if args.large_rebakes > 0:
@@ -649,6 +712,7 @@ def main():
                      "traversal_bytes_per_launch": bake_bytes},
         "masked_loss": masked,
         "voxel_cache": voxel,
+        "hashgrid_network": hashgrid,
         "roofline_render_loss": {"bound": "hbm", "achieved": loss_gbs, "peak": PEAK_HBM_GBS,
                                  "unit": "GB/s", "frac": loss_gbs / PEAK_HBM_GBS,
                                  "traffic": traffic.get("k_render_loss"),

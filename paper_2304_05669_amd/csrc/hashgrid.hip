@@ -49,6 +49,7 @@ constexpr int kWeights = kW1 + kW2 + kW3;   // 8512
 constexpr int kBlock = 256;
 constexpr int kChunk = 8192;              // points per weight-gradient partial
 constexpr int kWsRows = 3 * 64 + 2 * 64 + kOut;   // e, h1, h2, d1, d2, d3
+constexpr int kAggregateLevels = 6;       // levels whose table updates are combined per wavefront
 
 struct HgArgs {
     const float* params;
@@ -150,6 +151,30 @@ __device__ __forceinline__ void dense_relu(const float* W, const float* x, float
     }
 }
 
+// Table update of one vertex per lane, combined across the wavefront: lanes
+// naming the same slot are summed by a butterfly and one of them adds the
+// total.  On the coarse levels neighbouring pixels share vertices, and one
+// atomic per distinct slot replaces up to 64 on the same address.
+__device__ __forceinline__ void add_combined(float* t, uint32_t idx, float v0, float v1, int lane) {
+    uint64_t todo = __builtin_amdgcn_ballot_w64(true);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t lidx = __shfl(idx, leader, 64);
+        const bool mine = ((todo >> lane) & 1ull) && idx == lidx;
+        todo &= ~__builtin_amdgcn_ballot_w64(mine);
+        float s0 = mine ? v0 : 0.0f, s1 = mine ? v1 : 0.0f;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            s0 += __shfl_xor(s0, m, 64);
+            s1 += __shfl_xor(s1, m, 64);
+        }
+        if (lane == leader) {
+            atomicAdd(t + (int64_t)lidx * kFeat, s0);
+            atomicAdd(t + (int64_t)lidx * kFeat + 1, s1);
+        }
+    }
+}
+
 // Occupancy targets keep the compiler from hoisting the weight loads of the
 // unrolled products into hundreds of registers: 4 waves per SIMD (at most
 // 128 VGPRs) for the forward pass, 3 (at most 168) for the backward pass,
@@ -189,21 +214,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     const float* W1 = w;
     const float* W2 = w + kW1;
     const float* W3 = w + kW1 + kW2;
+    // every lane of a wavefront runs the body (the table updates combine
+    // lanes); a lane past the last point takes the origin and adds zeros
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < a.n) {
-        float p[3], h1[kHid], h2[kHid];
-        unit_pos(a, i, p);
-        encode_layer1(a.params, W1, p, h1, ws + i, wn);
+    const bool live = i < a.n;
+    const int lane = threadIdx.x & 63;
+    {
+        float p[3] = {0.0f, 0.0f, 0.0f}, h1[kHid], h2[kHid];
+        if (live) unit_pos(a, i, p);
+        encode_layer1(a.params, W1, p, h1, live ? ws + i : nullptr, wn);
         uint64_t m1 = 0, m2;
 #pragma unroll
         for (int o = 0; o < kHid; ++o) {
             m1 |= (uint64_t)(h1[o] > 0.0f) << o;
             h1[o] = fmaxf(h1[o], 0.0f);
-            ws[(int64_t)(64 + o) * wn + i] = h1[o];
+            if (live) ws[(int64_t)(64 + o) * wn + i] = h1[o];
         }
         dense_relu(W2, h1, h2, m2);
 #pragma unroll
-        for (int o = 0; o < kHid; ++o) ws[(int64_t)(128 + o) * wn + i] = h2[o];
+        for (int o = 0; o < kHid; ++o)
+            if (live) ws[(int64_t)(128 + o) * wn + i] = h2[o];
         float d3[kOut];
 #pragma unroll
         for (int o = 0; o < kOut; ++o) {
@@ -211,8 +241,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 #pragma unroll
             for (int j = 0; j < kHid; ++j) s = fmaf(W3[o * kHid + j], h2[j], s);
             const float y = 1.0f / (1.0f + expf(-s));
-            d3[o] = gy[o * gs + i] * y * (1.0f - y);
-            ws[(int64_t)(320 + o) * wn + i] = d3[o];
+            d3[o] = live ? gy[o * gs + i] * y * (1.0f - y) : 0.0f;
+            if (live) ws[(int64_t)(320 + o) * wn + i] = d3[o];
         }
         // d2 = (W3^T d3) masked, in h2's registers
 #pragma unroll
@@ -221,7 +251,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 #pragma unroll
             for (int o = 0; o < kOut; ++o) s = fmaf(W3[o * kHid + j], d3[o], s);
             h2[j] = ((m2 >> j) & 1ull) ? s : 0.0f;
-            ws[(int64_t)(256 + j) * wn + i] = h2[j];
+            if (live) ws[(int64_t)(256 + j) * wn + i] = h2[j];
             __builtin_amdgcn_sched_barrier(0);
         }
         // d1 = (W2^T d2) masked, in h1's registers
@@ -231,7 +261,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 #pragma unroll
             for (int j = 0; j < kHid; ++j) s = fmaf(W2[j * kHid + k], h2[j], s);
             h1[k] = ((m1 >> k) & 1ull) ? s : 0.0f;
-            ws[(int64_t)(192 + k) * wn + i] = h1[k];
+            if (live) ws[(int64_t)(192 + k) * wn + i] = h1[k];
             __builtin_amdgcn_sched_barrier(0);
         }
         // per level: feature gradients (W1^T d1, rows 2l and 2l + 1) into the
@@ -248,10 +278,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             float wt[8];
             corners(l, p, idx, wt);
             float* t = gparams + (int64_t)l * kT * kFeat;
+            if (l < kAggregateLevels) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                atomicAdd(t + (int64_t)idx[k] * kFeat, wt[k] * g0);
-                atomicAdd(t + (int64_t)idx[k] * kFeat + 1, wt[k] * g1);
+                for (int k = 0; k < 8; ++k) add_combined(t, idx[k], wt[k] * g0, wt[k] * g1, lane);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (live) {
+                        atomicAdd(t + (int64_t)idx[k] * kFeat, wt[k] * g0);
+                        atomicAdd(t + (int64_t)idx[k] * kFeat + 1, wt[k] * g1);
+                    }
+                }
             }
         }
     }

@@ -20,6 +20,7 @@ from .scenes import (  # noqa: F401
     serving_trace,
     emitter_observations,
     emission_mask,
+    hashgrid_params,
     emitter_schedule,
     icosphere,
     SERVING_TRIANGLES,

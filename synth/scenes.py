@@ -518,3 +518,15 @@ def emission_mask(emission: np.ndarray, tri: np.ndarray, seed: int = 2107) -> np
     on[seen] = lit[tri[seen]]
     alpha[on] = rng.uniform(0.5, 1.0, int(on.sum())).astype(np.float32)
     return alpha
+
+
+def hashgrid_params(seed: int = 2108) -> np.ndarray:
+    """Parameters of the hash-grid material network, laid out as tables
+    [32][2^19][2] then W1 [64][64], W2 [64][64], W3 [5][64]: table entries
+    U(-1e-4, 1e-4) (the encoding's usual initialisation), weights
+    N(0, 1 / 64) (unit gain through each layer).  float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_tab = 32 * (1 << 19) * 2
+    n_w = 64 * 64 + 64 * 64 + 5 * 64
+    return np.concatenate([rng.uniform(-1e-4, 1e-4, n_tab),
+                           rng.standard_normal(n_w) / 8.0]).astype(np.float32)
