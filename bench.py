@@ -47,10 +47,9 @@ LOSS_BYTES_PER_POINT = 112
 MASKED_LOSS_BYTES_PER_POINT = 120
 LAMBDA_D = 5e-4        # weight of the diffuse prior, as in Eq. 17
 VOXEL_RES = 256        # the radiance cache grid of Sec. 4.2
-# hash-grid network forward, per point: 32 levels x 8 vertices x 8 B of
-# table reads, 12 B position in, 20 B material out; 2 (64*64 + 64*64 + 5*64)
-# multiply-adds as flops
-HG_FWD_BYTES_PER_POINT = 32 * 8 * 8 + 12 + 20
+# hash-grid network forward, per point: 8 B per table vertex read (those of
+# non-zero weight, counted per run), 12 B position in, 20 B material out;
+# 2 (64*64 + 64*64 + 5*64) multiply-adds as flops
 HG_FWD_FLOPS_PER_POINT = 2 * (64 * 64 + 64 * 64 + 5 * 64)
 SHADING_PLANES = 39
 COUNTERS = os.path.join(ROOT, "profiles", "counters_room.json")
@@ -427,12 +426,27 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
     t_loss = float(np.mean(tm.spans("b", "c")))
     t_zero = float(np.mean(tm.spans("c", "d")))
     t_bwd = float(np.mean(tm.spans("d", "e")))
-    fwd_bytes = HG_FWD_BYTES_PER_POINT * N
+    # vertex reads the forward pass needs: a vertex with zero trilinear weight
+    # is not read (from level 20 on a single-precision position sits on a
+    # vertex); counted from the same single-precision cell arithmetic
+    lo = torch.tensor(bmin, dtype=torch.float32, device=dev)[:, None]
+    inv = 1.0 / (torch.tensor(bmax, dtype=torch.float32, device=dev)[:, None] - lo)
+    p = torch.clamp((pos - lo) * inv, 0.0, 1.0)
+    reads = torch.zeros(N, dtype=torch.float64, device=dev)
+    for lv in range(32):
+        nl = float(16 * 2 ** lv)
+        u = p * nl
+        f = u - torch.minimum(torch.floor(u), torch.full_like(u, nl - 1.0))
+        reads += torch.prod(1.0 + (f != 0).to(torch.float64), dim=0)
+    reads_pp = float(reads.mean().item())
+    bytes_pp = 8.0 * reads_pp + 32.0
+    del p, u, f, reads
     return {"points": N, "params": int(params.numel()), "forward_ms": t_fwd,
             "loss_ms": t_loss, "zero_grad_ms": t_zero, "backward_ms": t_bwd,
             "step_points_per_s": N / ((t_fwd + t_loss + t_zero + t_bwd) * 1e-3),
-            "forward_bytes_per_point": HG_FWD_BYTES_PER_POINT,
-            "forward_gbs": fwd_bytes / (t_fwd * 1e-3) / 1e9,
+            "forward_vertex_reads_per_point": reads_pp,
+            "forward_bytes_per_point": bytes_pp,
+            "forward_gbs": bytes_pp * N / (t_fwd * 1e-3) / 1e9,
             "forward_flops_per_point": HG_FWD_FLOPS_PER_POINT,
             "forward_tflops": HG_FWD_FLOPS_PER_POINT * N / (t_fwd * 1e-3) / 1e12,
             "traffic_forward": measured_traffic().get("k_hg_forward"),

@@ -119,11 +119,16 @@ __device__ __forceinline__ void encode_layer1(const float* __restrict__ tab, con
         corners(l, p, idx, w);
         const float2* t = t2 + (int64_t)l * kT;
         float e0 = 0.0f, e1 = 0.0f;
+        // from level 20 on (2^24 cells per axis and more) a single-precision
+        // position sits exactly on a vertex: 7 of the 8 weights are zero, and
+        // their reads are skipped
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const float2 v = t[idx[k]];
-            e0 = fmaf(w[k], v.x, e0);
-            e1 = fmaf(w[k], v.y, e1);
+            if (w[k] != 0.0f) {
+                const float2 v = t[idx[k]];
+                e0 = fmaf(w[k], v.x, e0);
+                e1 = fmaf(w[k], v.y, e1);
+            }
         }
         if (ws_e) {
             ws_e[(int64_t)(2 * l) * wn] = e0;
@@ -284,7 +289,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             } else {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    if (live) {
+                    if (live && wt[k] != 0.0f) {   // zero-weight vertices add nothing
                         atomicAdd(t + (int64_t)idx[k] * kFeat, wt[k] * g0);
                         atomicAdd(t + (int64_t)idx[k] * kFeat + 1, wt[k] * g1);
                     }
