@@ -24,7 +24,7 @@
 // stores its activations and layer gradients in a workspace.  The weight
 // gradients are sums over points of outer products (three small GEMMs with
 // the point count as the reduction dimension): a split-K kernel forms one
-// 64 x 64 partial per chunk of 8192 points from LDS tiles, and a final
+// 64 x 64 partial per chunk of 8192 points on the matrix cores, and a final
 // kernel adds the partials in chunk order, so weight gradients are
 // reproducible bit for bit.
 #include <hip/hip_runtime.h>
@@ -299,12 +299,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     }
 }
 
-// Weight-gradient partials: blockIdx.y picks the product (0: d1 x e -> W1,
-// 1: d2 x h1 -> W2, 2: d3 x h2 -> W3), blockIdx.x a chunk of kChunk points.
-// Thread t owns the 4 x 4 outputs at rows 4 (t / 16), columns 4 (t % 16).
+// Weight-gradient partials on the matrix cores: blockIdx.y picks the product
+// (0: d1 x e -> W1, 1: d2 x h1 -> W2, 2: d3 x h2 -> W3), blockIdx.x a chunk
+// of kChunk points; the workgroup's four wavefronts form the 64 x 64
+// partial as four 32 x 32 tiles with v_mfma_f32_32x32x2f32, the points being
+// the reduction dimension, two per instruction.  Operands are staged
+// through LDS in tiles of 64 points by the whole workgroup (32-point tiles:
+// 7 % slower).  Lane layout of that instruction: lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register r of lane l
+// holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+typedef float v16f __attribute__((ext_vector_type(16)));
+
 __global__ __launch_bounds__(kBlock) void k_hg_wgrad(const float* __restrict__ ws, int64_t wn,
                                                      int64_t n, float* __restrict__ part) {
-    constexpr int kTile = 32;
+    constexpr int kTile = 64;
     __shared__ float A[64][kTile + 1];
     __shared__ float B[64][kTile + 1];
     const int mat = blockIdx.y;
@@ -312,11 +320,17 @@ __global__ __launch_bounds__(kBlock) void k_hg_wgrad(const float* __restrict__ w
     const int a_row0 = mat == 0 ? 192 : mat == 1 ? 256 : 320;
     const int b_row0 = mat == 0 ? 0 : mat == 1 ? 64 : 128;
     const int t = threadIdx.x;
-    const int o0 = 4 * (t / 16), i0 = 4 * (t % 16);
-    float acc[4][4] = {};
+    const int wave = t >> 6, lane = t & 63;
+    const int ti = wave >> 1, tj = wave & 1;   // this wavefront's 32 x 32 tile
+    const int li = lane % 32, lk = lane / 32;
+    v16f acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     const int64_t p_begin = (int64_t)blockIdx.x * kChunk;
     const int64_t p_end = std::min<int64_t>(n, p_begin + kChunk);
     for (int64_t p0 = p_begin; p0 < p_end; p0 += kTile) {
+        // the workgroup stages 64 rows x 64 points of each operand
+        // (coalesced along points)
         for (int idx = t; idx < 64 * kTile; idx += kBlock) {
             const int r = idx / kTile, c = idx % kTile;
             const int64_t pp = p0 + c;
@@ -325,26 +339,19 @@ __global__ __launch_bounds__(kBlock) void k_hg_wgrad(const float* __restrict__ w
             B[r][c] = in ? ws[(int64_t)(b_row0 + r) * wn + pp] : 0.0f;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int c = 0; c < kTile; ++c) {
-            float av[4], bv[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                av[k] = A[o0 + k][c];
-                bv[k] = B[i0 + k][c];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) acc[k][m] = fmaf(av[k], bv[m], acc[k][m]);
-        }
+        for (int k0 = 0; k0 < kTile; k0 += 2)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[32 * ti + li][k0 + lk],
+                                                       B[32 * tj + li][k0 + lk], acc, 0, 0, 0);
         __syncthreads();
     }
     float* out = part + ((int64_t)mat * gridDim.x + blockIdx.x) * 4096;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) out[(o0 + k) * 64 + i0 + m] = acc[k][m];
+    for (int r = 0; r < 16; ++r) {
+        const int i = 32 * ti + 8 * (r / 4) + 4 * lk + (r % 4);
+        const int j = 32 * tj + li;
+        out[i * 64 + j] = acc[r];
+    }
 }
 
 // gparams[weights] += the partials summed in chunk order.
