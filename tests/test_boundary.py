@@ -71,6 +71,20 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_voxel_plan_create(pos, 0, 4, box0, box1, 0, C.byref(out)) == fipt.EINVAL
     assert L.fipt_voxel_pool(None, None, 1, None, 1, None) == fipt.EINVAL
     assert L.fipt_scene_set_voxel_radiance(None, None, 8, 2, box0, box1, None, None) == fipt.EINVAL
+    # hash-grid network: every argument checked before any launch
+    assert L.fipt_hashgrid_forward(None, None, 1, 1, box0, box1, None, 1, None) == fipt.EINVAL
+    assert L.fipt_hashgrid_forward(1, 1, 1, 0, box0, box1, 1, 1, None) == fipt.EINVAL
+    assert L.fipt_hashgrid_forward(1, 1, 1, 1, box1, box0, 1, 1, None) == fipt.EINVAL
+    assert b"bmin < bmax" in L.fipt_last_error()
+    assert L.fipt_hashgrid_forward(1, 1, 4, 8, box0, box1, 1, 8, None) == fipt.EINVAL  # stride < n
+    assert L.fipt_hashgrid_workspace_floats(0) == 0
+    # 325 floats per point (activations and layer gradients) + one 64 x 64
+    # partial per 8192-point chunk for each of the three products
+    assert L.fipt_hashgrid_workspace_floats(10000) == 325 * 10000 + 3 * 2 * 4096
+    need = L.fipt_hashgrid_workspace_floats(100)
+    assert L.fipt_hashgrid_backward(1, 1, 100, 100, box0, box1, 1, 100, 1, 1, need - 1,
+                                    None) == fipt.EINVAL
+    assert b"workspace" in L.fipt_last_error()
 
 
 # (scale, offset) applied to the room: the 4-wide nodes store bounds as
@@ -154,6 +168,10 @@ def test_binding_rejects_misshapen_buffers():
         fipt.fipt_render_loss_masked(sh, mat, obs, sig, alpha=z(9))
     with pytest.raises(ValueError):
         fipt.fipt_render_loss_masked(sh, mat, obs, sig, grad_alpha=z(11))
+    with pytest.raises(ValueError):
+        fipt.fipt_hashgrid_forward(z(100), z(3, 10), [0, 0, 0], [1, 1, 1])
+    with pytest.raises(ValueError):
+        fipt.fipt_hashgrid_forward(z(fipt.HG_PARAMS), z(3, 10), [0, 0, 0], [1, 1, 1], out=z(5, 9))
 
 
 @pytest.mark.parametrize("e", [-100, 100])
