@@ -3,8 +3,9 @@ oracle, through the C ABI: forward outputs, the table and weight
 gradients of the backward pass, and the chain into the factored loss.
 
 Sizes: 1 to 100,003 points for the forward pass (and sampled points of the
-room's 1,843,200 shading points), 20,000 points for the backward pass, with
-points outside the box and on its faces.  The kernels compute in single
+room's 1,843,200 shading points), 20,000 points for the backward pass against
+the oracle and the room's 1,843,200 points for its additivity, with points
+outside the box and on its faces.  The kernels compute in single
 precision against the float64 oracle; cell indices are the same integers
 on both sides by construction (single-precision positions, power-of-two
 resolutions)."""
@@ -145,3 +146,34 @@ def test_chain_into_factored_loss():
     g = P.grad.cpu().numpy()
     _close(g[hg.N_TABLE:], want[hg.N_TABLE:], 2e-3, "weight grads through the loss")
     _close(g[:hg.T * hg.FEATURES], want[:hg.T * hg.FEATURES], 2e-3, "level 0 grads through the loss")
+
+
+def test_backward_full_size_is_additive_over_point_sets():
+    """At the room's full 1,843,200 points (where the float64 oracle's
+    scatter would take minutes) the gradient is checked by a property that
+    holds at any size: the gradient of the whole point set equals the sum of
+    the gradients of its two halves (the sum is linear in the points)."""
+    sc = synth.room()
+    scene = fipt.Scene(sc.verts, sc.tris, device=0)
+    planes, _ = fipt.fipt_gen_points(scene, sc.cameras)
+    pos = planes[0:3].contiguous()
+    n = pos.shape[1]
+    params = _t(synth.hashgrid_params())
+    g = torch.randn((5, n), generator=torch.Generator().manual_seed(15)).to(DEV)
+    whole = fipt.fipt_hashgrid_backward(params, pos, sc.bmin, sc.bmax, g)
+    h = n // 2
+    parts = fipt.fipt_hashgrid_backward(params, pos[:, :h].contiguous(), sc.bmin, sc.bmax,
+                                        g[:, :h].contiguous())
+    parts = fipt.fipt_hashgrid_backward(params, pos[:, h:].contiguous(), sc.bmin, sc.bmax,
+                                        g[:, h:].contiguous(), grad_params=parts)
+    torch.cuda.synchronize()
+    a, b = whole.cpu().numpy().astype(np.float64), parts.cpu().numpy().astype(np.float64)
+    # a weight gradient is a single-precision sum of 225 chunk partials, and a
+    # table entry a single-precision sum of atomic adds in run-dependent
+    # order, with signs that cancel; splitting the points regroups those
+    # sums, which moves a few entries by ~2e-4 of their scale: the bound is
+    # the oracle comparison's
+    _close(a[hg.N_TABLE:], b[hg.N_TABLE:], 1e-3, "weight grads, whole vs halves")
+    _close(a[:hg.N_TABLE], b[:hg.N_TABLE], 1e-3, "table grads, whole vs halves")
+    assert np.abs(a[hg.N_TABLE:]).max() > 0 and np.abs(a[:hg.N_TABLE]).max() > 0
+    scene.destroy()
