@@ -450,7 +450,12 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
             "forward_flops_per_point": HG_FWD_FLOPS_PER_POINT,
             "forward_tflops": HG_FWD_FLOPS_PER_POINT * N / (t_fwd * 1e-3) / 1e12,
             "traffic_forward": measured_traffic().get("k_hg_forward"),
-            "kernel": "k_hg_forward"}
+            "kernel": "k_hg_forward",
+            "roofline_forward": {"bound": "hbm", "achieved": bytes_pp * N / (t_fwd * 1e-3) / 1e9,
+                                 "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": bytes_pp * N / (t_fwd * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                 "traffic": measured_traffic().get("k_hg_forward"),
+                                 "kernel": "k_hg_forward"}}
 
 
 def run_large(dev, rebakes, copy_gbs):
