@@ -17,6 +17,19 @@ from . import build as _build
 _lib = None
 
 WEAK_FURNACE = 1
+EOVERFLOW = -2
+
+
+class CandidateOverflow(RuntimeError):
+    """A ray met more candidate outcomes than the C oracle keeps (256): its
+    envelope would be incomplete, so the result is refused."""
+
+
+def _checked(rc: int, what: str) -> int:
+    if rc == EOVERFLOW:
+        raise CandidateOverflow(f"{what}: a ray met more than 256 candidate outcomes")
+    return rc
+
 
 _f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -50,6 +63,8 @@ def lib():
     L.orc_ggx_D.argtypes = [C.c_double, C.c_double]
     L.orc_ggx_G1.restype = C.c_double
     L.orc_ggx_G1.argtypes = [C.c_double, C.c_double]
+    L.orc_cast.restype = C.c_int
+    L.orc_trace_radiance.restype = C.c_int
     L.orc_cast.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int64, _i32p, _f64p,
                            _f64p, _i32p]
     L.orc_trace_radiance.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int64, _f64p]
@@ -176,7 +191,7 @@ def cast(osc: OracleScene, o: np.ndarray, d: np.ndarray):
     t = np.zeros(n)
     b = np.zeros((n, 2))
     nc = np.zeros(n, np.int32)
-    lib().orc_cast(osc.handle, o, d, n, tri, t, b, nc)
+    _checked(lib().orc_cast(osc.handle, o, d, n, tri, t, b, nc), "cast")
     return tri, t, b, nc
 
 
@@ -186,7 +201,7 @@ def trace_radiance(osc: OracleScene, o: np.ndarray, d: np.ndarray) -> np.ndarray
     o = np.ascontiguousarray(o, dtype=np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
     R = np.zeros((len(o), 3))
-    lib().orc_trace_radiance(osc.handle, o, d, len(o), R)
+    _checked(lib().orc_trace_radiance(osc.handle, o, d, len(o), R), "trace_radiance")
     return R
 
 
@@ -207,8 +222,8 @@ def primary(osc: OracleScene, idx=None, threads: int = 0):
     out = np.zeros((9, n), np.float64)
     tri = np.zeros(n, np.int32)
     amb = np.zeros(n, np.int32)
-    rc = lib().orc_primary(osc.handle, cams, sizes, len(cams), idx, n, out, tri,
-                           amb, int(threads))
+    rc = _checked(lib().orc_primary(osc.handle, cams, sizes, len(cams), idx, n, out, tri,
+                                    amb, int(threads)), "primary")
     if rc != 0:
         raise ValueError("pixel index out of range")
     return dict(points=out, tri=tri, n_outcomes=amb)
@@ -252,9 +267,9 @@ def bake(osc: OracleScene, pts: np.ndarray, tri: np.ndarray, idx=None,
     hi = np.zeros((P, n))
     sq = np.zeros((P, n))
     namb = C.c_int64(0)
-    lib().orc_bake(osc.handle, pts, tri, stride, idx, n, int(spp_d), int(spp_s), K,
-                   sigma, C.c_uint64(int(seed)), float(eps), int(flags), int(threads),
-                   mean, lo, hi, sq, C.byref(namb))
+    _checked(lib().orc_bake(osc.handle, pts, tri, stride, idx, n, int(spp_d), int(spp_s), K,
+                            sigma, C.c_uint64(int(seed)), float(eps), int(flags), int(threads),
+                            mean, lo, hi, sq, C.byref(namb)), "bake")
     return dict(mean=mean, lo=lo, hi=hi, sq=sq, n_ambiguous=int(namb.value))
 
 
@@ -273,8 +288,8 @@ def quadrature(osc: OracleScene, x, n, wo, lobe: int, sigma: float = 0.0,
     lobe < 0: Ld (returns 3 values); lobe >= 0: (Ls0, Ls1) at roughness
     ``sigma`` (returns 6 values)."""
     out = np.zeros(6)
-    lib().orc_quadrature(osc.handle, np.ascontiguousarray(x, np.float64),
+    _checked(lib().orc_quadrature(osc.handle, np.ascontiguousarray(x, np.float64),
                          np.ascontiguousarray(n, np.float64),
                          np.ascontiguousarray(wo, np.float64), int(lobe),
-                         float(sigma), int(n_theta), int(n_phi), float(eps), out)
+                         float(sigma), int(n_theta), int(n_phi), float(eps), out), "quadrature")
     return out[:3] if lobe < 0 else out

@@ -343,6 +343,10 @@ typedef struct {
 } hit_t;
 
 #define MAX_CAND 256
+/* Returned by every entry point that casts rays when some ray met more
+ * candidate outcomes than MAX_CAND: its envelope would be incomplete, so the
+ * result is refused rather than truncated. */
+#define ORC_EOVERFLOW (-2)
 
 typedef struct {
     hit_t nominal;          /* nearest exact hit, tri = -1 on a miss */
@@ -554,13 +558,15 @@ static int radiance_envelope(const scene_t* S, const cast_t* h, double R[3],
 }
 
 /* Rays cast one by one (test hook): nominal hit, barycentrics, outcome count. */
-void orc_cast(void* sp, const double* o, const double* d, int64_t n, int32_t* tri,
-              double* t, double* b, int32_t* n_cand)
+int orc_cast(void* sp, const double* o, const double* d, int64_t n, int32_t* tri,
+             double* t, double* b, int32_t* n_cand)
 {
     const scene_t* S = (const scene_t*)sp;
     cast_t* h = (cast_t*)malloc(sizeof(cast_t));
+    int overflow = 0;
     for (int64_t i = 0; i < n; ++i) {
         cast(S, o + 3 * i, d + 3 * i, h);
+        overflow |= h->overflow;
         tri[i] = h->nominal.tri;
         t[i] = h->nominal.t;
         b[2 * i] = h->nominal.b1;
@@ -568,19 +574,23 @@ void orc_cast(void* sp, const double* o, const double* d, int64_t n, int32_t* tr
         n_cand[i] = h->n_cand;
     }
     free(h);
+    return overflow ? ORC_EOVERFLOW : 0;
 }
 
 /* Radiance arriving along each ray (test hook): nominal hit, cache plus
  * emission, zero on a miss. */
-void orc_trace_radiance(void* sp, const double* o, const double* d, int64_t n, double* R)
+int orc_trace_radiance(void* sp, const double* o, const double* d, int64_t n, double* R)
 {
     const scene_t* S = (const scene_t*)sp;
     cast_t* h = (cast_t*)malloc(sizeof(cast_t));
+    int overflow = 0;
     for (int64_t i = 0; i < n; ++i) {
         cast(S, o + 3 * i, d + 3 * i, h);
+        overflow |= h->overflow;
         radiance(S, &h->nominal, 0, R + 3 * i);
     }
     free(h);
+    return overflow ? ORC_EOVERFLOW : 0;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -623,8 +633,8 @@ int orc_primary(void* sp, const float* cams, const int32_t* sizes, int n_cams,
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
-    int bad = 0;
-#pragma omp parallel
+    int bad = 0, overflow = 0;
+#pragma omp parallel reduction(| : overflow)
     {
         cast_t* h = (cast_t*)malloc(sizeof(cast_t));
 #pragma omp for schedule(dynamic, 16)
@@ -642,6 +652,7 @@ int orc_primary(void* sp, const float* cams, const int32_t* sizes, int n_cams,
             double o[3], d[3];
             camera_ray(cams + 10 * c, W, H, i, j, o, d);
             cast(S, o, d, h);
+            overflow |= h->overflow;
             ambig[q] = h->n_cand;
             tri_out[q] = h->nominal.tri;
             if (h->nominal.tri < 0) {
@@ -664,7 +675,7 @@ int orc_primary(void* sp, const float* cams, const int32_t* sizes, int n_cams,
         free(h);
     }
     free(offs);
-    return bad ? -1 : 0;
+    return bad ? -1 : overflow ? ORC_EOVERFLOW : 0;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -716,10 +727,11 @@ int orc_bake(void* sp, const float* pts, const int32_t* ptri, int64_t stride,
     const scene_t* S = (const scene_t*)sp;
     const int P = 3 + 6 * K;
     int64_t total_ambig = 0;
+    int overflow = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
-#pragma omp parallel reduction(+ : total_ambig)
+#pragma omp parallel reduction(+ : total_ambig) reduction(| : overflow)
     {
         cast_t* h = (cast_t*)malloc(sizeof(cast_t));
         double acc[3 + 6 * 16], alo[3 + 6 * 16], ahi[3 + 6 * 16], asq[3 + 6 * 16];
@@ -752,6 +764,7 @@ int orc_bake(void* sp, const float* pts, const int32_t* ptri, int64_t stride,
                         R[0] = R[1] = R[2] = Rl[0] = Rl[1] = Rl[2] = Rh[0] = Rh[1] = Rh[2] = 1.0;
                     } else {
                         cast(S, o, wi, h);
+                        overflow |= h->overflow;
                         total_ambig += radiance_envelope(S, h, R, Rl, Rh);
                     }
                     for (int c = 0; c < 3; ++c) {
@@ -776,6 +789,7 @@ int orc_bake(void* sp, const float* pts, const int32_t* ptri, int64_t stride,
                             R[0] = R[1] = R[2] = Rl[0] = Rl[1] = Rl[2] = Rh[0] = Rh[1] = Rh[2] = 1.0;
                         } else {
                             cast(S, o, wi, h);
+                            overflow |= h->overflow;
                             total_ambig += radiance_envelope(S, h, R, Rl, Rh);
                         }
                         double F0 = 1.0 - F1;
@@ -804,7 +818,7 @@ int orc_bake(void* sp, const float* pts, const int32_t* ptri, int64_t stride,
         free(h);
     }
     if (n_ambiguous) *n_ambiguous = total_ambig;
-    return 0;
+    return overflow ? ORC_EOVERFLOW : 0;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -831,6 +845,7 @@ int orc_quadrature(void* sp, const double* x, const double* nrm, const double* w
     orc_frame(n, t, b);
     for (int k = 0; k < 3; ++k) o[k] = x[k] + eps * n[k];
     for (int k = 0; k < 6; ++k) out[k] = 0.0;
+    int overflow = 0;
     double dphi = 2.0 * ORC_PI / n_phi;
     if (lobe < 0) {
         double dth = 0.5 * ORC_PI / n_theta;
@@ -841,6 +856,7 @@ int orc_quadrature(void* sp, const double* x, const double* nrm, const double* w
                 double l[3] = {sin(th) * cos(ph), sin(th) * sin(ph), cos(th)}, wi[3], R[3];
                 to_world(t, b, n, l, wi);
                 cast(S, o, wi, h);
+                overflow |= h->overflow;
                 radiance(S, &h->nominal, 0, R);
                 double wgt = cos(th) / ORC_PI * sin(th) * dth * dphi;
                 for (int c = 0; c < 3; ++c) out[c] += R[c] * wgt;
@@ -867,6 +883,7 @@ int orc_quadrature(void* sp, const double* x, const double* nrm, const double* w
                 double F1 = pow(1.0 - om, 5.0), F0 = 1.0 - F1;
                 double R[3];
                 cast(S, o, wi, h);
+                overflow |= h->overflow;
                 radiance(S, &h->nominal, 0, R);
                 double wgt = D * G * om / cos_o * sin(th) * dth * dphi;
                 for (int c = 0; c < 3; ++c) {
@@ -877,7 +894,7 @@ int orc_quadrature(void* sp, const double* x, const double* nrm, const double* w
         }
     }
     free(h);
-    return 0;
+    return overflow ? ORC_EOVERFLOW : 0;
 }
 
 int orc_max_threads(void)

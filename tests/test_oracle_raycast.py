@@ -129,3 +129,88 @@ def test_radiance_lookup():
     one = _single_triangle()
     oo = ob.OracleScene(one)
     np.testing.assert_array_equal(ob.trace_radiance(oo, np.array([0.2, 0.2, 1.0]), np.array([0.0, 0.0, 1.0])), 0.0)
+
+
+def test_closed_mesh_is_watertight_at_shared_edges():
+    """A ray that meets a shared edge of a closed surface hits it: in exact
+    arithmetic the closed barycentric test accepts the edge on both
+    triangles.  Float64 rounding can reject it on both (about one ray in
+    eight aimed exactly at an edge); the oracle then reports the nearest
+    triangle within its tolerance band, with barycentrics clamped onto it.
+    Rays from inside a closed icosphere aimed at points of every shared edge
+    must all hit, at the distance to that point, on one of the two triangles
+    of the edge, and report the other outcome as possible."""
+    v, f = synth.icosphere(2)
+    verts = (v * 1.5 + 0.25).astype(np.float32)
+    tris = f.astype(np.int32)
+    sc = synth.Scene(name="ico", verts=verts, tris=tris, cache_kind="triangle",
+                     cache=np.ones((3, len(tris)), np.float32),
+                     emission=np.zeros((3, len(tris)), np.float32))
+    osc = ob.OracleScene(sc)
+    # every edge and the two triangles that share it
+    owners = {}
+    for t_i, tri in enumerate(tris):
+        for a, b in ((tri[0], tri[1]), (tri[1], tri[2]), (tri[2], tri[0])):
+            owners.setdefault((min(a, b), max(a, b)), []).append(t_i)
+    edges = sorted(owners)
+    assert all(len(owners[e]) == 2 for e in edges)
+    rng = np.random.default_rng(77)
+    V = verts.astype(np.float64)
+    o_all, d_all, want_t, pairs = [], [], [], []
+    for (a, b) in edges:
+        for s in rng.uniform(0.02, 0.98, size=8):
+            tgt = V[a] + s * (V[b] - V[a])
+            o = V.mean(0) + rng.uniform(-0.3, 0.3, size=3)
+            d = tgt - o
+            o_all.append(o)
+            d_all.append(d / np.linalg.norm(d))
+            want_t.append(np.linalg.norm(d))
+            pairs.append(owners[(a, b)])
+    tri, t, bary, nc = ob.cast(osc, np.array(o_all), np.array(d_all))
+    pairs = np.array(pairs)
+    assert (tri >= 0).all(), f"{int((tri < 0).sum())} of {len(tri)} edge rays missed"
+    assert ((tri == pairs[:, 0]) | (tri == pairs[:, 1])).all()
+    np.testing.assert_allclose(t, want_t, rtol=1e-9)
+    assert (bary >= 0).all() and (bary.sum(1) <= 1 + 1e-15).all()
+    assert (nc >= 2).all()
+
+
+def test_silhouette_near_miss_outcomes():
+    """Past the free edge of a lone triangle: inside the tolerance band the
+    nominal result is a hit clamped onto the edge with a miss among the
+    possible outcomes; beyond the band it is a plain miss with one outcome."""
+    osc = ob.OracleScene(_single_triangle())
+    down = np.array([[0.0, 0.0, -1.0]])
+    for off in (1e-9, 1e-7):
+        tri, t, bary, nc = ob.cast(osc, np.array([[0.5 + off, 0.5 + off, 1.0]]), down)
+        assert tri[0] == 0 and nc[0] >= 2 and abs(t[0] - 1.0) < 1e-15
+        assert abs(bary[0].sum() - 1.0) < 1e-15 and (bary[0] >= 0).all()
+    tri, t, bary, nc = ob.cast(osc, np.array([[0.5 + 1e-4, 0.5 + 1e-4, 1.0]]), down)
+    assert tri[0] == -1 and nc[0] == 1
+
+
+def test_candidate_overflow_is_an_error():
+    """More coincident surfaces along one ray than the oracle keeps outcomes
+    for (256): the cast is refused, not truncated."""
+    import pytest
+    n = 300
+    v = np.tile(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), (n, 1))
+    t = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    sc = synth.Scene(name="pile", verts=v, tris=t, cache_kind="triangle",
+                     cache=np.ones((3, n), np.float32), emission=np.zeros((3, n), np.float32))
+    osc = ob.OracleScene(sc)
+    with pytest.raises(ob.CandidateOverflow):
+        ob.cast(osc, np.array([0.25, 0.25, 1.0]), np.array([0.0, 0.0, -1.0]))
+    with pytest.raises(ob.CandidateOverflow):
+        ob.trace_radiance(osc, np.array([0.25, 0.25, 1.0]), np.array([0.0, 0.0, -1.0]))
+    pts = np.zeros((9, 1), np.float32)
+    pts[0:3, 0] = (0.25, 0.25, 0.5)
+    pts[3:6, 0] = (0.0, 0.0, -1.0)
+    pts[6:9, 0] = (0.0, 0.0, -1.0)
+    with pytest.raises(ob.CandidateOverflow):
+        ob.bake(osc, pts, np.zeros(1, np.int32), spp_d=64, spp_s=1, sigma=(0.5,), seed=1)
+    # below the limit: fine, with every copy among the outcomes
+    few = synth.Scene(name="pile", verts=v[:60], tris=t[:20], cache_kind="triangle",
+                      cache=np.ones((3, 20), np.float32), emission=np.zeros((3, 20), np.float32))
+    tri, tt, _, nc = ob.cast(ob.OracleScene(few), np.array([0.25, 0.25, 1.0]), np.array([0.0, 0.0, -1.0]))
+    assert tri[0] == 0 and nc[0] == 20
