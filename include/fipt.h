@@ -309,6 +309,27 @@ int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels,
                      double* loss_dev, float* grad_dev, int64_t grad_stride,
                      float* Lr_dev, int64_t lr_stride, void* stream);
 
+/* fipt_render_loss for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, arithmetic and results (bit for
+ * bit), except that loss_dev needs room for one double only: the
+ * per-workgroup partial sums go to a static array the library holds on
+ * each GPU for the life of the process (FIPT_LOSS_SLOTS - 1 doubles,
+ * 16 KB).  The launch never uses more partials than that (its grid is
+ * capped at that many workgroups, each looping over its share of points),
+ * so no n is too large; the call still returns FIPT_EINVAL with a message
+ * should a launch ever need more.  The call allocates nothing (no hipMalloc
+ * or hipFree, no allocating library routine).  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (different streams, no ordering
+ * between them) race and may return a wrong loss; calls ordered on one
+ * stream are safe.  The first call on each GPU looks up the array's device
+ * address (FIPT_EHIP if that fails). */
+int fipt_render_loss_noalloc(const fipt_shading* sh, int64_t n, int32_t n_levels,
+                             const float* sigma_host, const float* material, int64_t mat_stride,
+                             const float* observed, int64_t obs_stride, int32_t tonemap,
+                             double* loss_dev, float* grad_dev, int64_t grad_stride,
+                             float* Lr_dev, int64_t lr_stride, void* stream);
+
 /* Emission-masked loss (Sec. 4.4, Eq. 12 and its tone-mapped form Eq. 15)
  * plus the diffuse prior (Sec. 4.5, Eq. 17), over the same inputs as
  * fipt_render_loss and an emission mask alpha[n] (device float, NULL for

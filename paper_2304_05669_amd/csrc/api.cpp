@@ -515,8 +515,30 @@ int fipt_render_loss(const fipt_shading* sh, int64_t n, int32_t n_levels, const 
                                lr_stride);
     if (rc) return rc;
     return launch_render_loss(sh->planes, sh->stride, n, n_levels, sigma_host, material, mat_stride,
-                              observed, obs_stride, tonemap, loss_dev, grad_dev, grad_stride,
-                              Lr_dev, lr_stride, nullptr, stream);
+                              observed, obs_stride, tonemap, loss_dev, loss_dev + 1, grad_dev,
+                              grad_stride, Lr_dev, lr_stride, nullptr, stream);
+}
+
+int fipt_render_loss_noalloc(const fipt_shading* sh, int64_t n, int32_t n_levels,
+                             const float* sigma_host, const float* material, int64_t mat_stride,
+                             const float* observed, int64_t obs_stride, int32_t tonemap,
+                             double* loss_dev, float* grad_dev, int64_t grad_stride,
+                             float* Lr_dev, int64_t lr_stride, void* stream) {
+    clear_error();
+    int rc = check_render_loss(sh, n, n_levels, sigma_host, material, mat_stride, observed,
+                               obs_stride, tonemap, loss_dev, grad_dev, grad_stride, Lr_dev,
+                               lr_stride);
+    if (rc) return rc;
+    double* partials = nullptr;
+    int64_t capacity = 0;
+    if ((rc = render_loss_scratch(&partials, &capacity))) return rc;
+    const int64_t need = render_loss_partials(n);
+    if (need > capacity)
+        return fail(FIPT_EINVAL, "render loss needs %lld partial sums, the static array holds %lld",
+                    (long long)need, (long long)capacity);
+    return launch_render_loss(sh->planes, sh->stride, n, n_levels, sigma_host, material, mat_stride,
+                              observed, obs_stride, tonemap, loss_dev, partials, grad_dev,
+                              grad_stride, Lr_dev, lr_stride, nullptr, stream);
 }
 
 int fipt_render_loss_masked(const fipt_shading* sh, int64_t n, int32_t n_levels,
@@ -534,8 +556,8 @@ int fipt_render_loss_masked(const fipt_shading* sh, int64_t n, int32_t n_levels,
         return fail(FIPT_EINVAL, "lambda_d must be finite and >= 0");
     const RenderLossMask mask{alpha, grad_alpha_dev, lambda_d};
     return launch_render_loss(sh->planes, sh->stride, n, n_levels, sigma_host, material, mat_stride,
-                              observed, obs_stride, tonemap, loss_dev, grad_dev, grad_stride,
-                              Lr_dev, lr_stride, &mask, stream);
+                              observed, obs_stride, tonemap, loss_dev, loss_dev + 1, grad_dev,
+                              grad_stride, Lr_dev, lr_stride, &mask, stream);
 }
 
 int fipt_scale_by(const float* x, int64_t n, const double* factor_dev, float* out, void* stream) {

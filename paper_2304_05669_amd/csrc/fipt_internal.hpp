@@ -207,11 +207,18 @@ struct RenderLossMask {
     float* grad_alpha;   // [n] or NULL
     double lambda_d;
 };
+// `partials` receives one double per workgroup (render_loss_partials(n)
+// of them) before the final sum writes loss[0].
 int launch_render_loss(const float* sh, int64_t sh_stride, int64_t n, int32_t K,
                        const float* sigma_host, const float* mat, int64_t mat_stride,
                        const float* obs, int64_t obs_stride, int32_t tone, double* loss,
-                       float* grad, int64_t grad_stride, float* Lr, int64_t lr_stride,
-                       const RenderLossMask* mask, void* stream);
+                       double* partials, float* grad, int64_t grad_stride, float* Lr,
+                       int64_t lr_stride, const RenderLossMask* mask, void* stream);
+// Workgroups (= partial sums) of the render-loss launch for n points.
+int render_loss_partials(int64_t n);
+// Device address of the library's static partials array on the current
+// device, and its capacity in doubles.
+int render_loss_scratch(double** out, int64_t* capacity);
 int launch_scale_by(const float* x, int64_t n, const double* f, float* out, void* stream);
 int launch_grid_gather(const float* grid, int32_t C, int32_t R, const float* bmin,
                        const float* bmax, const float* pos, int64_t pos_stride, int64_t n,

@@ -13,8 +13,20 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "fipt_internal.hpp"
+
+// Per-workgroup loss partials of fipt_render_loss_noalloc: one double per
+// workgroup of the render-loss grid, which is capped at FIPT_LOSS_SLOTS - 1
+// workgroups (each loops over its share of the points), so every point
+// count fits.  Each GPU holds its own copy (16 KB) for the life of the
+// process.  In host code the name is only a stand-in: the device address
+// is looked up once per device (render_loss_scratch below) and only that
+// address is handed to kernels.  Nothing in it needs clearing: every
+// workgroup writes its own slot before the final sum reads it.
+static __device__ __align__(256) double scratch[FIPT_LOSS_SLOTS - 1];
 
 namespace fipt {
 namespace {
@@ -388,19 +400,45 @@ void launch_rl_tone(bool g, bool l, bool mask, dim3 grid, hipStream_t st, const 
 
 }  // namespace
 
+int render_loss_scratch(double** out, int64_t* capacity) {
+    // device addresses of `scratch`, one per GPU, looked up on first use
+    // with that GPU current (the array's name is only a host-side stand-in)
+    static std::mutex mu;
+    static std::vector<double*> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(FIPT_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FIPT_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    *capacity = kMaxPartials;
+    return FIPT_OK;
+}
+
+int render_loss_partials(int64_t n) {
+    const int64_t want = (n + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, kMaxPartials));
+}
+
 int launch_render_loss(const float* sh, int64_t ss, int64_t n, int32_t K, const float* sigma,
                        const float* mat, int64_t ms, const float* obs, int64_t os, int32_t tone,
-                       double* loss, float* grad, int64_t gs, float* Lr, int64_t ls,
-                       const RenderLossMask* mask, void* stream) {
+                       double* loss, double* partials, float* grad, int64_t gs, float* Lr,
+                       int64_t ls, const RenderLossMask* mask, void* stream) {
     SigmaTable tab;
     for (int k = 0; k < FIPT_MAX_LEVELS; ++k) {
         tab.s[k] = k < K ? sigma[k] : 0.0f;
         tab.inv_gap[k] = (k + 1 < K) ? 1.0 / ((double)sigma[k + 1] - (double)sigma[k]) : 0.0;
     }
-    const int64_t want = (n + kBlock - 1) / kBlock;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, kMaxPartials));
+    const int blocks = render_loss_partials(n);
     hipStream_t st = (hipStream_t)stream;
-    double* partials = loss + 1;
     const dim3 grid(blocks);
     RLArgs a{sh, ss, n, K, mat, ms, obs, os, partials, grad, gs, Lr, ls,
              mask ? mask->alpha : nullptr, mask ? mask->grad_alpha : nullptr,

@@ -30,7 +30,7 @@ EXPORTS = (
     "fipt_scene_set_emission", "fipt_scene_info_get", "fipt_bvh_validate", "fipt_scene_destroy",
     "fipt_cast_rays", "fipt_gen_points",
     "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_render_loss",
-    "fipt_render_loss_masked", "fipt_scale_by",
+    "fipt_render_loss_noalloc", "fipt_render_loss_masked", "fipt_scale_by",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
     "fipt_scene_set_voxel_radiance", "fipt_voxel_plan_create", "fipt_voxel_plan_destroy",
@@ -118,6 +118,8 @@ def lib():
                                                 C.POINTER(Shading), _vp, _vp]),
         "fipt_render_loss": (C.c_int, [C.POINTER(Shading), _i64, _i32, _f32p, _vp, _i64, _vp, _i64,
                                        _i32, _vp, _vp, _i64, _vp, _i64, _vp]),
+        "fipt_render_loss_noalloc": (C.c_int, [C.POINTER(Shading), _i64, _i32, _f32p, _vp, _i64, _vp,
+                                               _i64, _i32, _vp, _vp, _i64, _vp, _i64, _vp]),
         "fipt_render_loss_masked": (C.c_int, [C.POINTER(Shading), _i64, _i32, _f32p, _vp, _i64, _vp,
                                               _i64, _vp, _i32, C.c_double, _vp, _vp, _i64, _vp, _vp,
                                               _i64, _vp]),
@@ -406,6 +408,35 @@ def fipt_render_loss(shading: torch.Tensor, material: torch.Tensor, observed: to
         _dev(grad, torch.float32, "grad") if want_grad else None, n,
         _dev(lr, torch.float32, "lr") if want_lr else None, n, _stream()))
     return loss_buf, (grad if want_grad else None), (lr if want_lr else None)
+
+
+def fipt_render_loss_noalloc(shading: torch.Tensor, material: torch.Tensor, observed: torch.Tensor,
+                             sigma, loss: torch.Tensor, grad: torch.Tensor = None,
+                             lr: torch.Tensor = None, tonemap: int = TONEMAP_NONE):
+    """fipt_render_loss with every buffer supplied by the caller and nothing
+    allocated, here or in the library: loss [1] float64 GPU receives the
+    loss, grad [5, n] and Lr [3, n] float32 GPU (or None) as for
+    fipt_render_loss.  Calls that overlap on one GPU race (see fipt.h)."""
+    K = len(sigma)
+    n = material.shape[1]
+    if shading.shape[0] != 3 + 6 * K or shading.shape[1] != n:
+        raise ValueError("shading must be [3 + 6K, n]")
+    if material.shape[0] != 5 or observed.shape != (3, n):
+        raise ValueError("material must be [5, n] and observed [3, n]")
+    _need(loss, (1,), "loss")
+    if grad is not None:
+        _need(grad, (5, n), "grad")
+    if lr is not None:
+        _need(lr, (3, n), "lr")
+    sh = Shading(_dev(shading, torch.float32, "shading"), n)
+    sig = _f32_array(sigma, K)
+    _check(lib().fipt_render_loss_noalloc(
+        C.byref(sh), n, K, sig, _dev(material, torch.float32, "material"), n,
+        _dev(observed, torch.float32, "observed"), n, int(tonemap),
+        _dev(loss, torch.float64, "loss"),
+        _dev(grad, torch.float32, "grad") if grad is not None else None, n,
+        _dev(lr, torch.float32, "lr") if lr is not None else None, n, _stream()))
+    return loss, grad, lr
 
 
 def fipt_render_loss_masked(shading: torch.Tensor, material: torch.Tensor, observed: torch.Tensor,

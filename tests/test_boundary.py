@@ -43,7 +43,14 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_render_loss(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, 0, 1, None, 10, None, 10,
                               None) == fipt.EINVAL
     assert b"increasing" in L.fipt_last_error()
+    assert L.fipt_render_loss_noalloc(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, 0, 1, None, 10, None,
+                                      10, None) == fipt.EINVAL
+    assert b"increasing" in L.fipt_last_error()
+    assert L.fipt_render_loss_noalloc(None, 10, 6, None, None, 10, None, 10, 0, None, None, 10,
+                                      None, 10, None) == fipt.EINVAL
     sig = (C.c_float * 2)(0.2, 0.5)
+    assert L.fipt_render_loss_noalloc(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, 0, None, None, 10,
+                                      None, 10, None) == fipt.EINVAL   # no loss buffer
     for lam in (-1e-3, float("nan"), float("inf")):
         assert L.fipt_render_loss_masked(C.byref(sh), 10, 2, sig, 1, 10, 1, 10, None, 0, lam, 1,
                                          None, 10, None, None, 10, None) == fipt.EINVAL
