@@ -31,8 +31,18 @@ import synth  # noqa: E402
 from paper_2304_05669_amd import fipt  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
-# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
-# operation per lane per cycle (packed FP32 instructions are not used)
+# published vector FP32 peak of MI355X (256 CUs at 2.4 GHz, packed FMA)
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic flops per unit of bake work, counted as the hot path's scope
+# counts them: ~20 per ray-box slab test (four per 4-wide node visited), ~30
+# per ray-triangle test, ~100 per lobe sample (random numbers, direction,
+# weights)
+FLOPS_PER_NODE = 4 * 20
+FLOPS_PER_TRI = 30
+FLOPS_PER_SAMPLE = 100
+# Secondary figure: the VALU issue rate of MI355X, 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz, one operation per lane per cycle (packed FP32
+# instructions are not used), against operations counted per instruction
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic VALU operations per unit of bake work
 OPS_PER_NODE = 81      # 4-wide node: four slab tests (6 FMA, 12 min/max, 1 compare
@@ -129,36 +139,187 @@ def traversal_bytes(scene, planes, tri, sc, out):
     samples = n * sc.spp * (1 + len(sc.sigma))
     total = nodes * 80 + tris * 48 + hits * 48 + n * 40 + n * P * 4
     ops = nodes * OPS_PER_NODE + tris * OPS_PER_TRI + samples * OPS_PER_SAMPLE + hits * OPS_PER_HIT
-    return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, bytes=total, ops=ops,
+    flops = nodes * FLOPS_PER_NODE + tris * FLOPS_PER_TRI + samples * FLOPS_PER_SAMPLE
+    return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, samples=samples, bytes=total,
+                ops=ops, flops=flops,
                 nodes_per_ray=nodes / max(rays, 1), tris_per_ray=tris / max(rays, 1),
                 node_loop_lane_use=nodes / max(64 * node_steps, 1),
                 tri_loop_lane_use=tris / max(64 * tri_steps, 1))
 
 
-def cpu_baseline(sc, planes, tri, budget_s):
-    """The oracle (double precision, brute force) on a bounded sample of the
-    same workload, with every host thread."""
+def oracle_bake_rate(sc, budget_s, seed):
+    """The bake oracle (double precision, every ray against every triangle)
+    on a bounded random sample of a workload's points, with every host
+    thread; its shading points are the oracle's own (camera rays cast by the
+    oracle).  Returns points, seconds, Gsamples/s, threads."""
     from oracle import bake as ob
     osc = ob.OracleScene(sc)
     threads = ob.max_threads()
-    n_pts = planes.shape[1]
     S = sc.spp * (1 + len(sc.sigma))
-    pts = planes.cpu().numpy()
-    tr = tri.cpu().numpy()
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
+
+    def run(k):
+        idx = np.sort(rng.choice(sc.n_points, k, replace=False)).astype(np.int64)
+        p32, t32 = ob.points_f32(ob.primary(osc, idx=idx))
+        t0 = time.perf_counter()
+        ob.bake(osc, p32, t32, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed, threads=threads)
+        return k, time.perf_counter() - t0
+
     # calibrate on one point per thread, then size the sample to the budget
-    idx = np.sort(rng.choice(n_pts, threads, replace=False))
+    # (the calibration run stands if it already took half the budget)
+    k, dt = run(threads)
+    if dt < 0.5 * budget_s:
+        k, dt = run(min(sc.n_points, max(1, int(budget_s / max(dt, 1e-3))) * threads))
+    g = k * S / dt / 1e9
+    return dict(points=k, seconds=dt, gsamples_per_s=g, threads=threads,
+                per_core_gsamples_per_s=g / threads,
+                full_workload_extrapolated_s=sc.n_points * S / (g * 1e9))
+
+
+def cpu_baseline(sc, budget_s, large_sc=None, large_budget_s=0.0, loss=None):
+    """The oracle timed on the host cores: the bake oracle on a bounded
+    sample of the room (the headline figure), on a smaller sample of the
+    2M-triangle room, and the loss+gradient oracle (numpy float64) over a
+    full room-sized point set."""
+    r = oracle_bake_rate(sc, budget_s, 0)
+    S = sc.spp * (1 + len(sc.sigma))
+    out = dict(value=r["gsamples_per_s"], unit="Gsamples/s", cores=r["threads"], kind="oracle",
+               sample=f"{r['points']} random points of the room x {S} lobe samples, brute-force "
+                      f"float64 over all {sc.n_tris} triangles, {r['seconds']:.1f} s",
+               per_core_gsamples_per_s=r["per_core_gsamples_per_s"],
+               room_full_bake_extrapolated_s=r["full_workload_extrapolated_s"])
+    if large_sc is not None and large_budget_s > 0:
+        lr = oracle_bake_rate(large_sc, large_budget_s, 1)
+        out["large_room"] = dict(lr, sample=f"{lr['points']} random points of the "
+                                             f"{large_sc.n_tris:,}-triangle room x "
+                                             f"{large_sc.spp * (1 + len(large_sc.sigma))} lobe samples")
+    if loss is not None:
+        out["loss_grad"] = loss
+    return out
+
+
+# Synthetic inputs of the loss+gradient oracle (a room-sized point set) and
+# the worker pool that times it on all cores.  Both are made before anything
+# initialises the GPU, so the workers are forked from a process without GPU
+# state; they inherit the inputs and return their chunk's loss and gradient.
+_LOSS_IN = None
+
+
+def _loss_chunk(bounds):
+    from oracle import render as orr
+    a, b = bounds
+    sh, mat, obs, sig = _LOSS_IN
+    loss, grad, _ = orr.loss_and_grad(sh[:, a:b], mat[:, a:b], obs[:, a:b], sig)
+    return loss, grad.astype(np.float64)
+
+
+def host_workers():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, int(os.environ.get("OMP_NUM_THREADS", n))))
+
+
+def make_loss_oracle_pool(n_points, K):
+    import multiprocessing as mp
+    global _LOSS_IN
+    sig = tuple(float(x) for x in np.asarray(synth.SIGMA_GRID, np.float32))
+    _LOSS_IN = (synth.random_shading(n_points, K, seed=31), synth.random_materials(n_points, seed=32),
+                synth.random_observations(n_points, seed=33), sig)
+    w = host_workers()
+    return mp.get_context("fork").Pool(w), w
+
+
+def loss_oracle_leg(pool, workers, dev):
+    """The numpy float64 loss+gradient oracle over the synthetic room-sized
+    point set, single-process and on all host cores, and the accuracy of the
+    GPU kernel and of the plain torch-autograd comparator (float32 and
+    float64) against it on the same inputs."""
+    from oracle import render as orr
+    sh, mat, obs, sig = _LOSS_IN
+    n = mat.shape[1]
     t0 = time.perf_counter()
-    ob.bake(osc, pts, tr, idx=idx, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed, threads=threads)
-    dt = time.perf_counter() - t0
-    k = max(1, int(budget_s / max(dt, 1e-3)))
-    idx = np.sort(rng.choice(n_pts, min(n_pts, k * threads), replace=False))
+    loss_o, grad_o, _ = orr.loss_and_grad(sh, mat, obs, sig)
+    t_single = time.perf_counter() - t0
+    edges = np.linspace(0, n, 4 * workers + 1).astype(np.int64)
     t0 = time.perf_counter()
-    ob.bake(osc, pts, tr, idx=idx, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed, threads=threads)
-    dt = time.perf_counter() - t0
-    return dict(value=len(idx) * S / dt / 1e9, unit="Gsamples/s", cores=threads, kind="oracle",
-                sample=f"{len(idx)} random points of the room x {S} lobe samples, "
-                       f"brute-force float64 over all {sc.n_tris} triangles, {dt:.1f} s")
+    parts = pool.map(_loss_chunk, list(zip(edges[:-1], edges[1:])))
+    t_all = time.perf_counter() - t0
+    loss_p = math.fsum(p[0] for p in parts)
+    grad_p = np.concatenate([p[1] for p in parts], axis=1)
+    assert abs(loss_p - loss_o) <= 1e-12 * abs(loss_o) and np.array_equal(grad_p, grad_o)
+    S, M, O = (torch.from_numpy(x).to(dev) for x in (sh, mat, obs))
+    tau = 1e-6 * np.abs(grad_o).max(axis=1, keepdims=True)
+
+    def err(loss, grad):
+        g = grad.detach().double().cpu().numpy()
+        return dict(loss_rel=abs(float(loss) - loss_o) / abs(loss_o),
+                    grad_max_rel=float((np.abs(g - grad_o) / np.maximum(np.abs(grad_o), tau)).max()))
+
+    buf, g_k, _ = fipt.fipt_render_loss(S, M, O, sig)
+    acc = {"k_render_loss": err(buf[0].item(), g_k)}
+    for dt, name in ((torch.float32, "torch_autograd_fp32"), (torch.float64, "torch_autograd_fp64")):
+        l_t, g_t = torch_factored_loss(S, M, O, sig, dt)
+        acc[name] = err(l_t.item(), g_t)
+    for v in acc.values():
+        v["meets_1e-4"] = v["grad_max_rel"] <= 1e-4 and v["loss_rel"] <= 1e-6
+    del S, M, O
+    return dict(points=n, single_process_s=t_single, all_cores_s=t_all, processes=workers,
+                points_per_s_single=n / t_single, points_per_s_all_cores=n / t_all,
+                accuracy_vs_oracle=acc,
+                inputs="synthetic: shading U-shaped per level, materials uniform (roughness "
+                       "touches every level), observations uniform; 1,843,200 points")
+
+
+def torch_factored_loss(shading, material, observed, sigma, dtype):
+    """The plain method: Eq. 5 with the lerp of Eq. 8 and the L2 loss of
+    Eq. 2 as a torch expression in `dtype`, its gradient with respect to the
+    material by autograd.  Same clamping as the kernel: t is clamped to
+    [0, 1] (zero roughness gradient outside the level table)."""
+    K = len(sigma)
+    N = material.shape[1]
+    g = torch.tensor(sigma, dtype=dtype, device=material.device)
+    m = material.detach().to(dtype).requires_grad_(True)
+    a, s, met = m[0:3], m[3], m[4]
+    j = (torch.searchsorted(g, s.detach().contiguous(), right=True) - 1).clamp_(0, K - 2)
+    t = ((s - g[j]) / (g[j + 1] - g[j])).clamp(0.0, 1.0)
+    sh = shading.to(dtype)
+    Ld = sh[0:3]
+    L0s = sh[3:3 + 3 * K].view(K, 3, N)
+    L1s = sh[3 + 3 * K:3 + 6 * K].view(K, 3, N)
+    i0 = j.view(1, 1, N).expand(1, 3, N)
+    L0 = (1.0 - t) * L0s.gather(0, i0)[0] + t * L0s.gather(0, i0 + 1)[0]
+    L1 = (1.0 - t) * L1s.gather(0, i0)[0] + t * L1s.gather(0, i0 + 1)[0]
+    kd = a * (1.0 - met)
+    ks = 0.04 * (1.0 - met) + a * met
+    Lr = kd * Ld + ks * L0 + L1
+    loss = ((Lr - observed.to(dtype)) ** 2).sum()
+    grad, = torch.autograd.grad(loss, m)
+    return loss, grad
+
+
+def run_comparator(shading, mat, obs, sigma, t_kernel_ms, reps=10):
+    """The hand-written fused kernel against the plain torch-autograd
+    expression of the same loss, on the same inputs and stream: forward +
+    backward time, float32 and float64 (the kernel's own arithmetic)."""
+    N = mat.shape[1]
+    out = {"points": N, "k_render_loss_ms": t_kernel_ms,
+           "k_render_loss_points_per_s": N / (t_kernel_ms * 1e-3)}
+    for dt, name in ((torch.float32, "torch_autograd_fp32"), (torch.float64, "torch_autograd_fp64")):
+        torch_factored_loss(shading, mat, obs, sigma, dt)
+        torch.cuda.synchronize()
+        tm = Timer()
+        for _ in range(reps):
+            tm.mark("a")
+            torch_factored_loss(shading, mat, obs, sigma, dt)
+            tm.mark("b")
+        torch.cuda.synchronize()
+        ms = float(np.mean(tm.spans("a", "b")))
+        out[name] = {"ms": ms, "points_per_s": N / (ms * 1e-3), "kernel_speedup": ms / t_kernel_ms}
+    out["note"] = ("accuracy of each against the float64 oracle on a room-sized synthetic set: "
+                   "cpu_baseline.loss_grad.accuracy_vs_oracle")
+    return out
 
 
 def serving_setup(dev):
@@ -242,17 +403,35 @@ def serve_single(scenes, pts, trace, log_every=20, tag="one-at-a-time"):
                 makespan_s=makespan, gsamples_per_s=trace_samples(trace) / makespan / 1e9)
 
 
-def run_serving(dev, n_requests, rate, log_every=20):
-    """Replay a Poisson trace of bake requests over eight resident rooms,
-    through the server and one request at a time."""
+def run_serving(dev, n_requests, load, n_burst=100, log_every=50):
+    """Serving below capacity: the capacity of the server is measured with
+    ``n_burst`` requests arriving at once, then a Poisson trace of
+    ``n_requests`` requests at ``load`` x that rate (rooms, point counts and
+    sample counts as the serving workload draws them) is replayed through the
+    server and, separately, one request at a time."""
     rooms, scenes, pts = serving_setup(dev)
-    trace = synth.serving_trace(n_requests, rate, [p[0].shape[1] for p in pts])
+    sizes = [p[0].shape[1] for p in pts]
+    burst = synth.serving_trace(n_burst, 1e9, sizes, seed=1105)
+    cap = serve_batched(scenes, pts, burst, log_every, "capacity")
+    cap_rps = n_burst / cap["makespan_s"]
+    rate = load * cap_rps
+    log(f"serving capacity {cap_rps:.1f} requests/s; trace at {rate:.1f} requests/s")
+    trace = synth.serving_trace(n_requests, rate, sizes, seed=1106)
     batched = serve_batched(scenes, pts, trace, log_every)
     single = serve_single(scenes, pts, trace, log_every)
     for s in scenes:
         s.destroy()
-    return dict(requests=len(trace), rate_per_s=rate, rooms=[r.n_tris for r in rooms],
-                lobe_samples=trace_samples(trace), batched=batched, one_at_a_time=single)
+    p99 = batched["p99_ms"] / single["p99_ms"]
+    return dict(requests=len(trace), load=load, rate_per_s=rate, rooms=[r.n_tris for r in rooms],
+                capacity=dict(requests=n_burst, requests_per_s=cap_rps,
+                              gsamples_per_s=cap["gsamples_per_s"]),
+                lobe_samples=trace_samples(trace), batched=batched, one_at_a_time=single,
+                p50_ratio_batched_to_single=batched["p50_ms"] / single["p50_ms"],
+                p99_ratio_batched_to_single=p99,
+                summary=("batched p99 more than 2 % below one-at-a-time" if p99 < 0.98 else
+                         "batched p99 within 2 % of one-at-a-time (continuous batching lowers "
+                         "the median, not the tail, at this load)" if p99 <= 1.02 else
+                         "batched p99 ABOVE one-at-a-time"))
 
 
 def serving_study(dev, n_trace, rate, n_sweep):
@@ -285,8 +464,57 @@ def serving_study(dev, n_trace, rate, n_sweep):
                 sweep=sweep)
 
 
+def bake_roofline(trav, t_bake_ms, traffic):
+    """Roofline of one bake launch: algorithmic flops (counted from the
+    instrumented twin of the kernel) over the launch time, against the
+    published FP32 vector peak; the issue-rate view and the traversal bytes
+    as secondary figures."""
+    tf = trav["flops"] / (t_bake_ms * 1e-3) / 1e12
+    tops = trav["ops"] / (t_bake_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / PEAK_FP32_TFLOPS, "traffic": traffic, "kernel": "k_bake",
+            "flops_per_launch": trav["flops"],
+            "flops_counted": "20 per ray-box test (80 per 4-wide node visited), 30 per "
+                             "ray-triangle test, 100 per lobe sample",
+            "issue_rate": {"achieved_tops": tops, "peak_tops": PEAK_VALU_TOPS,
+                           "frac": tops / PEAK_VALU_TOPS, "ops_per_launch": trav["ops"],
+                           "note": "VALU operations counted per instruction against one "
+                                   "operation per lane per cycle (no packed FP32)"},
+            "effective_traversal_gbs": trav["bytes"] / (t_bake_ms * 1e-3) / 1e9,
+            "traversal_bytes_per_launch": trav["bytes"],
+            "traversal_note": "bytes the node, triangle and radiance loads request, mostly "
+                              "served from L1/L2/MALL: not an HBM roofline"}
+
+
+def hbm_bandwidth(dev, n=1 << 28, reps=5):
+    """Achievable HBM bandwidth from the library's streaming kernel
+    (fipt_hbm_stream) on 1 GiB float arrays: copy (8 bytes per element) and
+    triad (12 bytes per element), best of the two; torch's copy_ beside it."""
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.ones(n, dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    res = {}
+    for kind, name, per in ((0, "copy", 8), (1, "triad", 12)):
+        fipt.fipt_hbm_stream(kind, a, c, b, 0.5)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fipt.fipt_hbm_stream(kind, a, c, b, 0.5)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"{name}_ms"] = ms
+        res[f"{name}_gbs"] = per * n / (ms * 1e-3) / 1e9
+    del a, b, c
+    res["torch_copy_gbs"], _ = copy_bandwidth(dev, n, reps)
+    res["bytes"] = {"copy": 8 * n, "triad": 12 * n}
+    res["achievable_gbs"] = max(res["copy_gbs"], res["triad_gbs"])
+    return res
+
+
 def copy_bandwidth(dev, n=1 << 28, reps=5):
-    """Achievable HBM bandwidth: a 1 GiB float32 device-to-device copy."""
+    """A 1 GiB float32 device-to-device copy by torch (copy_)."""
     x = torch.ones(n, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
     y.copy_(x)
@@ -512,6 +740,7 @@ def run_large(dev, rebakes, copy_gbs):
     scene.destroy()
     gbs = lambda ms: N * LOSS_BYTES_PER_POINT / (ms * 1e-3) / 1e9
     eff = trav["bytes"] / (t_bake * 1e-3) / 1e9
+    roof = bake_roofline(trav, t_bake, None)
     return {
         "workload": f"large room: {sc.n_tris:,} triangles, {len(sc.cameras)} cameras x 250x250 = "
                     f"{N:,} points, {sc.spp} spp per lobe, {K} roughness levels, {rebakes} re-bakes, "
@@ -526,8 +755,11 @@ def run_large(dev, rebakes, copy_gbs):
         "gsamples_per_s": N * S / (t_bake * 1e-3) / 1e9,
         "rays_per_s": trav["rays"] / (t_bake * 1e-3),
         "traversal": trav,
-        "effective_traversal_gbs": eff,
-        "effective_traversal_frac_of_achievable_hbm": eff / copy_gbs,
+        "roofline": roof,
+        "roofline_loss": {"bound": "hbm", "achieved": gbs(t_warm), "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": gbs(t_warm) / PEAK_HBM_GBS, "traffic": None,
+                          "bytes_per_point": LOSS_BYTES_PER_POINT, "kernel": "k_render_loss",
+                          "cold": {"achieved": gbs(t_cold), "frac": gbs(t_cold) / PEAK_HBM_GBS}},
         "loss_grad": {"points": N, "warm_ms": t_warm, "cold_ms": t_cold,
                       "warm_gbs": gbs(t_warm), "cold_gbs": gbs(t_cold),
                       "warm_frac_of_achievable_hbm": gbs(t_warm) / copy_gbs,
@@ -543,9 +775,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--cpu-large-budget-s", type=float, default=12.0,
+                    help="oracle budget on the 2M-triangle room (0 skips it)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=48)
-    ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--serving-load", type=float, default=0.9,
+                    help="offered load of the serving trace as a fraction of measured capacity")
+    ap.add_argument("--serving-rate", type=float, default=200.0,
+                    help="arrival rate of the --serving-study trace")
     ap.add_argument("--no-counters", action="store_true")
     ap.add_argument("--serving-study", action="store_true",
                     help="only run the serving study (capacity, the --serving-trace-requests "
@@ -562,6 +799,11 @@ def main():
         print("this benchmark runs on one GPU only (the hot path has no multi-GPU leg); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    room_points = 24 * 320 * 240
+    pool = workers = None
+    if not args.no_cpu and not (args.copy_calibration or args.serving_study):
+        # forked before anything touches the GPU
+        pool, workers = make_loss_oracle_pool(room_points, len(synth.SIGMA_GRID))
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(0)
@@ -575,13 +817,16 @@ def main():
         print(json.dumps(serving_study(dev, args.serving_trace_requests, args.serving_rate,
                                        args.serving_sweep_requests)), flush=True)
         return
-    copy_gbs, _ = copy_bandwidth(dev)
-    log(f"achievable HBM bandwidth (1 GiB copy): {copy_gbs:.0f} GB/s")
+    hbm = hbm_bandwidth(dev)
+    copy_gbs = hbm["achievable_gbs"]
+    log(f"achievable HBM bandwidth (1 GiB streaming kernel): copy {hbm['copy_gbs']:.0f} GB/s, "
+        f"triad {hbm['triad_gbs']:.0f} GB/s; torch copy_ {hbm['torch_copy_gbs']:.0f} GB/s")
 
     t_setup = time.perf_counter()
     sc = synth.room()
     scene = setup_room(sc, dev)
     N = sc.n_points
+    assert N == room_points
     K = len(sc.sigma)
     P = 3 + 6 * K
     S = sc.spp * (1 + K)
@@ -650,10 +895,19 @@ def main():
     if not args.no_counters:
         trav = traversal_bytes(scene, planes, tri, sc, shading)
         log(f"traversal: {trav}")
-    bake_bytes = trav["bytes"] if trav else None
-    bake_tops = trav["ops"] / (t_bake * 1e-3) / 1e12 if trav else None
     loss_gbs = N * LOSS_BYTES_PER_POINT / (t_loss * 1e-3) / 1e9
     traffic = measured_traffic()
+    # the material grid's gather and adjoint: each point reads its position
+    # (12 B) and writes (gather) or reads (adjoint) five values (20 B); the
+    # 5 x 128^3 grid is read once (gather) or written once (adjoint)
+    grid_bytes = N * 32 + 5 * R ** 3 * 4
+    roof_grid = {
+        kname: {"bound": "hbm", "achieved": grid_bytes / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": grid_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "ms": ms, "bytes_per_launch": grid_bytes, "kernel": kn}
+        for kname, ms, kn in (("gather", t_gather, "k_grid_gather"),
+                              ("adjoint", t_scatter, "k_scatter_records + k_scatter_segments + "
+                                                     "k_scatter_grid"))}
 
     flush = torch.ones((1 << 27,), dtype=torch.float32, device=dev)      # 512 MB
     t_loss_cold = loss_timing(shading, mat, obs, sc.sigma, flush=flush)
@@ -674,6 +928,8 @@ def main():
                         "points_per_s": N / (warm * 1e-3)}
     log(f"masked loss: {masked}")
     del flush, alpha
+    comparator = run_comparator(shading, mat, obs, sc.sigma, t_loss)
+    log(f"torch-autograd comparator: {comparator}")
     voxel = run_voxel(scene, sc, planes, tri, obs, shading)
     log(f"voxel cache: {voxel}")
     hashgrid = run_hashgrid(sc, planes, shading, obs)
@@ -682,18 +938,23 @@ def main():
     large = None
     if args.large_rebakes > 0:
         large = run_large(dev, args.large_rebakes, copy_gbs)
-        log(f"large room: {large['gsamples_per_s']:.2f} Gsamples/s, "
-            f"{large['effective_traversal_gbs']:.0f} GB/s effective traversal")
+        log(f"large room: {large['gsamples_per_s']:.2f} Gsamples/s, roofline "
+            f"{large['roofline']['frac']:.3f} of the FP32 peak")
 
     cpu = None
-    if not args.no_cpu:
-        log("cpu baseline: timing the oracle on a bounded sample ...")
-        cpu = cpu_baseline(sc, planes, tri, args.cpu_budget_s)
+    if pool is not None:
+        log("cpu baseline: timing the oracle on bounded samples ...")
+        loss_leg = loss_oracle_leg(pool, workers, dev)
+        pool.close()
+        pool.join()
+        cpu = cpu_baseline(sc, args.cpu_budget_s,
+                           synth.large_room() if args.cpu_large_budget_s > 0 else None,
+                           args.cpu_large_budget_s, loss_leg)
         log(f"cpu baseline: {cpu}")
 
     serving = None
     if args.serving_requests > 0:
-        serving = run_serving(dev, args.serving_requests, args.serving_rate)
+        serving = run_serving(dev, args.serving_requests, args.serving_load)
 
     out = {
         "metric": "Gsamples/s shading bake; factored loss+grad points/s; p50/p99 bake latency",
@@ -721,21 +982,22 @@ def main():
         "render_loss_cold_ms": t_loss_cold,
         "render_loss_cold_gbs": N * LOSS_BYTES_PER_POINT / (t_loss_cold * 1e-3) / 1e9,
         "achievable_hbm_gbs": copy_gbs,
+        "hbm_probe": hbm,
         "loss": loss_value,
         "traversal": trav,
-        "roofline": {"bound": "alu", "achieved": bake_tops, "peak": PEAK_VALU_TOPS,
-                     "unit": "Tops/s", "frac": bake_tops / PEAK_VALU_TOPS if trav else None,
-                     "traffic": traffic.get("k_bake"), "kernel": "k_bake",
-                     "ops_per_launch": trav["ops"] if trav else None,
-                     "effective_traversal_gbs": bake_bytes / (t_bake * 1e-3) / 1e9 if trav else None,
-                     "traversal_bytes_per_launch": bake_bytes},
-        "masked_loss": masked,
-        "voxel_cache": voxel,
-        "hashgrid_network": hashgrid,
+        "roofline": bake_roofline(trav, t_bake, traffic.get("k_bake")) if trav else None,
         "roofline_render_loss": {"bound": "hbm", "achieved": loss_gbs, "peak": PEAK_HBM_GBS,
                                  "unit": "GB/s", "frac": loss_gbs / PEAK_HBM_GBS,
                                  "traffic": traffic.get("k_render_loss"),
-                                 "bytes_per_point": LOSS_BYTES_PER_POINT, "kernel": "k_render_loss"},
+                                 "bytes_per_point": LOSS_BYTES_PER_POINT, "kernel": "k_render_loss",
+                                 "frac_of_achievable": loss_gbs / copy_gbs,
+                                 "cold": {"achieved": N * LOSS_BYTES_PER_POINT / (t_loss_cold * 1e-3) / 1e9,
+                                          "frac": N * LOSS_BYTES_PER_POINT / (t_loss_cold * 1e-3) / 1e9 / PEAK_HBM_GBS}},
+        "roofline_grid": roof_grid,
+        "torch_autograd_comparator": comparator,
+        "masked_loss": masked,
+        "voxel_cache": voxel,
+        "hashgrid_network": hashgrid,
         "cpu_baseline": cpu,
         "serving": serving,
         "large_room": large,

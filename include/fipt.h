@@ -357,6 +357,17 @@ int fipt_render_loss_masked(const fipt_shading* sh, int64_t n, int32_t n_levels,
  * round trip.  x and out may alias. */
 int fipt_scale_by(const float* x, int64_t n, const double* factor_dev, float* out, void* stream);
 
+/* ---- measurement ------------------------------------------------------- */
+
+/* Streaming bandwidth probe: kind 0 copies c[i] = a[i], kind 1 computes the
+ * triad c[i] = a[i] + s b[i], for i < n (device float arrays, 16-byte
+ * aligned; b unused for a copy).  Bytes moved: 8n (copy) or 12n (triad).
+ * Timed on large arrays (>= 1 GiB) it gives the HBM bandwidth a kernel can
+ * reach, the reference for the memory-bound kernels besides the published
+ * peak.  Asynchronous on `stream`. */
+int fipt_hbm_stream(int32_t kind, const float* a, const float* b, float* c, int64_t n, float s,
+                    void* stream);
+
 /* ---- trilinear material grid (stand-in for the paper's MLP_brdf, Eq. 14) */
 
 /* Values at n points pos[3][pos_stride] of a grid[channels][res][res][res]

@@ -568,6 +568,18 @@ int fipt_scale_by(const float* x, int64_t n, const double* factor_dev, float* ou
     return launch_scale_by(x, n, factor_dev, out, stream);
 }
 
+int fipt_hbm_stream(int32_t kind, const float* a, const float* b, float* c, int64_t n, float s,
+                    void* stream) {
+    clear_error();
+    if (kind != 0 && kind != 1) return fail(FIPT_EINVAL, "kind must be 0 (copy) or 1 (triad)");
+    if (!a || !c || (kind == 1 && !b)) return fail(FIPT_EINVAL, "NULL argument");
+    if (n < 1) return fail(FIPT_EINVAL, "n must be >= 1");
+    const uintptr_t mis = (reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(c) |
+                           (kind == 1 ? reinterpret_cast<uintptr_t>(b) : 0)) & 15u;
+    if (mis) return fail(FIPT_EINVAL, "arrays must be 16-byte aligned");
+    return launch_stream(kind, a, b, c, n, s, stream);
+}
+
 int fipt_grid_gather(const float* grid, int32_t channels, int32_t res, const float* bmin_host,
                      const float* bmax_host, const float* pos, int64_t pos_stride, int64_t n,
                      float* out, int64_t out_stride, void* stream) {

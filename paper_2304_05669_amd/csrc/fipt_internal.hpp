@@ -220,6 +220,9 @@ int render_loss_partials(int64_t n);
 // device, and its capacity in doubles.
 int render_loss_scratch(double** out, int64_t* capacity);
 int launch_scale_by(const float* x, int64_t n, const double* f, float* out, void* stream);
+// Bandwidth probe: kind 0 copy c = a, kind 1 triad c = a + s b.
+int launch_stream(int32_t kind, const float* a, const float* b, float* c, int64_t n, float s,
+                  void* stream);
 int launch_grid_gather(const float* grid, int32_t C, int32_t R, const float* bmin,
                        const float* bmax, const float* pos, int64_t pos_stride, int64_t n,
                        float* out, int64_t out_stride, void* stream);

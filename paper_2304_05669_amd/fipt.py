@@ -30,7 +30,7 @@ EXPORTS = (
     "fipt_scene_set_emission", "fipt_scene_info_get", "fipt_bvh_validate", "fipt_scene_destroy",
     "fipt_cast_rays", "fipt_gen_points",
     "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_render_loss",
-    "fipt_render_loss_noalloc", "fipt_render_loss_masked", "fipt_scale_by",
+    "fipt_render_loss_noalloc", "fipt_render_loss_masked", "fipt_scale_by", "fipt_hbm_stream",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
     "fipt_scene_set_voxel_radiance", "fipt_voxel_plan_create", "fipt_voxel_plan_destroy",
@@ -124,6 +124,7 @@ def lib():
                                               _i64, _vp, _i32, C.c_double, _vp, _vp, _i64, _vp, _vp,
                                               _i64, _vp]),
         "fipt_scale_by": (C.c_int, [_vp, _i64, _vp, _vp, _vp]),
+        "fipt_hbm_stream": (C.c_int, [_i32, _vp, _vp, _vp, _i64, C.c_float, _vp]),
         "fipt_grid_gather": (C.c_int, [_vp, _i32, _i32, _f32p, _f32p, _vp, _i64, _i64, _vp, _i64, _vp]),
         "fipt_grid_plan_create": (C.c_int, [_vp, _i64, _i32, _f32p, _f32p, _i32, C.POINTER(_vp)]),
         "fipt_grid_plan_destroy": (C.c_int, [_vp]),
@@ -496,6 +497,20 @@ def fipt_scale_by(x: torch.Tensor, factor: torch.Tensor, out: torch.Tensor = Non
                                _dev(factor, torch.float64, "factor"),
                                _dev(out, torch.float32, "out"), _stream()))
     return out
+
+
+def fipt_hbm_stream(kind: int, a: torch.Tensor, c: torch.Tensor, b: torch.Tensor = None,
+                    s: float = 1.0):
+    """Bandwidth probe: kind 0 copies a into c, kind 1 writes a + s b into c
+    (float32 GPU tensors of equal size)."""
+    n = a.numel()
+    _need(c, a.shape, "c")
+    if kind == 1:
+        _need(b, a.shape, "b")
+    _check(lib().fipt_hbm_stream(int(kind), _dev(a, torch.float32, "a"),
+                                 _dev(b, torch.float32, "b") if kind == 1 else None,
+                                 _dev(c, torch.float32, "c"), n, float(s), _stream()))
+    return c
 
 
 class FactoredLoss(torch.autograd.Function):

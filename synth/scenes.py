@@ -373,12 +373,15 @@ SERVING_TRIANGLES = (20000, 38600, 74600, 144000, 278000, 537000, 1040000, 20000
 
 
 def serving_rooms(seed: int = 1004, n_cams: int = 28, width: int = 320,
-                  height: int = 240, counts=SERVING_TRIANGLES) -> list:
+                  height: int = 240, counts=SERVING_TRIANGLES, which=None) -> list:
     """Eight rooms with log-spaced triangle counts; each has enough camera
     points (28 x 320 x 240 = 2,150,400) to serve requests of up to 2M
-    points as contiguous subsets."""
+    points as contiguous subsets.  `which` (indices into `counts`) builds
+    only those rooms, each identical to its place in the full list."""
     out = []
     for r, target in enumerate(counts):
+        if which is not None and r not in which:
+            continue
         cell, level, sub = _room_params(target)
         out.append(_room_scene(f"room{r}_{target}", seed * 100 + r, cell, level,
                                sub, n_cams, width, height, 64, 3, 1, 2004))

@@ -49,3 +49,44 @@ def assert_close_rel(gpu, oracle, tol: float, floor: float = 1e-6, what: str = "
     worst = float(rel.max()) if rel.size else 0.0
     assert worst <= tol, f"{what}: worst relative error {worst:.3e} > {tol:g} at {np.unravel_index(rel.argmax(), rel.shape)}"
     return worst
+
+
+def stratified_points(n_points: int, n_sample: int, seed: int) -> np.ndarray:
+    """One random point index from each of n_sample equal blocks of
+    [0, n_points), sorted (every camera of a multi-camera point set is
+    sampled)."""
+    rng = np.random.default_rng(seed)
+    edges = np.linspace(0, n_points, n_sample + 1).astype(np.int64)
+    return (edges[:-1] + (rng.random(n_sample) * (edges[1:] - edges[:-1])).astype(np.int64))
+
+
+def oracle_bake_chunked(bake, osc, pts, tri, idx, chunk: int = 64, label: str = "", **kw):
+    """The oracle's bake of points ``idx`` in chunks (one call per chunk,
+    results concatenated in order, identical to a single call), printing a
+    progress line after each chunk."""
+    import sys
+    import time
+    parts = []
+    t0 = time.perf_counter()
+    for a in range(0, len(idx), chunk):
+        parts.append(bake(osc, pts, tri, idx=idx[a:a + chunk], **kw))
+        print(f"oracle {label}: {min(a + chunk, len(idx))}/{len(idx)} points "
+              f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    out = {k: np.concatenate([p[k] for p in parts], axis=1) for k in ("mean", "lo", "hi", "sq")}
+    out["n_ambiguous"] = sum(p["n_ambiguous"] for p in parts)
+    return out
+
+
+def max_outside(n: int, rate: float = 1e-3, alpha: float = 0.01) -> int:
+    """The most points outside 1e-4 that a sample of n points may show when
+    the true fraction outside is `rate` (the criterion's 0.1 %): the
+    smallest k with P(Binomial(n, rate) > k) < alpha.  On samples too small
+    to resolve a 0.1 % fraction (n of a few hundred) a single legitimate
+    tie would otherwise fail a process that meets the criterion."""
+    from math import comb
+    cdf = 0.0
+    for k in range(n + 1):
+        cdf += comb(n, k) * rate ** k * (1.0 - rate) ** (n - k)
+        if 1.0 - cdf < alpha:
+            return k
+    return n

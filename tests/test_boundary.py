@@ -60,6 +60,11 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_server_create(0, 1024, 4, 1 << 20, C.byref(out)) == fipt.EINVAL
     assert L.fipt_grid_gather(None, 5, 128, None, None, None, 1, 1, None, 1, None) == fipt.EINVAL
     assert L.fipt_scale_by(None, 1, None, None, None) == fipt.EINVAL
+    assert L.fipt_hbm_stream(2, 16, 16, 16, 4, 1.0, None) == fipt.EINVAL
+    assert L.fipt_hbm_stream(1, 16, None, 16, 4, 1.0, None) == fipt.EINVAL
+    assert L.fipt_hbm_stream(0, 16, None, 16, 0, 1.0, None) == fipt.EINVAL
+    assert L.fipt_hbm_stream(0, 20, None, 16, 4, 1.0, None) == fipt.EINVAL
+    assert b"aligned" in L.fipt_last_error()
     assert L.fipt_scene_info_get(None, None) == fipt.EINVAL
     assert L.fipt_server_poll(None, 1) == fipt.EINVAL
     assert L.fipt_cast_rays(None, None, 1, 1, None, None, 1, None) == fipt.EINVAL

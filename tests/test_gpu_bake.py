@@ -12,7 +12,8 @@ import torch
 import synth
 from oracle import bake as ob
 from paper_2304_05669_amd import fipt
-from tests.parity import assert_bake_parity, bake_report
+from tests.parity import (assert_bake_parity, bake_report, max_outside, oracle_bake_chunked,
+                          stratified_points)
 
 pytestmark = pytest.mark.gpu
 
@@ -162,7 +163,7 @@ def test_traversal_counters(tiny, tiny_gpu, tiny_points):
     assert 0 < nodes <= 64 * node_steps and 0 < tris <= 64 * tri_steps
 
 
-def _sampled_room_parity(sc, n_sample, seed):
+def _sampled_room_parity(sc, n_sample, seed, chunk=64):
     """Full-size bake with the benchmark's launch; oracle on sampled points.
     The sampled points' oracle shading points are written into the GPU
     point buffer so both sides bake identical inputs; the GPU's own shading
@@ -170,8 +171,7 @@ def _sampled_room_parity(sc, n_sample, seed):
     scene = _scene(sc)
     planes, tri_g = fipt.fipt_gen_points(scene, sc.cameras)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(sc.n_points, n_sample, replace=False)).astype(np.int64)
+    idx = stratified_points(sc.n_points, n_sample, seed)
     osc = ob.OracleScene(sc)
     prim = ob.primary(osc, idx=idx)
     # shading points: GPU vs oracle at the sampled pixels
@@ -191,22 +191,35 @@ def _sampled_room_parity(sc, n_sample, seed):
     full_t = np.full(sc.n_points, -1, np.int32)
     full_p[:, idx] = p32
     full_t[idx] = t32
-    want = ob.bake(osc, full_p, full_t, idx=idx, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed)
+    want = oracle_bake_chunked(ob.bake, osc, full_p, full_t, idx, chunk=chunk, label=sc.name,
+                               spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed)
     scene.destroy()
     return got, want
 
 
 def test_room_full_size_sampled_parity():
+    """1024 of the room's 1,843,200 points (one per block of 1800, so every
+    camera is covered): >= 99.9 % within 1e-4, the rest within 1e-2 or the
+    tie envelope."""
     sc = synth.room()
-    got, want = _sampled_room_parity(sc, 32, seed=41)
+    got, want = _sampled_room_parity(sc, 1024, seed=41)
     r = bake_report(got, want)
     print("room parity:", r)
-    assert_bake_parity(got, want, min_frac=31 / 32)
+    assert_bake_parity(got, want)
 
 
 def test_large_room_full_size_sampled_parity():
+    """128 of the 2M-triangle room's 1,000,000 points at 1792 lobe samples
+    each (the oracle tests every ray against all 1,980,160 triangles, about
+    a second of the host's cores per point).  128 points cannot resolve a
+    0.1 % fraction: a process exactly at the criterion shows a point outside
+    1e-4 in 12 % of such samples.  The sample may hold as many points
+    outside 1e-4 as a 0.1 % rate exceeds with probability below 1 % (one),
+    each within 1e-2 or inside the oracle's tie envelope."""
     sc = synth.large_room()
-    got, want = _sampled_room_parity(sc, 8, seed=43)
+    got, want = _sampled_room_parity(sc, 128, seed=43, chunk=16)
     r = bake_report(got, want)
     print("large room parity:", r)
-    assert_bake_parity(got, want, min_frac=7 / 8)
+    k = max_outside(128)
+    assert k == 1
+    assert_bake_parity(got, want, min_frac=1.0 - k / 128)

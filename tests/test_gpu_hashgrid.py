@@ -101,8 +101,10 @@ def test_backward_parity_and_weight_determinism():
     _close(a[hg.N_TABLE + hg.N_W1:hg.N_TABLE + hg.N_W1 + hg.N_W2],
            want[hg.N_TABLE + hg.N_W1:hg.N_TABLE + hg.N_W1 + hg.N_W2], 1e-3, "W2 grad")
     _close(a[-hg.N_W3:], want[-hg.N_W3:], 1e-3, "W3 grad")
-    # table gradients: per level
-    for l in (0, 1, 2, 3, 10, 31):
+    # table gradients: every level (dense levels 0-2, the coarse levels whose
+    # wavefront-combined updates reach 5, the fine levels where zero-weight
+    # vertices are skipped)
+    for l in range(hg.LEVELS):
         sl = slice(l * hg.T * hg.FEATURES, (l + 1) * hg.T * hg.FEATURES)
         _close(a[sl], want[sl], 1e-3, f"table grad level {l}")
     # untouched entries stay exactly zero

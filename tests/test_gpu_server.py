@@ -152,3 +152,73 @@ def test_scene_pinned_while_requests_reference_it():
     finally:
         srv.destroy()
     s.destroy()
+
+
+def test_served_results_match_oracle():
+    """Served results against the oracle, not only against fipt_bake: four
+    requests on two of the serving rooms (18,860 and 525,440 triangles),
+    submitted together so their tiles share launches, one of them split
+    over several launches (tiles with a non-zero point offset into the
+    request), one on more than ten roughness levels (the chunked path).
+    Each request's RNG counter is its own point index, so the oracle bakes
+    the request's points at their request-local indices.  The sampled
+    points' shading points come from the oracle and are written into the
+    GPU point buffer first, so both sides bake identical inputs."""
+    from oracle import bake as ob
+    from tests.parity import assert_bake_parity, bake_report, max_outside, stratified_points
+
+    rooms = synth.serving_rooms(which=(0, 5))
+    assert len(rooms[0].tris) < 20000 and 500000 < len(rooms[1].tris) < 550000
+    built = []
+    for sc in rooms:
+        s = _scene(sc)
+        planes, tri = fipt.fipt_gen_points(s, sc.cameras)
+        built.append((sc, s, planes, tri, ob.OracleScene(sc)))
+    torch.cuda.synchronize()
+    reqs = [
+        # room, offset, count, spp_d, spp_s, sigma, seed
+        (0, 1000, 30000, 32, 32, synth.SIGMA_GRID, 21),            # several launches
+        (1, 500000, 20000, 24, 16, synth.SIGMA_GRID, 22),
+        (0, 200000, 3000, 20, 9, tuple(np.linspace(0.05, 1.0, 12)), 23),   # K > 10
+        (1, 7, 5000, 48, 48, (0.1, 0.5, 0.9), 24),
+    ]
+    # oracle shading points at the sampled pixels of every request
+    picks = []
+    for k, (ri, off, cnt, sd, ss, sig, seed) in enumerate(reqs):
+        sc, s, planes, tri, osc = built[ri]
+        local = stratified_points(cnt, 64, 100 + k)
+        local[0], local[-1] = 0, cnt - 1
+        prim = ob.primary(osc, idx=off + local)
+        p32, t32 = ob.points_f32(prim)
+        ii = torch.from_numpy(off + local).to(DEV)
+        planes[:, ii] = torch.from_numpy(p32).to(DEV)
+        tri[ii] = torch.from_numpy(t32).to(DEV)
+        picks.append((local, p32, t32))
+    torch.cuda.synchronize()
+    srv = fipt.Server(device=0, pool_bytes=512 << 20, max_inflight=8, samples_per_launch=1 << 21)
+    try:
+        tickets = [srv.submit(built[ri][1], built[ri][2], built[ri][3], sd, ss, sig, seed,
+                              offset=off, count=cnt)
+                   for (ri, off, cnt, sd, ss, sig, seed) in reqs]
+        for t in tickets:
+            assert srv.wait(t, timeout_s=120.0)
+        st = srv.stats()
+        # 30000 x 224 samples alone need four launches of 2^21
+        assert st.launches >= 4 and st.tiles > len(reqs), (st.launches, st.tiles)
+        for t, (ri, off, cnt, sd, ss, sig, seed), (local, p32, t32) in zip(tickets, reqs, picks):
+            sc, s, planes, tri, osc = built[ri]
+            got = srv.result(t).shading[:, torch.from_numpy(local).to(DEV)].cpu().numpy()
+            srv.release(t)
+            full_p = np.zeros((9, cnt), np.float32)
+            full_t = np.full(cnt, -1, np.int32)
+            full_p[:, local] = p32
+            full_t[local] = t32
+            want = ob.bake(osc, full_p, full_t, idx=local, spp_d=sd, spp_s=ss, sigma=sig, seed=seed)
+            print(f"served request {t} (room {ri}, {cnt} points):", bake_report(got, want))
+            # 64 points cannot resolve a 0.1 % fraction: allow the one
+            # legitimate tie such a sample may show (see max_outside)
+            assert_bake_parity(got, want, min_frac=1.0 - max_outside(64) / 64)
+    finally:
+        srv.destroy()
+        for _, s, _, _, _ in built:
+            s.destroy()

@@ -16,7 +16,7 @@ import synth
 from oracle import bake as ob
 from oracle import cache as oc
 from paper_2304_05669_amd import fipt
-from tests.parity import assert_bake_parity, bake_report
+from tests.parity import assert_bake_parity, bake_report, oracle_bake_chunked, stratified_points
 
 pytestmark = pytest.mark.gpu
 
@@ -114,8 +114,7 @@ def test_voxel_bake_parity_room_sampled():
     s = _voxel_scene(sc, cache, R, sc.bmin, sc.bmax)
     planes, tri_g = fipt.fipt_gen_points(s, sc.cameras)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(47)
-    idx = np.sort(rng.choice(sc.n_points, 32, replace=False)).astype(np.int64)
+    idx = stratified_points(sc.n_points, 1024, 47)
     osc = ob.OracleScene(sc)
     osc.set_voxel_cache(cache, R, sc.bmin, sc.bmax)
     prim = ob.primary(osc, idx=idx)
@@ -130,9 +129,10 @@ def test_voxel_bake_parity_room_sampled():
     full_t = np.full(sc.n_points, -1, np.int32)
     full_p[:, idx] = p32
     full_t[idx] = t32
-    want = ob.bake(osc, full_p, full_t, idx=idx, spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed)
+    want = oracle_bake_chunked(ob.bake, osc, full_p, full_t, idx, label="voxel room",
+                               spp_d=sc.spp, spp_s=sc.spp, seed=sc.seed)
     print("room voxel parity:", bake_report(got, want))
-    assert_bake_parity(got, want, min_frac=31 / 32)
+    assert_bake_parity(got, want)
     s.destroy()
 
 
