@@ -80,6 +80,19 @@ def lib():
     L.orc_quadrature.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, C.c_int,
                                  C.c_double, C.c_int, C.c_int, C.c_double, _f64p]
     L.orc_max_threads.restype = C.c_int
+    L.orc_refine.restype = C.c_int
+    L.orc_refine.argtypes = [C.c_void_p, _f32p, _i32p, C.c_int64, _i64p, C.c_int64,
+                             C.c_int, C.c_int, C.c_int, _f64p, C.c_uint64, C.c_double,
+                             _f32p, C.c_int, _f64p, _f64p, C.c_double, C.c_int, C.c_int,
+                             C.c_int, _f64p, _f64p, _f64p, _f64p, C.POINTER(C.c_int64)]
+    L.orc_refine_quadrature.restype = C.c_int
+    L.orc_refine_quadrature.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, C.c_int, C.c_double,
+                                        _f32p, C.c_int, _f64p, _f64p, C.c_double, C.c_int,
+                                        C.c_int, C.c_int, C.c_int, C.c_double, _f64p]
+    L.orc_brdf.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_double, C.c_double, _f64p]
+    L.orc_material_at.argtypes = [_f32p, C.c_int, _f64p, _f64p, _f64p, C.c_int64, _f64p]
+    L.orc_brdf_pdf.restype = C.c_double
+    L.orc_brdf_pdf.argtypes = [_f64p, _f64p, _f64p, C.c_double]
     _lib = L
     return L
 
@@ -293,3 +306,91 @@ def quadrature(osc: OracleScene, x, n, wo, lobe: int, sigma: float = 0.0,
                          np.ascontiguousarray(wo, np.float64), int(lobe),
                          float(sigma), int(n_theta), int(n_phi), float(eps), out), "quadrature")
     return out[:3] if lobe < 0 else out
+
+
+# -------------------------------------------------------------------------
+# stage-3 path-traced refinement (Sec. 4.3, Eq. 10 and 11)
+# -------------------------------------------------------------------------
+REFINE_BSDF_ONLY = 1
+
+
+def _grid_args(grid, lo, hi):
+    g = np.ascontiguousarray(grid, dtype=np.float32)
+    res = g.shape[-1]
+    if g.shape != (5, res, res, res):
+        raise ValueError("material grid must be [5, R, R, R]")
+    return (g.reshape(-1), int(res), np.ascontiguousarray(lo, dtype=np.float64),
+            np.ascontiguousarray(hi, dtype=np.float64))
+
+
+def refine(osc: OracleScene, pts: np.ndarray, tri: np.ndarray, grid, grid_lo, grid_hi, idx=None,
+           spp_d: int = 64, spp_s: int = 64, sigma=None, seed: int = 0, eps: float = 1e-4,
+           sigma_diffuse: float = 0.6, max_vertices: int = 8, flags: int = 0, threads: int = 0):
+    """Refined shading terms (Eq. 10 / 11) of the listed points, laid out
+    as ``bake``'s result; ``grid`` [5, R, R, R] is the current material
+    (a_r, a_g, a_b, sigma, m) over the box [grid_lo, grid_hi]."""
+    if sigma is None:
+        sigma = osc.scene.sigma
+    sigma = np.ascontiguousarray(np.asarray(sigma, dtype=np.float32), dtype=np.float64)
+    K = len(sigma)
+    pts = np.ascontiguousarray(pts, dtype=np.float32)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    stride = pts.shape[1]
+    if idx is None:
+        idx = np.arange(stride, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = len(idx)
+    P = 3 + 6 * K
+    mean, lo, hi, sq = (np.zeros((P, n)) for _ in range(4))
+    namb = C.c_int64(0)
+    g, res, glo, ghi = _grid_args(grid, grid_lo, grid_hi)
+    rc = lib().orc_refine(osc.handle, pts, tri, stride, idx, n, int(spp_d), int(spp_s), K, sigma,
+                          C.c_uint64(int(seed)), float(eps), g, res, glo, ghi, float(sigma_diffuse),
+                          int(max_vertices), int(flags), int(threads), mean, lo, hi, sq,
+                          C.byref(namb))
+    if rc == -1:
+        raise ValueError("refine: voxel cache, grid resolution below 2 or max_vertices outside [1, 16]")
+    _checked(rc, "refine")
+    return dict(mean=mean, lo=lo, hi=hi, sq=sq, n_ambiguous=int(namb.value))
+
+
+def refine_quadrature(osc: OracleScene, x, n, wo, lobe: int, grid, grid_lo, grid_hi,
+                      sigma: float = 0.0, sigma_diffuse: float = 0.6, n_theta: int = 128,
+                      n_phi: int = 256, n_theta2: int = 64, n_phi2: int = 128, eps: float = 1e-4):
+    """Deterministic nested quadrature of one refined shading integral for a
+    scene whose paths all end by their second vertex.  Returns (values
+    (3 for Ld, 6 for Ls0 and Ls1 at roughness sigma), weight of directions
+    that went deeper)."""
+    out = np.zeros(7)
+    g, res, glo, ghi = _grid_args(grid, grid_lo, grid_hi)
+    _checked(lib().orc_refine_quadrature(osc.handle, np.ascontiguousarray(x, np.float64),
+                                         np.ascontiguousarray(n, np.float64),
+                                         np.ascontiguousarray(wo, np.float64), int(lobe),
+                                         float(sigma), g, res, glo, ghi, float(sigma_diffuse),
+                                         int(n_theta), int(n_phi), int(n_theta2), int(n_phi2),
+                                         float(eps), out), "refine_quadrature")
+    return (out[:3] if lobe < 0 else out[:6]), out[6]
+
+
+def brdf(n, wo, wi, a, sigma, m):
+    """f of Eq. 1 with the cosine (RGB), as the refinement evaluates it."""
+    out = np.zeros(3)
+    lib().orc_brdf(*(np.ascontiguousarray(v, np.float64) for v in (n, wo, wi, a)), float(sigma),
+                   float(m), out)
+    return out
+
+
+def brdf_pdf(n, wo, wi, sigma):
+    """Density (per solid angle) of the refinement's BRDF sampling."""
+    return lib().orc_brdf_pdf(*(np.ascontiguousarray(v, np.float64) for v in (n, wo, wi)),
+                              float(sigma))
+
+
+def material_at(grid, grid_lo, grid_hi, x):
+    """The refinement's material lookup (trilinear, clamped) at points
+    x [n, 3]; returns [n, 5]."""
+    g, res, glo, ghi = _grid_args(grid, grid_lo, grid_hi)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((len(x), 5))
+    lib().orc_material_at(g, res, glo, ghi, x, len(x), out)
+    return out

@@ -905,3 +905,652 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------------- */
+/* stage-3 path-traced shading refinement (Sec. 4.3, Eq. 10 and 11)       */
+/* ---------------------------------------------------------------------- */
+/*
+ * The shading integrals are re-estimated by growing each stage-1 path
+ * (Eq. 9 is its one-vertex case) through glossy surfaces: the first
+ * direction and its weight come from the lobe g of the shading exactly as
+ * in the bake; at each hit x_i
+ *   - an emitter (a triangle with some channel of Le > 0) returns Le and
+ *     ends the path (an emitter reflects nothing);
+ *   - otherwise the current material (a, sigma, m) at x_i is read from a
+ *     trilinear grid; sigma > sigma_diffuse (0.6), or the last allowed
+ *     vertex, returns the radiance cache L'(x_i) and ends the path;
+ *   - otherwise the path continues with the full BRDF f of Eq. 1 at x_i
+ *     (cosine included): the radiance arriving at x_i is estimated by
+ *     multiple importance sampling of two strategies, a point drawn on an
+ *     emitter (uniform over emitter triangles, uniform on the triangle) and
+ *     a direction drawn from f (GGX half vectors or cosine-weighted, one
+ *     half each), combined by the balance heuristic; the BRDF direction is
+ *     also the one the path continues along.
+ * A flag turns emitter sampling off (BRDF sampling only, weight one).
+ *
+ * Random numbers: the first direction uses the stage-1 uniforms of
+ * (p, lobe, s); vertex i >= 1 draws two Philox blocks with counter
+ * (p lo, p hi, lobe | i << 8 | k << 16, s), k = 0 for the emitter choice
+ * (word 0, as floor(u0 n_emit / 2^32)), the point on it (words 1, 2) and
+ * the lobe choice (word 3), k = 1 for the direction (words 0, 1); a
+ * uniform is (u >> 8) 2^-24.
+ *
+ * Envelope: every ray cast and every sigma threshold decision along a path
+ * is an event; a cast with more than one possible outcome in single
+ * precision, or a sigma within 1e-4 of the threshold, is ambiguous.  The
+ * path is re-evaluated with each alternative outcome of each ambiguous
+ * event (one at a time, the rest nominal), and [lo, hi] spans them.
+ */
+#define ORC_REFINE_BSDF_ONLY 1
+#define ORC_MAX_EVENTS 64
+#define ORC_EINVAL (-1)
+
+typedef struct {
+    const float* grid;      /* [5][R^3] a_r a_g a_b sigma m, x fastest */
+    int res;
+    double lo[3], hi[3];
+    double sigma_diffuse;
+    int max_vertices;
+    int flags;
+    int n_emit;             /* emitter triangles, ascending index */
+    int32_t* emit;
+} refine_t;
+
+typedef struct {
+    int flip_event;         /* event whose outcome is replaced, -1: none */
+    int flip_choice;        /* candidate index (a cast); a decision is inverted */
+    int n_events;
+    int alts[ORC_MAX_EVENTS];   /* alternatives of each event of the run */
+    int overflow;
+} pathrun_t;
+
+static double unif24(uint32_t u) { return (double)(u >> 8) / 16777216.0; }
+
+static void vertex_philox(uint64_t seed, int64_t p, int lobe, int s, int vertex, int k,
+                          uint32_t u[4])
+{
+    uint32_t c[4] = {(uint32_t)(uint64_t)p, (uint32_t)((uint64_t)p >> 32),
+                     (uint32_t)lobe | ((uint32_t)vertex << 8) | ((uint32_t)k << 16), (uint32_t)s};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    philox(c, key, u);
+}
+
+/* Material at x: trilinear interpolation of the grid, nodes at
+ * lo + i (hi - lo) / (R - 1), coordinates clamped onto the box. */
+static void material_at(const refine_t* M, const double x[3], double mat[5])
+{
+    int i0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double u = (x[a] - M->lo[a]) / (M->hi[a] - M->lo[a]) * (M->res - 1);
+        u = fmin(fmax(u, 0.0), (double)(M->res - 1));
+        int i = (int)floor(u);
+        if (i > M->res - 2) i = M->res - 2;
+        i0[a] = i;
+        f[a] = u - i;
+    }
+    int64_t R = M->res, plane = R * R * R;
+    for (int c = 0; c < 5; ++c) {
+        double v = 0.0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    double w = (dx ? f[0] : 1 - f[0]) * (dy ? f[1] : 1 - f[1]) * (dz ? f[2] : 1 - f[2]);
+                    int64_t node = (i0[0] + dx) + R * ((i0[1] + dy) + R * (int64_t)(i0[2] + dz));
+                    v += w * (double)M->grid[c * plane + node];
+                }
+        mat[c] = v;
+    }
+}
+
+static int is_emitter(const scene_t* S, int64_t f)
+{
+    return S->emission[f] > 0.0 || S->emission[S->T + f] > 0.0 || S->emission[2 * S->T + f] > 0.0;
+}
+
+/* The BRDF of Eq. 1 with the cosine: kd/pi (n.wi) + F D G / (4 n.wo),
+ * F = ks F0 + F1 (Schlick split of Eq. 7), for unit n, wi, wo; zero unless
+ * both directions are above the surface. */
+static void brdf_f(const double n[3], const double wo[3], const double wi[3], const double a[3],
+                   double alpha, double m, double out[3])
+{
+    double ci = dot3(n, wi), co = dot3(n, wo);
+    out[0] = out[1] = out[2] = 0.0;
+    if (ci <= 0.0 || co <= 0.0) return;
+    double h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+    double hl = norm3(h);
+    for (int k = 0; k < 3; ++k) h[k] /= hl;
+    double nh = dot3(n, h), hi = dot3(h, wi);
+    double spec_base = 0.0, F1 = 0.0;
+    if (nh > 0.0 && hi > 0.0) {
+        double G = orc_ggx_G1(alpha, ci) * orc_ggx_G1(alpha, co);
+        spec_base = orc_ggx_D(alpha, nh) * G / (4.0 * co);
+        double om = 1.0 - hi;
+        F1 = om * om * om * om * om;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double kd = a[c] * (1.0 - m), ks = 0.04 * (1.0 - m) + a[c] * m;
+        out[c] = kd / ORC_PI * ci + (ks * (1.0 - F1) + F1) * spec_base;
+    }
+}
+
+/* Density of the BRDF sampling at a glossy vertex: one half GGX half
+ * vectors (D(h)(n.h) / (4 wo.h) in wi), one half cosine-weighted. */
+static double brdf_pdf(const double n[3], const double wo[3], const double wi[3], double alpha)
+{
+    double ci = dot3(n, wi);
+    if (ci <= 0.0) return 0.0;
+    double h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+    double hl = norm3(h);
+    for (int k = 0; k < 3; ++k) h[k] /= hl;
+    double nh = dot3(n, h), oh = dot3(wo, h);
+    double ps = (nh > 0.0 && oh > 0.0) ? orc_ggx_D(alpha, nh) * nh / (4.0 * oh) : 0.0;
+    return 0.5 * ps + 0.5 * ci / ORC_PI;
+}
+
+/* Unit face normal of triangle f and its area. */
+static double face_normal(const scene_t* S, int64_t f, double n[3])
+{
+    cross3(S->e1 + 3 * f, S->e2 + 3 * f, n);
+    double l = norm3(n);
+    for (int k = 0; k < 3; ++k) n[k] /= l;
+    return 0.5 * l;
+}
+
+/* One cast as an event of the run: the nominal outcome, or the chosen
+ * alternative when this event is the one being flipped. */
+static hit_t path_cast(const scene_t* S, const double o[3], const double d[3], pathrun_t* run,
+                       cast_t* h, int* clamp)
+{
+    cast(S, o, d, h);
+    run->overflow |= h->overflow;
+    int e = run->n_events++;
+    int amb = h->n_cand > 1 || (h->n_cand == 1 && h->cand[0].tri != h->nominal.tri);
+    if (e < ORC_MAX_EVENTS) run->alts[e] = amb ? h->n_cand : 0;
+    else run->overflow = 1;
+    if (e == run->flip_event) {
+        *clamp = 1;
+        return h->cand[run->flip_choice];
+    }
+    *clamp = 0;
+    return h->nominal;
+}
+
+/* Radiance arriving at the start of the ray (o, d) along a refined path
+ * (Eq. 10 and 11), the factor of the first lobe weight excluded. */
+static void refine_path(const scene_t* S, const refine_t* M, uint64_t seed, int64_t p, int lobe,
+                        int s, const double o0[3], const double d0[3], double eps, pathrun_t* run,
+                        cast_t* h, double C[3])
+{
+    double o[3] = {o0[0], o0[1], o0[2]}, d[3] = {d0[0], d0[1], d0[2]};
+    double T[3] = {1.0, 1.0, 1.0};
+    double pb_prev = -1.0;   /* density of the BRDF sampling that chose d; < 0: the lobe g */
+    int nee = !(M->flags & ORC_REFINE_BSDF_ONLY) && M->n_emit > 0;
+    C[0] = C[1] = C[2] = 0.0;
+    for (int vert = 1;; ++vert) {
+        int clamp;
+        hit_t hit = path_cast(S, o, d, run, h, &clamp);
+        if (hit.tri < 0) return;
+        int64_t f = hit.tri;
+        if (is_emitter(S, f)) {
+            double w = 1.0;
+            if (pb_prev >= 0.0 && nee) {
+                double nz[3];
+                double area = face_normal(S, f, nz);
+                double cz = fabs(dot3(nz, d));
+                double pl = cz > 0.0 ? hit.t * hit.t / (cz * M->n_emit * area) : INFINITY;
+                w = pb_prev / (pb_prev + pl);
+            }
+            for (int c = 0; c < 3; ++c) C[c] += T[c] * S->emission[c * S->T + f] * w;
+            return;
+        }
+        double y[3], ny[3], wo[3], mat[5];
+        for (int k = 0; k < 3; ++k) {
+            y[k] = o[k] + hit.t * d[k];
+            wo[k] = -d[k];
+        }
+        face_normal(S, f, ny);
+        if (dot3(ny, wo) < 0.0)
+            for (int k = 0; k < 3; ++k) ny[k] = -ny[k];
+        if (!(dot3(ny, wo) > 0.0)) return;
+        material_at(M, y, mat);
+        int diffuse = mat[3] > M->sigma_diffuse;
+        int e = run->n_events++;
+        if (e < ORC_MAX_EVENTS) run->alts[e] = fabs(mat[3] - M->sigma_diffuse) <= 1e-4 ? 1 : 0;
+        else run->overflow = 1;
+        if (e == run->flip_event) diffuse = !diffuse;
+        if (diffuse || vert >= M->max_vertices) {
+            double R[3];
+            radiance(S, &hit, clamp, R);
+            for (int c = 0; c < 3; ++c) C[c] += T[c] * R[c];
+            return;
+        }
+        /* a glossy vertex: BRDF of the current material */
+        double sg = fmin(fmax(mat[3], 0.02), 1.0), alpha = sg * sg;
+        double a[3] = {mat[0], mat[1], mat[2]}, met = mat[4];
+        double yo[3];
+        for (int k = 0; k < 3; ++k) yo[k] = y[k] + eps * ny[k];
+        uint32_t u[4], v[4];
+        vertex_philox(seed, p, lobe, s, vert, 0, u);
+        vertex_philox(seed, p, lobe, s, vert, 1, v);
+        if (nee) {
+            int k_e = (int)(((uint64_t)u[0] * (uint64_t)M->n_emit) >> 32);
+            int64_t fe = M->emit[k_e];
+            double su = sqrt(unif24(u[1])), b1 = su * (1.0 - unif24(u[2])), b2 = su * unif24(u[2]);
+            double z[3], l[3];
+            for (int k = 0; k < 3; ++k)
+                z[k] = S->v0[3 * fe + k] + b1 * S->e1[3 * fe + k] + b2 * S->e2[3 * fe + k];
+            for (int k = 0; k < 3; ++k) l[k] = z[k] - yo[k];
+            double dist = norm3(l);
+            for (int k = 0; k < 3; ++k) l[k] /= dist;
+            double nz[3];
+            double area = face_normal(S, fe, nz);
+            double cz = fabs(dot3(nz, l));
+            if (dot3(ny, l) > 0.0 && cz > 0.0) {
+                int cl2;
+                hit_t sh = path_cast(S, yo, l, run, h, &cl2);
+                if (sh.tri == fe) {
+                    double fv[3];
+                    brdf_f(ny, wo, l, a, alpha, met, fv);
+                    double pl = dist * dist / (cz * M->n_emit * area);
+                    double pb = brdf_pdf(ny, wo, l, alpha);
+                    for (int c = 0; c < 3; ++c)
+                        C[c] += T[c] * fv[c] * S->emission[c * S->T + fe] / (pl + pb);
+                }
+            }
+        }
+        /* the path goes on along a direction drawn from f */
+        double t_[3], b_[3], loc[3], w2[3];
+        orc_frame(ny, t_, b_);
+        if (unif24(u[3]) < 0.5) {
+            double mh[3];
+            orc_sample_ggx(alpha, unif24(v[0]), unif24(v[1]), loc);
+            to_world(t_, b_, ny, loc, mh);
+            double om = dot3(wo, mh);
+            if (om <= 0.0) return;
+            for (int k = 0; k < 3; ++k) w2[k] = 2.0 * om * mh[k] - wo[k];
+        } else {
+            orc_sample_cosine(unif24(v[0]), unif24(v[1]), loc);
+            to_world(t_, b_, ny, loc, w2);
+        }
+        if (dot3(ny, w2) <= 0.0) return;
+        double pb = brdf_pdf(ny, wo, w2, alpha);
+        if (!(pb > 0.0)) return;
+        double fv[3];
+        brdf_f(ny, wo, w2, a, alpha, met, fv);
+        for (int c = 0; c < 3; ++c) T[c] *= fv[c] / pb;
+        for (int k = 0; k < 3; ++k) {
+            o[k] = yo[k];
+            d[k] = w2[k];
+        }
+        pb_prev = pb;
+    }
+}
+
+/* One sample's contribution with its envelope over single flips of
+ * ambiguous events.  Returns 1 if some event was ambiguous. */
+static int refine_sample(const scene_t* S, const refine_t* M, uint64_t seed, int64_t p, int lobe,
+                         int s, const double o[3], const double d[3], double eps, cast_t* h,
+                         double C[3], double Cl[3], double Ch[3], int* overflow)
+{
+    pathrun_t run;
+    memset(&run, 0, sizeof(run));
+    run.flip_event = -1;
+    refine_path(S, M, seed, p, lobe, s, o, d, eps, &run, h, C);
+    *overflow |= run.overflow;
+    for (int c = 0; c < 3; ++c) Cl[c] = Ch[c] = C[c];
+    int n_ev = run.n_events < ORC_MAX_EVENTS ? run.n_events : ORC_MAX_EVENTS;
+    int alts[ORC_MAX_EVENTS];
+    memcpy(alts, run.alts, sizeof(int) * n_ev);
+    int amb = 0;
+    for (int e = 0; e < n_ev; ++e) {
+        for (int k = 0; k < alts[e]; ++k) {
+            pathrun_t r2;
+            memset(&r2, 0, sizeof(r2));
+            r2.flip_event = e;
+            r2.flip_choice = k;
+            double A[3];
+            refine_path(S, M, seed, p, lobe, s, o, d, eps, &r2, h, A);
+            *overflow |= r2.overflow;
+            for (int c = 0; c < 3; ++c) {
+                Cl[c] = fmin(Cl[c], A[c]);
+                Ch[c] = fmax(Ch[c], A[c]);
+            }
+            amb = 1;
+        }
+    }
+    return amb;
+}
+
+/*
+ * Refined shading terms of the listed points, laid out as orc_bake's.
+ * grid: [5][res^3] material (a_r, a_g, a_b, sigma, m) over [glo, ghi].
+ * Returns 0, ORC_EOVERFLOW, or ORC_EINVAL (voxel cache, which the
+ * refinement does not take, or bad arguments).
+ */
+int orc_refine(void* sp, const float* pts, const int32_t* ptri, int64_t stride, const int64_t* idx,
+               int64_t n_idx, int spp_d, int spp_s, int K, const double* sigma, uint64_t seed,
+               double eps, const float* grid, int res, const double* glo, const double* ghi,
+               double sigma_diffuse, int max_vertices, int flags, int n_threads, double* out,
+               double* lo, double* hi, double* sq, int64_t* n_ambiguous)
+{
+    const scene_t* S = (const scene_t*)sp;
+    if (S->cache_kind == 2 || res < 2 || max_vertices < 1 || max_vertices > 16) return ORC_EINVAL;
+    refine_t M;
+    memset(&M, 0, sizeof(M));
+    M.grid = grid;
+    M.res = res;
+    for (int a = 0; a < 3; ++a) {
+        M.lo[a] = glo[a];
+        M.hi[a] = ghi[a];
+    }
+    M.sigma_diffuse = sigma_diffuse;
+    M.max_vertices = max_vertices;
+    M.flags = flags;
+    M.emit = (int32_t*)malloc(sizeof(int32_t) * (S->T > 0 ? S->T : 1));
+    for (int64_t f = 0; f < S->T; ++f)
+        if (is_emitter(S, f)) M.emit[M.n_emit++] = (int32_t)f;
+    const int P = 3 + 6 * K;
+    int64_t total_ambig = 0;
+    int overflow = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel reduction(+ : total_ambig) reduction(| : overflow)
+    {
+        cast_t* h = (cast_t*)malloc(sizeof(cast_t));
+        double acc[3 + 6 * 16], alo[3 + 6 * 16], ahi[3 + 6 * 16], asq[3 + 6 * 16];
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < n_idx; ++q) {
+            int64_t p = idx[q];
+            for (int k = 0; k < P; ++k) acc[k] = alo[k] = ahi[k] = asq[k] = 0.0;
+            double x[3], n[3], wo[3];
+            for (int k = 0; k < 3; ++k) {
+                x[k] = (double)pts[k * stride + p];
+                n[k] = (double)pts[(3 + k) * stride + p];
+                wo[k] = (double)pts[(6 + k) * stride + p];
+            }
+            double cos_o = dot3(n, wo);
+            if (ptri[p] >= 0 && cos_o < 0.0) {
+                for (int k = 0; k < 3; ++k) n[k] = -n[k];
+                cos_o = -cos_o;
+            }
+            if (ptri[p] >= 0 && cos_o > 0.0) {
+                double t[3], b[3], o[3];
+                orc_frame(n, t, b);
+                for (int k = 0; k < 3; ++k) o[k] = x[k] + eps * n[k];
+                for (int s = 0; s < spp_d; ++s) {
+                    double xi1, xi2, l[3], wi[3], R[3], Rl[3], Rh[3];
+                    sample_uniforms(seed, p, 0, s, spp_d, &xi1, &xi2);
+                    orc_sample_cosine(xi1, xi2, l);
+                    to_world(t, b, n, l, wi);
+                    total_ambig += refine_sample(S, &M, seed, p, 0, s, o, wi, eps, h, R, Rl, Rh,
+                                                 &overflow);
+                    for (int c = 0; c < 3; ++c) {
+                        acc[c] += R[c];
+                        alo[c] += Rl[c];
+                        ahi[c] += Rh[c];
+                        asq[c] += R[c] * R[c];
+                    }
+                }
+                for (int k = 0; k < K; ++k) {
+                    double alpha = sigma[k] * sigma[k];
+                    for (int s = 0; s < spp_s; ++s) {
+                        double xi1, xi2, l[3], m[3], wi[3], F1 = 0.0;
+                        sample_uniforms(seed, p, 1 + k, s, spp_s, &xi1, &xi2);
+                        orc_sample_ggx(alpha, xi1, xi2, l);
+                        to_world(t, b, n, l, m);
+                        double w = spec_weight(alpha, n, wo, cos_o, m, wi, &F1, 0);
+                        if (w == 0.0) continue;
+                        double R[3], Rl[3], Rh[3];
+                        total_ambig += refine_sample(S, &M, seed, p, 1 + k, s, o, wi, eps, h, R, Rl,
+                                                     Rh, &overflow);
+                        double F0 = 1.0 - F1;
+                        int j0 = 3 + 3 * k, j1 = 3 + 3 * K + 3 * k;
+                        for (int c = 0; c < 3; ++c) {
+                            acc[j0 + c] += R[c] * F0 * w;
+                            alo[j0 + c] += Rl[c] * F0 * w;
+                            ahi[j0 + c] += Rh[c] * F0 * w;
+                            asq[j0 + c] += (R[c] * F0 * w) * (R[c] * F0 * w);
+                            acc[j1 + c] += R[c] * F1 * w;
+                            alo[j1 + c] += Rl[c] * F1 * w;
+                            ahi[j1 + c] += Rh[c] * F1 * w;
+                            asq[j1 + c] += (R[c] * F1 * w) * (R[c] * F1 * w);
+                        }
+                    }
+                }
+            }
+            for (int k = 0; k < P; ++k) {
+                double cnt = (k < 3) ? (double)spp_d : (double)spp_s;
+                out[k * n_idx + q] = acc[k] / cnt;
+                if (lo) lo[k * n_idx + q] = alo[k] / cnt;
+                if (hi) hi[k * n_idx + q] = ahi[k] / cnt;
+                if (sq) sq[k * n_idx + q] = asq[k] / (cnt * cnt);
+            }
+        }
+        free(h);
+    }
+    free(M.emit);
+    if (n_ambiguous) *n_ambiguous = total_ambig;
+    return overflow ? ORC_EOVERFLOW : 0;
+}
+
+/* Test hooks: the BRDF, its sampling density and the material lookup. */
+void orc_brdf(const double* n, const double* wo, const double* wi, const double* a, double sigma,
+              double m, double* out)
+{
+    double sg = fmin(fmax(sigma, 0.02), 1.0);
+    brdf_f(n, wo, wi, a, sg * sg, m, out);
+}
+
+double orc_brdf_pdf(const double* n, const double* wo, const double* wi, double sigma)
+{
+    double sg = fmin(fmax(sigma, 0.02), 1.0);
+    return brdf_pdf(n, wo, wi, sg * sg);
+}
+
+/* Radiance a path ends on at hit `hit` seen along d, for the quadrature
+ * below: Le at an emitter, L' at a diffuse hit (sigma > sigma_diffuse),
+ * and -1 in out[3] at a glossy hit (the caller integrates further). */
+static void end_radiance(const scene_t* S, const refine_t* M, const hit_t* hit, const double o[3],
+                         const double d[3], double out[4], double mat[5])
+{
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    if (hit->tri < 0) return;
+    if (is_emitter(S, hit->tri)) {
+        for (int c = 0; c < 3; ++c) out[c] = S->emission[c * S->T + hit->tri];
+        return;
+    }
+    double y[3];
+    for (int k = 0; k < 3; ++k) y[k] = o[k] + hit->t * d[k];
+    material_at(M, y, mat);
+    if (mat[3] > M->sigma_diffuse) {
+        radiance(S, hit, 0, out);
+        out[3] = 0.0;
+        return;
+    }
+    out[3] = -1.0;
+}
+
+/* The radiance leaving a glossy hit y (normal ny facing wo, material mat)
+ * toward wo, as the integral of f times the radiance its directions end on
+ * (Eq. 10 with paths of one more vertex): the diffuse part of f by a
+ * midpoint rule in (theta, phi) about ny, the specular part over half
+ * vectors (d omega_i = 4 (wo.m) d omega_m, theta_m = (pi/2) s^4).  The
+ * weight of directions that reach a further glossy surface is added to
+ * *deeper. */
+static void glossy_integral(const scene_t* S, const refine_t* M, cast_t* h, const double y[3],
+                            const double ny[3], const double wo[3], const double mat[5], double eps,
+                            int nt, int np, double L[3], double* deeper)
+{
+    double t[3], b[3], yo[3];
+    orc_frame(ny, t, b);
+    for (int k = 0; k < 3; ++k) yo[k] = y[k] + eps * ny[k];
+    double sg = fmin(fmax(mat[3], 0.02), 1.0), alpha = sg * sg, met = mat[4];
+    double co = dot3(ny, wo);
+    L[0] = L[1] = L[2] = 0.0;
+    double dphi = 2.0 * ORC_PI / np;
+    /* diffuse part: kd / pi (n.wi) */
+    double dth = 0.5 * ORC_PI / nt;
+    for (int i = 0; i < nt; ++i) {
+        double th = (i + 0.5) * dth;
+        for (int j = 0; j < np; ++j) {
+            double ph = (j + 0.5) * dphi;
+            double l[3] = {sin(th) * cos(ph), sin(th) * sin(ph), cos(th)}, wi[3], R[4], m2[5];
+            to_world(t, b, ny, l, wi);
+            cast(S, yo, wi, h);
+            end_radiance(S, M, &h->nominal, yo, wi, R, m2);
+            double wgt = cos(th) / ORC_PI * sin(th) * dth * dphi;
+            if (R[3] < 0.0) {
+                *deeper += wgt;
+                continue;
+            }
+            for (int c = 0; c < 3; ++c) L[c] += mat[c] * (1.0 - met) * R[c] * wgt;
+        }
+    }
+    /* specular part: (ks F0 + F1) D G / (4 n.wo) */
+    double ds = 1.0 / nt;
+    for (int i = 0; i < nt; ++i) {
+        double s = (i + 0.5) * ds;
+        double th = 0.5 * ORC_PI * s * s * s * s;
+        double dthm = 0.5 * ORC_PI * 4.0 * s * s * s * ds;
+        double cm = cos(th), D = orc_ggx_D(alpha, cm);
+        for (int j = 0; j < np; ++j) {
+            double ph = (j + 0.5) * dphi;
+            double l[3] = {sin(th) * cos(ph), sin(th) * sin(ph), cm}, m[3], wi[3];
+            to_world(t, b, ny, l, m);
+            double om = dot3(wo, m);
+            if (om <= 0.0) continue;
+            for (int k = 0; k < 3; ++k) wi[k] = 2.0 * om * m[k] - wo[k];
+            double ci = dot3(ny, wi);
+            if (ci <= 0.0) continue;
+            double G = orc_ggx_G1(alpha, ci) * orc_ggx_G1(alpha, co);
+            double F1 = pow(1.0 - om, 5.0);
+            double R[4], m2[5];
+            cast(S, yo, wi, h);
+            end_radiance(S, M, &h->nominal, yo, wi, R, m2);
+            double wgt = D * G * om / co * sin(th) * dthm * dphi;
+            if (R[3] < 0.0) {
+                *deeper += wgt;
+                continue;
+            }
+            for (int c = 0; c < 3; ++c) {
+                double ks = 0.04 * (1.0 - met) + mat[c] * met;
+                L[c] += (ks * (1.0 - F1) + F1) * R[c] * wgt;
+            }
+        }
+    }
+}
+
+/*
+ * Deterministic quadrature of one refined shading integral at one point
+ * (the expectation the Monte Carlo refinement estimates), for scenes in
+ * which every path ends by its second vertex: the outer integral over the
+ * lobe g as orc_quadrature takes it (lobe < 0: Ld; lobe >= 0: Ls0, Ls1 at
+ * roughness sigma), the radiance of a glossy first hit by glossy_integral.
+ * out[6]: the three or six values; out[6]: the weight of directions that
+ * went deeper than two vertices (zero when the scene is as required).
+ */
+int orc_refine_quadrature(void* sp, const double* x, const double* nrm, const double* wo, int lobe,
+                          double sigma, const float* grid, int res, const double* glo,
+                          const double* ghi, double sigma_diffuse, int n_theta, int n_phi,
+                          int n_theta2, int n_phi2, double eps, double* out)
+{
+    const scene_t* S = (const scene_t*)sp;
+    refine_t M;
+    memset(&M, 0, sizeof(M));
+    M.grid = grid;
+    M.res = res;
+    for (int a = 0; a < 3; ++a) {
+        M.lo[a] = glo[a];
+        M.hi[a] = ghi[a];
+    }
+    M.sigma_diffuse = sigma_diffuse;
+    M.max_vertices = 2;
+    double n[3] = {nrm[0], nrm[1], nrm[2]}, t[3], b[3], o[3];
+    double cos_o = dot3(n, wo);
+    orc_frame(n, t, b);
+    for (int k = 0; k < 3; ++k) o[k] = x[k] + eps * n[k];
+    double acc[6] = {0, 0, 0, 0, 0, 0}, deeper = 0.0;
+    int overflow = 0;
+    double dphi = 2.0 * ORC_PI / n_phi;
+#pragma omp parallel reduction(+ : deeper) reduction(| : overflow)
+    {
+        cast_t* h = (cast_t*)malloc(sizeof(cast_t));
+        double loc[6] = {0, 0, 0, 0, 0, 0};
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < n_theta; ++i) {
+            for (int j = 0; j < n_phi; ++j) {
+                double ph = (j + 0.5) * dphi, th, wgt_d = 0.0, wi[3], F1 = 0.0, wgt_s = 0.0;
+                if (lobe < 0) {
+                    double dth = 0.5 * ORC_PI / n_theta;
+                    th = (i + 0.5) * dth;
+                    double l[3] = {sin(th) * cos(ph), sin(th) * sin(ph), cos(th)};
+                    to_world(t, b, n, l, wi);
+                    wgt_d = cos(th) / ORC_PI * sin(th) * dth * dphi;
+                } else {
+                    double alpha = sigma * sigma, ds = 1.0 / n_theta, s = (i + 0.5) * ds;
+                    th = 0.5 * ORC_PI * s * s * s * s;
+                    double dthm = 0.5 * ORC_PI * 4.0 * s * s * s * ds;
+                    double cm = cos(th);
+                    double l[3] = {sin(th) * cos(ph), sin(th) * sin(ph), cm}, m[3];
+                    to_world(t, b, n, l, m);
+                    double om = dot3(wo, m);
+                    if (om <= 0.0) continue;
+                    for (int k = 0; k < 3; ++k) wi[k] = 2.0 * om * m[k] - wo[k];
+                    double ci = dot3(n, wi);
+                    if (ci <= 0.0) continue;
+                    double G = orc_ggx_G1(alpha, ci) * orc_ggx_G1(alpha, cos_o);
+                    F1 = pow(1.0 - om, 5.0);
+                    wgt_s = orc_ggx_D(alpha, cm) * G * om / cos_o * sin(th) * dthm * dphi;
+                }
+                double R[4], mat[5];
+                cast(S, o, wi, h);
+                overflow |= h->overflow;
+                end_radiance(S, &M, &h->nominal, o, wi, R, mat);
+                if (R[3] < 0.0) {
+                    double y[3], ny[3], w1[3];
+                    for (int k = 0; k < 3; ++k) {
+                        y[k] = o[k] + h->nominal.t * wi[k];
+                        w1[k] = -wi[k];
+                    }
+                    face_normal(S, h->nominal.tri, ny);
+                    if (dot3(ny, w1) < 0.0)
+                        for (int k = 0; k < 3; ++k) ny[k] = -ny[k];
+                    double dl = 0.0;
+                    glossy_integral(S, &M, h, y, ny, w1, mat, eps, n_theta2, n_phi2, R, &dl);
+                    deeper += dl * (lobe < 0 ? wgt_d : wgt_s);
+                }
+                if (lobe < 0) {
+                    for (int c = 0; c < 3; ++c) loc[c] += R[c] * wgt_d;
+                } else {
+                    for (int c = 0; c < 3; ++c) {
+                        loc[c] += R[c] * (1.0 - F1) * wgt_s;
+                        loc[3 + c] += R[c] * F1 * wgt_s;
+                    }
+                }
+            }
+        }
+#pragma omp critical
+        for (int k = 0; k < 6; ++k) acc[k] += loc[k];
+        free(h);
+    }
+    for (int k = 0; k < 6; ++k) out[k] = acc[k];
+    out[6] = deeper;
+    return overflow ? ORC_EOVERFLOW : 0;
+}
+
+/* Test hook: the refinement's material lookup at n points x[n][3]. */
+void orc_material_at(const float* grid, int res, const double* lo, const double* hi,
+                     const double* x, int64_t n, double* out)
+{
+    refine_t M;
+    memset(&M, 0, sizeof(M));
+    M.grid = grid;
+    M.res = res;
+    for (int a = 0; a < 3; ++a) {
+        M.lo[a] = lo[a];
+        M.hi[a] = hi[a];
+    }
+    for (int64_t i = 0; i < n; ++i) material_at(&M, x + 3 * i, out + 5 * i);
+}

@@ -23,11 +23,12 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 C = "oracle/fipt_oracle.c"
-# (name, file, [(old, new, which occurrence or None for the only one)])
+# (name, file, [(old, new, which occurrence or None for the only one)]
+#  [, pin files to run first])
 MUTANTS = [
     # microfacet model and the estimator of Eq. 6 / 7
     ("alpha = sigma instead of sigma^2", C,
-     [("double alpha = sigma[k] * sigma[k];", "double alpha = sigma[k];", None)]),
+     [("double alpha = sigma[k] * sigma[k];", "double alpha = sigma[k];", 0)]),
     ("one Smith G1 dropped", C,
      [("        G = orc_ggx_G1(alpha, ci) * orc_ggx_G1(alpha, cos_o);",
        "        G = orc_ggx_G1(alpha, cos_o);", None)]),
@@ -35,7 +36,7 @@ MUTANTS = [
      [("*F1 = one_minus * one_minus * one_minus * one_minus * one_minus;",
        "*F1 = one_minus * one_minus * one_minus * one_minus;", None)]),
     ("F0 and F1 terms swapped", C,
-     [("int j0 = 3 + 3 * k, j1 = 3 + 3 * K + 3 * k;", "int j1 = 3 + 3 * k, j0 = 3 + 3 * K + 3 * k;", None)]),
+     [("int j0 = 3 + 3 * k, j1 = 3 + 3 * K + 3 * k;", "int j1 = 3 + 3 * k, j0 = 3 + 3 * K + 3 * k;", 0)]),
     ("n.m missing from the sample weight", C,
      [("return G * om / (cos_o * cm);", "return G * om / cos_o;", None)]),
     ("GGX D with the denominator not squared", C,
@@ -59,7 +60,7 @@ MUTANTS = [
      [("t[2] = -s * n[0];", "t[2] = s * n[0];", None)]),
     ("mean divides by spp + 1", C,
      [("double cnt = (k < 3) ? (double)spp_d : (double)spp_s;\n                out[k * n_idx + q]",
-       "double cnt = (k < 3) ? (double)spp_d : (double)(spp_s + 1);\n                out[k * n_idx + q]", None)]),
+       "double cnt = (k < 3) ? (double)spp_d : (double)(spp_s + 1);\n                out[k * n_idx + q]", 0)]),
     # random numbers
     ("Philox Weyl constant off by two", C,
      [("k0 += 0x9E3779B9u;", "k0 += 0x9E3779B7u;", None)]),
@@ -89,6 +90,34 @@ MUTANTS = [
        "for (int c = 0; c < 3; ++c) R[c] = 0.0;", None)]),
     ("camera aspect inverted", C,
      [("double aspect = (double)W / (double)H;", "double aspect = (double)H / (double)W;", None)]),
+    # stage-3 refinement (Eq. 10 / 11): pins in test_oracle_refine.py first
+    ("refine: MIS weight of a BRDF-sampled emitter hit inverted", C,
+     [("w = pb_prev / (pb_prev + pl);", "w = pl / (pb_prev + pl);", None)], ["test_oracle_refine.py"]),
+    ("refine: emitter sample density without the emitter's cosine", C,
+     [("double pl = dist * dist / (cz * M->n_emit * area);",
+       "double pl = dist * dist / (M->n_emit * area);", None)], ["test_oracle_refine.py"]),
+    ("refine: mixture density counts the GGX half twice", C,
+     [("return 0.5 * ps + 0.5 * ci / ORC_PI;", "return ps + 0.5 * ci / ORC_PI;", None)],
+     ["test_oracle_refine.py"]),
+    ("refine: path throughput not divided by the density", C,
+     [("for (int c = 0; c < 3; ++c) T[c] *= fv[c] / pb;", "for (int c = 0; c < 3; ++c) T[c] *= fv[c];", None)],
+     ["test_oracle_refine.py"]),
+    ("refine: diffuse BRDF without 1/pi", C,
+     [("out[c] = kd / ORC_PI * ci + (ks * (1.0 - F1) + F1) * spec_base;",
+       "out[c] = kd * ci + (ks * (1.0 - F1) + F1) * spec_base;", None)], ["test_oracle_refine.py"]),
+    ("refine: Fresnel split without ks", C,
+     [("out[c] = kd / ORC_PI * ci + (ks * (1.0 - F1) + F1) * spec_base;",
+       "out[c] = kd / ORC_PI * ci + spec_base;", None)], ["test_oracle_refine.py"]),
+    ("refine: sigma threshold reversed", C,
+     [("int diffuse = mat[3] > M->sigma_diffuse;", "int diffuse = mat[3] < M->sigma_diffuse;", None)],
+     ["test_oracle_refine.py"]),
+    ("refine: points on emitters not uniform in area", C,
+     [("double su = sqrt(unif24(u[1])), b1", "double su = unif24(u[1]), b1", None)],
+     ["test_oracle_refine.py"]),
+    ("refine: material grid x and y swapped", C,
+     [("int64_t node = (i0[0] + dx) + R * ((i0[1] + dy) + R * (int64_t)(i0[2] + dz));",
+       "int64_t node = (i0[1] + dy) + R * ((i0[0] + dx) + R * (int64_t)(i0[2] + dz));", None)],
+     ["test_oracle_refine.py"]),
     # factored render, loss and gradient (Eq. 5, 8, 2)
     ("specular base reflectance 0.4 instead of 0.04", "oracle/render.py",
      [("ks = 0.04 * (1.0 - m) + a * m", "ks = 0.4 * (1.0 - m) + a * m", None)]),
@@ -172,12 +201,12 @@ def _apply(repo: str, path: str, edits) -> None:
         assert r.returncode == 0, r.stderr
 
 
-def _run_pins(name, path, edits, threads: int = 2, limit_s: int = 300):
+def _run_pins(name, path, edits, first=None, threads: int = 2, limit_s: int = 300):
     with tempfile.TemporaryDirectory(prefix="orc_mut_") as tmp:
         repo = _workspace(tmp)
         if path:
             _apply(repo, path, edits)
-        first = FIRST.get(path, [])
+        first = (first or []) + [f for f in FIRST.get(path, []) if f not in (first or [])]
         order = first + [f for f in ORACLE_TESTS if f not in first]
         env = dict(os.environ, OMP_NUM_THREADS=str(threads), PYTHONDONTWRITEBYTECODE="1")
         env.pop("PYTHONPATH", None)
