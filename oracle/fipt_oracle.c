@@ -928,6 +928,8 @@ int orc_max_threads(void)
  *     also the one the path continues along.
  * A flag turns emitter sampling off (BRDF sampling only, weight one).
  *
+ * At a glossy vertex local directions are taken in the frame (t, b, n) with
+ * t the unit first edge of the hit triangle and b = n x t.
  * Random numbers: the first direction uses the stage-1 uniforms of
  * (p, lobe, s); vertex i >= 1 draws two Philox blocks with counter
  * (p lo, p hi, lobe | i << 8 | k << 16, s), k = 0 for the emitter choice
@@ -1159,9 +1161,14 @@ static void refine_path(const scene_t* S, const refine_t* M, uint64_t seed, int6
                 }
             }
         }
-        /* the path goes on along a direction drawn from f */
+        /* the path goes on along a direction drawn from f, in the frame of
+         * the hit triangle's first edge: t = e1 / |e1|, b = n x t (no sign
+         * decision on n, whose components a single-precision cross product
+         * of the edges may leave a hair from zero) */
         double t_[3], b_[3], loc[3], w2[3];
-        orc_frame(ny, t_, b_);
+        double el = norm3(S->e1 + 3 * f);
+        for (int k = 0; k < 3; ++k) t_[k] = S->e1[3 * f + k] / el;
+        cross3(ny, t_, b_);
         if (unif24(u[3]) < 0.5) {
             double mh[3];
             orc_sample_ggx(alpha, unif24(v[0]), unif24(v[1]), loc);
