@@ -611,6 +611,37 @@ def run_voxel(scene, sc, planes, tri, obs, out, reps=3):
                     "observation per pixel (4 + 12 B)"}
 
 
+def run_refine(scene, sc, planes, tri, grid, out, t_bake_ms, reps=3):
+    """The stage-3 refinement (Eq. 10 / 11) of the room's shadings under the
+    current material (the differentiation workload's 128^3 grid): paths
+    grown through glossy hits (roughness <= 0.6) to an emitter or a rough
+    hit, at most eight vertices, emitter sampling with MIS at glossy
+    vertices; same points and lobe samples as the bake."""
+    N = planes.shape[1]
+    S = sc.spp * (1 + len(sc.sigma))
+    bmin, bmax = sc.bmin.tolist(), sc.bmax.tolist()
+
+    def once():
+        fipt.fipt_refine(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, grid, bmin, bmax,
+                         out=out)
+
+    once()
+    torch.cuda.synchronize()
+    tm = Timer()
+    for _ in range(reps):
+        tm.mark("a")
+        once()
+        tm.mark("b")
+    torch.cuda.synchronize()
+    ms = float(np.mean(tm.spans("a", "b")))
+    glossy = float((grid[3] <= 0.6).float().mean().item())
+    return {"points": N, "lobe_samples_per_point": S, "max_vertices": 8, "sigma_diffuse": 0.6,
+            "ms": ms, "gsamples_per_s": N * S / (ms * 1e-3) / 1e9, "bake_ms": t_bake_ms,
+            "cost_vs_bake": ms / t_bake_ms, "kernel": "k_refine",
+            "material": "differentiation workload's 128^3 grid (roughness U[0.02, 1] per node; "
+                        f"{glossy:.0%} of nodes glossy)"}
+
+
 def run_hashgrid(sc, planes, shading, obs, reps=5):
     """The paper's material network (Eq. 14) on the room's points: forward
     (hash encoding + MLP), the factored loss with its material gradient,
@@ -930,6 +961,8 @@ def main():
     del flush, alpha
     comparator = run_comparator(shading, mat, obs, sc.sigma, t_loss)
     log(f"torch-autograd comparator: {comparator}")
+    refine = run_refine(scene, sc, planes, tri, grid, torch.empty_like(shading), t_bake)
+    log(f"stage-3 refinement: {refine}")
     voxel = run_voxel(scene, sc, planes, tri, obs, shading)
     log(f"voxel cache: {voxel}")
     hashgrid = run_hashgrid(sc, planes, shading, obs)
@@ -996,6 +1029,7 @@ def main():
         "roofline_grid": roof_grid,
         "torch_autograd_comparator": comparator,
         "masked_loss": masked,
+        "refinement": refine,
         "voxel_cache": voxel,
         "hashgrid_network": hashgrid,
         "cpu_baseline": cpu,

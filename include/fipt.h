@@ -288,6 +288,55 @@ int fipt_bake_traversal_stats(fipt_scene s, const fipt_points* pts,
                               const fipt_bake_params* p, const fipt_shading* out,
                               uint64_t* stats_dev, void* stream);
 
+/* ---- stage-3 path-traced shading refinement (Sec. 4.3, Eq. 10 / 11) ---- */
+
+#define FIPT_REFINE_BSDF_ONLY 1   /* no emitter sampling: BRDF sampling only */
+
+/* The current material estimate and the path rules of the refinement:
+ *   material      device float [5][res^3] (a_r, a_g, a_b, sigma, m), node
+ *                 (i, j, k) at bmin + (i, j, k) (bmax - bmin) / (res - 1),
+ *                 x fastest; read trilinearly at each hit, positions clamped
+ *                 onto the box (as fipt_grid_gather); 2 <= res <= 1024;
+ *   sigma_diffuse a hit with roughness above it ends the path at the cache
+ *                 (the paper's 0.6);
+ *   max_vertices  the path ends at the cache at this vertex at the latest,
+ *                 1..16 (1 gives the stage-1 bake for non-emitters);
+ *   flags         0 or FIPT_REFINE_BSDF_ONLY. */
+typedef struct fipt_refine_params {
+    const float* material;
+    int32_t res;
+    float bmin[3];
+    float bmax[3];
+    float sigma_diffuse;
+    int32_t max_vertices;
+    int32_t flags;
+} fipt_refine_params;
+
+/* Refined shading terms (same layout, sampling and counters as fipt_bake):
+ * each lobe sample's first direction and weight are the bake's; the path
+ * then grows (Eq. 10): a hit on an emitter (some channel of its emission
+ * > 0) returns its emission only; otherwise a hit whose roughness exceeds
+ * sigma_diffuse, or the max_vertices-th vertex, returns the radiance cache
+ * at the hit (Eq. 11); otherwise the hit is glossy and the radiance leaving
+ * it toward the previous vertex is estimated with the BRDF of Eq. 1 (with
+ * the cosine; GGX alpha = max(sigma, 0.02)^2): a point on an emitter
+ * (emitter triangle uniform by index in ascending original index, point
+ * uniform in area) and a direction drawn from f (GGX half vector or cosine,
+ * one half each) combined by the balance heuristic, the path continuing
+ * along the latter (local directions at a vertex in the frame of its
+ * triangle's first edge: t = (v1 - v0) / |v1 - v0|, b = n x t, n the face
+ * normal facing the incoming ray).  Vertex i >= 1 of sample s of lobe l of point p draws
+ * Philox4x32-10 blocks with counter (p lo, p hi, l | i << 8 | k << 16, s),
+ * k = 0 (word 0: the emitter, floor(u n_emitters / 2^32); words 1, 2: the
+ * point; word 3: GGX when (u >> 8) 2^-24 < 1/2) and k = 1 (words 0, 1: the
+ * direction); uniforms are (u >> 8) 2^-24.  The scene's cache must be per
+ * triangle or per vertex (FIPT_EINVAL for a voxel cache).  The call lists
+ * the scene's emitters in its own memory first, so refinements of one
+ * scene run in call order (the call makes `stream` wait for the previous
+ * one).  Allocates nothing; asynchronous on `stream`. */
+int fipt_refine(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
+                const fipt_refine_params* r, const fipt_shading* out, void* stream);
+
 /* ---- factored re-render and loss (Eq. 5, 8, 2 / 15) -------------------- */
 
 /* For n points, with material[5][mat_stride] = (a_r, a_g, a_b, sigma, m) and

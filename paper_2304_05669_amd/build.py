@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfipt.so")
 ARCH = os.environ.get("FIPT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "bvh_build.cpp", "grid.cpp", "server.cpp", "bake.hip", "loss.hip", "emission.hip", "voxel.hip", "hashgrid.hip", "stream.hip"]
+SOURCES = ["api.cpp", "bvh_build.cpp", "grid.cpp", "server.cpp", "bake.hip", "loss.hip", "emission.hip", "voxel.hip", "hashgrid.hip", "stream.hip", "refine.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]

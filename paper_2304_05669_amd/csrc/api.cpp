@@ -80,6 +80,10 @@ void scene_free(fipt_scene s) {
     if (s->d_vox_total) (void)hipFree(s->d_vox_total);
     if (s->d_vox_tiles) (void)hipFree(s->d_vox_tiles);
     if (s->d_order) (void)hipFree(s->d_order);
+    if (s->d_leaf_of) (void)hipFree(s->d_leaf_of);
+    if (s->d_emit) (void)hipFree(s->d_emit);
+    if (s->d_emit_blocks) (void)hipFree(s->d_emit_blocks);
+    if (s->refine_done) (void)hipEventDestroy(s->refine_done);
     if (s->d_tri_idx) (void)hipFree(s->d_tri_idx);
     if (s->d_counters) (void)hipFree(s->d_counters);
     for (hipEvent_t& e : s->slot_done)
@@ -187,10 +191,22 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris, 
         (rc = dev_alloc(&s->d_rad, bvh.tris.size(), &s->bytes)) ||
         (rc = dev_alloc(&s->d_order, bvh.order.size(), &s->bytes)) ||
         (rc = dev_alloc(&s->d_tri_idx, (size_t)(3 * n_tris), &s->bytes)) ||
-        (rc = dev_alloc(&s->d_counters, (size_t)kBakeSlots * kXcdCount, &s->bytes))) {
+        (rc = dev_alloc(&s->d_counters, (size_t)kBakeSlots * kXcdCount, &s->bytes)) ||
+        (rc = dev_alloc(&s->d_leaf_of, (size_t)n_tris, &s->bytes)) ||
+        (rc = dev_alloc(&s->d_emit, (size_t)n_tris + 1, &s->bytes)) ||
+        (rc = dev_alloc(&s->d_emit_blocks, (size_t)((n_tris + 255) / 256), &s->bytes))) {
         scene_free(s);
         return rc;
     }
+    {
+        hipError_t e = hipEventCreateWithFlags(&s->refine_done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            scene_free(s);
+            return fail(FIPT_EHIP, "scene events: %s", hipGetErrorString(e));
+        }
+    }
+    std::vector<int32_t> leaf_of(bvh.order.size());
+    for (size_t i = 0; i < bvh.order.size(); ++i) leaf_of[bvh.order[i]] = (int32_t)i;
     for (hipEvent_t& ev : s->slot_done) {
         hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -209,6 +225,9 @@ int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris, 
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->d_tri_idx, tris, sizeof(int32_t) * 3 * n_tris, hipMemcpyHostToDevice,
                            st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_leaf_of, leaf_of.data(), sizeof(int32_t) * leaf_of.size(),
+                           hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vectors go out of scope
     if (e != hipSuccess) {
         scene_free(s);
@@ -475,6 +494,68 @@ int fipt_bake_traversal_stats(fipt_scene s, const fipt_points* pts, const fipt_b
         return fail(FIPT_EINVAL, "stats_dev is NULL");
     }
     return bake_common(s, pts, p, out, stats_dev, stream);
+}
+
+int fipt_refine(fipt_scene s, const fipt_points* pts, const fipt_bake_params* p,
+                const fipt_refine_params* r, const fipt_shading* out, void* stream) {
+    clear_error();
+    if (!s) return fail(FIPT_EINVAL, "scene is NULL");
+    int rc = check_points(pts, "pts");
+    if (rc) return rc;
+    if ((rc = check_bake_params(p))) return rc;
+    if (!out || !out->planes) return fail(FIPT_EINVAL, "out is NULL");
+    if (out->stride < pts->n)
+        return fail(FIPT_EINVAL, "out->stride (%lld) < n (%lld)", (long long)out->stride,
+                    (long long)pts->n);
+    if (!r || !r->material) return fail(FIPT_EINVAL, "refine params or material grid is NULL");
+    if (r->res < 2 || r->res > 1024) return fail(FIPT_EINVAL, "res must be in [2, 1024]");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(r->bmin[k]) || !std::isfinite(r->bmax[k]) || !(r->bmax[k] > r->bmin[k]))
+            return fail(FIPT_EINVAL, "the material box must be finite with bmin < bmax");
+    if (!std::isfinite(r->sigma_diffuse)) return fail(FIPT_EINVAL, "sigma_diffuse is not finite");
+    if (r->max_vertices < 1 || r->max_vertices > 16)
+        return fail(FIPT_EINVAL, "max_vertices must be in [1, 16], got %d", r->max_vertices);
+    if (r->flags & ~FIPT_REFINE_BSDF_ONLY) return fail(FIPT_EINVAL, "unknown flags %d", r->flags);
+    if (s->cache_kind == FIPT_CACHE_VOXEL)
+        return fail(FIPT_EINVAL, "the refinement takes a per-triangle or per-vertex cache, not a voxel cache");
+    DeviceGuard g(s->device);
+    if (g.rc) return g.rc;
+    BakeLaunch b = make_bake_launch(s, pts, p, out);
+    hipStream_t st = (hipStream_t)stream;
+    // refinements of one scene run in call order (they rewrite its emitter
+    // list); the work counters come from the bake's slot ring
+    std::lock_guard<std::mutex> rk(s->refine_mu);
+    hipError_t e = hipStreamWaitEvent(st, s->refine_done, 0);
+    if (e != hipSuccess) return fail(FIPT_EHIP, "refine wait: %s", hipGetErrorString(e));
+    rc = launch_emitter_list(s->d_rad, s->d_leaf_of, s->n_tris, s->d_emit_blocks, s->d_emit,
+                             s->d_emit + s->n_tris, stream);
+    if (rc) return rc;
+    RefineLaunch rl;
+    rl.grid = r->material;
+    rl.res = r->res;
+    for (int k = 0; k < 3; ++k) {
+        rl.bmin[k] = r->bmin[k];
+        rl.bmax[k] = r->bmax[k];
+    }
+    rl.sigma_diffuse = r->sigma_diffuse;
+    rl.max_vertices = r->max_vertices;
+    rl.flags = r->flags;
+    rl.emit = s->d_emit;
+    rl.n_emit = s->d_emit + s->n_tris;
+    {
+        std::lock_guard<std::mutex> lk(s->slot_mu);
+        const int k = s->next_slot;
+        s->next_slot = (k + 1) % kBakeSlots;
+        e = hipStreamWaitEvent(st, s->slot_done[k], 0);
+        if (e != hipSuccess) return fail(FIPT_EHIP, "refine slot wait: %s", hipGetErrorString(e));
+        rc = launch_refine(b, rl, s->d_counters + (size_t)k * kXcdCount, stream);
+        if (rc) return rc;
+        e = hipEventRecord(s->slot_done[k], st);
+        if (e != hipSuccess) return fail(FIPT_EHIP, "refine slot event: %s", hipGetErrorString(e));
+    }
+    e = hipEventRecord(s->refine_done, st);
+    if (e != hipSuccess) return fail(FIPT_EHIP, "refine event: %s", hipGetErrorString(e));
+    return FIPT_OK;
 }
 
 namespace {

@@ -398,5 +398,56 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// ---- work distribution shared by the persistent bake kernels ---------------
+// Lobe of flattened sample q: 0 for the first spp_d (diffuse) samples, then
+// 1 + (q - spp_d) / spp_s.  The quotient is below 17 and r < 2^20 (spp <=
+// 65536, K <= 16), so the float estimate is off by at most one, at exact
+// multiples, and the correction makes it exact.
+__device__ __forceinline__ int lobe_of(int q, int spp_d, int spp_s) {
+    if (q < spp_d) return 0;
+    const int r = q - spp_d;
+    int l = (int)((float)r * __builtin_amdgcn_rcpf((float)spp_s));
+    if ((int)__umul24((unsigned)l, (unsigned)spp_s) > r) --l;
+    else if ((int)__umul24((unsigned)(l + 1), (unsigned)spp_s) <= r) ++l;
+    return 1 + l;
+}
+
+// Output plane of accumulator slot j: slot 0..2 -> Ld; slot 3 + 6k + c ->
+// Ls0 level k; slot 3 + 6k + 3 + c -> Ls1 level k.
+__device__ __forceinline__ int slot_plane(int j, int K) {
+    if (j < 3) return j;
+    const int r = j - 3, k = r / 6, c = r - 6 * k;
+    return c < 3 ? 3 + 3 * k + c : 3 + 3 * K + 3 * k + (c - 3);
+}
+
+
+// The point index is the same in every lane of a wavefront; saying so lets
+// the compiler keep the point's data in scalar registers.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Dynamic point hand-out.  The points of a launch are cut into kXcdCount
+// contiguous shares, one per XCD, each with its own counter: a wavefront
+// takes the next point of its XCD's share, so each XCD's L2 sees one
+// contiguous run of points; when that share is used up it takes points from
+// the other shares in turn.  Returns -1 once every share is exhausted
+// (`tried` counts the shares found empty).  Each point's result does not
+// depend on which wavefront bakes it.
+__device__ __forceinline__ int64_t next_point(int32_t* counters, int home, int& tried,
+                                              int64_t total, int lane) {
+    while (tried < kXcdCount) {
+        const int x = (home + tried) % kXcdCount;
+        int32_t grab = 0;
+        if (lane == 0) grab = atomicAdd(counters + x, 1);
+        const int64_t p = total * x / kXcdCount + __builtin_amdgcn_readfirstlane(grab);
+        if (p < total * (x + 1) / kXcdCount) return p;
+        ++tried;
+    }
+    return -1;
+}
+
 }  // namespace dev
 }  // namespace fipt

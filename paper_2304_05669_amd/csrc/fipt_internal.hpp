@@ -186,6 +186,25 @@ struct BakeLaunch {
 // launcher zeroes them on `stream` before the kernel.
 int launch_bake(const BakeLaunch& b, int32_t* counters_dev, uint64_t* stats, void* stream);
 
+// Stage-3 refinement (fipt_refine): the material grid, the path rules and
+// the scene's emitter list (leaf positions, count on the device).
+struct RefineLaunch {
+    const float* grid;    // [5][res^3]
+    int32_t res;
+    float bmin[3], bmax[3];
+    float sigma_diffuse;
+    int32_t max_vertices;
+    int32_t flags;
+    const int32_t* emit;
+    const int32_t* n_emit;
+};
+// Emitters (some channel of emission > 0) in ascending original index into
+// list (leaf positions) and their number into *count; blocks: one int32 per
+// 256 triangles of scratch.
+int launch_emitter_list(const TriRad* rad, const int32_t* leaf_of, int64_t n_tris, int32_t* blocks,
+                        int32_t* list, int32_t* count, void* stream);
+int launch_refine(const BakeLaunch& b, const RefineLaunch& r, int32_t* counters, void* stream);
+
 // MI355X has 8 XCDs (dies, each with its own L2); the dispatcher places
 // workgroup i of a launch on XCD i % kXcdCount.
 constexpr int kXcdCount = 8;
@@ -275,6 +294,11 @@ struct fipt_scene_s {
     int32_t vox_res = 0;
     float vox_lo[3] = {0, 0, 0}, vox_scale[3] = {0, 0, 0};
     int32_t* d_order = nullptr;    // leaf position -> original triangle
+    int32_t* d_leaf_of = nullptr;  // original triangle -> leaf position
+    int32_t* d_emit = nullptr;     // [T + 1] emitters' leaf positions (refinement), count last
+    int32_t* d_emit_blocks = nullptr;  // [ceil(T / 256)] scan scratch of the emitter list
+    hipEvent_t refine_done = nullptr;  // last refinement's completion (it rewrites d_emit)
+    std::mutex refine_mu;
     int32_t* d_tri_idx = nullptr;  // original [T][3] vertex indices
     int32_t* d_counters = nullptr;  // [kBakeSlots][kXcdCount]
     hipEvent_t slot_done[kBakeSlots] = {};

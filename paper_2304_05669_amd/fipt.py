@@ -29,7 +29,7 @@ EXPORTS = (
     "fipt_last_error", "fipt_version", "fipt_scene_create", "fipt_scene_set_radiance",
     "fipt_scene_set_emission", "fipt_scene_info_get", "fipt_bvh_validate", "fipt_scene_destroy",
     "fipt_cast_rays", "fipt_gen_points",
-    "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_render_loss",
+    "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_refine", "fipt_render_loss",
     "fipt_render_loss_noalloc", "fipt_render_loss_masked", "fipt_scale_by", "fipt_hbm_stream",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
@@ -66,6 +66,15 @@ class BakeParams(C.Structure):
     _fields_ = [("spp_d", C.c_int32), ("spp_s", C.c_int32), ("n_levels", C.c_int32),
                 ("sigma", C.c_float * MAX_LEVELS), ("seed", C.c_uint64), ("ray_eps", C.c_float),
                 ("flags", C.c_int32)]
+
+
+class RefineParams(C.Structure):
+    _fields_ = [("material", C.c_void_p), ("res", C.c_int32), ("bmin", C.c_float * 3),
+                ("bmax", C.c_float * 3), ("sigma_diffuse", C.c_float), ("max_vertices", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+REFINE_BSDF_ONLY = 1
 
 
 class SceneInfo(C.Structure):
@@ -114,6 +123,8 @@ def lib():
         "fipt_lobe_uniforms": (C.c_int, [_u64, _i64, _i64, _i32, _i32, _vp, _vp]),
         "fipt_gen_points": (C.c_int, [_vp, C.POINTER(Camera), _i32, C.POINTER(Points), _vp]),
         "fipt_bake": (C.c_int, [_vp, C.POINTER(Points), C.POINTER(BakeParams), C.POINTER(Shading), _vp]),
+        "fipt_refine": (C.c_int, [_vp, C.POINTER(Points), C.POINTER(BakeParams), C.POINTER(RefineParams),
+                                  C.POINTER(Shading), _vp]),
         "fipt_bake_traversal_stats": (C.c_int, [_vp, C.POINTER(Points), C.POINTER(BakeParams),
                                                 C.POINTER(Shading), _vp, _vp]),
         "fipt_render_loss": (C.c_int, [C.POINTER(Shading), _i64, _i32, _f32p, _vp, _i64, _vp, _i64,
@@ -371,6 +382,37 @@ def fipt_bake(scene: Scene, planes: torch.Tensor, tri: torch.Tensor, spp_d: int,
     else:
         _check(lib().fipt_bake_traversal_stats(scene.handle, C.byref(pts), C.byref(par), C.byref(sh),
                                                _dev(stats, torch.int64, "stats"), _stream()))
+    return out
+
+
+def fipt_refine(scene: Scene, planes: torch.Tensor, tri: torch.Tensor, spp_d: int, spp_s: int,
+                sigma, seed: int, material: torch.Tensor, bmin, bmax, sigma_diffuse: float = 0.6,
+                max_vertices: int = 8, flags: int = 0, ray_eps: float = 1e-4,
+                out: torch.Tensor = None):
+    """Refined shading terms (stage 3): the bake's samples, paths grown
+    through glossy hits of the material grid [5, R, R, R] (a_r, a_g, a_b,
+    sigma, m) over the box [bmin, bmax]; returns [3 + 6K, n] float32."""
+    K = len(sigma)
+    n = planes.shape[1]
+    R = material.shape[-1]
+    _need(material, (5, R, R, R), "material")
+    if out is None:
+        out = torch.empty((3 + 6 * K, n), dtype=torch.float32, device=planes.device)
+    if out.shape[0] != 3 + 6 * K or out.shape[1] < n:
+        raise ValueError("out must be [3 + 6K, >= n]")
+    pts = make_points(planes, tri)
+    par = make_params(spp_d, spp_s, sigma, seed, ray_eps)
+    rp = RefineParams()
+    rp.material = _dev(material, torch.float32, "material")
+    rp.res = int(R)
+    rp.bmin = (C.c_float * 3)(*[float(v) for v in bmin])
+    rp.bmax = (C.c_float * 3)(*[float(v) for v in bmax])
+    rp.sigma_diffuse = float(sigma_diffuse)
+    rp.max_vertices = int(max_vertices)
+    rp.flags = int(flags)
+    sh = Shading(_dev(out, torch.float32, "out"), out.shape[1])
+    _check(lib().fipt_refine(scene.handle, C.byref(pts), C.byref(par), C.byref(rp), C.byref(sh),
+                             _stream()))
     return out
 
 

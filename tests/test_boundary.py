@@ -36,6 +36,7 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_scene_create(None, 3, None, 1, 0, None, C.byref(out)) == fipt.EINVAL
     assert b"NULL" in L.fipt_last_error()
     assert L.fipt_bake(None, None, None, None, None) == fipt.EINVAL
+    assert L.fipt_refine(None, None, None, None, None, None) == fipt.EINVAL
     assert L.fipt_render_loss(None, 10, 6, None, None, 10, None, 10, 0, None, None, 10, None, 10,
                               None) == fipt.EINVAL
     sig = (C.c_float * 2)(0.5, 0.2)
