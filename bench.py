@@ -937,8 +937,7 @@ def main():
                 "unit": "GB/s", "frac": grid_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                 "ms": ms, "bytes_per_launch": grid_bytes, "kernel": kn}
         for kname, ms, kn in (("gather", t_gather, "k_grid_gather"),
-                              ("adjoint", t_scatter, "k_scatter_records + k_scatter_segments + "
-                                                     "k_scatter_grid"))}
+                              ("adjoint", t_scatter, "k_grid_adjoint + k_grid_adjoint_combine"))}
 
     flush = torch.ones((1 << 27,), dtype=torch.float32, device=dev)      # 512 MB
     t_loss_cold = loss_timing(shading, mat, obs, sc.sigma, flush=flush)

@@ -429,11 +429,19 @@ int fipt_grid_gather(const float* grid, int32_t channels, int32_t res,
                      void* stream);
 
 /* Adjoint of fipt_grid_gather for a fixed point set.  The plan sorts the
- * points by grid cell once (host positions pos_host[3][n]) so the adjoint
- * sums every node's contributions in a fixed order: results are bitwise
- * reproducible, with no atomics.  The plan owns device memory.
- * 1 <= n < 2^31, 2 <= res <= 1024; FIPT_EINVAL also when the sorted points
- * make 2^28 or more segments (runs of at most 48 points of one cell). */
+ * points once (host positions pos_host[3][n]) by node brick (8 x 8 x 8
+ * nodes) and grid cell, and cuts each cell's points into columns of at most
+ * 8; the adjoint sums each column in double in point order and adds the
+ * column sums into the nodes as 64-bit fixed-point integers, with a scale
+ * per work unit (at most 256 columns of one brick) and channel fixed by the
+ * unit's largest column sum, so every node's sum is independent of the order
+ * of the additions; the units of one brick are added in double in unit
+ * order.  Results are bitwise reproducible.  The rounding of a column sum is
+ * at most 2^-63 of (columns in its unit) x (largest column sum in the unit).
+ * The plan owns device memory (16 bytes per point, 8 per column, 16 per unit
+ * and 32 KB per unit of a brick of several).
+ * 1 <= n < 2^31, 2 <= res <= 1024; FIPT_EINVAL also when the columns number
+ * 2^31 or more. */
 int fipt_grid_plan_create(const float* pos_host, int64_t n, int32_t res,
                           const float* bmin_host, const float* bmax_host,
                           int32_t device, fipt_grid_plan* out);
@@ -441,8 +449,9 @@ int fipt_grid_plan_destroy(fipt_grid_plan plan);
 
 /* grad_grid[channels][res^3] = sum over points of trilinear weight times
  * grad_points[channels][gp_stride] (device), for the plan's points.
- * Overwrites grad_grid entirely.  Uses the plan's scratch buffers, so calls
- * with the same plan must not overlap (one stream, or ordered streams). */
+ * Overwrites grad_grid entirely; a node that a non-finite gradient reaches
+ * is NaN.  Uses the plan's scratch, so calls with the same plan must not
+ * overlap (one stream, or ordered streams). */
 int fipt_grid_scatter(fipt_grid_plan plan, const float* grad_points, int32_t channels,
                       int64_t gp_stride, float* grad_grid, void* stream);
 

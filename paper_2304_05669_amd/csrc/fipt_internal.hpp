@@ -246,24 +246,41 @@ int launch_grid_gather(const float* grid, int32_t C, int32_t R, const float* bmi
                        const float* bmax, const float* pos, int64_t pos_stride, int64_t n,
                        float* out, int64_t out_stride, void* stream);
 
+// The grid adjoint works on node bricks of kBrickX x kBrickY x kBrickZ
+// nodes.  A point's home brick holds the lower corner of its cell; its points
+// are cut into columns of at most kColumnMax points of one cell, and a brick
+// lists its home columns and the columns of the lower neighbours' cells whose
+// upper corners are its nodes (halo columns).  A brick's column list is cut
+// into work units of at most kAdjUnit columns, one workgroup each; a brick of
+// several units has its units' node sums combined in unit order.
+constexpr int kBrickX = 8, kBrickY = 8, kBrickZ = 8;
+constexpr int kBrickNodes = kBrickX * kBrickY * kBrickZ;
+#ifndef FIPT_COLUMN_MAX
+#define FIPT_COLUMN_MAX 8
+#endif
+constexpr int kColumnMax = FIPT_COLUMN_MAX;
+#ifndef FIPT_ADJ_UNIT
+#define FIPT_ADJ_UNIT 256
+#endif
+constexpr int kAdjUnit = FIPT_ADJ_UNIT;
+
 struct GridPlanDev {
     int32_t res;
     int64_t n_points;
     float bmin[3], bmax[3];
-    int32_t* perm;          // [n] points sorted by cell (stable)
-    int32_t* seg_start;     // [n_seg + 1] segment ranges into perm (<= 48 points each)
-    int32_t* seg_cell;      // [n_seg] segment's linear cell index (x fastest, res-1 per axis)
-    int64_t n_seg;
-    int32_t* cell_seg;      // [n_cell + 1] ranges of each occupied cell's segments
-    int64_t n_cell;
-    uint64_t* node_mask;    // [ceil(res^3 / 64)] bit v & 63 of word v >> 6: node v is active
-    int32_t* node_rank;     // [ceil(res^3 / 64)] active nodes before each mask word
-    int32_t* node_start;    // [n_act + 1] ranges into node_src, active nodes in index order
-    int32_t* node_src;      // [entries] (segment index << 3) | corner, 8 per segment
-    int64_t n_act;
-    float* pos;             // [3][n_points] positions in sorted (perm) order
-    double* seg_part;       // [8 corners][n_seg][channels] scratch (room for 8 channels)
-    float* gp_rec;          // [n_points][8] scratch: per-point gradient records
+    int32_t nb[3];          // bricks per axis, ceil(res / brick extent)
+    int64_t n_bricks;
+    float4* pts;            // [n_points] (x, y, z, point index as int bits), by (home brick, cell, index)
+    int2* cols;             // [n_cols] (first point in pts, count | (lx+1) << 5 | (ly+1) << 11 | (lz+1) << 17),
+                            // (lx, ly, lz) the cell's position relative to the brick's first node, >= -1
+    int64_t n_cols;
+    int4* units;            // [n_units] (brick, first column, end column, scratch slot or -1 when the
+                            // unit is its brick's only one), every brick at least once, most columns first
+    int64_t n_units;
+    int4* multi;            // [n_multi] (brick, first scratch slot, unit count, 0): bricks of several units
+    int64_t n_multi;
+    double* part;           // [n_slots][8][kBrickNodes] node sums of the units of those bricks
+    int64_t n_slots;
 };
 int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_t gp_stride,
                         float* grad_grid, void* stream);

@@ -1,17 +1,16 @@
 // Host set-up of the deterministic adjoint of the trilinear material grid
 // (fipt_grid_plan_*) and the scatter entry point.
 //
-// The plan sorts the points by grid cell once and cuts every cell's run into
-// segments of at most 48 points.  The adjoint then runs with no atomics:
-// the per-point gradient planes are first copied into 32-byte records (so
-// the cell-ordered pass reads one line per point, not one per channel);
-// every segment sums weight * gradient of its points into the eight corners
-// of its cell (points in index order); and every grid node sums, for each
-// occupied cell it is a corner of (in cell order), that cell's segment
-// partials (in order), writing zero where no cell contributes.  The plan
-// lists each node's contributions as (segment, corner) pairs, and a node
-// finds its list through a bit mask of the active nodes with a prefix count
-// per 64 nodes.  The result is bitwise reproducible.
+// The plan sorts the points once by home brick (the node brick that holds
+// the lower corner of the point's cell), cell and index, and cuts every
+// cell's run into columns of at most kColumnMax points.  A brick's column
+// list holds its home columns and the halo columns: those of cells in the
+// lower neighbouring bricks whose upper corners are nodes of this brick.
+// The adjoint runs one workgroup per brick: every thread sums one column in
+// double in point order, and the column sums are added into the brick's
+// nodes as 64-bit fixed-point integers whose scale the brick derives from
+// its largest column sum, so the node sums do not depend on the order of
+// the additions; the result is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,9 +33,7 @@ namespace {
 
 void plan_free(fipt_grid_plan p) {
     if (!p) return;
-    void* ptrs[] = {p->d.perm,       p->d.seg_start, p->d.seg_cell, p->d.cell_seg,
-                    p->d.node_mask,  p->d.node_rank, p->d.node_start, p->d.node_src,
-                    p->d.pos,        p->d.seg_part,  p->d.gp_rec};
+    void* ptrs[] = {p->d.pts, p->d.cols, p->d.units, p->d.multi, p->d.part};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -75,11 +72,14 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(FIPT_EINVAL, "device %d not available", device);
     // cell of every point, exactly as the device computes it
-    const int64_t cr = res - 1;
-    std::vector<std::pair<int64_t, int32_t>> key(n);
+    const int64_t B[3] = {kBrickX, kBrickY, kBrickZ};
+    int64_t nb[3];
+    for (int k = 0; k < 3; ++k) nb[k] = (res + B[k] - 1) / B[k];
     double scale[3];
     for (int k = 0; k < 3; ++k) scale[k] = (double)(res - 1) / ((double)bmax[k] - (double)bmin[k]);
     const double top = (double)(res - 1);
+    // key: home brick (x fastest) << 40 | cell within the brick << 31 | point
+    std::vector<uint64_t> key(n);
     for (int64_t p = 0; p < n; ++p) {
         int64_t idx[3];
         for (int k = 0; k < 3; ++k) {
@@ -88,66 +88,94 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
             const double u = std::fmin(std::fmax(((double)x - (double)bmin[k]) * scale[k], 0.0), top);
             idx[k] = std::min<int64_t>((int64_t)std::floor(u), res - 2);
         }
-        key[p] = {idx[0] + cr * (idx[1] + cr * idx[2]), (int32_t)p};
+        const uint64_t hb = (uint64_t)(idx[0] / B[0] + nb[0] * (idx[1] / B[1] + nb[1] * (idx[2] / B[2])));
+        const uint64_t lc = (uint64_t)(idx[0] % B[0] + B[0] * (idx[1] % B[1] + B[1] * (idx[2] % B[2])));
+        key[p] = hb << 40 | lc << 31 | (uint64_t)p;
     }
     std::sort(key.begin(), key.end());
-    // segments: runs of at most kSegmentMax points of one cell, so a cell
-    // seen by many pixels does not serialise on one thread
-    constexpr int64_t kSegmentMax = 48;
-    std::vector<int32_t> perm(n), seg_start, seg_cell, cell_seg, cell_id;
-    for (int64_t q = 0; q < n; ++q) {
-        perm[q] = key[q].second;
-        const bool new_cell = q == 0 || key[q].first != key[q - 1].first;
-        if (new_cell || q - seg_start.back() >= kSegmentMax) {
-            if (new_cell) {
-                cell_seg.push_back((int32_t)seg_start.size());
-                cell_id.push_back((int32_t)key[q].first);
+    // columns: runs of at most kColumnMax points of one cell; each goes to
+    // its home brick and to the up to seven bricks above it whose first
+    // node is the cell's upper corner on some axis
+    const int64_t n_bricks = nb[0] * nb[1] * nb[2];
+    struct Col {
+        int64_t brick;
+        int32_t start, word;
+    };
+    std::vector<Col> cols;
+    cols.reserve(n / 2 + 16);
+    for (int64_t q = 0; q < n;) {
+        const uint64_t cell_key = key[q] >> 31;
+        int64_t e = q + 1;
+        while (e < n && (key[e] >> 31) == cell_key) ++e;
+        const int64_t hb = (int64_t)(cell_key >> 9);
+        const int64_t lc = (int64_t)(cell_key & 511);
+        const int64_t l[3] = {lc % B[0], (lc / B[0]) % B[1], lc / (B[0] * B[1])};
+        const int64_t h[3] = {hb % nb[0], (hb / nb[0]) % nb[1], hb / (nb[0] * nb[1])};
+        for (int64_t a = q; a < e; a += kColumnMax) {
+            const int32_t cnt = (int32_t)std::min<int64_t>(kColumnMax, e - a);
+            for (int t = 0; t < 8; ++t) {
+                int64_t tb[3], tl[3];
+                bool ok = true;
+                for (int k = 0; k < 3; ++k) {
+                    const int d = (t >> k) & 1;
+                    // shifting to the next brick on axis k needs the cell on
+                    // the brick's last layer and a brick above
+                    if (d && (l[k] != B[k] - 1 || h[k] + 1 >= nb[k])) ok = false;
+                    tb[k] = h[k] + d;
+                    tl[k] = l[k] - d * B[k];
+                }
+                if (!ok) continue;
+                const int64_t brick = tb[0] + nb[0] * (tb[1] + nb[1] * tb[2]);
+                const int32_t word = cnt | (int32_t)(tl[0] + 1) << 5 | (int32_t)(tl[1] + 1) << 11 |
+                                     (int32_t)(tl[2] + 1) << 17;
+                cols.push_back({brick, (int32_t)a, word});
             }
-            seg_start.push_back((int32_t)q);
-            seg_cell.push_back((int32_t)key[q].first);
         }
+        q = e;
     }
-    seg_start.push_back((int32_t)n);
-    cell_seg.push_back((int32_t)seg_cell.size());
-    const int64_t S = (int64_t)seg_cell.size();
-    const int64_t M = (int64_t)cell_id.size();
-    // node lists index their entries with 32 bits: eight per segment, each
-    // entry holding the segment index and the corner in 32 bits
-    if (8 * S >= (int64_t(1) << 31))
-        return fail(FIPT_EINVAL, "%lld segments: too many for one plan", (long long)S);
-    std::vector<std::pair<int64_t, int32_t>> nk;
-    nk.reserve(8 * M);
-    for (int64_t m = 0; m < M; ++m) {
-        const int64_t c = cell_id[m];
-        const int64_t i = c % cr, j = (c / cr) % cr, k = c / (cr * cr);
-        for (int corner = 0; corner < 8; ++corner) {
-            const int64_t ni = i + (corner & 1), nj = j + ((corner >> 1) & 1), nkk = k + (corner >> 2);
-            nk.push_back({ni + res * (nj + (int64_t)res * nkk), (int32_t)((m << 3) | corner)});
+    if ((int64_t)cols.size() >= (int64_t(1) << 31))
+        return fail(FIPT_EINVAL, "%lld columns: too many for one plan", (long long)cols.size());
+    // every brick's columns together, in cell order (halo cells first on an
+    // axis), then point order
+    std::stable_sort(cols.begin(), cols.end(), [](const Col& a, const Col& b) {
+        if (a.brick != b.brick) return a.brick < b.brick;
+        return (a.word >> 5) < (b.word >> 5);  // (lz, ly, lx), each + 1 in six bits
+    });
+    std::vector<int32_t> brick_col(n_bricks + 1, 0);
+    for (const Col& c : cols) ++brick_col[c.brick + 1];
+    for (int64_t b = 0; b < n_bricks; ++b) brick_col[b + 1] += brick_col[b];
+    std::vector<int2> cword(cols.size());
+    for (size_t c = 0; c < cols.size(); ++c) cword[c] = make_int2(cols[c].start, cols[c].word);
+    // work units: every brick's columns in runs of at most kAdjUnit (a brick
+    // with no columns is one empty unit, which writes zeros)
+    std::vector<int4> units, multi;
+    int32_t slots = 0;
+    for (int64_t b = 0; b < n_bricks; ++b) {
+        const int32_t c0 = brick_col[b], c1 = brick_col[b + 1];
+        const int32_t nu = std::max<int32_t>(1, (c1 - c0 + kAdjUnit - 1) / kAdjUnit);
+        if (nu == 1) {
+            units.push_back(make_int4((int32_t)b, c0, c1, -1));
+            continue;
         }
+        multi.push_back(make_int4((int32_t)b, slots, nu, 0));
+        for (int32_t u = 0; u < nu; ++u)
+            units.push_back(make_int4((int32_t)b, c0 + u * kAdjUnit,
+                                      std::min<int32_t>(c1, c0 + (u + 1) * kAdjUnit), slots + u));
+        slots += nu;
     }
-    std::sort(nk.begin(), nk.end());
-    const int64_t n_nodes = (int64_t)res * res * res;
-    const int64_t n_words = (n_nodes + 63) / 64;
-    std::vector<uint64_t> node_mask(n_words, 0);
-    // each node's list: for every occupied cell it is a corner of (cell
-    // order), that cell's segments (segment order), as (segment << 3) | corner
-    std::vector<int32_t> node_rank(n_words, 0), node_start, node_src;
-    node_src.reserve(8 * S);
-    for (size_t e = 0; e < nk.size(); ++e) {
-        if (e == 0 || nk[e].first != nk[e - 1].first) {
-            node_start.push_back((int32_t)node_src.size());
-            node_mask[nk[e].first >> 6] |= uint64_t(1) << (nk[e].first & 63);
-        }
-        const int32_t m = nk[e].second >> 3, corner = nk[e].second & 7;
-        for (int32_t g = cell_seg[m]; g < cell_seg[m + 1]; ++g) node_src.push_back((g << 3) | corner);
+    // heaviest units first: the hardware deals workgroups to the XCDs in
+    // turn, and the long units start early instead of forming the tail
+    std::stable_sort(units.begin(), units.end(),
+                     [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
+    // points in sorted order: (x, y, z, index)
+    std::vector<float4> pts(n);
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t p = (int64_t)(key[q] & 0x7fffffffu);
+        int32_t pi = (int32_t)p;
+        float w;
+        std::memcpy(&w, &pi, 4);
+        pts[q] = make_float4(pos[p], pos[n + p], pos[2 * n + p], w);
     }
-    node_start.push_back((int32_t)node_src.size());
-    for (int64_t w = 1; w < n_words; ++w)
-        node_rank[w] = node_rank[w - 1] + __builtin_popcountll(node_mask[w - 1]);
-    // positions stored in sorted order: the adjoint reads them contiguously
-    std::vector<float> pcopy(3 * n);
-    for (int k = 0; k < 3; ++k)
-        for (int64_t q = 0; q < n; ++q) pcopy[k * n + q] = pos[k * n + perm[q]];
 
     int prev = -1;
     (void)hipGetDevice(&prev);
@@ -162,28 +190,27 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
         d.bmin[k] = bmin[k];
         d.bmax[k] = bmax[k];
     }
-    d.n_seg = S;
-    d.n_cell = M;
-    d.n_act = (int64_t)node_start.size() - 1;
+    for (int k = 0; k < 3; ++k) d.nb[k] = (int32_t)nb[k];
+    d.n_bricks = n_bricks;
+    d.n_cols = (int64_t)cols.size();
+    d.n_units = (int64_t)units.size();
+    d.n_multi = (int64_t)multi.size();
+    d.n_slots = slots;
     int rc;
-    if ((rc = upload(&d.perm, perm, &p->bytes)) || (rc = upload(&d.seg_start, seg_start, &p->bytes)) ||
-        (rc = upload(&d.seg_cell, seg_cell, &p->bytes)) || (rc = upload(&d.cell_seg, cell_seg, &p->bytes)) ||
-        (rc = upload(&d.node_mask, node_mask, &p->bytes)) ||
-        (rc = upload(&d.node_rank, node_rank, &p->bytes)) ||
-        (rc = upload(&d.node_start, node_start, &p->bytes)) ||
-        (rc = upload(&d.node_src, node_src, &p->bytes)) || (rc = upload(&d.pos, pcopy, &p->bytes))) {
+    if ((rc = upload(&d.pts, pts, &p->bytes)) || (rc = upload(&d.cols, cword, &p->bytes)) ||
+        (rc = upload(&d.units, units, &p->bytes)) || (rc = upload(&d.multi, multi, &p->bytes))) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return rc;
     }
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d.seg_part), sizeof(double) * 64 * std::max<int64_t>(S, 1));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d.gp_rec), sizeof(float) * 8 * n);
+    const size_t part_bytes = sizeof(double) * 8 * kBrickNodes * std::max<int64_t>(slots, 1);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d.part), part_bytes);
     if (e != hipSuccess) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
-        return fail(FIPT_ENOMEM, "hipMalloc partials: %s", hipGetErrorString(e));
+        return fail(FIPT_ENOMEM, "hipMalloc unit sums: %s", hipGetErrorString(e));
     }
-    p->bytes += (int64_t)(sizeof(double) * 64 * S + sizeof(float) * 8 * n);
+    p->bytes += (int64_t)part_bytes;
     if (prev >= 0) (void)hipSetDevice(prev);
     *out = p;
     return FIPT_OK;

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -245,124 +246,205 @@ __global__ __launch_bounds__(kBlock) void k_grid_gather(const float* __restrict_
     }
 }
 
-// Adjoint, pass 1: per segment, the eight corner sums of weight * gradient
-// over the segment's points (taken in index order), double.
+// Adjoint of the gather: one workgroup per work unit (at most kAdjUnit
+// columns of one node brick; a brick with no columns is one empty unit).  Each thread sums one column (at most
+// kColumnMax points of one cell, in point order) into the eight corners of
+// its cell in double.  The column sums meet in the brick's nodes as 64-bit
+// fixed-point integers: the unit's largest column sum m and its column count
+// n fix a per-channel scale 2^(62 - E) with n m < 2^E, so no sum of rounded
+// column sums can overflow, and integer addition makes the node sums
+// independent of the order in which threads add them.  A brick's only unit
+// writes the nodes; the units of a brick of several write their node sums in
+// double to the plan's scratch, and a second kernel adds them in unit order.
+// A node reached by a non-finite gradient is NaN.
+#ifndef FIPT_ADJ_BATCH
+#define FIPT_ADJ_BATCH 8
+#endif
+constexpr int kAdjBlock = kAdjUnit;
+constexpr int kAdjBatch = FIPT_ADJ_BATCH;   // point records requested together
+
 template <int C>
-__global__ __launch_bounds__(kBlock) void k_scatter_segments(GridPlanDev plan, GridFrame g) {
-    // eight consecutive threads share one segment, one per corner, so the
-    // segment's point loads are broadcast within each group of eight
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t m = tid >> 3;
-    const int corner = (int)(tid & 7);
-    if (m >= plan.n_seg) return;
-    double acc[C];
+__device__ __forceinline__ void column_sums(const GridPlanDev& P, const GridFrame& g, int2 col,
+                                            int ci, int cj, int ck, const float* __restrict__ gp,
+                                            int64_t gs, double (&s)[8][C]) {
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch) acc[ch] = 0.0;
-    const int64_t n = plan.n_points;
-    const float* pos = plan.pos;
-    // the plan fixed the cell (with the same float64 arithmetic)
-    const int32_t cid = plan.seg_cell[m];
-    const int cr = g.res - 1;
-    const int ci = cid % cr, cj = (cid / cr) % cr, ck = cid / (cr * cr);
-    const bool hx = corner & 1, hy = (corner >> 1) & 1, hz = corner >> 2;
-    // Positions are stored in sorted order; gradients come in point order.
-    // Eight points at a time: their loads are issued together (the gradient
-    // loads depend on the permutation), then added in point order.
-    const int32_t q1 = plan.seg_start[m + 1];
-    const float4* rec = reinterpret_cast<const float4*>(plan.gp_rec);
-    for (int32_t q = plan.seg_start[m]; q < q1; q += 8) {
-        int32_t pp[8];
+    for (int c = 0; c < 8; ++c)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) pp[u] = plan.perm[min(q + u, q1 - 1)];
-        double w[8];
-        float gv[8][8];
+        for (int ch = 0; ch < C; ++ch) s[c][ch] = 0.0;
+    // kAdjBatch point records of the column, then all their gradients, are
+    // requested before any is used (a short column's tail repeats its last
+    // point, whose lines are already on their way)
+    const int cnt = col.y & 31;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int32_t qq = min(q + u, q1 - 1);
-            const double fx = grid_u(g, pos[qq], 0) - ci;
-            const double fy = grid_u(g, pos[n + qq], 1) - cj;
-            const double fz = grid_u(g, pos[2 * n + qq], 2) - ck;
-            w[u] = (hx ? fx : 1 - fx) * (hy ? fy : 1 - fy) * (hz ? fz : 1 - fz);
-            const float4 r0 = rec[2 * (int64_t)pp[u]];
-            gv[u][0] = r0.x;
-            gv[u][1] = r0.y;
-            gv[u][2] = r0.z;
-            gv[u][3] = r0.w;
-            if (C > 4) {
-                const float4 r1 = rec[2 * (int64_t)pp[u] + 1];
-                gv[u][4] = r1.x;
-                gv[u][5] = r1.y;
-                gv[u][6] = r1.z;
-                gv[u][7] = r1.w;
-            }
+    for (int v0 = 0; v0 < kColumnMax; v0 += kAdjBatch) {
+        if (v0 >= cnt) break;
+        float4 r[kAdjBatch];
+#pragma unroll
+        for (int v = 0; v < kAdjBatch; ++v) r[v] = P.pts[col.x + min(v0 + v, cnt - 1)];
+        float gv[kAdjBatch][C];
+#pragma unroll
+        for (int v = 0; v < kAdjBatch; ++v) {
+            const int32_t pi = __float_as_int(r[v].w);
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) gv[v][ch] = gp[ch * gs + pi];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (q + u < q1) {
+        for (int v = 0; v < kAdjBatch; ++v) {
+            if (v0 + v < cnt) {
+                const double fx = grid_u(g, r[v].x, 0) - ci, fy = grid_u(g, r[v].y, 1) - cj,
+                             fz = grid_u(g, r[v].z, 2) - ck;
+                const double wx[2] = {1 - fx, fx}, wy[2] = {1 - fy, fy}, wz[2] = {1 - fz, fz};
 #pragma unroll
-                for (int ch = 0; ch < C; ++ch) acc[ch] += w[u] * (double)gv[u][ch];
-            }
-        }
-    }
-    double* dst = plan.seg_part + ((int64_t)corner * plan.n_seg + m) * C;
+                for (int c = 0; c < 8; ++c) {
+                    const double w = wx[c & 1] * wy[(c >> 1) & 1] * wz[c >> 2];
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch) dst[ch] = acc[ch];
-}
-
-// Adjoint, pass 0: per-point gradient planes into 32-byte records (channel
-// ch of point p at rec[8 p + ch]; unused channels zero), both sides
-// coalesced.
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_scatter_records(const float* __restrict__ gp, int64_t gs,
-                                                          int64_t n, float* __restrict__ rec) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= n) return;
-    float v[8];
-#pragma unroll
-    for (int ch = 0; ch < 8; ++ch) v[ch] = ch < C ? gp[ch * gs + p] : 0.0f;
-    float4* r = reinterpret_cast<float4*>(rec) + 2 * p;
-    r[0] = make_float4(v[0], v[1], v[2], v[3]);
-    r[1] = make_float4(v[4], v[5], v[6], v[7]);
-}
-
-// Adjoint, pass 2: per grid node, the partials of its (segment, corner)
-// list -- every occupied cell it is a corner of, in the plan's cell order,
-// and that cell's segments in order; nodes next to no occupied cell get
-// zero, so the whole gradient grid is written in one pass.  Four entries
-// and their partials are fetched together, then added in order.
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_scatter_grid(GridPlanDev plan, float* __restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t R = plan.res;
-    const int64_t plane = R * R * R;
-    if (v >= plane) return;
-    double s[C];
-#pragma unroll
-    for (int ch = 0; ch < C; ++ch) s[ch] = 0.0;
-    const uint64_t word = plan.node_mask[v >> 6];
-    const uint64_t bit = uint64_t(1) << (v & 63);
-    if (word & bit) {
-        const int64_t a = plan.node_rank[v >> 6] + __popcll(word & (bit - 1));
-        const int32_t e0 = plan.node_start[a], e1 = plan.node_start[a + 1];
-        for (int32_t e = e0; e < e1; e += 4) {
-            double pv[4][C];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t src = plan.node_src[min(e + u, e1 - 1)];
-                const double* pp = plan.seg_part + ((int64_t)(src & 7) * plan.n_seg + (src >> 3)) * C;
-#pragma unroll
-                for (int ch = 0; ch < C; ++ch) pv[u][ch] = pp[ch];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (e + u < e1) {
-#pragma unroll
-                    for (int ch = 0; ch < C; ++ch) s[ch] += pv[u][ch];
+                    for (int ch = 0; ch < C; ++ch) s[c][ch] += w * (double)gv[v][ch];
                 }
+            }
+        }
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(kAdjBlock) void k_grid_adjoint(GridPlanDev P, GridFrame g,
+                                                            const float* __restrict__ gp, int64_t gs,
+                                                            float* __restrict__ out) {
+    __shared__ unsigned long long acc[C][kBrickNodes];
+    __shared__ unsigned bad[kBrickNodes];
+    __shared__ double wmax[kAdjBlock / 64][C];
+    __shared__ int expo[C];
+    const int tid = threadIdx.x;
+    const int4 unit = P.units[blockIdx.x];
+    const int64_t brick = unit.x;
+    const int bx = (int)(brick % P.nb[0]), by = (int)((brick / P.nb[0]) % P.nb[1]),
+              bz = (int)(brick / ((int64_t)P.nb[0] * P.nb[1]));
+    const int ox = bx * kBrickX, oy = by * kBrickY, oz = bz * kBrickZ;
+    for (int i = tid; i < kBrickNodes; i += kAdjBlock) {
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) acc[ch][i] = 0;
+        bad[i] = 0;
+    }
+    __syncthreads();
+    const int32_t ci = unit.y + tid;
+    const bool live = ci < unit.z;
+    double s[8][C];
+    double m[C];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) m[ch] = 0.0;
+    int lx = 0, ly = 0, lz = 0;
+    // the column's sums and their largest magnitude per channel over the
+    // corners this brick owns; non-finite sums flag their nodes
+    if (live) {
+        const int2 col = P.cols[ci];
+        lx = ((col.y >> 5) & 63) - 1;
+        ly = ((col.y >> 11) & 63) - 1;
+        lz = ((col.y >> 17) & 63) - 1;
+        column_sums<C>(P, g, col, ox + lx, oy + ly, oz + lz, gp, gs, s);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int nx = lx + (c & 1), ny = ly + ((c >> 1) & 1), nz = lz + (c >> 2);
+            if (nx < 0 || ny < 0 || nz < 0 || nx >= kBrickX || ny >= kBrickY || nz >= kBrickZ)
+                continue;
+            const int node = nx + kBrickX * (ny + kBrickY * nz);
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) {
+                const double a = fabs(s[c][ch]);
+                if (a <= DBL_MAX) m[ch] = fmax(m[ch], a);
+                else atomicOr(&bad[node], 1u << ch);
+            }
         }
     }
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch) out[ch * plane + v] = (float)s[ch];
+    for (int ch = 0; ch < C; ++ch) {
+        double v = m[ch];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        if ((tid & 63) == 0) wmax[tid >> 6][ch] = v;
+    }
+    __syncthreads();
+    if (tid < C) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kAdjBlock / 64; ++w) v = fmax(v, wmax[w][tid]);
+        int e = 0;
+        // every node sum is at most (columns) * v in magnitude
+        if (v > 0.0) (void)frexp(v * (double)(unit.z - unit.y), &e);
+        expo[tid] = e;
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int nx = lx + (c & 1), ny = ly + ((c >> 1) & 1), nz = lz + (c >> 2);
+            if (nx < 0 || ny < 0 || nz < 0 || nx >= kBrickX || ny >= kBrickY || nz >= kBrickZ)
+                continue;
+            const int node = nx + kBrickX * (ny + kBrickY * nz);
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) {
+                const double v = s[c][ch];
+                if (v != 0.0 && fabs(v) <= DBL_MAX) {
+                    const long long q = (long long)rint(ldexp(v, 62 - expo[ch]));
+                    atomicAdd(&acc[ch][node], (unsigned long long)q);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (unit.w >= 0) {
+        // one of several units of its brick: node sums in double, in the
+        // brick's scratch slot of this unit
+        double* dst = P.part + (int64_t)unit.w * 8 * kBrickNodes;
+        for (int i = tid; i < kBrickNodes; i += kAdjBlock) {
+            const unsigned f = bad[i];
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+                dst[ch * kBrickNodes + i] = (f >> ch) & 1 ? __longlong_as_double(0x7ff8000000000000ll)
+                                                          : ldexp((double)(long long)acc[ch][i], expo[ch] - 62);
+        }
+        return;
+    }
+    const int64_t R = P.res;
+    const int64_t plane = R * R * R;
+    for (int i = tid; i < kBrickNodes; i += kAdjBlock) {
+        const int x = ox + i % kBrickX, y = oy + (i / kBrickX) % kBrickY,
+                  z = oz + i / (kBrickX * kBrickY);
+        if (x >= R || y >= R || z >= R) continue;
+        const int64_t v = x + R * (y + R * (int64_t)z);
+        const unsigned f = bad[i];
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) {
+            const double d = ldexp((double)(long long)acc[ch][i], expo[ch] - 62);
+            out[ch * plane + v] = (f >> ch) & 1 ? __int_as_float(0x7fc00000) : (float)d;
+        }
+    }
+}
+
+// The bricks of several units: their units' node sums added in unit order,
+// one thread per (node, channel).
+template <int C>
+__global__ __launch_bounds__(kAdjBlock) void k_grid_adjoint_combine(GridPlanDev P,
+                                                                    float* __restrict__ out) {
+    constexpr int kPer = (kBrickNodes * C + kAdjBlock - 1) / kAdjBlock;   // workgroups per brick
+    const int4 mb = P.multi[blockIdx.x / kPer];
+    const int j = (blockIdx.x % kPer) * kAdjBlock + threadIdx.x;   // ch * kBrickNodes + node
+    if (j >= kBrickNodes * C) return;
+    const int ch = j / kBrickNodes, i = j % kBrickNodes;
+    const int64_t brick = mb.x;
+    const int x = (int)(brick % P.nb[0]) * kBrickX + i % kBrickX,
+              y = (int)((brick / P.nb[0]) % P.nb[1]) * kBrickY + (i / kBrickX) % kBrickY,
+              z = (int)(brick / ((int64_t)P.nb[0] * P.nb[1])) * kBrickZ + i / (kBrickX * kBrickY);
+    const int64_t R = P.res;
+    if (x >= R || y >= R || z >= R) return;
+    const double* src = P.part + (int64_t)mb.y * 8 * kBrickNodes + j;
+    double t = 0.0;
+    int u = 0;
+    for (; u + 4 <= mb.z; u += 4) {
+        const double a = src[(int64_t)u * 8 * kBrickNodes], b = src[(int64_t)(u + 1) * 8 * kBrickNodes],
+                     c = src[(int64_t)(u + 2) * 8 * kBrickNodes], d = src[(int64_t)(u + 3) * 8 * kBrickNodes];
+        t = (((t + a) + b) + c) + d;
+    }
+    for (; u < mb.z; ++u) t += src[(int64_t)u * 8 * kBrickNodes];
+    out[(int64_t)ch * R * R * R + x + R * (y + R * (int64_t)z)] = (float)t;
 }
 
 __global__ void k_scale_by(const float* __restrict__ x, int64_t n, const double* __restrict__ f,
@@ -482,36 +564,22 @@ int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_
                         float* grad_grid, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     const GridFrame g = make_frame(p.bmin, p.bmax, p.res);
-    if (C < 1 || C > 8) return fail(FIPT_EINVAL, "channels must be in [1, 8]");
-    if (p.n_seg > 0) {
-        const unsigned rb = (unsigned)((p.n_points + kBlock - 1) / kBlock);
-        const unsigned cb = (unsigned)((8 * p.n_seg + kBlock - 1) / kBlock);
-        switch (C) {
-#define FIPT_SC(N)                                                                                \
-    case N:                                                                                       \
-        hipLaunchKernelGGL(k_scatter_records<N>, dim3(rb), dim3(kBlock), 0, st, gp, gs, p.n_points, \
-                           p.gp_rec);                                                             \
-        hipLaunchKernelGGL(k_scatter_segments<N>, dim3(cb), dim3(kBlock), 0, st, p, g);            \
-        break
-            FIPT_SC(1); FIPT_SC(2); FIPT_SC(3); FIPT_SC(4);
-            FIPT_SC(5); FIPT_SC(6); FIPT_SC(7); FIPT_SC(8);
-#undef FIPT_SC
-        }
-        const int rc = check("grid_scatter segments");
-        if (rc) return rc;
-    }
-    const int64_t nodes = (int64_t)p.res * p.res * p.res;
-    const dim3 nb((unsigned)((nodes + kBlock - 1) / kBlock));
+    const dim3 nu((unsigned)p.n_units);
+    const unsigned per = (unsigned)((kBrickNodes * C + kAdjBlock - 1) / kAdjBlock);
     switch (C) {
-#define FIPT_SG(N)                                                                           \
-    case N:                                                                                  \
-        hipLaunchKernelGGL(k_scatter_grid<N>, nb, dim3(kBlock), 0, st, p, grad_grid);        \
+#define FIPT_SG(N)                                                                             \
+    case N:                                                                                    \
+        hipLaunchKernelGGL(k_grid_adjoint<N>, nu, dim3(kAdjBlock), 0, st, p, g, gp, gs, grad_grid); \
+        if (p.n_multi > 0)                                                                     \
+            hipLaunchKernelGGL(k_grid_adjoint_combine<N>, dim3((unsigned)(p.n_multi * per)), dim3(kAdjBlock), 0, st, p, grad_grid); \
         break
         FIPT_SG(1); FIPT_SG(2); FIPT_SG(3); FIPT_SG(4);
         FIPT_SG(5); FIPT_SG(6); FIPT_SG(7); FIPT_SG(8);
 #undef FIPT_SG
+        default:
+            return fail(FIPT_EINVAL, "channels must be in [1, 8]");
     }
-    return check("grid_scatter nodes");
+    return check("grid_adjoint");
 }
 
 }  // namespace fipt

@@ -253,6 +253,109 @@ def test_grid_scatter_writes_every_node(n, C, R):
     assert_close_rel(got, want.reshape(C, -1), 1e-5, what="grid scatter")
 
 
+def test_grid_scatter_dynamic_range_per_brick():
+    """The fixed-point node sums take their scale per 8^3-node brick from the
+    brick's own largest column sum: gradients of 1e-30 in one half of the
+    grid and 1e+30 in the other both come out to float rounding plus 2^-40
+    of the largest contribution magnitude near the node's brick, so the
+    small half is not lost to the large one."""
+    R = 40
+    bmin = np.zeros(3, np.float32)
+    bmax = np.ones(3, np.float32)
+    rng = np.random.default_rng(21)
+    n = 60000
+    pos = rng.uniform(0, 1, size=(3, n)).astype(np.float32)
+    gp = rng.standard_normal((3, n))
+    gp *= np.where(pos[0] < 0.5, 1e-30, 1e30)[None, :]
+    gp[2, ::7] *= 1e-6  # small and large values inside one brick
+    gp = gp.astype(np.float32)
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    got = plan.scatter(_t(gp)).cpu().numpy().astype(np.float64).reshape(3, R, R, R)
+    want = orr.grid_scatter(gp, pos, bmin, bmax, R).reshape(3, R, R, R)
+    absw = orr.grid_scatter(np.abs(gp), pos, bmin, bmax, R).reshape(3, R, R, R)
+    # a brick's largest column sum is at most the largest absw over its
+    # nodes; 2^-40 of it leaves room for 2^22 columns per brick
+    B = 8
+    step = np.zeros_like(absw)
+    for bz in range(0, R, B):
+        for by in range(0, R, B):
+            for bx in range(0, R, B):
+                mx = absw[:, bz:bz + B, by:by + B, bx:bx + B].max(axis=(1, 2, 3))
+                step[:, bz:bz + B, by:by + B, bx:bx + B] = mx[:, None, None, None] * 2.0 ** -40
+    err = np.abs(got - want)
+    assert np.all(err <= 2e-7 * np.abs(want) + step)
+    # the 1e-30 half is resolved: its bricks' steps are ~1e-42
+    small = step[:, :, :, :16]
+    assert small.max() < 1e-38 and np.abs(want[:, :, :, :16]).max() > 1e-31
+
+
+def test_grid_scatter_nonfinite_gradient_marks_its_nodes():
+    """A NaN or infinite gradient reaches the eight nodes of its point's cell
+    as NaN, in its channel only; every other node is the sum of the finite
+    contributions."""
+    R = 24
+    bmin = np.zeros(3, np.float32)
+    bmax = np.ones(3, np.float32)
+    rng = np.random.default_rng(22)
+    n = 20000
+    pos = rng.uniform(0, 1, size=(3, n)).astype(np.float32)
+    gp = rng.standard_normal((2, n)).astype(np.float32)
+    bad = [5, 777]
+    gp[0, bad[0]] = np.nan
+    gp[1, bad[1]] = np.inf
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    got = plan.scatter(_t(gp)).cpu().numpy().reshape(2, R, R, R)
+    clean = gp.copy()
+    clean[0, bad[0]] = 0.0
+    clean[1, bad[1]] = 0.0
+    want = orr.grid_scatter(clean, pos, bmin, bmax, R).reshape(2, R, R, R)
+    expect_nan = np.zeros(got.shape, bool)
+    for ch, p in enumerate(bad):
+        u = np.clip((pos[:, p].astype(np.float64) - bmin) * (R - 1) / (bmax - bmin), 0, R - 1)
+        i = np.minimum(np.floor(u).astype(int), R - 2)
+        expect_nan[ch, i[2]:i[2] + 2, i[1]:i[1] + 2, i[0]:i[0] + 2] = True
+    assert np.array_equal(np.isnan(got), expect_nan)
+    ok = ~expect_nan
+    assert_close_rel(np.where(ok, got, 0).reshape(2, -1), np.where(ok, want, 0).reshape(2, -1), 1e-5,
+                     what="finite nodes")
+
+
+def test_grid_scatter_dense_cluster_many_units():
+    """Points packed into a few cells (thousands per cell, tens of thousands
+    per 8^3-node brick) make bricks whose columns span several work units:
+    their units' node sums are combined in unit order, equal to the oracle
+    and bitwise repeatable, a NaN among them still marks only its nodes."""
+    R = 32
+    bmin = np.zeros(3, np.float32)
+    bmax = np.ones(3, np.float32)
+    rng = np.random.default_rng(23)
+    n = 150000
+    pos = rng.uniform(0, 1, size=(3, n))
+    # 80 % of the points inside a cube of 2 x 2 x 2 cells at a brick corner
+    k = int(0.8 * n)
+    pos[:, :k] = (7.0 + 2.0 * rng.uniform(0, 1, size=(3, k))) / (R - 1)
+    pos = pos.astype(np.float32)
+    gp = rng.standard_normal((4, n)).astype(np.float32)
+    gp[3, 11] = np.nan
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    got = plan.scatter(_t(gp))
+    again = plan.scatter(_t(gp))
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(got, nan=7.0), torch.nan_to_num(again, nan=7.0))
+    got = got.cpu().numpy().reshape(4, R, R, R)
+    clean = gp.copy()
+    clean[3, 11] = 0.0
+    want = orr.grid_scatter(clean, pos, bmin, bmax, R).reshape(4, R, R, R)
+    u = np.clip(pos[:, 11].astype(np.float64) * (R - 1), 0, R - 1)
+    i = np.minimum(np.floor(u).astype(int), R - 2)
+    expect_nan = np.zeros(got.shape, bool)
+    expect_nan[3, i[2]:i[2] + 2, i[1]:i[1] + 2, i[0]:i[0] + 2] = True
+    assert np.array_equal(np.isnan(got), expect_nan)
+    ok = ~expect_nan
+    assert_close_rel(np.where(ok, got, 0).reshape(4, -1), np.where(ok, want, 0).reshape(4, -1), 1e-5,
+                     what="dense cluster")
+
+
 def test_grid_scatter_rejects_misshapen_buffers():
     pos = np.random.default_rng(3).uniform(0, 1, size=(3, 100)).astype(np.float32)
     plan = fipt.GridPlan(pos, 8, np.zeros(3, np.float32), np.ones(3, np.float32))
