@@ -66,6 +66,7 @@ typedef struct fipt_grid_plan_s* fipt_grid_plan;
 typedef struct fipt_emission_plan_s* fipt_emission_plan;
 typedef struct fipt_voxel_plan_s* fipt_voxel_plan;
 typedef struct fipt_server_s* fipt_server;
+typedef struct fipt_hashgrid_plan_s* fipt_hashgrid_plan;
 
 /* Pinhole camera: rays leave `pos` through pixel centres; `fwd` is the view
  * direction, `up` fixes the roll, `vfov_deg` the vertical field of view;
@@ -506,18 +507,31 @@ int fipt_hashgrid_forward(const float* params, const float* pos, int64_t pos_str
 /* Floats of workspace fipt_hashgrid_backward needs for n points. */
 int64_t fipt_hashgrid_workspace_floats(int64_t n);
 
+/* Table-gradient plan of a fixed point set (device positions pos[3][pos_stride],
+ * copied into the plan): for every level, each (point, corner) with a
+ * nonzero trilinear weight, sorted by table slot, then point, then corner,
+ * with its weight, and the slot ranges.  Built on the device on `stream`
+ * (a stable radix sort per level); returns once the plan is complete.
+ * 1 <= n < 2^28; bmin_host < bmax_host (host float [3]).  The plan owns
+ * device memory (12 bytes per point, 8 per nonzero (point, corner) per
+ * level, at most 8 per point and level, and 2 MB per level). */
+int fipt_hashgrid_plan_create(const float* pos, int64_t pos_stride, int64_t n, const float* bmin_host,
+                              const float* bmax_host, void* stream, fipt_hashgrid_plan* out);
+int fipt_hashgrid_plan_destroy(fipt_hashgrid_plan plan);
+
 /* Adds d(sum over points and outputs of grad_material * material) /
  * d params into grad_params (device float [FIPT_HG_PARAMS]; the caller
- * zeroes it first for a plain gradient).  grad_material: device
- * [5][gm_stride].  workspace: device, at least
- * fipt_hashgrid_workspace_floats(n) floats, overwritten.  The table
- * gradient is summed with float atomics (its last bits depend on
- * scheduling); the weight gradients are summed in a fixed order.  Calls
- * that share a workspace must not overlap.  Asynchronous on `stream`. */
-int fipt_hashgrid_backward(const float* params, const float* pos, int64_t pos_stride, int64_t n,
-                           const float* bmin_host, const float* bmax_host,
-                           const float* grad_material, int64_t gm_stride, float* grad_params,
-                           float* workspace, int64_t workspace_floats, void* stream);
+ * zeroes it first for a plain gradient), for the plan's points.
+ * grad_material: device [5][gm_stride], gm_stride >= n.  workspace: device,
+ * at least fipt_hashgrid_workspace_floats(n) floats, overwritten.  Each table
+ * entry's gradient is the sum over its (point, corner) list in the plan's
+ * order, in double; the weight gradients are summed in a fixed order: the
+ * result is reproducible bit for bit.  A vertex of zero weight receives
+ * nothing.  Calls that share a workspace must not overlap.  Asynchronous on
+ * `stream`. */
+int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const float* grad_material,
+                           int64_t gm_stride, float* grad_params, float* workspace,
+                           int64_t workspace_floats, void* stream);
 
 /* ---- emission re-estimation (Sec. 4.4, Eq. 13) ------------------------- */
 

@@ -18,19 +18,24 @@
 // the MALL.
 //
 // Backward: one thread per point recomputes the forward pass, back-propagates
-// through the MLP, adds each feature gradient into the table entries of its
-// 8 vertices per level with float atomics (the order of those additions, and
-// so the last bits of the table gradient, depends on scheduling), and
-// stores its activations and layer gradients in a workspace.  The weight
-// gradients are sums over points of outer products (three small GEMMs with
-// the point count as the reduction dimension): a split-K kernel forms one
-// 64 x 64 partial per chunk of 8192 points on the matrix cores, and a final
-// kernel adds the partials in chunk order, so weight gradients are
-// reproducible bit for bit.
+// through the MLP, stores its per-level feature gradients (W1^T d1, two per
+// level) and its activations and layer gradients in a workspace.  The table
+// gradient is then a gather: a plan built once for the point set lists, per
+// level, every (point, corner) with a nonzero trilinear weight sorted by
+// table slot (then point, then corner), and one group of lanes per slot sums
+// weight x feature gradient over its list in that order, in double, adding
+// the total into the slot's entry; no atomics, so the table gradient is
+// reproducible bit for bit.  The weight gradients are sums over points of
+// outer products (three small GEMMs with the point count as the reduction
+// dimension): a split-K kernel forms one 64 x 64 partial per chunk of 2048
+// points on the matrix cores, and a final kernel adds the partials in chunk
+// order, so weight gradients are reproducible too.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "fipt_internal.hpp"
 
@@ -47,9 +52,9 @@ constexpr int64_t kTable = (int64_t)kLevels * kT * kFeat;
 constexpr int kW1 = kHid * kIn, kW2 = kHid * kHid, kW3 = kOut * kHid;
 constexpr int kWeights = kW1 + kW2 + kW3;   // 8512
 constexpr int kBlock = 256;
-constexpr int kChunk = 8192;              // points per weight-gradient partial
+constexpr int kChunk = 2048;              // points per weight-gradient partial
 constexpr int kWsRows = 3 * 64 + 2 * 64 + kOut;   // e, h1, h2, d1, d2, d3
-constexpr int kAggregateLevels = 6;       // levels whose table updates are combined per wavefront
+constexpr int kFeatGradRows = kLevels * kFeat;     // per-level feature gradients, [32][n] float2
 
 struct HgArgs {
     const float* params;
@@ -156,30 +161,6 @@ __device__ __forceinline__ void dense_relu(const float* W, const float* x, float
     }
 }
 
-// Table update of one vertex per lane, combined across the wavefront: lanes
-// naming the same slot are summed by a butterfly and one of them adds the
-// total.  On the coarse levels neighbouring pixels share vertices, and one
-// atomic per distinct slot replaces up to 64 on the same address.
-__device__ __forceinline__ void add_combined(float* t, uint32_t idx, float v0, float v1, int lane) {
-    uint64_t todo = __builtin_amdgcn_ballot_w64(true);
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const uint32_t lidx = __shfl(idx, leader, 64);
-        const bool mine = ((todo >> lane) & 1ull) && idx == lidx;
-        todo &= ~__builtin_amdgcn_ballot_w64(mine);
-        float s0 = mine ? v0 : 0.0f, s1 = mine ? v1 : 0.0f;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            s0 += __shfl_xor(s0, m, 64);
-            s1 += __shfl_xor(s1, m, 64);
-        }
-        if (lane == leader) {
-            atomicAdd(t + (int64_t)lidx * kFeat, s0);
-            atomicAdd(t + (int64_t)lidx * kFeat + 1, s1);
-        }
-    }
-}
-
 // Occupancy targets keep the compiler from hoisting the weight loads of the
 // unrolled products into hundreds of registers: 4 waves per SIMD (at most
 // 128 VGPRs) for the forward pass, 3 (at most 168) for the backward pass,
@@ -212,18 +193,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 }
 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_hg_backward(HgArgs a, const float* __restrict__ gy,
-                                                        int64_t gs, float* __restrict__ gparams,
-                                                        float* __restrict__ ws, int64_t wn) {
+                                                        int64_t gs, float* __restrict__ ws, int64_t wn,
+                                                        float2* __restrict__ fgrad) {
     __shared__ float w[kWeights];
     load_weights(a.params, w);
     const float* W1 = w;
     const float* W2 = w + kW1;
     const float* W3 = w + kW1 + kW2;
-    // every lane of a wavefront runs the body (the table updates combine
-    // lanes); a lane past the last point takes the origin and adds zeros
+    // a lane past the last point runs the body at the origin and stores
+    // nothing
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = i < a.n;
-    const int lane = threadIdx.x & 63;
     {
         float p[3] = {0.0f, 0.0f, 0.0f}, h1[kHid], h2[kHid];
         if (live) unit_pos(a, i, p);
@@ -269,33 +249,156 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             if (live) ws[(int64_t)(192 + k) * wn + i] = h1[k];
             __builtin_amdgcn_sched_barrier(0);
         }
-        // per level: feature gradients (W1^T d1, rows 2l and 2l + 1) into the
-        // table entries of the cell's 8 vertices
+        // per level: feature gradients (W1^T d1, rows 2l and 2l + 1), stored
+        // for the table-gradient gather
+        if (live) {
 #pragma unroll 1
-        for (int l = 0; l < kLevels; ++l) {
-            float g0 = 0.0f, g1 = 0.0f;
+            for (int l = 0; l < kLevels; ++l) {
+                float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
-            for (int o = 0; o < kHid; ++o) {
-                g0 = fmaf(W1[o * kIn + 2 * l], h1[o], g0);
-                g1 = fmaf(W1[o * kIn + 2 * l + 1], h1[o], g1);
-            }
-            uint32_t idx[8];
-            float wt[8];
-            corners(l, p, idx, wt);
-            float* t = gparams + (int64_t)l * kT * kFeat;
-            if (l < kAggregateLevels) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) add_combined(t, idx[k], wt[k] * g0, wt[k] * g1, lane);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (live && wt[k] != 0.0f) {   // zero-weight vertices add nothing
-                        atomicAdd(t + (int64_t)idx[k] * kFeat, wt[k] * g0);
-                        atomicAdd(t + (int64_t)idx[k] * kFeat + 1, wt[k] * g1);
-                    }
+                for (int o = 0; o < kHid; ++o) {
+                    g0 = fmaf(W1[o * kIn + 2 * l], h1[o], g0);
+                    g1 = fmaf(W1[o * kIn + 2 * l + 1], h1[o], g1);
                 }
+                fgrad[(int64_t)l * wn + i] = make_float2(g0, g1);
             }
         }
+    }
+}
+
+// ---- table-gradient plan ---------------------------------------------------
+// Sort keys of level l: the slot of each (point, corner) with a nonzero
+// weight, kT (after every slot) for the others; values p << 3 | corner, in
+// point order, so the stable radix sort leaves each slot's list in (point,
+// corner) order.  `nnz` counts the nonzero weights.
+__global__ __launch_bounds__(kBlock) void k_hgp_keys(HgArgs a, int l, uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals,
+                                                     unsigned long long* __restrict__ nnz) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int c = 0;
+    if (i < a.n) {
+        float p[3];
+        unit_pos(a, i, p);
+        uint32_t idx[8];
+        float w[8];
+        corners(l, p, idx, w);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            keys[8 * i + k] = w[k] != 0.0f ? idx[k] : kT;
+            vals[8 * i + k] = (uint32_t)(i << 3) | (uint32_t)k;
+            c += w[k] != 0.0f;
+        }
+    }
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(nnz, (unsigned long long)c);
+}
+
+// Entries (p << 3 | corner, weight bits) of the sorted nonzero list, and the
+// slot ranges: off[s] = first entry of slot s, off[kT] = nnz.
+__global__ __launch_bounds__(kBlock) void k_hgp_entries(HgArgs a, int l, const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ vals, int64_t nnz,
+                                                        int2* __restrict__ ent, uint32_t* __restrict__ off) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i > nnz) return;
+    const uint32_t cur = i < nnz ? keys[i] : kT;
+    const int64_t prev = i > 0 ? (int64_t)keys[i - 1] : -1;
+    for (int64_t t = prev + 1; t <= (int64_t)cur; ++t) off[t] = (uint32_t)i;
+    if (i == nnz) return;
+    const uint32_t e = vals[i];
+    float p[3];
+    unit_pos(a, e >> 3, p);
+    uint32_t idx[8];
+    float w[8];
+    corners(l, p, idx, w);
+    float wk = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wk = (int)(e & 7) == k ? w[k] : wk;
+    ent[i] = make_int2((int)e, __float_as_int(wk));
+}
+
+// Table gradient of one level, slots of at most kHeavy entries: L lanes per
+// slot (a power of two up to 64); lane j sums entries j, j + L, ... of the
+// slot's list in double (four entries' loads, then their four gradient
+// loads, in flight together), a fixed butterfly adds the L partial sums, and
+// the first lane adds the total into the slot's two features.
+constexpr uint32_t kHeavy = 256;
+
+__device__ __forceinline__ void gather_sum(const int2* __restrict__ ent, const float2* __restrict__ fg,
+                                           uint32_t first, uint32_t e1, uint32_t stride, double& s0,
+                                           double& s1) {
+    for (uint32_t e = first; e < e1; e += 4 * stride) {
+        int2 en[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) en[u] = ent[min(e + u * stride, e1 - 1)];
+        float2 d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = fg[(uint32_t)en[u].x >> 3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (e + u * stride < e1) {
+                const double w = (double)__int_as_float(en[u].y);
+                s0 += w * (double)d[u].x;
+                s1 += w * (double)d[u].y;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hg_table_grad(const int2* __restrict__ ent,
+                                                          const uint32_t* __restrict__ off,
+                                                          const float2* __restrict__ fg, int64_t n_slots,
+                                                          int L, float* __restrict__ t) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t slot = g / L;
+    const int j = (int)(g % L);
+    double s0 = 0.0, s1 = 0.0;
+    uint32_t e0 = 0, e1 = 0;
+    if (slot < n_slots) {
+        e0 = off[slot];
+        e1 = off[slot + 1];
+        if (e1 - e0 > kHeavy) e1 = e0;   // a heavy slot: k_hg_table_grad_heavy
+        gather_sum(ent, fg, e0 + j, e1, L, s0, s1);
+    }
+    for (int m = 1; m < L; m <<= 1) {
+        s0 += __shfl_xor(s0, m, 64);
+        s1 += __shfl_xor(s1, m, 64);
+    }
+    if (j == 0 && e1 > e0) {
+        t[2 * slot] += (float)s0;
+        t[2 * slot + 1] += (float)s1;
+    }
+}
+
+// The heavy slots of a level (more than kHeavy entries; the plan lists
+// them): one workgroup per slot, thread j summing entries j, j + kBlock, ...;
+// each wavefront's butterfly, then the four wavefront totals in order.
+__global__ __launch_bounds__(kBlock) void k_hg_table_grad_heavy(const int2* __restrict__ ent,
+                                                                const uint32_t* __restrict__ off,
+                                                                const uint32_t* __restrict__ heavy,
+                                                                const float2* __restrict__ fg,
+                                                                float* __restrict__ t) {
+    __shared__ double part[kBlock / 64][2];
+    const uint32_t slot = heavy[blockIdx.x];
+    const uint32_t e0 = off[slot], e1 = off[slot + 1];
+    double s0 = 0.0, s1 = 0.0;
+    gather_sum(ent, fg, e0 + threadIdx.x, e1, kBlock, s0, s1);
+    for (int m = 1; m < 64; m <<= 1) {
+        s0 += __shfl_xor(s0, m, 64);
+        s1 += __shfl_xor(s1, m, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6][0] = s0;
+        part[threadIdx.x >> 6][1] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            a += part[w][0];
+            b += part[w][1];
+        }
+        t[2 * slot] += (float)a;
+        t[2 * slot + 1] += (float)b;
     }
 }
 
@@ -364,8 +467,16 @@ __global__ __launch_bounds__(kBlock) void k_hg_wreduce(const float* __restrict__
     if (j < kW1) { mat = 0; r = j; }
     else if (j < kW1 + kW2) { mat = 1; r = j - kW1; }
     else { mat = 2; r = j - kW1 - kW2; }
+    // chunk order; four partials' loads in flight at a time
+    const float* src = part + (int64_t)mat * n_chunks * 4096 + r;
     float s = 0.0f;
-    for (int64_t c = 0; c < n_chunks; ++c) s += part[((int64_t)mat * n_chunks + c) * 4096 + r];
+    int64_t c = 0;
+    for (; c + 4 <= n_chunks; c += 4) {
+        const float a = src[c * 4096], b = src[(c + 1) * 4096], d = src[(c + 2) * 4096],
+                    e = src[(c + 3) * 4096];
+        s = (((s + a) + b) + d) + e;
+    }
+    for (; c < n_chunks; ++c) s += src[c * 4096];
     gparams[kTable + j] += s;
 }
 
@@ -377,9 +488,10 @@ int check_hg(const char* what) {
     return FIPT_OK;
 }
 
+// (params may be NULL for the plan, which reads only positions)
 int make_args(const float* params, const float* pos, int64_t ps, int64_t n, const float* lo,
-              const float* hi, HgArgs& a) {
-    if (!params || !pos || !lo || !hi) return fail(FIPT_EINVAL, "NULL argument");
+              const float* hi, HgArgs& a, bool need_params = true) {
+    if ((need_params && !params) || !pos || !lo || !hi) return fail(FIPT_EINVAL, "NULL argument");
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(FIPT_EINVAL, "n must be in [1, 2^31)");
     if (ps < n) return fail(FIPT_EINVAL, "pos_stride < n");
     for (int k = 0; k < 3; ++k) {
@@ -396,17 +508,183 @@ int make_args(const float* params, const float* pos, int64_t ps, int64_t n, cons
     return FIPT_OK;
 }
 
+// Lanes per slot of a level's table gather: the power of two nearest above
+// a quarter of the mean list length of the level's (light, nonempty) slots,
+// at most 64.
+int lanes_per_slot(int64_t nnz, int64_t n_slots) {
+    const int64_t mean = nnz / std::max<int64_t>(n_slots, 1);
+    int L = 1;
+    while (L < 64 && 4 * L < mean) L *= 2;
+    return L;
+}
+
+// Slots of level l: the dense levels index (16 2^l + 1)^3 vertices.
+int64_t level_slots(int l) {
+    if (l < 3) {
+        const int64_t r = (16 << l) + 1;
+        return r * r * r;
+    }
+    return kT;
+}
+
 }  // namespace
 }  // namespace fipt
 
+struct fipt_hashgrid_plan_s {
+    int32_t device = 0;
+    int64_t n = 0;
+    float lo[3], hi[3];
+    float* pos = nullptr;                 // [3][n] device copy of the positions
+    int2* ent[FIPT_HG_LEVELS] = {};       // per level: (p << 3 | corner, weight bits), by slot
+    uint32_t* off[FIPT_HG_LEVELS] = {};   // per level: [2^19 + 1] slot ranges into ent
+    uint32_t* heavy[FIPT_HG_LEVELS] = {}; // per level: the slots of more than kHeavy entries
+    int64_t n_heavy[FIPT_HG_LEVELS] = {};
+    int64_t nnz[FIPT_HG_LEVELS] = {};
+    int lanes[FIPT_HG_LEVELS] = {};
+};
+
 using namespace fipt;
+
+namespace {
+void hg_plan_free(fipt_hashgrid_plan p) {
+    if (!p) return;
+    (void)hipFree(p->pos);
+    for (int l = 0; l < FIPT_HG_LEVELS; ++l) {
+        (void)hipFree(p->ent[l]);
+        (void)hipFree(p->off[l]);
+        (void)hipFree(p->heavy[l]);
+    }
+    delete p;
+}
+}  // namespace
 
 extern "C" {
 
 int64_t fipt_hashgrid_workspace_floats(int64_t n) {
     if (n < 1) return 0;
     const int64_t chunks = (n + kChunk - 1) / kChunk;
-    return (int64_t)kWsRows * n + 3 * chunks * 4096;
+    return (int64_t)(kWsRows + kFeatGradRows) * n + 3 * chunks * 4096;
+}
+
+int fipt_hashgrid_plan_create(const float* pos, int64_t pos_stride, int64_t n, const float* bmin_host,
+                              const float* bmax_host, void* stream, fipt_hashgrid_plan* out) {
+    clear_error();
+    if (!out) return fail(FIPT_EINVAL, "out is NULL");
+    *out = nullptr;
+    HgArgs a;
+    int rc = make_args(nullptr, pos, pos_stride, n, bmin_host, bmax_host, a, false);
+    if (rc) return rc;
+    if (n >= (int64_t(1) << 28)) return fail(FIPT_EINVAL, "n must be below 2^28");
+    hipStream_t st = (hipStream_t)stream;
+    fipt_hashgrid_plan p = new fipt_hashgrid_plan_s();
+    (void)hipGetDevice(&p->device);
+    p->n = n;
+    for (int k = 0; k < 3; ++k) {
+        p->lo[k] = bmin_host[k];
+        p->hi[k] = bmax_host[k];
+    }
+    const int64_t m = 8 * n;
+    uint32_t *k_in = nullptr, *k_out = nullptr, *v_in = nullptr, *v_out = nullptr;
+    unsigned long long* d_nnz = nullptr;
+    void* tmp = nullptr;
+    size_t tmp_bytes = 0;
+    auto cleanup = [&]() {
+        (void)hipFree(k_in);
+        (void)hipFree(k_out);
+        (void)hipFree(v_in);
+        (void)hipFree(v_out);
+        (void)hipFree(d_nnz);
+        (void)hipFree(tmp);
+    };
+    auto bail = [&](int code, const char* what) {
+        (void)hipStreamSynchronize(st);
+        cleanup();
+        hg_plan_free(p);
+        return fail(code, "hashgrid plan: %s", what);
+    };
+    if (hipMalloc(reinterpret_cast<void**>(&p->pos), sizeof(float) * 3 * n) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&k_in), sizeof(uint32_t) * m) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&k_out), sizeof(uint32_t) * m) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&v_in), sizeof(uint32_t) * m) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&v_out), sizeof(uint32_t) * m) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&d_nnz), sizeof(unsigned long long) * kLevels) != hipSuccess)
+        return bail(FIPT_ENOMEM, "hipMalloc failed");
+    for (int k = 0; k < 3; ++k)
+        if (hipMemcpyAsync(p->pos + k * n, pos + k * pos_stride, sizeof(float) * n, hipMemcpyDeviceToDevice,
+                           st) != hipSuccess)
+            return bail(FIPT_EHIP, "copying the positions failed");
+    a.pos = p->pos;
+    a.ps = n;
+    if (hipMemsetAsync(d_nnz, 0, sizeof(unsigned long long) * kLevels, st) != hipSuccess)
+        return bail(FIPT_EHIP, "hipMemsetAsync failed");
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k_in, k_out, v_in, v_out, (int)m, 0, 20, st) !=
+            hipSuccess ||
+        hipMalloc(&tmp, tmp_bytes) != hipSuccess)
+        return bail(FIPT_ENOMEM, "radix sort scratch");
+    for (int l = 0; l < kLevels; ++l) {
+        hipLaunchKernelGGL(k_hgp_keys, dim3(grid_points(n)), dim3(kBlock), 0, st, a, l, k_in, v_in,
+                           d_nnz + l);
+        if (hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k_in, k_out, v_in, v_out, (int)m, 0, 20, st) !=
+            hipSuccess)
+            return bail(FIPT_EHIP, "radix sort failed");
+        // the nonzero count sizes the level's entry list
+        unsigned long long h_nnz = 0;
+        if (hipMemcpyAsync(&h_nnz, d_nnz + l, sizeof(h_nnz), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return bail(FIPT_EHIP, "counting the entries failed");
+        p->nnz[l] = (int64_t)h_nnz;
+        if (hipMalloc(reinterpret_cast<void**>(&p->ent[l]), sizeof(int2) * std::max<int64_t>(p->nnz[l], 1)) !=
+                hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&p->off[l]), sizeof(uint32_t) * (kT + 1)) != hipSuccess)
+            return bail(FIPT_ENOMEM, "hipMalloc entries failed");
+        hipLaunchKernelGGL(k_hgp_entries, dim3(grid_points(p->nnz[l] + 1)), dim3(kBlock), 0, st, a, l, k_out,
+                           v_out, p->nnz[l], p->ent[l], p->off[l]);
+        // slots of more than kHeavy entries get a workgroup each; the others
+        // share lanes by the mean length of their lists
+        const int64_t slots = level_slots(l);
+        std::vector<uint32_t> h_off(slots + 1);
+        if (hipMemcpyAsync(h_off.data(), p->off[l], sizeof(uint32_t) * (slots + 1), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return bail(FIPT_EHIP, "reading the slot ranges failed");
+        std::vector<uint32_t> heavy;
+        int64_t light_n = 0, light_slots = 0;
+        for (int64_t q = 0; q < slots; ++q) {
+            const uint32_t c = h_off[q + 1] - h_off[q];
+            if (c > kHeavy) {
+                heavy.push_back((uint32_t)q);
+            } else if (c > 0) {
+                light_n += c;
+                ++light_slots;
+            }
+        }
+        p->lanes[l] = lanes_per_slot(light_n, light_slots);
+        p->n_heavy[l] = (int64_t)heavy.size();
+        if (hipMalloc(reinterpret_cast<void**>(&p->heavy[l]), sizeof(uint32_t) * std::max<size_t>(heavy.size(), 1)) !=
+            hipSuccess)
+            return bail(FIPT_ENOMEM, "hipMalloc heavy slots failed");
+        if (!heavy.empty() && hipMemcpyAsync(p->heavy[l], heavy.data(), sizeof(uint32_t) * heavy.size(),
+                                             hipMemcpyHostToDevice, st) != hipSuccess)
+            return bail(FIPT_EHIP, "copying the heavy slots failed");
+        if (hipStreamSynchronize(st) != hipSuccess) return bail(FIPT_EHIP, "building a level failed");
+    }
+    if (check_hg("hashgrid plan") != FIPT_OK || hipStreamSynchronize(st) != hipSuccess)
+        return bail(FIPT_EHIP, "building the entry lists failed");
+    cleanup();
+    *out = p;
+    return FIPT_OK;
+}
+
+int fipt_hashgrid_plan_destroy(fipt_hashgrid_plan p) {
+    clear_error();
+    if (!p) return FIPT_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    hg_plan_free(p);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return FIPT_OK;
 }
 
 int fipt_hashgrid_forward(const float* params, const float* pos, int64_t pos_stride, int64_t n,
@@ -423,13 +701,14 @@ int fipt_hashgrid_forward(const float* params, const float* pos, int64_t pos_str
     return check_hg("hashgrid_forward");
 }
 
-int fipt_hashgrid_backward(const float* params, const float* pos, int64_t pos_stride, int64_t n,
-                           const float* bmin_host, const float* bmax_host,
-                           const float* grad_material, int64_t gm_stride, float* grad_params,
-                           float* workspace, int64_t workspace_floats, void* stream) {
+int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const float* grad_material,
+                           int64_t gm_stride, float* grad_params, float* workspace,
+                           int64_t workspace_floats, void* stream) {
     clear_error();
+    if (!plan) return fail(FIPT_EINVAL, "plan is NULL");
+    const int64_t n = plan->n;
     HgArgs a;
-    int rc = make_args(params, pos, pos_stride, n, bmin_host, bmax_host, a);
+    int rc = make_args(params, plan->pos, n, n, plan->lo, plan->hi, a);
     if (rc) return rc;
     if (!grad_material || !grad_params || !workspace) return fail(FIPT_EINVAL, "NULL argument");
     if (gm_stride < n) return fail(FIPT_EINVAL, "gm_stride < n");
@@ -437,12 +716,27 @@ int fipt_hashgrid_backward(const float* params, const float* pos, int64_t pos_st
         return fail(FIPT_EINVAL, "workspace holds %lld floats, %lld needed", (long long)workspace_floats,
                     (long long)fipt_hashgrid_workspace_floats(n));
     hipStream_t st = (hipStream_t)stream;
+    float2* fgrad = reinterpret_cast<float2*>(workspace + (int64_t)kWsRows * n);
     hipLaunchKernelGGL(k_hg_backward, dim3(grid_points(n)), dim3(kBlock), 0, st, a, grad_material,
-                       gm_stride, grad_params, workspace, n);
+                       gm_stride, workspace, n, fgrad);
     rc = check_hg("hashgrid_backward");
     if (rc) return rc;
+    for (int l = 0; l < kLevels; ++l) {
+        if (plan->nnz[l] == 0) continue;
+        const int64_t slots = level_slots(l);
+        const int L = plan->lanes[l];
+        hipLaunchKernelGGL(k_hg_table_grad, dim3((unsigned)((slots * L + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, st, plan->ent[l], plan->off[l], fgrad + (int64_t)l * n, slots, L,
+                           grad_params + (int64_t)l * kT * kFeat);
+        if (plan->n_heavy[l] > 0)
+            hipLaunchKernelGGL(k_hg_table_grad_heavy, dim3((unsigned)plan->n_heavy[l]), dim3(kBlock), 0, st,
+                               plan->ent[l], plan->off[l], plan->heavy[l], fgrad + (int64_t)l * n,
+                               grad_params + (int64_t)l * kT * kFeat);
+    }
+    rc = check_hg("hashgrid_table_grad");
+    if (rc) return rc;
     const int64_t chunks = (n + kChunk - 1) / kChunk;
-    float* part = workspace + (int64_t)kWsRows * n;
+    float* part = workspace + (int64_t)(kWsRows + kFeatGradRows) * n;
     hipLaunchKernelGGL(k_hg_wgrad, dim3((unsigned)chunks, 3), dim3(kBlock), 0, st, workspace, n, n,
                        part);
     rc = check_hg("hashgrid_wgrad");

@@ -35,7 +35,7 @@ EXPORTS = (
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
     "fipt_scene_set_voxel_radiance", "fipt_voxel_plan_create", "fipt_voxel_plan_destroy",
     "fipt_voxel_pool", "fipt_hashgrid_forward", "fipt_hashgrid_workspace_floats",
-    "fipt_hashgrid_backward",
+    "fipt_hashgrid_plan_create", "fipt_hashgrid_plan_destroy", "fipt_hashgrid_backward",
     "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
     "fipt_server_result", "fipt_server_release", "fipt_server_cancel", "fipt_server_stats_get",
     "fipt_server_destroy",
@@ -113,8 +113,9 @@ def lib():
         "fipt_voxel_pool": (C.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
         "fipt_hashgrid_forward": (C.c_int, [_vp, _vp, _i64, _i64, _f32p, _f32p, _vp, _i64, _vp]),
         "fipt_hashgrid_workspace_floats": (_i64, [_i64]),
-        "fipt_hashgrid_backward": (C.c_int, [_vp, _vp, _i64, _i64, _f32p, _f32p, _vp, _i64, _vp,
-                                             _vp, _i64, _vp]),
+        "fipt_hashgrid_plan_create": (C.c_int, [_vp, _i64, _i64, _f32p, _f32p, _vp, C.POINTER(_vp)]),
+        "fipt_hashgrid_plan_destroy": (C.c_int, [_vp]),
+        "fipt_hashgrid_backward": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]),
         "fipt_scene_set_emission": (C.c_int, [_vp, _vp, _vp]),
         "fipt_scene_info_get": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
         "fipt_scene_destroy": (C.c_int, [_vp]),
@@ -752,26 +753,48 @@ def fipt_hashgrid_forward(params: torch.Tensor, pos: torch.Tensor, bmin, bmax,
     return out
 
 
-def fipt_hashgrid_backward(params: torch.Tensor, pos: torch.Tensor, bmin, bmax,
-                           grad_material: torch.Tensor, grad_params: torch.Tensor = None,
-                           workspace: torch.Tensor = None):
-    """Adds d(sum grad_material * material) / d params into grad_params
-    (zeros if None) and returns it."""
+class HashGridPlan:
+    """Table-gradient plan of a fixed point set for the hash-grid network's
+    backward pass: per level, every (point, corner) of nonzero weight sorted
+    by table slot, built on the GPU once.  Holds ``pos`` [3, n] and the box
+    for the forward pass too."""
+
+    def __init__(self, pos: torch.Tensor, bmin, bmax):
+        if pos.dim() != 2 or pos.shape[0] != 3:
+            raise ValueError(f"pos must be [3, n], got {tuple(pos.shape)}")
+        self.pos = pos.contiguous()
+        self.n = int(pos.shape[1])
+        self.bmin, self.bmax = list(map(float, bmin)), list(map(float, bmax))
+        h = C.c_void_p()
+        _check(lib().fipt_hashgrid_plan_create(_dev(self.pos, torch.float32, "pos"), self.n, self.n,
+                                               _f32_array(self.bmin, 3), _f32_array(self.bmax, 3),
+                                               _stream(), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.fipt_hashgrid_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def fipt_hashgrid_backward(plan: HashGridPlan, params: torch.Tensor, grad_material: torch.Tensor,
+                           grad_params: torch.Tensor = None, workspace: torch.Tensor = None):
+    """Adds d(sum grad_material * material) / d params, for the plan's
+    points, into grad_params (zeros if None) and returns it."""
     _need(params, (HG_PARAMS,), "params")
-    n = pos.shape[1]
-    _need(pos, (3, n), "pos")
+    n = plan.n
     _need(grad_material, (5, n), "grad_material")
     if grad_params is None:
-        grad_params = torch.zeros((HG_PARAMS,), dtype=torch.float32, device=pos.device)
+        grad_params = torch.zeros((HG_PARAMS,), dtype=torch.float32, device=params.device)
     _need(grad_params, (HG_PARAMS,), "grad_params")
     need = int(lib().fipt_hashgrid_workspace_floats(n))
     if workspace is None:
-        workspace = torch.empty((need,), dtype=torch.float32, device=pos.device)
+        workspace = torch.empty((need,), dtype=torch.float32, device=params.device)
     if workspace.dim() != 1 or workspace.shape[0] < need:
         raise ValueError(f"workspace must hold at least {need} floats")
-    _check(lib().fipt_hashgrid_backward(_dev(params, torch.float32, "params"),
-                                        _dev(pos, torch.float32, "pos"), n, n, _f32_array(bmin, 3),
-                                        _f32_array(bmax, 3),
+    _check(lib().fipt_hashgrid_backward(plan.handle, _dev(params, torch.float32, "params"),
                                         _dev(grad_material, torch.float32, "grad_material"), n,
                                         _dev(grad_params, torch.float32, "grad_params"),
                                         _dev(workspace, torch.float32, "workspace"),
@@ -780,21 +803,20 @@ def fipt_hashgrid_backward(params: torch.Tensor, pos: torch.Tensor, bmin, bmax,
 
 
 class HashGridMaterial(torch.autograd.Function):
-    """material [5, n] = Sigmoid(MLP(hash encoding(pos))); differentiable in
-    ``params`` through the library's backward pass."""
+    """material [5, n] = Sigmoid(MLP(hash encoding(plan.pos))); differentiable
+    in ``params`` through the library's backward pass."""
 
     @staticmethod
-    def forward(ctx, params, pos, bmin, bmax):
-        ctx.save_for_backward(params, pos)
-        ctx.box = (list(bmin), list(bmax))
-        return fipt_hashgrid_forward(params.detach(), pos, bmin, bmax)
+    def forward(ctx, params, plan):
+        ctx.save_for_backward(params)
+        ctx.plan = plan
+        return fipt_hashgrid_forward(params.detach(), plan.pos, plan.bmin, plan.bmax)
 
     @staticmethod
     def backward(ctx, g):
-        params, pos = ctx.saved_tensors
-        bmin, bmax = ctx.box
-        gp = fipt_hashgrid_backward(params.detach(), pos, bmin, bmax, g.contiguous())
-        return gp, None, None, None
+        (params,) = ctx.saved_tensors
+        gp = fipt_hashgrid_backward(ctx.plan, params.detach(), g.contiguous())
+        return gp, None
 
 
 class GridGather(torch.autograd.Function):

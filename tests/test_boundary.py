@@ -91,13 +91,21 @@ def test_invalid_arguments_rejected_on_host():
     assert b"bmin < bmax" in L.fipt_last_error()
     assert L.fipt_hashgrid_forward(1, 1, 4, 8, box0, box1, 1, 8, None) == fipt.EINVAL  # stride < n
     assert L.fipt_hashgrid_workspace_floats(0) == 0
-    # 325 floats per point (activations and layer gradients) + one 64 x 64
-    # partial per 8192-point chunk for each of the three products
-    assert L.fipt_hashgrid_workspace_floats(10000) == 325 * 10000 + 3 * 2 * 4096
-    need = L.fipt_hashgrid_workspace_floats(100)
-    assert L.fipt_hashgrid_backward(1, 1, 100, 100, box0, box1, 1, 100, 1, 1, need - 1,
-                                    None) == fipt.EINVAL
-    assert b"workspace" in L.fipt_last_error()
+    # 325 floats per point (activations and layer gradients) + 64 (the
+    # per-level feature gradients) + one 64 x 64 partial per 2048-point chunk
+    # for each of the three products
+    assert L.fipt_hashgrid_workspace_floats(10000) == (325 + 64) * 10000 + 3 * 5 * 4096
+    assert L.fipt_hashgrid_backward(None, 1, 1, 100, 1, 1, 1 << 30, None) == fipt.EINVAL
+    assert b"plan" in L.fipt_last_error()
+    h = C.c_void_p()
+    assert L.fipt_hashgrid_plan_create(None, 1, 1, box0, box1, None, C.byref(h)) == fipt.EINVAL
+    assert L.fipt_hashgrid_plan_create(1, 1, 1, box1, box0, None, C.byref(h)) == fipt.EINVAL
+    assert b"bmin < bmax" in L.fipt_last_error()
+    assert L.fipt_hashgrid_plan_create(1, 1 << 28, 1 << 28, box0, box1, None,
+                                       C.byref(h)) == fipt.EINVAL
+    assert b"2^28" in L.fipt_last_error()
+    assert L.fipt_hashgrid_plan_create(1, 4, 8, box0, box1, None, C.byref(h)) == fipt.EINVAL
+    assert h.value is None
 
 
 # (scale, offset) applied to the room: the 4-wide nodes store bounds as

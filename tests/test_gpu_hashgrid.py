@@ -84,26 +84,27 @@ def _close(got, want, tol, what):
     assert not bad.any(), f"{what}: {bad.sum()} entries off, worst {np.max(np.abs(g - want) / scale):.3e}"
 
 
-def test_backward_parity_and_weight_determinism():
+def test_backward_parity_and_determinism():
     n = 20000
     params = _params(5)
     x = _points(n, 6)
     gy = np.random.default_rng(7).standard_normal((5, n)).astype(np.float32)
     P, X, G = _t(params), _t(x), _t(gy)
-    g1 = fipt.fipt_hashgrid_backward(P, X, LO, HI, G)
-    g2 = fipt.fipt_hashgrid_backward(P, X, LO, HI, G)
+    plan = fipt.HashGridPlan(X, LO, HI)
+    g1 = fipt.fipt_hashgrid_backward(plan, P, G)
+    g2 = fipt.fipt_hashgrid_backward(plan, P, G)
     torch.cuda.synchronize()
     want = hg.backward(params, x, LO, HI, gy)
     a = g1.cpu().numpy()
-    # weight gradients: summed in a fixed order
-    assert torch.equal(g1[hg.N_TABLE:], g2[hg.N_TABLE:])
+    # the whole gradient, tables included, is summed in a fixed order
+    assert torch.equal(g1, g2)
     _close(a[hg.N_TABLE:hg.N_TABLE + hg.N_W1], want[hg.N_TABLE:hg.N_TABLE + hg.N_W1], 1e-3, "W1 grad")
     _close(a[hg.N_TABLE + hg.N_W1:hg.N_TABLE + hg.N_W1 + hg.N_W2],
            want[hg.N_TABLE + hg.N_W1:hg.N_TABLE + hg.N_W1 + hg.N_W2], 1e-3, "W2 grad")
     _close(a[-hg.N_W3:], want[-hg.N_W3:], 1e-3, "W3 grad")
     # table gradients: every level (dense levels 0-2, the coarse levels whose
-    # wavefront-combined updates reach 5, the fine levels where zero-weight
-    # vertices are skipped)
+    # slots gather thousands of entries over 64 lanes, the fine levels where
+    # zero-weight vertices are left out of the lists)
     for l in range(hg.LEVELS):
         sl = slice(l * hg.T * hg.FEATURES, (l + 1) * hg.T * hg.FEATURES)
         _close(a[sl], want[sl], 1e-3, f"table grad level {l}")
@@ -118,15 +119,20 @@ def test_backward_accumulates_and_rejects_small_workspace():
     x = _points(n, 9)
     gy = np.random.default_rng(10).standard_normal((5, n)).astype(np.float32)
     P, X, G = _t(params), _t(x), _t(gy)
-    once = fipt.fipt_hashgrid_backward(P, X, LO, HI, G)
-    twice = fipt.fipt_hashgrid_backward(P, X, LO, HI, G, grad_params=once.clone())
+    plan = fipt.HashGridPlan(X, LO, HI)
+    once = fipt.fipt_hashgrid_backward(plan, P, G)
+    twice = fipt.fipt_hashgrid_backward(plan, P, G, grad_params=once.clone())
     torch.cuda.synchronize()
-    w = slice(hg.N_TABLE, None)
-    torch.testing.assert_close(twice[w], 2 * once[w], rtol=1e-6, atol=0)
+    # every entry is one fixed-order sum added onto what is there: x + x
+    assert torch.equal(twice, 2 * once)
     with pytest.raises(ValueError):
-        fipt.fipt_hashgrid_backward(P, X, LO, HI, G, workspace=torch.empty(10, device=DEV))
+        fipt.fipt_hashgrid_backward(plan, P, G, workspace=torch.empty(10, device=DEV))
+    with pytest.raises(ValueError):
+        fipt.fipt_hashgrid_backward(plan, P, G[:, :499].contiguous())
     with pytest.raises(fipt.FiptError):
         fipt.fipt_hashgrid_forward(P, X, HI, LO)
+    with pytest.raises(fipt.FiptError):
+        fipt.HashGridPlan(X, HI, LO)
 
 
 def test_chain_into_factored_loss():
@@ -138,7 +144,7 @@ def test_chain_into_factored_loss():
     sh = synth.random_shading(n, 6, seed=13)
     obs = synth.random_observations(n, seed=14)
     P = _t(params).requires_grad_(True)
-    mat = fipt.HashGridMaterial.apply(P, _t(x), LO, HI)
+    mat = fipt.HashGridMaterial.apply(P, fipt.HashGridPlan(_t(x), LO, HI))
     loss = fipt.FactoredLoss.apply(mat, _t(sh), _t(obs), SIG, 0)
     loss.backward()
     mat_o, _ = hg.forward(params, x, LO, HI)
@@ -162,19 +168,24 @@ def test_backward_full_size_is_additive_over_point_sets():
     n = pos.shape[1]
     params = _t(synth.hashgrid_params())
     g = torch.randn((5, n), generator=torch.Generator().manual_seed(15)).to(DEV)
-    whole = fipt.fipt_hashgrid_backward(params, pos, sc.bmin, sc.bmax, g)
+    plan = fipt.HashGridPlan(pos, sc.bmin, sc.bmax)
+    whole = fipt.fipt_hashgrid_backward(plan, params, g)
+    again = fipt.fipt_hashgrid_backward(plan, params, g)
+    del plan
     h = n // 2
-    parts = fipt.fipt_hashgrid_backward(params, pos[:, :h].contiguous(), sc.bmin, sc.bmax,
-                                        g[:, :h].contiguous())
-    parts = fipt.fipt_hashgrid_backward(params, pos[:, h:].contiguous(), sc.bmin, sc.bmax,
-                                        g[:, h:].contiguous(), grad_params=parts)
+    p1 = fipt.HashGridPlan(pos[:, :h], sc.bmin, sc.bmax)
+    parts = fipt.fipt_hashgrid_backward(p1, params, g[:, :h].contiguous())
+    del p1
+    p2 = fipt.HashGridPlan(pos[:, h:], sc.bmin, sc.bmax)
+    parts = fipt.fipt_hashgrid_backward(p2, params, g[:, h:].contiguous(), grad_params=parts)
+    del p2
     torch.cuda.synchronize()
+    assert torch.equal(whole, again)
     a, b = whole.cpu().numpy().astype(np.float64), parts.cpu().numpy().astype(np.float64)
-    # a weight gradient is a single-precision sum of 225 chunk partials, and a
-    # table entry a single-precision sum of atomic adds in run-dependent
-    # order, with signs that cancel; splitting the points regroups those
-    # sums, which moves a few entries by ~2e-4 of their scale: the bound is
-    # the oracle comparison's
+    # a weight gradient is a single-precision sum of 900 chunk partials, and a
+    # table entry the single-precision sum of the two halves' totals, with
+    # signs that cancel; splitting the points regroups those sums: the bound
+    # is the oracle comparison's
     _close(a[hg.N_TABLE:], b[hg.N_TABLE:], 1e-3, "weight grads, whole vs halves")
     _close(a[:hg.N_TABLE], b[:hg.N_TABLE], 1e-3, "table grads, whole vs halves")
     assert np.abs(a[hg.N_TABLE:]).max() > 0 and np.abs(a[:hg.N_TABLE]).max() > 0
