@@ -9,10 +9,12 @@
 // BRDF of Eq. 1, the radiance arriving there estimated by emitter sampling
 // and BRDF sampling combined with the balance heuristic.
 //
-// Mapping: as the chunked bake, one wavefront per point from a persistent
-// grid; its 64 lanes take 64 consecutive (lobe, sample) pairs and each lane
-// follows its own path to the end; the lobes of a chunk are then summed by
-// the fixed xor butterfly, so a point's result depends only on the inputs.
+// Mapping: one wavefront per point from a persistent grid.  With at most 10
+// roughness levels each lane owns one path at a time and takes the point's
+// next sample when its path ends (refine_point_refill); with more, the 64
+// lanes take 64 consecutive (lobe, sample) pairs and follow them to the end
+// (refine_point).  Either way the lobes are summed by the fixed xor
+// butterfly, so a point's result depends only on the inputs.
 //
 // The emitters (triangles with some channel of emission > 0, in ascending
 // original index) are listed on the device at the start of each call by an
@@ -449,6 +451,305 @@ __device__ void refine_point(const RefineArgs& A, int64_t p, int lane, int32_t* 
     if (64 + lane < P) b.out[(int64_t)dev::slot_plane(64 + lane, K) * os + p] = acc_b / (float)spp_s;
 }
 
+// Refine point p with the calling wavefront, each lane owning one path at a
+// time (the refill bake's layout): every iteration traces one ray per busy
+// lane (a path segment, or the shadow ray of a glossy vertex's emitter
+// sample); a lane whose path has ended adds its radiance into its current
+// lobe's sums, and once kRefillMin lanes are free they take the next samples
+// of the point in lane order (a ballot), so the schedule, and the result,
+// depend only on the inputs.  Each path's arithmetic and random numbers are
+// those of refine_path.
+constexpr int kRefillMin = 40;
+constexpr int kRefillMaxK = 10;
+enum PathState { kIdle = 0, kTracing = 1, kFinished = 2 };
+
+__device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, int32_t* stack, int n_emit) {
+    const BakeLaunch& b = A.b;
+    const DeviceScene& sc = b.sc;
+    const int K = b.K;
+    const int P = 3 + 6 * K;
+    const int64_t ps = b.pts_stride;
+    const int32_t tri = b.ptri[p];
+    V3 x = v3(b.pts[p], b.pts[ps + p], b.pts[2 * ps + p]);
+    V3 n = v3(b.pts[3 * ps + p], b.pts[4 * ps + p], b.pts[5 * ps + p]);
+    const V3 wo0 = v3(b.pts[6 * ps + p], b.pts[7 * ps + p], b.pts[8 * ps + p]);
+    float cos_o = dev::dot(n, wo0);
+    if (tri >= 0 && cos_o < 0.0f) {
+        n = v3(-n.x, -n.y, -n.z);
+        cos_o = -cos_o;
+    }
+    const int64_t os = b.out_stride;
+    if (!(tri >= 0 && cos_o > 0.0f)) {
+        for (int j = lane; j < P; j += 64) b.out[(int64_t)j * os + p] = 0.0f;
+        return;
+    }
+    V3 pft, pfb;
+    dev::make_frame(n, pft, pfb);
+    const V3 o0 = x + b.eps * n;
+    const int64_t rng_p = p + b.p_offset;
+    const int spp_d = b.spp_d, spp_s = b.spp_s;
+    const int S = spp_d + K * spp_s;
+    const bool nee = A.nee && n_emit > 0;
+
+    // output slot j belongs to lane j; lobe sums flushed as in the refill bake
+    float own = 0.0f;
+    float cur0 = 0.0f, cur1 = 0.0f, cur2 = 0.0f, cur3 = 0.0f, cur4 = 0.0f, cur5 = 0.0f;
+    int cur_lobe = -1;
+    auto flush = [&](bool need) {
+        uint64_t m = dev::ballot(need);
+        while (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            const int l = __shfl(cur_lobe, leader, 64);
+            const bool in = need && cur_lobe == l;
+            m &= ~dev::ballot(in);
+            const float s0 = dev::wave_sum(in ? cur0 : 0.0f);
+            const float s1 = dev::wave_sum(in ? cur1 : 0.0f);
+            const float s2 = dev::wave_sum(in ? cur2 : 0.0f);
+            float s3 = 0.0f, s4 = 0.0f, s5 = 0.0f;
+            if (l > 0) {
+                s3 = dev::wave_sum(in ? cur3 : 0.0f);
+                s4 = dev::wave_sum(in ? cur4 : 0.0f);
+                s5 = dev::wave_sum(in ? cur5 : 0.0f);
+            }
+            const int r = lane - (l == 0 ? 0 : 3 + 6 * (l - 1));
+            if (r >= 0 && r < (l == 0 ? 3 : 6))
+                own += r == 0 ? s0 : r == 1 ? s1 : r == 2 ? s2 : r == 3 ? s3 : r == 4 ? s4 : s5;
+        }
+    };
+
+    int state = kIdle;
+    int lobe = 0, s = 0;
+    float w0 = 0.0f, w1 = 0.0f;
+    // the path: the ray to trace, throughput, radiance so far, the density
+    // of the BRDF sample that led here (-1 for the stage-1 sample), vertex
+    V3 o = o0, d = v3(0.0f, 0.0f, 1.0f), T = v3(1.0f, 1.0f, 1.0f), C = v3(0.0f, 0.0f, 0.0f);
+    float pb_prev = -1.0f;
+    int vert = 1;
+    // a shadow ray in flight: its emitter and what it adds when unoccluded;
+    // then the continuation (valid or not)
+    bool shadow = false;
+    int32_t fe = -1;
+    V3 cn = v3(0.0f, 0.0f, 0.0f);
+    bool cont = false;
+    V3 o2 = o0, d2 = d, T2 = T;
+    float pb2 = 0.0f;
+    uint32_t z0 = 0, z1 = 0;
+    int next_q = 0;
+
+    while (true) {
+        const uint64_t tracing = dev::ballot(state == kTracing);
+        const int n_free = 64 - __popcll(tracing);
+        if ((n_free >= kRefillMin && next_q < S) || tracing == 0) {
+            const bool done = state == kFinished;
+            flush(done && cur_lobe >= 0 && cur_lobe != lobe);
+            if (done) {
+                if (cur_lobe != lobe) {
+                    cur0 = cur1 = cur2 = cur3 = cur4 = cur5 = 0.0f;
+                    cur_lobe = lobe;
+                }
+                cur0 += C.x * w0;
+                cur1 += C.y * w0;
+                cur2 += C.z * w0;
+                cur3 += C.x * w1;
+                cur4 += C.y * w1;
+                cur5 += C.z * w1;
+                state = kIdle;
+            }
+            if (next_q >= S && tracing == 0) break;
+            if (next_q < S) {
+                if (state == kIdle) {
+                    const int rank = __popcll(~tracing & ((1ull << lane) - 1ull));
+                    const int q = next_q + rank;
+                    if (q < S) {
+                        lobe = dev::lobe_of(q, spp_d, spp_s);
+                        s = lobe == 0 ? q : (q - spp_d) - (lobe - 1) * spp_s;
+                        float xi1, xi2;
+                        dev::lobe_uniforms(b.seed, rng_p, lobe, s, lobe == 0 ? b.w_d : b.w_s, xi1, xi2);
+                        float sp_, cp_;
+                        sincospif(2.0f * xi2, &sp_, &cp_);
+                        bool shoot = false;
+                        if (lobe == 0) {
+                            const float r = dev::sqrt_hw(xi1);
+                            d = dev::to_world(pft, pfb, n, r * cp_, r * sp_, dev::sqrt_hw(1.0f - xi1));
+                            w0 = 1.0f;
+                            w1 = 0.0f;
+                            shoot = true;
+                        } else {
+                            const float sg = b.sigma[lobe - 1];
+                            const float alpha = sg * sg;
+                            const float a2 = alpha * alpha;
+                            const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
+                            const float cos_m = rsqrtf(1.0f + tan2);
+                            const float sin_m = dev::sqrt_hw(tan2) * cos_m;
+                            const V3 m = dev::to_world(pft, pfb, n, sin_m * cp_, sin_m * sp_, cos_m);
+                            const float om = dev::dot(wo0, m);
+                            if (om > 0.0f) {
+                                d = (2.0f * om) * m - wo0;
+                                const float ci = dev::dot(n, d);
+                                if (ci > 0.0f) {
+                                    const float G = dev::smith_g1(a2, ci) * dev::smith_g1(a2, cos_o);
+                                    const float w = G * om * dev::rcp(cos_o * cos_m);
+                                    const float f = 1.0f - om;
+                                    const float f2 = f * f;
+                                    const float F1 = f2 * f2 * f;
+                                    w0 = w * (1.0f - F1);
+                                    w1 = w * F1;
+                                    shoot = true;
+                                }
+                            }
+                        }
+                        if (shoot) {
+                            o = o0;
+                            T = v3(1.0f, 1.0f, 1.0f);
+                            C = v3(0.0f, 0.0f, 0.0f);
+                            pb_prev = -1.0f;
+                            vert = 1;
+                            shadow = false;
+                            state = kTracing;
+                        }
+                        // an invalid specular sample counts as zero: the lane
+                        // stays idle and takes another sample next time
+                    }
+                }
+                next_q = min(S, next_q + n_free);
+            }
+        }
+        if (state != kTracing) continue;
+        const dev::Hit h = dev::trace<false>(sc, o, d, stack, kBlock, z0, z1);
+        if (shadow) {
+            // the emitter sample's contribution, then the continuation
+            if (h.leaf == fe) C = C + cn;
+            shadow = false;
+            if (cont) {
+                o = o2;
+                d = d2;
+                T = T2;
+                pb_prev = pb2;
+                ++vert;
+            } else {
+                state = kFinished;
+            }
+            continue;
+        }
+        if (h.leaf < 0) {
+            state = kFinished;
+            continue;
+        }
+        const float4 r2 = dev::load_global(reinterpret_cast<const float4*>(sc.rad + h.leaf) + 2);
+        if (r2.y > 0.0f || r2.z > 0.0f || r2.w > 0.0f) {
+            float w = 1.0f;
+            if (pb_prev >= 0.0f && nee) {
+                V3 v0, e1, e2, nz;
+                const float area = tri_frame(sc.tris, h.leaf, v0, e1, e2, nz);
+                const float cz = fabsf(dev::dot(nz, d));
+                const float pl = h.t * h.t * dev::rcp(cz * (float)n_emit * area);
+                w = pb_prev * dev::rcp(pb_prev + pl);
+            }
+            C = C + v3(T.x * r2.y * w, T.y * r2.z * w, T.z * r2.w * w);
+            state = kFinished;
+            continue;
+        }
+        V3 v0, e1, e2, ny;
+        tri_frame(sc.tris, h.leaf, v0, e1, e2, ny);
+        const double yd[3] = {(double)v0.x + (double)h.u * e1.x + (double)h.v * e2.x,
+                              (double)v0.y + (double)h.u * e1.y + (double)h.v * e2.y,
+                              (double)v0.z + (double)h.u * e1.z + (double)h.v * e2.z};
+        const V3 y = v3((float)yd[0], (float)yd[1], (float)yd[2]);
+        const V3 wo = v3(-d.x, -d.y, -d.z);
+        if (dev::dot(ny, wo) < 0.0f) ny = v3(-ny.x, -ny.y, -ny.z);
+        if (!(dev::dot(ny, wo) > 0.0f)) {
+            state = kFinished;
+            continue;
+        }
+        const Material mt = material_at(A.mat, yd);
+        if (mt.sigma > A.sigma_diffuse || vert >= A.max_vertices) {
+            const V3 R = dev::radiance(sc, h);
+            C = C + v3(T.x * R.x, T.y * R.y, T.z * R.z);
+            state = kFinished;
+            continue;
+        }
+        // a glossy vertex: the emitter sample (traced next), then the
+        // continuation drawn from f
+        const float sg = fminf(fmaxf(mt.sigma, 0.02f), 1.0f);
+        const float alpha = sg * sg, a2 = alpha * alpha;
+        const V3 yo = y + b.eps * ny;
+        const uint4 u = vertex_philox(b.seed, rng_p, lobe, s, vert, 0);
+        const uint4 vv = vertex_philox(b.seed, rng_p, lobe, s, vert, 1);
+        bool shoot_shadow = false;
+        V3 l = v3(0.0f, 0.0f, 1.0f);
+        if (nee) {
+            fe = A.emit[__umulhi(u.x, (uint32_t)n_emit)];
+            V3 q0, q1, q2, nz;
+            const float area = tri_frame(sc.tris, fe, q0, q1, q2, nz);
+            const float su = dev::sqrt_hw(unif24(u.y)), xb = unif24(u.z);
+            const V3 z = q0 + (su * (1.0f - xb)) * q1 + (su * xb) * q2;
+            l = z - yo;
+            const float dist = sqrtf(dev::dot(l, l));
+            l = (1.0f / dist) * l;
+            const float cz = fabsf(dev::dot(nz, l));
+            if (dev::dot(ny, l) > 0.0f && cz > 0.0f) {
+                const V3 fv = brdf_f(ny, wo, l, mt, a2);
+                const float pl = dist * dist * dev::rcp(cz * (float)n_emit * area);
+                const float inv = dev::rcp(pl + brdf_pdf(ny, wo, l, a2));
+                const float4 e = dev::load_global(reinterpret_cast<const float4*>(sc.rad + fe) + 2);
+                cn = v3(T.x * fv.x * e.y * inv, T.y * fv.y * e.z * inv, T.z * fv.z * e.w * inv);
+                shoot_shadow = true;
+            }
+        }
+        const V3 ft = normalize(e1);
+        const V3 fb = dev::cross(ny, ft);
+        const float xi1 = unif24(vv.x), xi2 = unif24(vv.y);
+        float sp_, cp_;
+        sincospif(2.0f * xi2, &sp_, &cp_);
+        V3 w2 = v3(0.0f, 0.0f, 0.0f);
+        cont = true;
+        if (unif24(u.w) < 0.5f) {
+            const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
+            const float cos_m = rsqrtf(1.0f + tan2);
+            const float sin_m = dev::sqrt_hw(tan2) * cos_m;
+            const V3 m = dev::to_world(ft, fb, ny, sin_m * cp_, sin_m * sp_, cos_m);
+            const float om = dev::dot(wo, m);
+            if (!(om > 0.0f)) cont = false;
+            else w2 = (2.0f * om) * m - wo;
+        } else {
+            const float r = dev::sqrt_hw(xi1);
+            w2 = dev::to_world(ft, fb, ny, r * cp_, r * sp_, dev::sqrt_hw(1.0f - xi1));
+        }
+        float pb = 0.0f;
+        if (cont && !(dev::dot(ny, w2) > 0.0f)) cont = false;
+        if (cont) {
+            pb = brdf_pdf(ny, wo, w2, a2);
+            if (!(pb > 0.0f)) cont = false;
+        }
+        if (cont) {
+            const V3 fv = brdf_f(ny, wo, w2, mt, a2);
+            const float ipb = dev::rcp(pb);
+            T2 = v3(T.x * fv.x * ipb, T.y * fv.y * ipb, T.z * fv.z * ipb);
+            o2 = yo;
+            d2 = w2;
+            pb2 = pb;
+        }
+        if (shoot_shadow) {
+            o = yo;
+            d = l;
+            shadow = true;
+        } else if (cont) {
+            o = o2;
+            d = d2;
+            T = T2;
+            pb_prev = pb2;
+            ++vert;
+        } else {
+            state = kFinished;
+        }
+    }
+    flush(cur_lobe >= 0);
+    if (lane < P) {
+        const float cnt = lane < 3 ? (float)spp_d : (float)spp_s;
+        b.out[(int64_t)dev::slot_plane(lane, K) * os + p] = own / cnt;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs A, int32_t* counters) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
@@ -456,8 +757,12 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs A, int32_t* counte
     const int n_emit = __builtin_amdgcn_readfirstlane(*A.n_emit);
     const int home = (int)(blockIdx.x % kXcdCount);
     int tried = 0;
-    for (int64_t p; (p = dev::next_point(counters, home, tried, A.b.n, lane)) >= 0;)
-        refine_point(A, p, lane, stack, n_emit);
+    // the refill layout gives every output slot its own lane (3 + 6K <= 64)
+    const bool refill = A.b.K <= kRefillMaxK;
+    for (int64_t p; (p = dev::next_point(counters, home, tried, A.b.n, lane)) >= 0;) {
+        if (refill) refine_point_refill(A, p, lane, stack, n_emit);
+        else refine_point(A, p, lane, stack, n_emit);
+    }
 }
 
 __global__ void k_zero_counters_r(int32_t* counters) {

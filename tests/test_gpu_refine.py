@@ -97,6 +97,22 @@ def test_tiny_refine_parity(tiny_case, flags):
     assert np.mean(np.abs(base - want["mean"][:, ::16]) > 1e-3 * np.abs(base).max()) > 0.2
 
 
+def test_tiny_refine_parity_many_levels(tiny_case):
+    """With more than 10 roughness levels (3 + 6K output slots beyond the 64
+    lanes of a wavefront) the kernel takes its chunked form, 64 (lobe,
+    sample) pairs per step instead of a path per lane: the same criterion
+    on 1024 of the tiny box's points at K = 12."""
+    sc, osc, pts, tri, grid, s = tiny_case
+    sigma = np.linspace(0.05, 0.6, 12).astype(np.float32)
+    idx = np.arange(0, sc.n_points, 4)
+    sub, subt = np.ascontiguousarray(pts[:, idx]), np.ascontiguousarray(tri[idx])
+    want = ob.refine(osc, sub, subt, grid, *BOX, spp_d=32, spp_s=32, sigma=sigma, seed=sc.seed)
+    got = _refine_gpu(s, sub, subt, grid, *BOX, 32, 32, sigma, sc.seed)
+    assert got.shape == (3 + 6 * 12, len(idx))
+    r = assert_refine_parity(got, want)
+    print("tiny refine parity, K = 12:", r)
+
+
 @pytest.mark.parametrize("flags", [0, fipt.REFINE_BSDF_ONLY])
 def test_tiny_rough_material_parity(tiny_case, flags):
     """A rough material (random 8^3 grid, roughness U[0.02, 1] per node):
