@@ -70,6 +70,10 @@ KERNEL_SOURCES = {
     "k_render_loss_masked": ("loss.hip", "fipt_internal.hpp"),
     "k_bake_voxel": ("bake.hip", "device.hpp", "fipt_internal.hpp", "bvh_build.cpp"),
     "k_hg_forward": ("hashgrid.hip", "fipt_internal.hpp"),
+    "k_hg_backward": ("hashgrid.hip", "fipt_internal.hpp"),
+    "k_hg_table_grad": ("hashgrid.hip", "fipt_internal.hpp"),
+    "k_grid_adjoint": ("loss.hip", "grid.cpp", "fipt_internal.hpp"),
+    "k_grid_gather": ("loss.hip", "fipt_internal.hpp"),
 }
 
 
@@ -706,6 +710,17 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
         reads += torch.prod(1.0 + (f != 0).to(torch.float64), dim=0)
     reads_pp = float(reads.mean().item())
     bytes_pp = 8.0 * reads_pp + 32.0
+    # the backward call's algorithmic bytes per point: the per-point kernel
+    # (vertex gathers, position and output gradient in, 325 activations and
+    # layer gradients and 64 feature gradients out), the table gather (an
+    # 8-byte entry and an 8-byte feature gradient per nonzero (point, corner),
+    # as many as the forward's vertex reads), the weight-gradient products
+    # (the 325 workspace floats read once); the tables' read-modify-write of
+    # touched slots is not counted
+    bwd_pp = 8.0 * reads_pp + 32.0 + 4.0 * (325 + 64) + 16.0 * reads_pp + 4.0 * 325
+    bwd_note = ("8 B x vertex reads + 32 B + 4 B x (325 + 64) stores (per-point kernel); 16 B x vertex "
+                "reads (table gather); 4 B x 325 (weight-gradient products); table read-modify-write "
+                "not counted")
     del p, u, f, reads
     return {"points": N, "params": int(params.numel()), "forward_ms": t_fwd,
             "loss_ms": t_loss, "zero_grad_ms": t_zero, "backward_ms": t_bwd,
@@ -723,7 +738,14 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
                                  "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                  "frac": bytes_pp * N / (t_fwd * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                  "traffic": measured_traffic().get("k_hg_forward"),
-                                 "kernel": "k_hg_forward"}}
+                                 "kernel": "k_hg_forward"},
+            "backward_bytes_per_point": bwd_pp,
+            "backward_bytes_note": bwd_note,
+            "roofline_backward": {"bound": "hbm", "achieved": bwd_pp * N / (t_bwd * 1e-3) / 1e9,
+                                  "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                  "frac": bwd_pp * N / (t_bwd * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                  "traffic": measured_traffic().get("k_hg_backward"),
+                                  "kernel": "k_hg_backward + k_hg_table_grad + k_hg_wgrad + k_hg_wreduce"}}
 
 
 def run_large(dev, rebakes, copy_gbs):
@@ -944,9 +966,10 @@ def main():
     roof_grid = {
         kname: {"bound": "hbm", "achieved": grid_bytes / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": grid_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                "ms": ms, "bytes_per_launch": grid_bytes, "kernel": kn}
-        for kname, ms, kn in (("gather", t_gather, "k_grid_gather"),
-                              ("adjoint", t_scatter, "k_grid_adjoint + k_grid_adjoint_combine"))}
+                "ms": ms, "bytes_per_launch": grid_bytes, "kernel": kn, "traffic": traffic.get(tk)}
+        for kname, ms, kn, tk in (("gather", t_gather, "k_grid_gather", "k_grid_gather"),
+                                  ("adjoint", t_scatter, "k_grid_adjoint + k_grid_adjoint_combine",
+                                   "k_grid_adjoint"))}
 
     flush = torch.ones((1 << 27,), dtype=torch.float32, device=dev)      # 512 MB
     t_loss_cold = loss_timing(shading, mat, obs, sc.sigma, flush=flush)

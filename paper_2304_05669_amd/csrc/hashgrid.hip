@@ -293,17 +293,11 @@ __global__ __launch_bounds__(kBlock) void k_hgp_keys(HgArgs a, int l, uint32_t* 
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(nnz, (unsigned long long)c);
 }
 
-// Entries (p << 3 | corner, weight bits) of the sorted nonzero list, and the
-// slot ranges: off[s] = first entry of slot s, off[kT] = nnz.
-__global__ __launch_bounds__(kBlock) void k_hgp_entries(HgArgs a, int l, const uint32_t* __restrict__ keys,
-                                                        const uint32_t* __restrict__ vals, int64_t nnz,
-                                                        int2* __restrict__ ent, uint32_t* __restrict__ off) {
+// Entries (p << 3 | corner, weight bits) of the sorted nonzero list.
+__global__ __launch_bounds__(kBlock) void k_hgp_entries(HgArgs a, int l, const uint32_t* __restrict__ vals,
+                                                        int64_t nnz, int2* __restrict__ ent) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i > nnz) return;
-    const uint32_t cur = i < nnz ? keys[i] : kT;
-    const int64_t prev = i > 0 ? (int64_t)keys[i - 1] : -1;
-    for (int64_t t = prev + 1; t <= (int64_t)cur; ++t) off[t] = (uint32_t)i;
-    if (i == nnz) return;
+    if (i >= nnz) return;
     const uint32_t e = vals[i];
     float p[3];
     unit_pos(a, e >> 3, p);
@@ -314,6 +308,21 @@ __global__ __launch_bounds__(kBlock) void k_hgp_entries(HgArgs a, int l, const u
 #pragma unroll
     for (int k = 0; k < 8; ++k) wk = (int)(e & 7) == k ? w[k] : wk;
     ent[i] = make_int2((int)e, __float_as_int(wk));
+}
+
+// Slot ranges: off[s] = the first sorted entry whose slot is >= s (a binary
+// search per slot), so off[kT] = nnz.
+__global__ __launch_bounds__(kBlock) void k_hgp_offsets(const uint32_t* __restrict__ keys, int64_t nnz,
+                                                        uint32_t* __restrict__ off) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s > (int64_t)kT) return;
+    int64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < s) lo = mid + 1;
+        else hi = mid;
+    }
+    off[s] = (uint32_t)lo;
 }
 
 // Table gradient of one level, slots of at most kHeavy entries: L lanes per
@@ -637,8 +646,11 @@ int fipt_hashgrid_plan_create(const float* pos, int64_t pos_stride, int64_t n, c
                 hipSuccess ||
             hipMalloc(reinterpret_cast<void**>(&p->off[l]), sizeof(uint32_t) * (kT + 1)) != hipSuccess)
             return bail(FIPT_ENOMEM, "hipMalloc entries failed");
-        hipLaunchKernelGGL(k_hgp_entries, dim3(grid_points(p->nnz[l] + 1)), dim3(kBlock), 0, st, a, l, k_out,
-                           v_out, p->nnz[l], p->ent[l], p->off[l]);
+        if (p->nnz[l] > 0)
+            hipLaunchKernelGGL(k_hgp_entries, dim3(grid_points(p->nnz[l])), dim3(kBlock), 0, st, a, l, v_out,
+                               p->nnz[l], p->ent[l]);
+        hipLaunchKernelGGL(k_hgp_offsets, dim3(grid_points(kT + 1)), dim3(kBlock), 0, st, k_out, p->nnz[l],
+                           p->off[l]);
         // slots of more than kHeavy entries get a workgroup each; the others
         // share lanes by the mean length of their lists
         const int64_t slots = level_slots(l);
