@@ -9,17 +9,16 @@
 // Parameters, one float array: tables [32][2^19][2], then W1 [64][64],
 // W2 [64][64], W3 [5][64] (row = output).
 //
-// Forward: one thread per point (one point per thread and no grid-stride
-// loop, so the compiler cannot hoist the weight reads out of a loop into
-// registers); each workgroup copies the three weight matrices (34 KB) into
-// LDS, and every thread of a workgroup reads the same weight at once (an
-// LDS broadcast); the point's hidden activations stay in registers.  The 256 table gathers per point (8 vertices x 32 levels, 8
-// bytes each) are the memory traffic; the tables (134 MB) live in HBM and
-// the MALL.
+// Forward: one lane per point for the encoding (the 256 table gathers per
+// point, 8 vertices x 32 levels of 8 bytes, are the memory traffic; the
+// tables, 134 MB, live in HBM and the MALL) and the two hidden layers on the
+// matrix cores over the wavefront's 64 points (see below), the weights in
+// LDS; the five outputs on the vector ALUs.
 //
-// Backward: one thread per point recomputes the forward pass, back-propagates
-// through the MLP, stores its per-level feature gradients (W1^T d1, two per
-// level) and its activations and layer gradients in a workspace.  The table
+// Backward: each wavefront recomputes the forward pass of its 64 points,
+// back-propagates through the MLP (W2^T and W1^T on the matrix cores too),
+// stores the per-level feature gradients (W1^T d1, two per level) and the
+// activations and layer gradients in a workspace.  The table
 // gradient is then a gather: a plan built once for the point set lists, per
 // level, every (point, corner) with a nonzero trilinear weight sorted by
 // table slot (then point, then corner), and one group of lanes per slot sums
@@ -103,166 +102,336 @@ __device__ __forceinline__ void unit_pos(const HgArgs& a, int64_t i, float p[3])
         p[k] = fminf(fmaxf((a.pos[k * a.ps + i] - a.lo[k]) * a.inv[k], 0.0f), 1.0f);
 }
 
-__device__ __forceinline__ void load_weights(const float* __restrict__ params, float* w) {
-    for (int i = threadIdx.x; i < kWeights; i += kBlock) w[i] = params[kTable + i];
-    __syncthreads();
+// ---- the backward pass on the matrix cores -----------------------------------
+// One wavefront holds 64 points as two tiles of 32 (points 0-31 and 32-63 of
+// the wavefront).  A 64 x 64 layer over them is four 32 x 32 output tiles of
+// v_mfma_f32_32x32x2f32, two input features per instruction: lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32], and accumulator register r of lane
+// l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] (dfeat below).  The
+// encoding arrives one level (two features) at a time with a lane per point;
+// v_permlane32_swap turns the two feature registers into the B operands of
+// both point tiles.  A layer's output feeds the next layer as B without any
+// data movement: its reduction takes the features in the order the output
+// registers hold them (register r of the two half-waves, features f and
+// f + 4), and the weights are read from LDS in that same order.  The weights
+// live in LDS with rows of 65 floats, so that a row-wise read (W) and a
+// column-wise read (W^T) both reach distinct banks across the 32 lanes.
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int kWs = 65;                                      // LDS row stride of W1 and W2
+constexpr int kLdsW = 2 * kHid * kWs + kW3;                  // floats of weights in LDS
+
+__device__ __forceinline__ int dfeat(int i, int r, int h) { return 32 * i + 8 * (r >> 2) + 4 * h + (r & 3); }
+
+__device__ __forceinline__ v16f mfma2(float a, float b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-// z1 = W1 e, level by level: each level's two features are folded into the
-// 64 accumulators as soon as they are interpolated (and stored to ws_e when
-// it is not NULL, rows 2l and 2l + 1).
-__device__ __forceinline__ void encode_layer1(const float* __restrict__ tab, const float* W1,
-                                              const float p[3], float z1[kHid],
-                                              float* __restrict__ ws_e, int64_t wn) {
+// (lanes 0-31 of x, lanes 0-31 of y) and (lanes 32-63 of x, lanes 32-63 of y)
+__device__ __forceinline__ void swap_halves(float x, float y, float& lo_pair, float& hi_pair) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    lo_pair = __uint_as_float(r[0]);
+    hi_pair = __uint_as_float(r[1]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_hg_backward(HgArgs a, const float* __restrict__ gy,
+                                                             int64_t gs, float* __restrict__ ws,
+                                                             int64_t wn, float2* __restrict__ fgrad) {
+    __shared__ float w[kLdsW];
+    {
+        const float* src = a.params + kTable;
+        for (int q = threadIdx.x; q < kW1 + kW2; q += kBlock) {
+            const int m = q / kW1, rc = q % kW1;
+            w[m * kHid * kWs + (rc / kIn) * kWs + rc % kIn] = src[q];
+        }
+        for (int q = threadIdx.x; q < kW3; q += kBlock) w[2 * kHid * kWs + q] = src[kW1 + kW2 + q];
+    }
+    __syncthreads();
+    const float* W1 = w;                   // W1[o][c] at o * kWs + c
+    const float* W2 = w + kHid * kWs;      // W2[o][c] at o * kWs + c
+    const float* W3 = w + 2 * kHid * kWs;  // W3[o][c] at o * 64 + c
+    const int lane = threadIdx.x & 63, h = lane >> 5, lo = lane & 31;
+    const int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);
+    const int64_t i = base + lane;          // this lane's point in the encoding
+    const bool live = i < a.n;
+    v16f z[2][2];                           // z1, then h1 = relu(z1): [output tile][point tile]
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) z1[o] = 0.0f;
-    const float2* t2 = reinterpret_cast<const float2*>(tab);
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) z[u][j][r] = 0.0f;
+    {
+        float p[3] = {0.0f, 0.0f, 0.0f};
+        if (live) unit_pos(a, i, p);
+        const float2* t2 = reinterpret_cast<const float2*>(a.params);
 #pragma unroll 1
-    for (int l = 0; l < kLevels; ++l) {
-        uint32_t idx[8];
-        float w[8];
-        corners(l, p, idx, w);
-        const float2* t = t2 + (int64_t)l * kT;
-        float e0 = 0.0f, e1 = 0.0f;
-        // from level 20 on (2^24 cells per axis and more) a single-precision
-        // position sits exactly on a vertex: 7 of the 8 weights are zero, and
-        // their reads are skipped
+        for (int l = 0; l < kLevels; ++l) {
+            uint32_t idx[8];
+            float wt[8];
+            corners(l, p, idx, wt);
+            const float2* t = t2 + (int64_t)l * kT;
+            float e0 = 0.0f, e1 = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (w[k] != 0.0f) {
-                const float2 v = t[idx[k]];
-                e0 = fmaf(w[k], v.x, e0);
-                e1 = fmaf(w[k], v.y, e1);
+            for (int k = 0; k < 8; ++k) {
+                if (wt[k] != 0.0f) {
+                    const float2 v = t[idx[k]];
+                    e0 = fmaf(wt[k], v.x, e0);
+                    e1 = fmaf(wt[k], v.y, e1);
+                }
+            }
+            if (live) {
+                ws[(int64_t)(2 * l) * wn + i] = e0;
+                ws[(int64_t)(2 * l + 1) * wn + i] = e1;
+            }
+            float b0, b1;   // features 2l (lanes 0-31) and 2l + 1 (lanes 32-63) of point tiles 0 and 1
+            swap_halves(e0, e1, b0, b1);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float av = W1[(32 * u + lo) * kWs + 2 * l + h];
+                z[u][0] = mfma2(av, b0, z[u][0]);
+                z[u][1] = mfma2(av, b1, z[u][1]);
             }
         }
-        if (ws_e) {
-            ws_e[(int64_t)(2 * l) * wn] = e0;
-            ws_e[(int64_t)(2 * l + 1) * wn] = e1;
+    }
+    // h1 = relu(z1), stored (rows 64 + f)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                z[u][j][r] = fmaxf(z[u][j][r], 0.0f);
+                const int64_t pt = base + 32 * j + lo;
+                if (pt < a.n) ws[(int64_t)(64 + dfeat(u, r, h)) * wn + pt] = z[u][j][r];
+            }
+    // z2 = W2 h1, h2 = relu(z2), stored (rows 128 + f)
+    v16f y[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) y[u][j][r] = 0.0f;
+#pragma unroll
+    for (int ui = 0; ui < 2; ++ui)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int c = dfeat(ui, r, h);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float av = W2[(32 * u + lo) * kWs + c];
+                y[u][0] = mfma2(av, z[ui][0][r], y[u][0]);
+                y[u][1] = mfma2(av, z[ui][1][r], y[u][1]);
+            }
         }
 #pragma unroll
-        for (int o = 0; o < kHid; ++o)
-            z1[o] = fmaf(W1[o * kIn + 2 * l + 1], e1, fmaf(W1[o * kIn + 2 * l], e0, z1[o]));
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                y[u][j][r] = fmaxf(y[u][j][r], 0.0f);
+                const int64_t pt = base + 32 * j + lo;
+                if (pt < a.n) ws[(int64_t)(128 + dfeat(u, r, h)) * wn + pt] = y[u][j][r];
+            }
+    // outputs: each lane sums its half of the features of its two points;
+    // the halves meet with a swap, one point per lane
+    float d3[kOut];
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) {
+        float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float wv = W3[o * kHid + dfeat(u, r, h)];
+                s0 = fmaf(wv, y[u][0][r], s0);
+                s1 = fmaf(wv, y[u][1][r], s1);
+            }
+        float pa, pb;
+        swap_halves(s0, s1, pa, pb);
+        const float sv = pa + pb;           // point base + lane
+        const float yv = 1.0f / (1.0f + expf(-sv));
+        d3[o] = live ? gy[o * gs + i] * yv * (1.0f - yv) : 0.0f;
+        if (live) ws[(int64_t)(320 + o) * wn + i] = d3[o];
     }
-}
-
-// h = relu(W x) for 64 x 64 W, with a bit mask of the positive outputs.
-__device__ __forceinline__ void dense_relu(const float* W, const float* x, float* h, uint64_t& pos) {
-    pos = 0;
+    // d2 = (W3^T d3) masked by h2 > 0, in y's registers (rows 256 + f); the
+    // d3 of both point tiles reach every lane with a swap
+    float da[kOut], db[kOut];
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) {
-        float s = 0.0f;
+    for (int o = 0; o < kOut; ++o) swap_halves(d3[o], d3[o], da[o], db[o]);
 #pragma unroll
-        for (int i = 0; i < kHid; ++i) s = fmaf(W[o * kHid + i], x[i], s);
-        h[o] = fmaxf(s, 0.0f);
-        pos |= (uint64_t)(s > 0.0f) << o;
-        // one output at a time: keep the scheduler from hoisting the weight
-        // reads of later outputs (it would spill them)
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-// Occupancy targets keep the compiler from hoisting the weight loads of the
-// unrolled products into hundreds of registers: 4 waves per SIMD (at most
-// 128 VGPRs) for the forward pass, 3 (at most 168) for the backward pass,
-// whose layer gradients hold two 64-vectors at once.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_hg_forward(HgArgs a, float* __restrict__ out,
-                                                       int64_t os) {
-    __shared__ float w[kWeights];
-    load_weights(a.params, w);
-    const float* W1 = w;
-    const float* W2 = w + kW1;
-    const float* W3 = w + kW1 + kW2;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < a.n) {
-        float p[3], h1[kHid], h2[kHid];
-        unit_pos(a, i, p);
-        encode_layer1(a.params, W1, p, h1, nullptr, 0);
-        uint64_t m1, m2;
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int o = 0; o < kHid; ++o) h1[o] = fmaxf(h1[o], 0.0f);
-        dense_relu(W2, h1, h2, m2);
-        (void)m1;
+        for (int r = 0; r < 16; ++r) {
+            const int c = dfeat(u, r, h);
+            float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
-        for (int o = 0; o < kOut; ++o) {
-            float s = 0.0f;
+            for (int o = 0; o < kOut; ++o) {
+                const float wv = W3[o * kHid + c];
+                s0 = fmaf(wv, da[o], s0);
+                s1 = fmaf(wv, db[o], s1);
+            }
+            y[u][0][r] = y[u][0][r] > 0.0f ? s0 : 0.0f;
+            y[u][1][r] = y[u][1][r] > 0.0f ? s1 : 0.0f;
 #pragma unroll
-            for (int j = 0; j < kHid; ++j) s = fmaf(W3[o * kHid + j], h2[j], s);
-            out[o * os + i] = 1.0f / (1.0f + expf(-s));
+            for (int jj = 0; jj < 2; ++jj) {
+                const int64_t pt = base + 32 * jj + lo;
+                if (pt < a.n) ws[(int64_t)(256 + c) * wn + pt] = y[u][jj][r];
+            }
         }
-    }
+    // d1 = (W2^T d2) masked by h1 > 0, into z's registers (rows 192 + f)
+    v16f g[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) g[u][jj][r] = 0.0f;
+#pragma unroll
+    for (int ui = 0; ui < 2; ++ui)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int c = dfeat(ui, r, h);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float av = W2[c * kWs + 32 * u + lo];
+                g[u][0] = mfma2(av, y[ui][0][r], g[u][0]);
+                g[u][1] = mfma2(av, y[ui][1][r], g[u][1]);
+            }
+        }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                z[u][jj][r] = z[u][jj][r] > 0.0f ? g[u][jj][r] : 0.0f;
+                const int64_t pt = base + 32 * jj + lo;
+                if (pt < a.n) ws[(int64_t)(192 + dfeat(u, r, h)) * wn + pt] = z[u][jj][r];
+            }
+    // feature gradients W1^T d1: features 2l and 2l + 1 sit in registers r,
+    // r + 1 (r even) of one lane, stored as one float2 per level
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) g[u][jj][r] = 0.0f;
+#pragma unroll
+    for (int ui = 0; ui < 2; ++ui)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int c = dfeat(ui, r, h);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float av = W1[c * kWs + 32 * u + lo];
+                g[u][0] = mfma2(av, z[ui][0][r], g[u][0]);
+                g[u][1] = mfma2(av, z[ui][1][r], g[u][1]);
+            }
+        }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const int64_t pt = base + 32 * jj + lo;
+            if (pt < a.n) {
+#pragma unroll
+                for (int r = 0; r < 16; r += 2)
+                    fgrad[(int64_t)(dfeat(u, r, h) >> 1) * wn + pt] = make_float2(g[u][jj][r], g[u][jj][r + 1]);
+            }
+        }
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_hg_backward(HgArgs a, const float* __restrict__ gy,
-                                                        int64_t gs, float* __restrict__ ws, int64_t wn,
-                                                        float2* __restrict__ fgrad) {
-    __shared__ float w[kWeights];
-    load_weights(a.params, w);
+// The forward pass in the same layout: the two hidden layers on the matrix
+// cores, the five outputs summed per half-wave on the vector ALUs.
+__global__ __launch_bounds__(kBlock) void k_hg_forward(HgArgs a, float* __restrict__ out, int64_t os) {
+    __shared__ float w[kLdsW];
+    {
+        const float* src = a.params + kTable;
+        for (int q = threadIdx.x; q < kW1 + kW2; q += kBlock) {
+            const int m = q / kW1, rc = q % kW1;
+            w[m * kHid * kWs + (rc / kIn) * kWs + rc % kIn] = src[q];
+        }
+        for (int q = threadIdx.x; q < kW3; q += kBlock) w[2 * kHid * kWs + q] = src[kW1 + kW2 + q];
+    }
+    __syncthreads();
     const float* W1 = w;
-    const float* W2 = w + kW1;
-    const float* W3 = w + kW1 + kW2;
-    // a lane past the last point runs the body at the origin and stores
-    // nothing
+    const float* W2 = w + kHid * kWs;
+    const float* W3 = w + 2 * kHid * kWs;
+    const int lane = threadIdx.x & 63, h = lane >> 5, lo = lane & 31;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = i < a.n;
+    v16f z[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) z[u][j][r] = 0.0f;
     {
-        float p[3] = {0.0f, 0.0f, 0.0f}, h1[kHid], h2[kHid];
+        float p[3] = {0.0f, 0.0f, 0.0f};
         if (live) unit_pos(a, i, p);
-        encode_layer1(a.params, W1, p, h1, live ? ws + i : nullptr, wn);
-        uint64_t m1 = 0, m2;
-#pragma unroll
-        for (int o = 0; o < kHid; ++o) {
-            m1 |= (uint64_t)(h1[o] > 0.0f) << o;
-            h1[o] = fmaxf(h1[o], 0.0f);
-            if (live) ws[(int64_t)(64 + o) * wn + i] = h1[o];
-        }
-        dense_relu(W2, h1, h2, m2);
-#pragma unroll
-        for (int o = 0; o < kHid; ++o)
-            if (live) ws[(int64_t)(128 + o) * wn + i] = h2[o];
-        float d3[kOut];
-#pragma unroll
-        for (int o = 0; o < kOut; ++o) {
-            float s = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kHid; ++j) s = fmaf(W3[o * kHid + j], h2[j], s);
-            const float y = 1.0f / (1.0f + expf(-s));
-            d3[o] = live ? gy[o * gs + i] * y * (1.0f - y) : 0.0f;
-            if (live) ws[(int64_t)(320 + o) * wn + i] = d3[o];
-        }
-        // d2 = (W3^T d3) masked, in h2's registers
-#pragma unroll
-        for (int j = 0; j < kHid; ++j) {
-            float s = 0.0f;
-#pragma unroll
-            for (int o = 0; o < kOut; ++o) s = fmaf(W3[o * kHid + j], d3[o], s);
-            h2[j] = ((m2 >> j) & 1ull) ? s : 0.0f;
-            if (live) ws[(int64_t)(256 + j) * wn + i] = h2[j];
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        // d1 = (W2^T d2) masked, in h1's registers
-#pragma unroll
-        for (int k = 0; k < kHid; ++k) {
-            float s = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kHid; ++j) s = fmaf(W2[j * kHid + k], h2[j], s);
-            h1[k] = ((m1 >> k) & 1ull) ? s : 0.0f;
-            if (live) ws[(int64_t)(192 + k) * wn + i] = h1[k];
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        // per level: feature gradients (W1^T d1, rows 2l and 2l + 1), stored
-        // for the table-gradient gather
-        if (live) {
+        const float2* t2 = reinterpret_cast<const float2*>(a.params);
 #pragma unroll 1
-            for (int l = 0; l < kLevels; ++l) {
-                float g0 = 0.0f, g1 = 0.0f;
+        for (int l = 0; l < kLevels; ++l) {
+            uint32_t idx[8];
+            float wt[8];
+            corners(l, p, idx, wt);
+            const float2* t = t2 + (int64_t)l * kT;
+            float e0 = 0.0f, e1 = 0.0f;
 #pragma unroll
-                for (int o = 0; o < kHid; ++o) {
-                    g0 = fmaf(W1[o * kIn + 2 * l], h1[o], g0);
-                    g1 = fmaf(W1[o * kIn + 2 * l + 1], h1[o], g1);
+            for (int k = 0; k < 8; ++k) {
+                if (wt[k] != 0.0f) {
+                    const float2 v = t[idx[k]];
+                    e0 = fmaf(wt[k], v.x, e0);
+                    e1 = fmaf(wt[k], v.y, e1);
                 }
-                fgrad[(int64_t)l * wn + i] = make_float2(g0, g1);
+            }
+            float b0, b1;
+            swap_halves(e0, e1, b0, b1);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float av = W1[(32 * u + lo) * kWs + 2 * l + h];
+                z[u][0] = mfma2(av, b0, z[u][0]);
+                z[u][1] = mfma2(av, b1, z[u][1]);
             }
         }
+    }
+    v16f y[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) y[u][j][r] = 0.0f;
+#pragma unroll
+    for (int ui = 0; ui < 2; ++ui)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int c = dfeat(ui, r, h);
+            const float h0 = fmaxf(z[ui][0][r], 0.0f), h1 = fmaxf(z[ui][1][r], 0.0f);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float av = W2[(32 * u + lo) * kWs + c];
+                y[u][0] = mfma2(av, h0, y[u][0]);
+                y[u][1] = mfma2(av, h1, y[u][1]);
+            }
+        }
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) {
+        float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float wv = W3[o * kHid + dfeat(u, r, h)];
+                s0 = fmaf(wv, fmaxf(y[u][0][r], 0.0f), s0);
+                s1 = fmaf(wv, fmaxf(y[u][1][r], 0.0f), s1);
+            }
+        float pa, pb;
+        swap_halves(s0, s1, pa, pb);
+        if (live) out[o * os + i] = 1.0f / (1.0f + expf(-(pa + pb)));
     }
 }
 
@@ -420,7 +589,6 @@ __global__ __launch_bounds__(kBlock) void k_hg_table_grad_heavy(const int2* __re
 // 7 % slower).  Lane layout of that instruction: lane l supplies
 // A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register r of lane l
 // holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-typedef float v16f __attribute__((ext_vector_type(16)));
 
 __global__ __launch_bounds__(kBlock) void k_hg_wgrad(const float* __restrict__ ws, int64_t wn,
                                                      int64_t n, float* __restrict__ part) {
