@@ -11,7 +11,7 @@
 //
 // Mapping: one wavefront per point from a persistent grid.  With at most 10
 // roughness levels each lane owns one path at a time and takes the point's
-// next sample when its path ends (refine_point_refill); with more, the 64
+// next sample when its path ends (refine_point_spec); with more, the 64
 // lanes take 64 consecutive (lobe, sample) pairs and follow them to the end
 // (refine_point).  Either way the lobes are summed by the fixed xor
 // butterfly, so a point's result depends only on the inputs.
@@ -452,18 +452,26 @@ __device__ void refine_point(const RefineArgs& A, int64_t p, int lane, int32_t* 
 }
 
 // Refine point p with the calling wavefront, each lane owning one path at a
-// time (the refill bake's layout): every iteration traces one ray per busy
-// lane (a path segment, or the shadow ray of a glossy vertex's emitter
-// sample); a lane whose path has ended adds its radiance into its current
+// time (the refill bake's layout).  The busy lanes walk the tree together in
+// the bake's node loop with speculative leaf parking; a ray is a path segment
+// or the shadow ray of a glossy vertex's emitter sample.  Lanes whose ray has
+// ended take their next ray together once kHitMin of them wait (or no ray is
+// in flight); a lane whose path has ended adds its radiance into its current
 // lobe's sums, and once kRefillMin lanes are free they take the next samples
 // of the point in lane order (a ballot), so the schedule, and the result,
 // depend only on the inputs.  Each path's arithmetic and random numbers are
 // those of refine_path.
 constexpr int kRefillMin = 40;
 constexpr int kRefillMaxK = 10;
-enum PathState { kIdle = 0, kTracing = 1, kFinished = 2 };
+constexpr int kHitMin = 16;        // ended rays processed together once this many wait
+constexpr int kSearchMin = 8;      // leave the node loop below this many searchers
+enum PathState { kIdle = 0, kTracing = 1, kFinished = 2, kHit = 3 };
 
-__device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, int32_t* stack, int n_emit) {
+// A leaf reference: negative but not kDone (INT_MIN).
+__device__ __forceinline__ bool is_leaf(int32_t ref) { return (uint32_t)ref > (uint32_t)dev::kDone; }
+using dev::kDone;
+
+__device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int32_t* stack, int n_emit) {
     const BakeLaunch& b = A.b;
     const DeviceScene& sc = b.sc;
     const int K = b.K;
@@ -533,91 +541,31 @@ __device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, in
     bool cont = false;
     V3 o2 = o0, d2 = d, T2 = T;
     float pb2 = 0.0f;
-    uint32_t z0 = 0, z1 = 0;
     int next_q = 0;
 
-    while (true) {
-        const uint64_t tracing = dev::ballot(state == kTracing);
-        const int n_free = 64 - __popcll(tracing);
-        if ((n_free >= kRefillMin && next_q < S) || tracing == 0) {
-            const bool done = state == kFinished;
-            flush(done && cur_lobe >= 0 && cur_lobe != lobe);
-            if (done) {
-                if (cur_lobe != lobe) {
-                    cur0 = cur1 = cur2 = cur3 = cur4 = cur5 = 0.0f;
-                    cur_lobe = lobe;
-                }
-                cur0 += C.x * w0;
-                cur1 += C.y * w0;
-                cur2 += C.z * w0;
-                cur3 += C.x * w1;
-                cur4 += C.y * w1;
-                cur5 += C.z * w1;
-                state = kIdle;
-            }
-            if (next_q >= S && tracing == 0) break;
-            if (next_q < S) {
-                if (state == kIdle) {
-                    const int rank = __popcll(~tracing & ((1ull << lane) - 1ull));
-                    const int q = next_q + rank;
-                    if (q < S) {
-                        lobe = dev::lobe_of(q, spp_d, spp_s);
-                        s = lobe == 0 ? q : (q - spp_d) - (lobe - 1) * spp_s;
-                        float xi1, xi2;
-                        dev::lobe_uniforms(b.seed, rng_p, lobe, s, lobe == 0 ? b.w_d : b.w_s, xi1, xi2);
-                        float sp_, cp_;
-                        sincospif(2.0f * xi2, &sp_, &cp_);
-                        bool shoot = false;
-                        if (lobe == 0) {
-                            const float r = dev::sqrt_hw(xi1);
-                            d = dev::to_world(pft, pfb, n, r * cp_, r * sp_, dev::sqrt_hw(1.0f - xi1));
-                            w0 = 1.0f;
-                            w1 = 0.0f;
-                            shoot = true;
-                        } else {
-                            const float sg = b.sigma[lobe - 1];
-                            const float alpha = sg * sg;
-                            const float a2 = alpha * alpha;
-                            const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
-                            const float cos_m = rsqrtf(1.0f + tan2);
-                            const float sin_m = dev::sqrt_hw(tan2) * cos_m;
-                            const V3 m = dev::to_world(pft, pfb, n, sin_m * cp_, sin_m * sp_, cos_m);
-                            const float om = dev::dot(wo0, m);
-                            if (om > 0.0f) {
-                                d = (2.0f * om) * m - wo0;
-                                const float ci = dev::dot(n, d);
-                                if (ci > 0.0f) {
-                                    const float G = dev::smith_g1(a2, ci) * dev::smith_g1(a2, cos_o);
-                                    const float w = G * om * dev::rcp(cos_o * cos_m);
-                                    const float f = 1.0f - om;
-                                    const float f2 = f * f;
-                                    const float F1 = f2 * f2 * f;
-                                    w0 = w * (1.0f - F1);
-                                    w1 = w * F1;
-                                    shoot = true;
-                                }
-                            }
-                        }
-                        if (shoot) {
-                            o = o0;
-                            T = v3(1.0f, 1.0f, 1.0f);
-                            C = v3(0.0f, 0.0f, 0.0f);
-                            pb_prev = -1.0f;
-                            vert = 1;
-                            shadow = false;
-                            state = kTracing;
-                        }
-                        // an invalid specular sample counts as zero: the lane
-                        // stays idle and takes another sample next time
-                    }
-                }
-                next_q = min(S, next_q + n_free);
-            }
-        }
-        if (state != kTracing) continue;
-        const dev::Hit h = dev::trace<false>(sc, o, d, stack, kBlock, z0, z1);
+    // traversal state of the lane's ray
+    int32_t ref = kDone;
+    int32_t* top = stack;
+    dev::RaySlab rs = dev::ray_slab(o, d, sc.box_scale);
+    dev::Hit h;
+    h.leaf = -1;
+    h.t = INFINITY;
+    h.u = h.v = 0.0f;
+    int32_t best_orig = INT_MAX;
+    auto start_ray = [&]() {
+        rs = dev::ray_slab(o, d, sc.box_scale);
+        ref = 0;
+        top = stack;
+        h.leaf = -1;
+        h.t = INFINITY;
+        h.u = h.v = 0.0f;
+        best_orig = INT_MAX;
+        state = kTracing;
+    };
+    // what a lane does with its ended ray: the next ray of its path
+    // (start_ray) or the end of the path (kFinished)
+    auto process_hit = [&]() {
         if (shadow) {
-            // the emitter sample's contribution, then the continuation
             if (h.leaf == fe) C = C + cn;
             shadow = false;
             if (cont) {
@@ -626,14 +574,15 @@ __device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, in
                 T = T2;
                 pb_prev = pb2;
                 ++vert;
+                start_ray();
             } else {
                 state = kFinished;
             }
-            continue;
+            return;
         }
         if (h.leaf < 0) {
             state = kFinished;
-            continue;
+            return;
         }
         const float4 r2 = dev::load_global(reinterpret_cast<const float4*>(sc.rad + h.leaf) + 2);
         if (r2.y > 0.0f || r2.z > 0.0f || r2.w > 0.0f) {
@@ -647,7 +596,7 @@ __device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, in
             }
             C = C + v3(T.x * r2.y * w, T.y * r2.z * w, T.z * r2.w * w);
             state = kFinished;
-            continue;
+            return;
         }
         V3 v0, e1, e2, ny;
         tri_frame(sc.tris, h.leaf, v0, e1, e2, ny);
@@ -659,17 +608,15 @@ __device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, in
         if (dev::dot(ny, wo) < 0.0f) ny = v3(-ny.x, -ny.y, -ny.z);
         if (!(dev::dot(ny, wo) > 0.0f)) {
             state = kFinished;
-            continue;
+            return;
         }
         const Material mt = material_at(A.mat, yd);
         if (mt.sigma > A.sigma_diffuse || vert >= A.max_vertices) {
             const V3 R = dev::radiance(sc, h);
             C = C + v3(T.x * R.x, T.y * R.y, T.z * R.z);
             state = kFinished;
-            continue;
+            return;
         }
-        // a glossy vertex: the emitter sample (traced next), then the
-        // continuation drawn from f
         const float sg = fminf(fmaxf(mt.sigma, 0.02f), 1.0f);
         const float alpha = sg * sg, a2 = alpha * alpha;
         const V3 yo = y + b.eps * ny;
@@ -733,15 +680,125 @@ __device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, in
             o = yo;
             d = l;
             shadow = true;
+            start_ray();
         } else if (cont) {
             o = o2;
             d = d2;
             T = T2;
             pb_prev = pb2;
             ++vert;
+            start_ray();
         } else {
             state = kFinished;
         }
+    };
+
+    while (true) {
+        // ---- lanes whose ray has ended take their next ray, together --------
+        uint64_t tracing = dev::ballot(state == kTracing);
+        const uint64_t ended = dev::ballot(state == kHit);
+        if (ended != 0 && (__popcll(ended) >= kHitMin || tracing == 0)) {
+            if (state == kHit) process_hit();
+            tracing = dev::ballot(state == kTracing);
+        }
+        // ---- fold finished paths and refill free lanes -----------------------
+        const uint64_t busy = tracing | dev::ballot(state == kHit);
+        const int n_free = 64 - __popcll(busy);
+        if ((n_free >= kRefillMin && next_q < S) || busy == 0) {
+            const bool done = state == kFinished;
+            flush(done && cur_lobe >= 0 && cur_lobe != lobe);
+            if (done) {
+                if (cur_lobe != lobe) {
+                    cur0 = cur1 = cur2 = cur3 = cur4 = cur5 = 0.0f;
+                    cur_lobe = lobe;
+                }
+                cur0 += C.x * w0;
+                cur1 += C.y * w0;
+                cur2 += C.z * w0;
+                cur3 += C.x * w1;
+                cur4 += C.y * w1;
+                cur5 += C.z * w1;
+                state = kIdle;
+            }
+            if (next_q >= S && busy == 0) break;
+            if (next_q < S) {
+                if (state == kIdle) {
+                    const int rank = __popcll(~busy & ((1ull << lane) - 1ull));
+                    const int q = next_q + rank;
+                    if (q < S) {
+                        lobe = dev::lobe_of(q, spp_d, spp_s);
+                        s = lobe == 0 ? q : (q - spp_d) - (lobe - 1) * spp_s;
+                        float xi1, xi2;
+                        dev::lobe_uniforms(b.seed, rng_p, lobe, s, lobe == 0 ? b.w_d : b.w_s, xi1, xi2);
+                        float sp_, cp_;
+                        sincospif(2.0f * xi2, &sp_, &cp_);
+                        bool shoot = false;
+                        if (lobe == 0) {
+                            const float r = dev::sqrt_hw(xi1);
+                            d = dev::to_world(pft, pfb, n, r * cp_, r * sp_, dev::sqrt_hw(1.0f - xi1));
+                            w0 = 1.0f;
+                            w1 = 0.0f;
+                            shoot = true;
+                        } else {
+                            const float sg = b.sigma[lobe - 1];
+                            const float alpha = sg * sg;
+                            const float a2 = alpha * alpha;
+                            const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
+                            const float cos_m = rsqrtf(1.0f + tan2);
+                            const float sin_m = dev::sqrt_hw(tan2) * cos_m;
+                            const V3 m = dev::to_world(pft, pfb, n, sin_m * cp_, sin_m * sp_, cos_m);
+                            const float om = dev::dot(wo0, m);
+                            if (om > 0.0f) {
+                                d = (2.0f * om) * m - wo0;
+                                const float ci = dev::dot(n, d);
+                                if (ci > 0.0f) {
+                                    const float G = dev::smith_g1(a2, ci) * dev::smith_g1(a2, cos_o);
+                                    const float w = G * om * dev::rcp(cos_o * cos_m);
+                                    const float f = 1.0f - om;
+                                    const float f2 = f * f;
+                                    const float F1 = f2 * f2 * f;
+                                    w0 = w * (1.0f - F1);
+                                    w1 = w * F1;
+                                    shoot = true;
+                                }
+                            }
+                        }
+                        if (shoot) {
+                            o = o0;
+                            T = v3(1.0f, 1.0f, 1.0f);
+                            C = v3(0.0f, 0.0f, 0.0f);
+                            pb_prev = -1.0f;
+                            vert = 1;
+                            shadow = false;
+                            start_ray();
+                        }
+                    }
+                }
+                next_q = min(S, next_q + n_free);
+            }
+        }
+        // ---- traversal: inner nodes until every lane has parked a leaf ----
+        // (lanes not tracing hold ref == kDone)
+        int32_t pend = kDone;
+        while (true) {
+            if (is_leaf(ref) && pend == kDone) {
+                pend = ref;
+                dev::stack_pop(ref, top, stack, kBlock);
+            }
+            const bool inner = ref >= 0;
+            const uint64_t searching = dev::ballot(inner) & dev::ballot(pend == kDone);
+            const int n_searching = __builtin_popcount((uint32_t)searching) +
+                                    __builtin_popcount((uint32_t)(searching >> 32));
+            if (searching == 0 || (n_searching < kSearchMin && dev::ballot(pend != kDone) != 0)) break;
+            if (inner) dev::node4_step(sc.nodes, ref, top, stack, kBlock, rs, h.t);
+        }
+        if (pend != kDone) {
+            const int32_t lr = ~pend;
+            const int32_t first = lr >> 3;
+            const int32_t cnt = (lr & 7) + 1;
+            for (int k = 0; k < cnt; ++k) dev::tri_test(sc.tris, first + k, o, d, h, best_orig);
+        }
+        if (state == kTracing && ref == kDone) state = kHit;
     }
     flush(cur_lobe >= 0);
     if (lane < P) {
@@ -750,6 +807,9 @@ __device__ void refine_point_refill(const RefineArgs& A, int64_t p, int lane, in
     }
 }
 
+// The chunked layout (any K) or the per-lane paths (K <= kRefillMaxK), one
+// instance each, so that each gets its own register allocation.
+template <bool CHUNKED>
 __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs A, int32_t* counters) {
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
@@ -757,11 +817,9 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs A, int32_t* counte
     const int n_emit = __builtin_amdgcn_readfirstlane(*A.n_emit);
     const int home = (int)(blockIdx.x % kXcdCount);
     int tried = 0;
-    // the refill layout gives every output slot its own lane (3 + 6K <= 64)
-    const bool refill = A.b.K <= kRefillMaxK;
     for (int64_t p; (p = dev::next_point(counters, home, tried, A.b.n, lane)) >= 0;) {
-        if (refill) refine_point_refill(A, p, lane, stack, n_emit);
-        else refine_point(A, p, lane, stack, n_emit);
+        if (CHUNKED) refine_point(A, p, lane, stack, n_emit);
+        else refine_point_spec(A, p, lane, stack, n_emit);
     }
 }
 
@@ -811,7 +869,11 @@ int launch_refine(const BakeLaunch& b, const RefineLaunch& r, int32_t* counters,
     blocks = std::max<int64_t>(kXcdCount, (blocks + kXcdCount - 1) / kXcdCount * kXcdCount);
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_zero_counters_r, dim3(1), dim3(64), 0, st, counters);
-    hipLaunchKernelGGL(k_refine, dim3((unsigned)blocks), dim3(kBlock), 0, st, A, counters);
+    // the per-lane paths give every output slot its own lane (3 + 6K <= 64)
+    if (A.b.K <= kRefillMaxK)
+        hipLaunchKernelGGL(k_refine<false>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A, counters);
+    else
+        hipLaunchKernelGGL(k_refine<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, A, counters);
     return check("refine");
 }
 
