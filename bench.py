@@ -55,6 +55,10 @@ OPS_PER_HIT = 12       # radiance: barycentric blend of the corner cache + emiss
 LOSS_BYTES_PER_POINT = 112
 # the masked loss also reads alpha and writes d loss / d alpha
 MASKED_LOSS_BYTES_PER_POINT = 120
+# fused material fetch + loss + adjoint, per point: position 12 B, Ld 12 B,
+# the bracketing levels of Ls0 and Ls1 48 B, Lgt 12 B (material and its
+# gradient stay on chip or in the grid, counted once per grid)
+FUSED_LOSS_BYTES_PER_POINT = 84
 LAMBDA_D = 5e-4        # weight of the diffuse prior, as in Eq. 17
 VOXEL_RES = 256        # the radiance cache grid of Sec. 4.2
 # hash-grid network forward, per point: 8 B per table vertex read (those of
@@ -74,6 +78,7 @@ KERNEL_SOURCES = {
     "k_hg_table_grad": ("hashgrid.hip", "fipt_internal.hpp"),
     "k_grid_adjoint": ("loss.hip", "grid.cpp", "fipt_internal.hpp"),
     "k_grid_gather": ("loss.hip", "fipt_internal.hpp"),
+    "k_grid_render_loss": ("loss.hip", "grid.cpp", "fipt_internal.hpp"),
 }
 
 
@@ -912,6 +917,15 @@ def main():
     grad_pts = torch.empty((5, N), dtype=torch.float32, device=dev)
     grad_grid = torch.empty_like(grid)
     loss_buf = torch.empty((fipt.LOSS_SLOTS,), dtype=torch.float64, device=dev)
+    # the step works on the points in the grid plan's order (by node brick,
+    # cell, index): the generated points are put into that order before the
+    # bake, the observations once here, so the fused loss reads every
+    # per-point plane contiguously and each workgroup's corners are local
+    obs_q = plan.permute(obs)
+    planes_q = torch.empty_like(planes)
+    tri_q = torch.empty_like(tri)
+    shading_q = torch.empty_like(shading)
+    grad_grid_q = torch.empty_like(grid)
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t_setup:.1f} s: {sc.n_tris} triangles, {N} points")
 
@@ -921,20 +935,16 @@ def main():
         if timed:
             tm.mark("a")
         fipt.fipt_gen_points(scene, sc.cameras, planes=planes, tri=tri)
+        plan.permute(planes, out=planes_q)
+        plan.permute(tri.view(1, N), out=tri_q.view(1, N))
         if timed:
             tm.mark("b")
-        fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=shading)
+        fipt.fipt_bake(scene, planes_q, tri_q, sc.spp, sc.spp, sc.sigma, sc.seed, out=shading_q)
         if timed:
             tm.mark("c")
-        fipt.fipt_grid_gather(grid, bmin, bmax, pos, out=mat)
+        plan.render_loss(grid, shading_q, obs_q, sc.sigma, loss_buf=loss_buf, grad_grid=grad_grid_q)
         if timed:
             tm.mark("d")
-        fipt.fipt_render_loss(shading, mat, obs, sc.sigma, loss_buf=loss_buf, grad=grad_pts)
-        if timed:
-            tm.mark("e")
-        plan.scatter(grad_pts, out=grad_grid)
-        if timed:
-            tm.mark("f")
 
     for _ in range(args.warmup):
         step(False)
@@ -948,10 +958,23 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     t_pts = float(np.mean(tm.spans("a", "b")))
     t_bake = float(np.mean(tm.spans("b", "c")))
-    t_gather = float(np.mean(tm.spans("c", "d")))
-    t_loss = float(np.mean(tm.spans("d", "e")))
-    t_scatter = float(np.mean(tm.spans("e", "f")))
+    t_fused = float(np.mean(tm.spans("c", "d")))
     loss_value = float(loss_buf[0].item())
+    # the same loss and gradient as three separate calls (gather, render-loss,
+    # adjoint) on the points in camera order, timed alone
+    sep = Timer()
+    for i in range(args.steps + 1):
+        sep.mark("c")
+        fipt.fipt_grid_gather(grid, bmin, bmax, pos, out=mat)
+        sep.mark("d")
+        fipt.fipt_render_loss(shading, mat, obs, sc.sigma, loss_buf=loss_buf, grad=grad_pts)
+        sep.mark("e")
+        plan.scatter(grad_pts, out=grad_grid)
+        sep.mark("f")
+    torch.cuda.synchronize()
+    t_gather = float(np.mean(sep.spans("c", "d")[1:]))
+    t_loss = float(np.mean(sep.spans("d", "e")[1:]))
+    t_scatter = float(np.mean(sep.spans("e", "f")[1:]))
 
     trav = None
     if not args.no_counters:
@@ -963,6 +986,7 @@ def main():
     # (12 B) and writes (gather) or reads (adjoint) five values (20 B); the
     # 5 x 128^3 grid is read once (gather) or written once (adjoint)
     grid_bytes = N * 32 + 5 * R ** 3 * 4
+    fused_bytes = N * FUSED_LOSS_BYTES_PER_POINT + 2 * 5 * R ** 3 * 4
     roof_grid = {
         kname: {"bound": "hbm", "achieved": grid_bytes / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": grid_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
@@ -1037,10 +1061,27 @@ def main():
                                "128 spp per lobe, 6 roughness levels; 128^3 material grid",
                    "points": N, "lobe_samples_per_point": S, "triangles": sc.n_tris,
                    "parallelism": "single GPU"},
-        "breakdown_ms": {"points": t_pts, "bake": t_bake, "grid_gather": t_gather,
-                         "render_loss_fwd_bwd": t_loss, "grid_scatter": t_scatter},
+        "breakdown_ms": {"points_and_plan_order": t_pts, "bake": t_bake,
+                         "fused_grid_loss_fwd_bwd": t_fused},
         "bake_gsamples_per_s": N * S / (t_bake * 1e-3) / 1e9,
-        "loss_grad_points_per_s": N / ((t_loss + t_gather + t_scatter) * 1e-3),
+        "loss_grad_points_per_s": N / (t_fused * 1e-3),
+        "loss_grad": {"kernels": "k_grid_render_loss + k_final_sum + k_grid_adjoint + "
+                                 "k_grid_adjoint_combine (one call, points in the grid plan's order)",
+                      "ms": t_fused, "points_per_s": N / (t_fused * 1e-3),
+                      "roofline": {"bound": "hbm", "achieved": fused_bytes / (t_fused * 1e-3) / 1e9,
+                                   "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": fused_bytes / (t_fused * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                   "bytes_per_launch": fused_bytes,
+                                   "bytes_counted": "per point: position 12 B, Ld 12 B, the two "
+                                                    "bracketing levels of Ls0 and Ls1 48 B, Lgt 12 B; "
+                                                    "the 5 x 128^3 grid read once and its gradient "
+                                                    "written once",
+                                   "traffic": traffic.get("k_grid_render_loss")},
+                      "separate_calls": {"grid_gather_ms": t_gather, "render_loss_ms": t_loss,
+                                         "grid_scatter_ms": t_scatter,
+                                         "points_per_s": N / ((t_loss + t_gather + t_scatter) * 1e-3),
+                                         "note": "the same computation as three calls on the points "
+                                                 "in camera order"}},
         "render_loss_points_per_s": N / (t_loss * 1e-3),
         "render_loss_gbs": loss_gbs,
         "render_loss_cold_ms": t_loss_cold,

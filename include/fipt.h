@@ -439,8 +439,9 @@ int fipt_grid_gather(const float* grid, int32_t channels, int32_t res,
  * of the additions; the units of one brick are added in double in unit
  * order.  Results are bitwise reproducible.  The rounding of a column sum is
  * at most 2^-63 of (columns in its unit) x (largest column sum in the unit).
- * The plan owns device memory (16 bytes per point, 8 per column, 16 per unit
- * and 32 KB per unit of a brick of several).
+ * The plan owns device memory (20 bytes per point, 12 per column entry, 160
+ * per column of the point order, 16 per unit and 32 KB per unit of a brick
+ * of several).
  * 1 <= n < 2^31, 2 <= res <= 1024; FIPT_EINVAL also when the columns number
  * 2^31 or more. */
 int fipt_grid_plan_create(const float* pos_host, int64_t n, int32_t res,
@@ -455,6 +456,48 @@ int fipt_grid_plan_destroy(fipt_grid_plan plan);
  * overlap (one stream, or ordered streams). */
 int fipt_grid_scatter(fipt_grid_plan plan, const float* grad_points, int32_t channels,
                       int64_t gp_stride, float* grad_grid, void* stream);
+
+/* The plan's point order: order_host[q] (host, n int32) receives the index,
+ * among the positions the plan was created from, of the q-th point in the
+ * plan's order (by node brick, cell, then index).  Synchronous. */
+int fipt_grid_plan_order(fipt_grid_plan plan, int32_t* order_host);
+
+/* Per-point data into the plan's order: dst[c][q] = src[c][order[q]] for
+ * c < planes and q < n (device float planes of the plan's n points; an
+ * int32 plane can be moved as float bits).  src and dst must not overlap.
+ * A set-up step: a point set whose material is fitted for many steps is put
+ * into the plan's order once (shading terms, observations, or the points
+ * before their bake). */
+int fipt_grid_plan_permute(fipt_grid_plan plan, const float* src, int32_t planes,
+                           int64_t src_stride, float* dst, int64_t dst_stride, void* stream);
+
+/* One loss-and-gradient step of the differentiation workload, fused: for
+ * the plan's n points in the plan's order (fipt_grid_plan_permute), the
+ * material (a_r, a_g, a_b, sigma, m) of point q is the trilinear value of
+ * grid[5][res^3] (the plan's res and box) at the plan's position q, rounded
+ * to float as fipt_grid_gather stores it (the stand-in for Sigmoid(MLP_brdf)
+ * of Eq. 14); Lr, the loss and d loss / d material are those of
+ * fipt_render_loss (Eq. 5, Eq. 8, Eq. 2 / 15) with sh and observed in plan
+ * order; grad_grid[5][res^3] receives the adjoint of the material fetch
+ * applied to that gradient (the gradient as stored in float).  The material
+ * and the per-point gradient equal fipt_grid_gather + fipt_render_loss on
+ * the same plan-ordered inputs bit for bit; the loss is summed in a fixed
+ * order over the plan order.  The adjoint sums each column (at most 8
+ * points of one cell, never across a multiple of 16 points of the plan's
+ * order) in single precision, weight times gradient, by a fixed segmented
+ * scan, then adds the column sums into the nodes as fipt_grid_scatter does
+ * (64-bit fixed point at a per-unit scale), so a node differs from
+ * fipt_grid_scatter's by at most the float rounding of its column sums
+ * (about 2^-21 of the sum of the absolute contributions) plus the
+ * fixed-point quantum; everything is bitwise reproducible.  loss_dev holds
+ * FIPT_LOSS_SLOTS doubles (the rest is scratch).  grad_points[5][gp_stride]
+ * (plan order), when not NULL, also receives the per-point gradient.  Uses
+ * the plan's scratch (160 bytes per column), so calls with one plan must
+ * not overlap.  Allocates nothing; asynchronous on `stream`. */
+int fipt_grid_render_loss(fipt_grid_plan plan, const float* grid, const fipt_shading* sh,
+                          int32_t n_levels, const float* sigma_host, const float* observed,
+                          int64_t obs_stride, int32_t tonemap, double* loss_dev,
+                          float* grad_grid, float* grad_points, int64_t gp_stride, void* stream);
 
 /* ---- voxel radiance cache (Sec. 4.2) ------------------------------------ */
 

@@ -281,9 +281,23 @@ struct GridPlanDev {
     int64_t n_multi;
     double* part;           // [n_slots][8][kBrickNodes] node sums of the units of those bricks
     int64_t n_slots;
+    int32_t* hcol;          // [n_cols] home column (numbered in point order) of each column entry
+    int32_t* colq;          // [n_points] home column of each point in sorted order
+    int64_t n_home;         // home columns: each cell's run of points cut into columns
+    float* csum;            // [n_home][40] column sums of the fused loss: channel ch, corner c at
+                            // ch * 8 + c (160-byte records)
 };
 int launch_grid_scatter(const GridPlanDev& p, const float* gp, int32_t C, int64_t gp_stride,
                         float* grad_grid, void* stream);
+// Fused material fetch + render + loss + adjoint over a plan's points given
+// in the plan's order; per-point gradients also go to gq[5][gqs] when gq is
+// not NULL.
+int launch_grid_render_loss(const GridPlanDev& p, const float* grid, const float* sh, int64_t ss,
+                            int32_t K, const float* sigma, const float* obs, int64_t os,
+                            int32_t tone, double* loss, double* partials, float* gq, int64_t gqs,
+                            float* grad_grid, void* stream);
+int launch_plan_permute(const GridPlanDev& p, const float* src, int32_t planes, int64_t ss,
+                        float* dst, int64_t ds, void* stream);
 
 }  // namespace fipt
 

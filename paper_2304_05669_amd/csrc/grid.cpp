@@ -33,7 +33,8 @@ namespace {
 
 void plan_free(fipt_grid_plan p) {
     if (!p) return;
-    void* ptrs[] = {p->d.pts, p->d.cols, p->d.units, p->d.multi, p->d.part};
+    void* ptrs[] = {p->d.pts, p->d.cols, p->d.units, p->d.multi, p->d.part, p->d.hcol, p->d.colq,
+                    p->d.csum};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -99,10 +100,15 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     const int64_t n_bricks = nb[0] * nb[1] * nb[2];
     struct Col {
         int64_t brick;
-        int32_t start, word;
+        int32_t start, word, home;
     };
     std::vector<Col> cols;
     cols.reserve(n / 2 + 16);
+    // home column of every point in sorted order; a column never crosses a
+    // multiple of 16 points, so the fused loss kernel finds each column's
+    // points within one row of 16 lanes
+    std::vector<int32_t> colq(n);
+    int32_t n_home = 0;
     for (int64_t q = 0; q < n;) {
         const uint64_t cell_key = key[q] >> 31;
         int64_t e = q + 1;
@@ -111,8 +117,11 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
         const int64_t lc = (int64_t)(cell_key & 511);
         const int64_t l[3] = {lc % B[0], (lc / B[0]) % B[1], lc / (B[0] * B[1])};
         const int64_t h[3] = {hb % nb[0], (hb / nb[0]) % nb[1], hb / (nb[0] * nb[1])};
-        for (int64_t a = q; a < e; a += kColumnMax) {
-            const int32_t cnt = (int32_t)std::min<int64_t>(kColumnMax, e - a);
+        for (int64_t a = q; a < e;) {
+            const int32_t cnt = (int32_t)std::min<int64_t>(std::min<int64_t>(kColumnMax, e - a),
+                                                           16 - (a & 15));
+            const int32_t home = n_home++;
+            for (int64_t v = a; v < a + cnt; ++v) colq[v] = home;
             for (int t = 0; t < 8; ++t) {
                 int64_t tb[3], tl[3];
                 bool ok = true;
@@ -128,8 +137,9 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
                 const int64_t brick = tb[0] + nb[0] * (tb[1] + nb[1] * tb[2]);
                 const int32_t word = cnt | (int32_t)(tl[0] + 1) << 5 | (int32_t)(tl[1] + 1) << 11 |
                                      (int32_t)(tl[2] + 1) << 17;
-                cols.push_back({brick, (int32_t)a, word});
+                cols.push_back({brick, (int32_t)a, word, home});
             }
+            a += cnt;
         }
         q = e;
     }
@@ -145,28 +155,36 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     for (const Col& c : cols) ++brick_col[c.brick + 1];
     for (int64_t b = 0; b < n_bricks; ++b) brick_col[b + 1] += brick_col[b];
     std::vector<int2> cword(cols.size());
-    for (size_t c = 0; c < cols.size(); ++c) cword[c] = make_int2(cols[c].start, cols[c].word);
-    // work units: every brick's columns in runs of at most kAdjUnit (a brick
-    // with no columns is one empty unit, which writes zeros)
-    std::vector<int4> units, multi;
-    int32_t slots = 0;
-    for (int64_t b = 0; b < n_bricks; ++b) {
-        const int32_t c0 = brick_col[b], c1 = brick_col[b + 1];
-        const int32_t nu = std::max<int32_t>(1, (c1 - c0 + kAdjUnit - 1) / kAdjUnit);
-        if (nu == 1) {
-            units.push_back(make_int4((int32_t)b, c0, c1, -1));
-            continue;
-        }
-        multi.push_back(make_int4((int32_t)b, slots, nu, 0));
-        for (int32_t u = 0; u < nu; ++u)
-            units.push_back(make_int4((int32_t)b, c0 + u * kAdjUnit,
-                                      std::min<int32_t>(c1, c0 + (u + 1) * kAdjUnit), slots + u));
-        slots += nu;
+    std::vector<int32_t> hcol(cols.size());
+    for (size_t c = 0; c < cols.size(); ++c) {
+        cword[c] = make_int2(cols[c].start, cols[c].word);
+        hcol[c] = cols[c].home;
     }
-    // heaviest units first: the hardware deals workgroups to the XCDs in
-    // turn, and the long units start early instead of forming the tail
-    std::stable_sort(units.begin(), units.end(),
-                     [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
+    // work units: every brick's columns in runs of at most `per` (a brick
+    // with no columns is one empty unit, which writes zeros)
+    auto make_units = [&](int32_t per, std::vector<int4>& units, std::vector<int4>& multi) {
+        int32_t slots = 0;
+        for (int64_t b = 0; b < n_bricks; ++b) {
+            const int32_t c0 = brick_col[b], c1 = brick_col[b + 1];
+            const int32_t nu = std::max<int32_t>(1, (c1 - c0 + per - 1) / per);
+            if (nu == 1) {
+                units.push_back(make_int4((int32_t)b, c0, c1, -1));
+                continue;
+            }
+            multi.push_back(make_int4((int32_t)b, slots, nu, 0));
+            for (int32_t u = 0; u < nu; ++u)
+                units.push_back(make_int4((int32_t)b, c0 + u * per,
+                                          std::min<int32_t>(c1, c0 + (u + 1) * per), slots + u));
+            slots += nu;
+        }
+        // heaviest units first: the hardware deals workgroups to the XCDs in
+        // turn, and the long units start early instead of forming the tail
+        std::stable_sort(units.begin(), units.end(),
+                         [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
+        return slots;
+    };
+    std::vector<int4> units, multi;
+    const int32_t slots = make_units(kAdjUnit, units, multi);
     // points in sorted order: (x, y, z, index)
     std::vector<float4> pts(n);
     for (int64_t q = 0; q < n; ++q) {
@@ -196,9 +214,11 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
     d.n_units = (int64_t)units.size();
     d.n_multi = (int64_t)multi.size();
     d.n_slots = slots;
+    d.n_home = n_home;
     int rc;
     if ((rc = upload(&d.pts, pts, &p->bytes)) || (rc = upload(&d.cols, cword, &p->bytes)) ||
-        (rc = upload(&d.units, units, &p->bytes)) || (rc = upload(&d.multi, multi, &p->bytes))) {
+        (rc = upload(&d.units, units, &p->bytes)) || (rc = upload(&d.multi, multi, &p->bytes)) ||
+        (rc = upload(&d.hcol, hcol, &p->bytes)) || (rc = upload(&d.colq, colq, &p->bytes))) {
         plan_free(p);
         if (prev >= 0) (void)hipSetDevice(prev);
         return rc;
@@ -211,6 +231,14 @@ int fipt_grid_plan_create(const float* pos, int64_t n, int32_t res, const float*
         return fail(FIPT_ENOMEM, "hipMalloc unit sums: %s", hipGetErrorString(e));
     }
     p->bytes += (int64_t)part_bytes;
+    const size_t cs_bytes = sizeof(float) * 40 * (size_t)std::max<int32_t>(n_home, 1);
+    e = hipMalloc(reinterpret_cast<void**>(&d.csum), cs_bytes);
+    if (e != hipSuccess) {
+        plan_free(p);
+        if (prev >= 0) (void)hipSetDevice(prev);
+        return fail(FIPT_ENOMEM, "hipMalloc column sums: %s", hipGetErrorString(e));
+    }
+    p->bytes += (int64_t)cs_bytes;
     if (prev >= 0) (void)hipSetDevice(prev);
     *out = p;
     return FIPT_OK;
@@ -235,6 +263,59 @@ int fipt_grid_scatter(fipt_grid_plan p, const float* grad_points, int32_t channe
     if (channels < 1 || channels > 8) return fail(FIPT_EINVAL, "channels must be in [1, 8]");
     if (gp_stride < p->d.n_points) return fail(FIPT_EINVAL, "gp_stride < plan point count");
     return launch_grid_scatter(p->d, grad_points, channels, gp_stride, grad_grid, stream);
+}
+
+int fipt_grid_plan_order(fipt_grid_plan p, int32_t* order_host) {
+    clear_error();
+    if (!p || !order_host) return fail(FIPT_EINVAL, "NULL argument");
+    std::vector<float4> pts(p->d.n_points);
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(p->device) != hipSuccess) return fail(FIPT_EHIP, "hipSetDevice(%d) failed", p->device);
+    const hipError_t e = hipMemcpy(pts.data(), p->d.pts, sizeof(float4) * pts.size(), hipMemcpyDeviceToHost);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail(FIPT_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+    for (size_t q = 0; q < pts.size(); ++q) std::memcpy(order_host + q, &pts[q].w, 4);
+    return FIPT_OK;
+}
+
+int fipt_grid_plan_permute(fipt_grid_plan p, const float* src, int32_t planes, int64_t src_stride,
+                           float* dst, int64_t dst_stride, void* stream) {
+    clear_error();
+    if (!p || !src || !dst) return fail(FIPT_EINVAL, "NULL argument");
+    if (planes < 1) return fail(FIPT_EINVAL, "planes must be >= 1");
+    if (src_stride < p->d.n_points || dst_stride < p->d.n_points)
+        return fail(FIPT_EINVAL, "a stride is smaller than the plan's point count");
+    const char* s0 = reinterpret_cast<const char*>(src);
+    const char* d0 = reinterpret_cast<const char*>(dst);
+    const int64_t span_s = 4 * ((planes - 1) * src_stride + p->d.n_points);
+    const int64_t span_d = 4 * ((planes - 1) * dst_stride + p->d.n_points);
+    if (s0 < d0 + span_d && d0 < s0 + span_s) return fail(FIPT_EINVAL, "src and dst overlap");
+    return launch_plan_permute(p->d, src, planes, src_stride, dst, dst_stride, stream);
+}
+
+int fipt_grid_render_loss(fipt_grid_plan p, const float* grid, const fipt_shading* sh,
+                          int32_t n_levels, const float* sigma_host, const float* observed,
+                          int64_t obs_stride, int32_t tonemap, double* loss_dev, float* grad_grid,
+                          float* grad_points, int64_t gp_stride, void* stream) {
+    clear_error();
+    if (!p || !grid || !sh || !sh->planes || !sigma_host || !observed || !loss_dev || !grad_grid)
+        return fail(FIPT_EINVAL, "NULL argument");
+    const int64_t n = p->d.n_points;
+    if (n_levels < 2 || n_levels > FIPT_MAX_LEVELS)
+        return fail(FIPT_EINVAL, "n_levels must be in [2, %d], got %d", FIPT_MAX_LEVELS, n_levels);
+    for (int k = 0; k < n_levels; ++k) {
+        if (!std::isfinite(sigma_host[k])) return fail(FIPT_EINVAL, "sigma[%d] is not finite", k);
+        if (k > 0 && !(sigma_host[k] > sigma_host[k - 1]))
+            return fail(FIPT_EINVAL, "sigma must be strictly increasing");
+    }
+    if (sh->stride < n || obs_stride < n) return fail(FIPT_EINVAL, "a stride is smaller than n");
+    if (grad_points && gp_stride < n) return fail(FIPT_EINVAL, "gp_stride < n");
+    if (tonemap != FIPT_TONEMAP_NONE && tonemap != FIPT_TONEMAP_LOG_SRGB)
+        return fail(FIPT_EINVAL, "unknown tonemap %d", tonemap);
+    return launch_grid_render_loss(p->d, grid, sh->planes, sh->stride, n_levels, sigma_host,
+                                   observed, obs_stride, tonemap, loss_dev, loss_dev + 1,
+                                   grad_points, gp_stride, grad_grid, stream);
 }
 
 }  // extern "C"

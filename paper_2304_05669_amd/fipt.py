@@ -32,6 +32,7 @@ EXPORTS = (
     "fipt_bake", "fipt_lobe_uniforms", "fipt_bake_traversal_stats", "fipt_refine", "fipt_render_loss",
     "fipt_render_loss_noalloc", "fipt_render_loss_masked", "fipt_scale_by", "fipt_hbm_stream",
     "fipt_grid_gather", "fipt_grid_plan_create", "fipt_grid_plan_destroy", "fipt_grid_scatter",
+    "fipt_grid_plan_order", "fipt_grid_plan_permute", "fipt_grid_render_loss",
     "fipt_emission_plan_create", "fipt_emission_plan_destroy", "fipt_emission_median",
     "fipt_scene_set_voxel_radiance", "fipt_voxel_plan_create", "fipt_voxel_plan_destroy",
     "fipt_voxel_pool", "fipt_hashgrid_forward", "fipt_hashgrid_workspace_floats",
@@ -141,6 +142,10 @@ def lib():
         "fipt_grid_plan_create": (C.c_int, [_vp, _i64, _i32, _f32p, _f32p, _i32, C.POINTER(_vp)]),
         "fipt_grid_plan_destroy": (C.c_int, [_vp]),
         "fipt_grid_scatter": (C.c_int, [_vp, _vp, _i32, _i64, _vp, _vp]),
+        "fipt_grid_plan_order": (C.c_int, [_vp, _vp]),
+        "fipt_grid_plan_permute": (C.c_int, [_vp, _vp, _i32, _i64, _vp, _i64, _vp]),
+        "fipt_grid_render_loss": (C.c_int, [_vp, _vp, C.POINTER(Shading), _i32, _f32p, _vp, _i64, _i32,
+                                            _vp, _vp, _vp, _i64, _vp]),
         "fipt_emission_plan_create": (C.c_int, [_vp, _i64, _i64, _i32, C.POINTER(_vp)]),
         "fipt_emission_plan_destroy": (C.c_int, [_vp]),
         "fipt_emission_median": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i64, _vp]),
@@ -642,6 +647,59 @@ class GridPlan:
                                        Cn, grad_points.shape[1], _dev(out, torch.float32, "out"),
                                        _stream()))
         return out
+
+    def order(self):
+        """numpy int32 [n]: the original index of each point in the plan's order."""
+        import numpy as np
+        out = np.empty(self.n, dtype=np.int32)
+        _check(lib().fipt_grid_plan_order(self.handle, out.ctypes.data))
+        return out
+
+    def permute(self, src: torch.Tensor, out: torch.Tensor = None):
+        """[planes, n] float32 (or int32) GPU in point order -> the same planes in the plan's order."""
+        if src.dim() != 2 or src.shape[1] != self.n:
+            raise ValueError(f"src must be [planes, {self.n}], got {tuple(src.shape)}")
+        if src.dtype not in (torch.float32, torch.int32):
+            raise ValueError("src must be float32 or int32")
+        if out is None:
+            out = torch.empty_like(src)
+        _need(out, tuple(src.shape), "out")
+        if out.dtype != src.dtype:
+            raise ValueError("out must have src's dtype")
+        _check(lib().fipt_grid_plan_permute(self.handle, _dev(src, src.dtype, "src"), src.shape[0], self.n,
+                                            _dev(out, out.dtype, "out"), self.n, _stream()))
+        return out
+
+    def render_loss(self, grid: torch.Tensor, shading: torch.Tensor, observed: torch.Tensor, sigma,
+                    tonemap: int = TONEMAP_NONE, loss_buf: torch.Tensor = None,
+                    grad_grid: torch.Tensor = None, grad_points: torch.Tensor = None):
+        """Fused material fetch + render + loss + grid adjoint for the plan's points, with
+        shading [3 + 6K, n] and observed [3, n] in the plan's order.  Returns
+        (loss_buf, grad_grid [5, R, R, R]); loss_buf[0] is the loss.  grad_points [5, n]
+        (plan order), when given, receives the per-point material gradient."""
+        K = len(sigma)
+        R = self.res
+        if grid.shape != (5, R, R, R):
+            raise ValueError(f"grid must be [5, {R}, {R}, {R}], got {tuple(grid.shape)}")
+        if shading.shape != (3 + 6 * K, self.n) or observed.shape != (3, self.n):
+            raise ValueError("shading must be [3 + 6K, n] and observed [3, n]")
+        dev = grid.device
+        if loss_buf is None:
+            loss_buf = torch.empty((LOSS_SLOTS,), dtype=torch.float64, device=dev)
+        _need(loss_buf, (LOSS_SLOTS,), "loss_buf")
+        if grad_grid is None:
+            grad_grid = torch.empty_like(grid)
+        _need(grad_grid, (5, R, R, R), "grad_grid")
+        if grad_points is not None:
+            _need(grad_points, (5, self.n), "grad_points")
+        sh = Shading(_dev(shading, torch.float32, "shading"), self.n)
+        _check(lib().fipt_grid_render_loss(
+            self.handle, _dev(grid, torch.float32, "grid"), C.byref(sh), K, _f32_array(sigma, K),
+            _dev(observed, torch.float32, "observed"), self.n, int(tonemap),
+            _dev(loss_buf, torch.float64, "loss_buf"), _dev(grad_grid, torch.float32, "grad_grid"),
+            _dev(grad_points, torch.float32, "grad_points") if grad_points is not None else None,
+            self.n, _stream()))
+        return loss_buf, grad_grid
 
     def __del__(self):
         try:

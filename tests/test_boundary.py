@@ -106,6 +106,14 @@ def test_invalid_arguments_rejected_on_host():
     assert b"2^28" in L.fipt_last_error()
     assert L.fipt_hashgrid_plan_create(1, 4, 8, box0, box1, None, C.byref(h)) == fipt.EINVAL
     assert h.value is None
+    # the fused grid loss and the plan-order helpers refuse a missing plan
+    # or buffer before touching the device
+    sh = fipt.Shading(1, 100)
+    sig = (C.c_float * 6)(0.02, 0.1, 0.25, 0.5, 0.75, 1.0)
+    assert L.fipt_grid_render_loss(None, 1, C.byref(sh), 6, sig, 1, 100, 0, 1, 1, None, 100,
+                                   None) == fipt.EINVAL
+    assert L.fipt_grid_plan_order(None, 1) == fipt.EINVAL
+    assert L.fipt_grid_plan_permute(None, 1, 1, 100, 2, 100, None) == fipt.EINVAL
 
 
 # (scale, offset) applied to the room: the 4-wide nodes store bounds as

@@ -393,3 +393,112 @@ def test_grid_gather_autograd_end_to_end():
     absg = orr.grid_scatter(np.abs(grad_o), pos, bmin, bmax, R)
     err = np.abs(G.grad.cpu().numpy().astype(np.float64) - gg_o)
     assert np.all(err <= 1e-4 * absg + 1e-6 * np.abs(gg_o).max())
+
+
+@pytest.mark.parametrize("n,R,tone", [(100003, 128, 0), (60001, 32, 1), (1, 8, 0)])
+def test_fused_grid_render_loss_parity(n, R, tone):
+    """fipt_grid_render_loss (material fetch + render + loss + adjoint over
+    plan-ordered points) against the oracle's gather, loss and scatter, and
+    bit for bit against the three separate calls on the same plan-ordered
+    inputs (the loss up to its summation order)."""
+    bmin = np.zeros(3, np.float32)
+    bmax = np.array([6.0, 5.0, 3.0], np.float32)
+    rng = np.random.default_rng(n + R)
+    # surface-like points (two planes) plus a volume share, some outside the box
+    pos = rng.uniform(-0.05, 1.05, size=(3, n)) * bmax[:, None]
+    pos[2, : n // 3] = 0.0
+    pos[0, n // 3: n // 2] = 6.0
+    pos = pos.astype(np.float32)
+    grid = synth.material_grid(R, seed=R + 3)
+    sh = synth.random_shading(n, 6, seed=n % 91)
+    obs = synth.random_observations(n, seed=n % 79 + 4)
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    order = plan.order()
+    assert np.array_equal(np.sort(order), np.arange(n))
+    sh_q = plan.permute(_t(sh))
+    obs_q = plan.permute(_t(obs))
+    pos_q = plan.permute(_t(pos))
+    assert torch.equal(pos_q.cpu(), torch.from_numpy(pos[:, order]))
+    buf, gg = plan.render_loss(_t(grid), sh_q, obs_q, SIG, tone)
+    torch.cuda.synchronize()
+    loss_g = float(buf[0].item())
+    mat_o = orr.grid_gather(grid, pos, bmin, bmax)
+    loss_o, grad_o, _ = orr.loss_and_grad(sh, mat_o, obs, SIG, tone)
+    assert abs(loss_g - loss_o) <= 1e-6 * abs(loss_o), (loss_g, loss_o)
+    gg_o = orr.grid_scatter(grad_o, pos, bmin, bmax, R)
+    absg = orr.grid_scatter(np.abs(grad_o), pos, bmin, bmax, R)
+    err = np.abs(gg.cpu().numpy().astype(np.float64).reshape(5, -1) - gg_o.reshape(5, -1))
+    assert np.all(err <= 1e-4 * absg.reshape(5, -1) + 1e-6 * np.abs(gg_o).max())
+    # the separate calls on the plan-ordered inputs give the same per-point
+    # gradient bits; a second call repeats the first bit for bit
+    mat_q = fipt.fipt_grid_gather(_t(grid), bmin, bmax, pos_q)
+    buf_s, gp_s, _ = fipt.fipt_render_loss(sh_q, mat_q, obs_q, SIG, tone)
+    gq = torch.empty((5, n), dtype=torch.float32, device=DEV)
+    buf2, gg2 = plan.render_loss(_t(grid), sh_q, obs_q, SIG, tone, grad_points=gq)
+    torch.cuda.synchronize()
+    assert torch.equal(gq, gp_s)
+    assert torch.equal(gg2, gg)
+    assert float(buf2[0].item()) == loss_g
+    assert abs(float(buf_s[0].item()) - loss_g) <= 1e-12 * abs(loss_g)
+
+
+def test_fused_grid_render_loss_room_full_size():
+    """The differentiation workload's shape: the room's 1,843,200 shading
+    points, a 128^3 grid; the fused call's per-point gradient equals
+    render-loss on the plan-ordered inputs bit for bit, its grid gradient
+    equals the separate adjoint's to the float rounding of its column sums
+    (bounded by the sum of absolute contributions), and its loss matches the
+    oracle's."""
+    sc = synth.room()
+    R = 128
+    scene = fipt.Scene(sc.verts, sc.tris, device=0)
+    planes, _ = fipt.fipt_gen_points(scene, sc.cameras)
+    pos = np.ascontiguousarray(planes[0:3].cpu().numpy())
+    scene.destroy()
+    n = pos.shape[1]
+    bmin, bmax = sc.bmin.astype(np.float32), sc.bmax.astype(np.float32)
+    grid = synth.material_grid(R, seed=1006)
+    sh = synth.random_shading(n, 6, seed=5)
+    obs = synth.random_observations(n, seed=6)
+    plan = fipt.GridPlan(pos, R, bmin, bmax)
+    sh_q = plan.permute(_t(sh))
+    obs_q = plan.permute(_t(obs))
+    pos_q = plan.permute(_t(pos))
+    gq = torch.empty((5, n), dtype=torch.float32, device=DEV)
+    buf, gg = plan.render_loss(_t(grid), sh_q, obs_q, SIG, 0, grad_points=gq)
+    mat_q = fipt.fipt_grid_gather(_t(grid), bmin, bmax, pos_q)
+    _, gp_s, _ = fipt.fipt_render_loss(sh_q, mat_q, obs_q, SIG, 0)
+    # the separate adjoint reads the gradient by original point index
+    order = torch.from_numpy(plan.order().astype(np.int64)).to(DEV)
+    gp_orig = torch.empty_like(gp_s)
+    gp_orig[:, order] = gp_s
+    gg_s = plan.scatter(gp_orig)
+    absg = plan.scatter(gp_orig.abs())
+    torch.cuda.synchronize()
+    assert torch.equal(gq, gp_s)
+    err = (gg.double() - gg_s.double()).abs()
+    # float rounding of the column sums, plus each path's fixed-point
+    # quantum (2^-63 of a work unit's columns times its largest column sum)
+    bound = 1e-6 * absg.double() + 1e-12 * float(gg_s.abs().max())
+    bad = err > bound
+    assert not bool(bad.any()), (int(bad.sum()), float((err / bound).max()),
+                                 err[bad][:8].tolist(), absg.double()[bad][:8].tolist(),
+                                 gg_s.double()[bad][:8].tolist())
+    mat_o = orr.grid_gather(grid, pos, bmin, bmax)
+    loss_o, _, _ = orr.loss_and_grad(sh, mat_o, obs, SIG, 0)
+    assert abs(float(buf[0].item()) - loss_o) <= 1e-6 * abs(loss_o)
+
+
+def test_fused_grid_render_loss_rejects_bad_arguments():
+    pos = np.random.default_rng(0).uniform(0, 1, size=(3, 100)).astype(np.float32)
+    plan = fipt.GridPlan(pos, 8, np.zeros(3, np.float32), np.ones(3, np.float32))
+    sh = torch.zeros((39, 100), dtype=torch.float32, device=DEV)
+    obs = torch.zeros((3, 100), dtype=torch.float32, device=DEV)
+    with pytest.raises(ValueError):
+        plan.render_loss(torch.zeros((5, 8, 8, 7), device=DEV), sh, obs, SIG)
+    with pytest.raises(ValueError):
+        plan.render_loss(torch.zeros((5, 8, 8, 8), device=DEV), sh[:, :99].contiguous(), obs, SIG)
+    with pytest.raises(fipt.FiptError):
+        plan.render_loss(torch.zeros((5, 8, 8, 8), device=DEV), sh, obs, (0.5, 0.2, 0.1, 0.3, 0.6, 0.9))
+    with pytest.raises(ValueError):
+        plan.permute(obs[:, :50].contiguous())
