@@ -420,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_permute(const float4* __restric
 #define FIPT_ADJ_BATCH 8
 #endif
 constexpr int kAdjBlock = kAdjUnit;
+static_assert(kAdjBlock == kBlock, "block_sum and the loss partials assume one workgroup size");
 constexpr int kAdjBatch = FIPT_ADJ_BATCH;   // point records requested together
 
 template <int C>
@@ -596,14 +597,26 @@ __global__ __launch_bounds__(kAdjBlock) void k_grid_adjoint(GridPlanDev P, GridF
 // column) instead of summing its points; the largest magnitude per channel
 // over the corners the brick owns fixes the unit's fixed-point scale, and
 // the sums are added into the brick's nodes as 64-bit integers.
+// The launch has one workgroup more than units: the last sums the loss
+// kernel's per-workgroup partials in index order (as k_final_sum).
 __global__ __launch_bounds__(kAdjBlock) void k_grid_adjoint_sums(GridPlanDev P,
-                                                                 float* __restrict__ out) {
+                                                                 float* __restrict__ out,
+                                                                 const double* partials, int n_part,
+                                                                 double* loss) {
     constexpr int C = 5;
     __shared__ unsigned long long acc[C][kBrickNodes];
     __shared__ unsigned bad[kBrickNodes];
     __shared__ float wmax[kAdjBlock / 64][C];
     __shared__ int expo[C];
     const int tid = threadIdx.x;
+    if (blockIdx.x == gridDim.x - 1) {
+        const int per = (n_part + kAdjBlock - 1) / kAdjBlock;
+        double t = 0.0;
+        for (int i = tid * per; i < min(n_part, (tid + 1) * per); ++i) t += partials[i];
+        const double tot = block_sum(t, reinterpret_cast<double*>(wmax));
+        if (tid == 0) *loss = tot;
+        return;
+    }
     const int4 unit = P.units[blockIdx.x];
     const int64_t brick = unit.x;
     const int bx = (int)(brick % P.nb[0]), by = (int)((brick / P.nb[0]) % P.nb[1]),
@@ -875,10 +888,8 @@ int launch_grid_render_loss(const GridPlanDev& p, const float* grid, const float
         hipLaunchKernelGGL(k_grid_render_loss_log<false>, gr, bl, 0, st, p, grid, g, sh, ss, K, obs, os, tab, partials, gq, gqs);
     int rc = check("grid_render_loss");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, st, partials, blocks, loss);
-    if ((rc = check("grid_render_loss final sum"))) return rc;
-    hipLaunchKernelGGL(k_grid_adjoint_sums, dim3((unsigned)p.n_units), dim3(kAdjBlock), 0, st, p,
-                       grad_grid);
+    hipLaunchKernelGGL(k_grid_adjoint_sums, dim3((unsigned)p.n_units + 1), dim3(kAdjBlock), 0, st, p,
+                       grad_grid, partials, blocks, loss);
     if (p.n_multi > 0) {
         const unsigned per = (unsigned)((kBrickNodes * 5 + kAdjBlock - 1) / kAdjBlock);
         hipLaunchKernelGGL(k_grid_adjoint_combine<5>, dim3((unsigned)(p.n_multi * per)), dim3(kAdjBlock),
