@@ -38,6 +38,7 @@ PEAK_FP32_TFLOPS = 157.3
 # per ray-triangle test, ~100 per lobe sample (random numbers, direction,
 # weights)
 FLOPS_PER_NODE = 4 * 20
+FLOPS_PER_CHAIN_LEVEL = 3 * 20   # a chain level tests the three siblings
 FLOPS_PER_TRI = 30
 FLOPS_PER_SAMPLE = 100
 # Secondary figure: the VALU issue rate of MI355X, 256 CUs x 4 SIMDs x 16
@@ -47,6 +48,7 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic VALU operations per unit of bake work
 OPS_PER_NODE = 81      # 4-wide node: four slab tests (6 FMA, 12 min/max, 1 compare
                        # each) and a five-comparator ordering of the hit children
+OPS_PER_CHAIN_LEVEL = 60   # three slab tests of siblings below a point's chain, three comparators
 OPS_PER_TRI = 40       # Moller-Trumbore: 2 cross products, 4 dots, reciprocal, compares
 OPS_PER_SAMPLE = 180   # Philox4x32-10 (~100 integer ops) + direction and weights
 OPS_PER_HIT = 12       # radiance: barycentric blend of the corner cache + emission
@@ -139,18 +141,23 @@ def traversal_bytes(scene, planes, tri, sc, out):
     child references the node step reads of its 128-byte line), 48 B per
     triangle tested, 48 B radiance record per hit, 40 B per point read and
     156 B per point written."""
-    stats = torch.zeros(6, dtype=torch.int64, device=planes.device)
+    stats = torch.zeros(7, dtype=torch.int64, device=planes.device)
     fipt.fipt_bake(scene, planes, tri, sc.spp, sc.spp, sc.sigma, sc.seed, out=out, stats=stats)
     torch.cuda.synchronize()
-    rays, nodes, tris, hits, node_steps, tri_steps = [int(v) for v in stats.cpu()]
+    rays, nodes, tris, hits, node_steps, tri_steps, chain = [int(v) for v in stats.cpu()]
     n = planes.shape[1]
     P = 3 + 6 * len(sc.sigma)
     samples = n * sc.spp * (1 + len(sc.sigma))
+    # a chain level's node is read once per wavefront (scalar loads), not
+    # per lane: its bytes are not counted per ray
     total = nodes * 80 + tris * 48 + hits * 48 + n * 40 + n * P * 4
-    ops = nodes * OPS_PER_NODE + tris * OPS_PER_TRI + samples * OPS_PER_SAMPLE + hits * OPS_PER_HIT
-    flops = nodes * FLOPS_PER_NODE + tris * FLOPS_PER_TRI + samples * FLOPS_PER_SAMPLE
+    ops = (nodes * OPS_PER_NODE + chain * OPS_PER_CHAIN_LEVEL + tris * OPS_PER_TRI +
+           samples * OPS_PER_SAMPLE + hits * OPS_PER_HIT)
+    flops = (nodes * FLOPS_PER_NODE + chain * FLOPS_PER_CHAIN_LEVEL + tris * FLOPS_PER_TRI +
+             samples * FLOPS_PER_SAMPLE)
     return dict(rays=rays, nodes=nodes, tris=tris, hits=hits, samples=samples, bytes=total,
-                ops=ops, flops=flops,
+                ops=ops, flops=flops, chain_levels=chain,
+                chain_levels_per_ray=chain / max(rays, 1),
                 nodes_per_ray=nodes / max(rays, 1), tris_per_ray=tris / max(rays, 1),
                 node_loop_lane_use=nodes / max(64 * node_steps, 1),
                 tri_loop_lane_use=tris / max(64 * tri_steps, 1))
@@ -483,7 +490,8 @@ def bake_roofline(trav, t_bake_ms, traffic):
     return {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": tf / PEAK_FP32_TFLOPS, "traffic": traffic, "kernel": "k_bake",
             "flops_per_launch": trav["flops"],
-            "flops_counted": "20 per ray-box test (80 per 4-wide node visited), 30 per "
+            "flops_counted": "20 per ray-box test (80 per 4-wide node visited, 60 per chain "
+                             "level: the three siblings of the point's chain child), 30 per "
                              "ray-triangle test, 100 per lobe sample",
             "issue_rate": {"achieved_tops": tops, "peak_tops": PEAK_VALU_TOPS,
                            "frac": tops / PEAK_VALU_TOPS, "ops_per_launch": trav["ops"],

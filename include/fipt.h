@@ -147,6 +147,9 @@ typedef struct fipt_traversal_stats {
     uint64_t hits;          /* rays that hit a surface                       */
     uint64_t node_steps;    /* wavefront iterations of the node loop         */
     uint64_t tri_steps;     /* wavefront iterations of the triangle loop     */
+    uint64_t chain_levels;  /* levels of a point's origin chain a ray starts
+                               below (lane count; each tests the three
+                               siblings of the chain's child)               */
 } fipt_traversal_stats;
 
 /* ---- library ----------------------------------------------------------- */
@@ -283,7 +286,7 @@ int fipt_lobe_uniforms(uint64_t seed, int64_t p0, int64_t n_points, int32_t lobe
                        int32_t n_samples, float* out, void* stream);
 
 /* Same bake, instrumented: also accumulates traversal counters into
- * `stats_dev` (device, 6 uint64 in fipt_traversal_stats order, added to).
+ * `stats_dev` (device, 7 uint64 in fipt_traversal_stats order, added to).
  * Slower than fipt_bake; meant for measuring algorithmic bytes per ray. */
 int fipt_bake_traversal_stats(fipt_scene s, const fipt_points* pts,
                               const fipt_bake_params* p, const fipt_shading* out,

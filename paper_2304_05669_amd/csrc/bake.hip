@@ -199,7 +199,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                                                   int32_t* stack, uint32_t& n_rays,
                                                   uint32_t& n_nodes, uint32_t& n_tris,
                                                   uint32_t& n_hits, uint32_t& n_node_steps,
-                                                  uint32_t& n_tri_steps) {
+                                                  uint32_t& n_tri_steps, uint32_t& n_chain) {
     const int K = b.K;
     const int P = 3 + 6 * K;
     const int64_t ps = b.pts_stride;
@@ -224,6 +224,9 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
     const int spp_d = b.spp_d, spp_s = b.spp_s;
     const int S = spp_d + K * spp_s;
     const DeviceScene& sc = b.sc;
+    // the boxes around o that every ray of the point enters first
+    int32_t chain, chain_end;
+    const int chain_len = dev::point_chain(sc.nodes, sc.box_scale, o, lane, chain, chain_end);
 
     // Lane j owns output slot j (slot layout as slot_plane).  Each lane sums
     // its contributions for its current lobe in cur[]; a lane's lobes only
@@ -343,8 +346,15 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                         if (shoot) {
                             if (COUNT) ++n_rays;
                             rs = dev::ray_slab(o, d, sc.box_scale);
-                            ref = 0;
+                            // start below the point's chain: its siblings
+                            // the ray hits are pushed level by level
                             top = stack;
+                            for (int i = 0; i < chain_len; ++i) {
+                                const int32_t cw = __builtin_amdgcn_readlane(chain, i);
+                                if (COUNT) ++n_chain;
+                                dev::chain_step(sc.nodes, cw >> 2, cw & 3, rs, top, kBlock);
+                            }
+                            ref = chain_end;
                             h.leaf = -1;
                             h.t = INFINITY;
                             h.u = h.v = 0.0f;
@@ -414,20 +424,21 @@ __global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake(BakeLaunch 
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
-    uint32_t n_rays = 0, n_nodes = 0, n_tris = 0, n_hits = 0, n_node_steps = 0, n_tri_steps = 0;
+    uint32_t n_rays = 0, n_nodes = 0, n_tris = 0, n_hits = 0, n_node_steps = 0, n_tri_steps = 0,
+             n_chain = 0;
     const int home = (int)(blockIdx.x % kXcdCount);   // the XCD this workgroup runs on
     int tried = 0;
     for (int64_t p; (p = next_point(counters, home, tried, b.n, lane)) >= 0;) {
         if (REFILL)
             bake_point_refill<COUNT, VOXEL>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits,
-                                     n_node_steps, n_tri_steps);
+                                     n_node_steps, n_tri_steps, n_chain);
         else
             bake_point<COUNT, VOXEL>(b, b.sigma, p, lane, stack, n_rays, n_nodes, n_tris, n_hits);
     }
     if (COUNT) {
         // lane counters -> wave totals -> one 64-bit atomic per wave
-        uint64_t v[6] = {n_rays, n_nodes, n_tris, n_hits, n_node_steps, n_tri_steps};
-        for (int k = 0; k < 6; ++k) {
+        uint64_t v[7] = {n_rays, n_nodes, n_tris, n_hits, n_node_steps, n_tri_steps, n_chain};
+        for (int k = 0; k < 7; ++k) {
             uint64_t x = v[k];
             for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
             if (lane == 0) atomicAdd((unsigned long long*)(stats + k), (unsigned long long)x);
@@ -475,7 +486,7 @@ __global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake_tiles(const
     __shared__ int32_t s_stack[kStackSize * kBlock];
     const int lane = threadIdx.x & 63;
     int32_t* stack = s_stack + threadIdx.x;
-    uint32_t a = 0, bb = 0, c = 0, d = 0, e = 0, f = 0;   // counters, unused here
+    uint32_t a = 0, bb = 0, c = 0, d = 0, e = 0, f = 0, g = 0;   // counters, unused here
     const int64_t total = tiles[n_tiles - 1].first + tiles[n_tiles - 1].job.n;
     const int home = (int)(blockIdx.x % kXcdCount);       // the XCD this workgroup runs on
     int tried = 0;
@@ -491,7 +502,7 @@ __global__ __launch_bounds__(kBlock) FIPT_BAKE_OCCUPANCY void k_bake_tiles(const
         const float* sigma = tiles[lo].job.sigma;
         const int64_t q = p - tiles[lo].first;
         if (job.K <= kRefillMaxK)
-            bake_point_refill<false, false>(job, sigma, q, lane, stack, a, bb, c, d, e, f);
+            bake_point_refill<false, false>(job, sigma, q, lane, stack, a, bb, c, d, e, f, g);
         else
             bake_point<false, false>(job, sigma, q, lane, stack, a, bb, c, d);
     }

@@ -270,6 +270,150 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
     ref = c0;
 }
 
+// ---- the chain of boxes around a point ------------------------------------
+// Every ray of a point starts at the same origin o, so every ray walks the
+// same nodes first: while some child box of the current node contains o,
+// that child is entered at distance 0, nearest of all, and only its
+// siblings differ from ray to ray.  The bake finds that chain once per point
+// and starts each ray below it, having tested only the siblings of the
+// chain's children.  Which child is entered does not change the result: the
+// chain's child is visited whether or not a given ray's slab test would
+// accept it, and every sibling the ray's test accepts is pushed, so every
+// box the plain traversal would visit is still visited.
+constexpr int kChainMax = 16;   // levels kept (one per lane of the first 16)
+
+// Node data through the constant address space: with a wave-uniform node
+// the compiler reads it with scalar loads into scalar registers.
+typedef const __attribute__((address_space(4))) int4* cint4p;
+typedef const __attribute__((address_space(4))) float4* cfloat4p;
+__device__ __forceinline__ int4 load_uniform(const void* p) {
+    const gint4 v = *(const __attribute__((address_space(4))) gint4*)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 load_uniform_f(const void* p) {
+    const gfloat4 v = *(const __attribute__((address_space(4))) gfloat4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// Half j of the four packed in a (lo01, lo23) or (hi01, hi23) word pair.
+template <int J>
+__device__ __forceinline__ float half_of(uint32_t w01, uint32_t w23) {
+    return J == 0 ? half_lo(w01) : J == 1 ? half_hi(w01) : J == 2 ? half_lo(w23) : half_hi(w23);
+}
+
+// The chain of point origin o (same value in every lane): lane i of `chain`
+// receives node << 2 | slot for level i (the node and which of its children
+// contains o); returns the number of levels; `end` is the reference the
+// traversal continues from (the last chain child, or the node where no
+// child contains o, or the root).  Containment is tested on the decoded
+// half-precision bounds in units of the node scale.
+__device__ __forceinline__ int point_chain(const Bvh4Node* nodes, float scale, V3 o, int lane,
+                                           int32_t& chain, int32_t& end) {
+    const float inv = 1.0f / scale;   // a power of two: exact
+    const float ux = o.x * inv, uy = o.y * inv, uz = o.z * inv;
+    int L = 0;
+    int32_t node = 0;
+    chain = 0;
+    while (L < kChainMax) {
+        const char* nb = reinterpret_cast<const char*>(nodes) + ((uint32_t)node << 7);
+        const int4 qx = load_uniform(nb), qy = load_uniform(nb + 16), qz = load_uniform(nb + 32);
+        const float4 og = load_uniform_f(nb + 48);
+        const int4 ch = load_uniform(nb + 64);
+        int slot = -1;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            const uint32_t lx = j < 2 ? qx.x : qx.y, hx = j < 2 ? qx.z : qx.w;
+            const uint32_t ly = j < 2 ? qy.x : qy.y, hy = j < 2 ? qy.z : qy.w;
+            const uint32_t lz = j < 2 ? qz.x : qz.y, hz = j < 2 ? qz.z : qz.w;
+            const float x0 = og.x + ((j & 1) ? half_hi(lx) : half_lo(lx));
+            const float x1 = og.x + ((j & 1) ? half_hi(hx) : half_lo(hx));
+            const float y0 = og.y + ((j & 1) ? half_hi(ly) : half_lo(ly));
+            const float y1 = og.y + ((j & 1) ? half_hi(hy) : half_lo(hy));
+            const float z0 = og.z + ((j & 1) ? half_hi(lz) : half_lo(lz));
+            const float z1 = og.z + ((j & 1) ? half_hi(hz) : half_lo(hz));
+            const bool in = (x0 <= ux) & (ux <= x1) & (y0 <= uy) & (uy <= y1) & (z0 <= uz) &
+                            (uz <= z1);
+            slot = in ? j : slot;   // the lowest slot that contains o
+        }
+        slot = __builtin_amdgcn_readfirstlane(slot);
+        if (slot < 0) break;
+        if (lane == L) chain = (int32_t)((uint32_t)node << 2 | (uint32_t)slot);
+        ++L;
+        const int32_t child = __builtin_amdgcn_readfirstlane(
+            slot == 0 ? ch.x : slot == 1 ? ch.y : slot == 2 ? ch.z : ch.w);
+        if (child < 0) {
+            end = child;   // a leaf (an unused slot never contains o)
+            return L;
+        }
+        node = child;
+    }
+    end = node;
+    return L;
+}
+
+// Entry distance of child J of a node whose planes the lane does not
+// select beforehand (the node's words are wave-uniform): both plane
+// distances per axis, then near and far by the direction's sign.  No hit
+// yet, so the far bound is not clipped.
+template <int J>
+__device__ __forceinline__ float chain_key(const int4& qx, const int4& qy, const int4& qz,
+                                           const RaySlab& r, float bx, float by, float bz) {
+    const float lx = fmaf(half_of<J>(qx.x, qx.y), r.ax, bx), hx = fmaf(half_of<J>(qx.z, qx.w), r.ax, bx);
+    const float ly = fmaf(half_of<J>(qy.x, qy.y), r.ay, by), hy = fmaf(half_of<J>(qy.z, qy.w), r.ay, by);
+    const float lz = fmaf(half_of<J>(qz.x, qz.y), r.az, bz), hz = fmaf(half_of<J>(qz.z, qz.w), r.az, bz);
+    const bool sx = r.ax < 0.0f, sy = r.ay < 0.0f, sz = r.az < 0.0f;
+    const float tn = fmaxf(fmaxf(sx ? hx : lx, sy ? hy : ly), fmaxf(sz ? hz : lz, 0.0f));
+    const float tf = fminf(fminf(sx ? lx : hx, sy ? ly : hy), sz ? lz : hz);
+    return tn <= tf ? tn : INFINITY;
+}
+
+template <int A, int B, int C>
+__device__ __forceinline__ void chain_siblings3(const int4& qx, const int4& qy, const int4& qz,
+                                                const int4& ch, const RaySlab& r, float bx,
+                                                float by, float bz, int32_t*& top, int stride) {
+    float ka = chain_key<A>(qx, qy, qz, r, bx, by, bz);
+    float kb = chain_key<B>(qx, qy, qz, r, bx, by, bz);
+    float kc = chain_key<C>(qx, qy, qz, r, bx, by, bz);
+    const int32_t refs[4] = {ch.x, ch.y, ch.z, ch.w};
+    int32_t ca = refs[A], cb = refs[B], cc = refs[C];
+    order2(ka, ca, kb, cb);
+    order2(kb, cb, kc, cc);
+    order2(ka, ca, kb, cb);
+    if (kc < INFINITY) {
+        *top = cc;
+        top += stride;
+    }
+    if (kb < INFINITY) {
+        *top = cb;
+        top += stride;
+    }
+    if (ka < INFINITY) {
+        *top = ca;
+        top += stride;
+    }
+}
+
+// One chain level for a ray: the three siblings of the chain's child at
+// node `node` (slot `skip`) are tested and the hit ones pushed, farthest
+// first, as the plain step would push them (the chain's child, entered at
+// distance 0, is visited next without a push).
+__device__ __forceinline__ void chain_step(const Bvh4Node* nodes, int32_t node, int skip,
+                                           const RaySlab& r, int32_t*& top, int stride) {
+    const char* nb = reinterpret_cast<const char*>(nodes) + ((uint32_t)node << 7);
+    const int4 qx = load_uniform(nb), qy = load_uniform(nb + 16), qz = load_uniform(nb + 32);
+    const float4 og = load_uniform_f(nb + 48);
+    const int4 ch = load_uniform(nb + 64);
+    const float bx = fmaf(og.x, r.ax, -r.oxi);
+    const float by = fmaf(og.y, r.ay, -r.oyi);
+    const float bz = fmaf(og.z, r.az, -r.ozi);
+    switch (skip) {
+        case 0: chain_siblings3<1, 2, 3>(qx, qy, qz, ch, r, bx, by, bz, top, stride); break;
+        case 1: chain_siblings3<0, 2, 3>(qx, qy, qz, ch, r, bx, by, bz, top, stride); break;
+        case 2: chain_siblings3<0, 1, 3>(qx, qy, qz, ch, r, bx, by, bz, top, stride); break;
+        default: chain_siblings3<0, 1, 2>(qx, qy, qz, ch, r, bx, by, bz, top, stride); break;
+    }
+}
+
 // Triangle test (Moller-Trumbore) of leaf-order triangle `i`; updates the
 // closest hit, exact distance ties going to the lower original index.  A
 // triangle parallel to the ray (det = 0) needs no early exit: its

@@ -369,11 +369,11 @@ def fipt_bake(scene: Scene, planes: torch.Tensor, tri: torch.Tensor, spp_d: int,
               sigma, seed: int, ray_eps: float = 1e-4, out: torch.Tensor = None,
               stats: torch.Tensor = None):
     """Bake Ld, Ls0[K], Ls1[K] for the points; returns [3 + 6K, n] float32.
-    If ``stats`` (int64 GPU tensor of 6) is given, the instrumented kernel
+    If ``stats`` (int64 GPU tensor of 7) is given, the instrumented kernel
     adds rays, nodes, triangles, hits, node-loop and triangle-loop
     wavefront steps to it."""
-    if stats is not None and tuple(stats.shape) != (6,):
-        raise ValueError("stats must be an int64 tensor of 6")
+    if stats is not None and tuple(stats.shape) != (7,):
+        raise ValueError("stats must be an int64 tensor of 7")
     K = len(sigma)
     n = planes.shape[1]
     if out is None:

@@ -149,16 +149,18 @@ def test_invalid_arguments_raise(tiny, tiny_gpu, tiny_points):
 
 def test_traversal_counters(tiny, tiny_gpu, tiny_points):
     pts, tri, _ = tiny_points
-    stats = torch.zeros(6, dtype=torch.int64, device=DEV)
+    stats = torch.zeros(7, dtype=torch.int64, device=DEV)
     a = fipt.fipt_bake(tiny_gpu, torch.from_numpy(pts).to(DEV), torch.from_numpy(tri).to(DEV),
                        64, 64, tiny.sigma, 2, stats=stats)
     b = _bake(tiny_gpu, pts, tri, 64, 64, tiny.sigma, 2)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(a.cpu().numpy(), b)
-    rays, nodes, tris, hits, node_steps, tri_steps = [int(v) for v in stats.cpu()]
+    rays, nodes, tris, hits, node_steps, tri_steps, chain = [int(v) for v in stats.cpu()]
     assert 0 < rays <= 4096 * 448
     assert hits <= rays and hits > 0.99 * rays      # a closed box
-    assert nodes >= rays and tris >= hits
+    # every ray starts below its point's chain (at least the root contains
+    # the origin in a closed box) or at the root
+    assert chain >= rays and tris >= hits
     # lane utilisation of the two loops is a fraction
     assert 0 < nodes <= 64 * node_steps and 0 < tris <= 64 * tri_steps
 
