@@ -811,7 +811,29 @@ def run_large(dev, rebakes, copy_gbs):
     flush = torch.ones((1 << 27,), dtype=torch.float32, device=dev)      # 512 MB
     t_warm = loss_timing(out, mat, obs, sc.sigma)
     t_cold = loss_timing(out, mat, obs, sc.sigma, flush=flush)
-    del flush
+    # the fused step (material fetch, render, loss, adjoint) on the same
+    # shadings put into the grid plan's order
+    plan = fipt.GridPlan(planes[0:3].cpu().numpy(), 128, sc.bmin.tolist(), sc.bmax.tolist())
+    out_q, obs_q = plan.permute(out), plan.permute(obs)
+    gg = torch.empty_like(grid)
+    lb = torch.empty((fipt.LOSS_SLOTS,), dtype=torch.float64, device=dev)
+    fused = {}
+    plan.render_loss(grid, out_q, obs_q, sc.sigma, loss_buf=lb, grad_grid=gg)
+    for name, fl in (("warm", None), ("cold", flush)):
+        ts = []
+        torch.cuda._sleep(5_000_000)     # the host queues the launches ahead of the GPU
+        for _ in range(10):
+            if fl is not None:
+                fl.sum()                                  # evicts L2 and the MALL
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record()
+            plan.render_loss(grid, out_q, obs_q, sc.sigma, loss_buf=lb, grad_grid=gg)
+            s1.record()
+            ts.append((s0, s1))
+        torch.cuda.synchronize()
+        fused[name] = float(np.median([a.elapsed_time(b) for a, b in ts]))
+    fused_bytes = N * FUSED_LOSS_BYTES_PER_POINT + 2 * 5 * 128 ** 3 * 4
+    del flush, plan, out_q, obs_q
     scene.destroy()
     gbs = lambda ms: N * LOSS_BYTES_PER_POINT / (ms * 1e-3) / 1e9
     eff = trav["bytes"] / (t_bake * 1e-3) / 1e9
@@ -841,6 +863,15 @@ def run_large(dev, rebakes, copy_gbs):
                       "cold_frac_of_achievable_hbm": gbs(t_cold) / copy_gbs,
                       "bytes_per_point": LOSS_BYTES_PER_POINT,
                       "material": "gathered from a 128^3 grid (spatially coherent roughness)"},
+        "fused_loss_grad": {"kernels": "fipt_grid_render_loss (material fetch + render + loss + "
+                                       "grid adjoint, points in the plan's order)",
+                            "warm_ms": fused["warm"], "cold_ms": fused["cold"],
+                            "points_per_s": N / (fused["warm"] * 1e-3),
+                            "roofline": {"bound": "hbm",
+                                         "achieved": fused_bytes / (fused["warm"] * 1e-3) / 1e9,
+                                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                         "frac": fused_bytes / (fused["warm"] * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                         "bytes_per_launch": fused_bytes, "traffic": None}},
     }
 
 
