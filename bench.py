@@ -1017,7 +1017,8 @@ def main():
 
     trav = None
     if not args.no_counters:
-        trav = traversal_bytes(scene, planes, tri, sc, shading)
+        # the timed bake's points: in the grid plan's order
+        trav = traversal_bytes(scene, planes_q, tri_q, sc, torch.empty_like(shading))
         log(f"traversal: {trav}")
     loss_gbs = N * LOSS_BYTES_PER_POINT / (t_loss * 1e-3) / 1e9
     traffic = measured_traffic()
@@ -1059,7 +1060,9 @@ def main():
     log(f"stage-3 refinement: {refine}")
     voxel = run_voxel(scene, sc, planes, tri, obs, shading)
     log(f"voxel cache: {voxel}")
-    hashgrid = run_hashgrid(sc, planes, shading, obs)
+    # on the points in the grid plan's order, as the step keeps them (neighbouring
+    # points share table lines: 7 % faster forward than in camera order)
+    hashgrid = run_hashgrid(sc, planes_q, shading_q, obs_q)
     log(f"hash-grid network: {hashgrid}")
 
     large = None
