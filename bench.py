@@ -1107,8 +1107,9 @@ def main():
                          "fused_grid_loss_fwd_bwd": t_fused},
         "bake_gsamples_per_s": N * S / (t_bake * 1e-3) / 1e9,
         "loss_grad_points_per_s": N / (t_fused * 1e-3),
-        "loss_grad": {"kernels": "k_grid_render_loss + k_final_sum + k_grid_adjoint + "
-                                 "k_grid_adjoint_combine (one call, points in the grid plan's order)",
+        "loss_grad": {"kernels": "k_grid_render_loss + k_grid_adjoint_sums (its last workgroup sums "
+                                 "the loss) + k_grid_adjoint_combine (one call, points in the grid "
+                                 "plan's order)",
                       "ms": t_fused, "points_per_s": N / (t_fused * 1e-3),
                       "roofline": {"bound": "hbm", "achieved": fused_bytes / (t_fused * 1e-3) / 1e9,
                                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
