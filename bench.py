@@ -1056,7 +1056,7 @@ def main():
     del flush, alpha
     comparator = run_comparator(shading, mat, obs, sc.sigma, t_loss)
     log(f"torch-autograd comparator: {comparator}")
-    refine = run_refine(scene, sc, planes, tri, grid, torch.empty_like(shading), t_bake)
+    refine = run_refine(scene, sc, planes_q, tri_q, grid, torch.empty_like(shading), t_bake)
     log(f"stage-3 refinement: {refine}")
     voxel = run_voxel(scene, sc, planes, tri, obs, shading)
     log(f"voxel cache: {voxel}")
