@@ -580,16 +580,61 @@ __global__ __launch_bounds__(kBlock) void k_hg_table_grad_heavy(const int2* __re
     }
 }
 
+// Staging pieces of k_hg_wgrad<true>: thread t's piece j of a 64-point tile
+// is row (t + 256 j) / 16, points 4 ((t + 256 j) % 16) .. + 3 of the A
+// operand (rows of A past `rows` are zero) and of the B operand.
+__device__ __forceinline__ void wgrad_piece(const float* __restrict__ ws, int64_t wn, int64_t p0,
+                                            int64_t p_end, int idx, int rows, int a_row0, int b_row0,
+                                            float4& ra, float4& rb) {
+    const int r = idx >> 4, c = (idx & 15) * 4;
+    const int64_t pp = p0 + c;
+    const float* pa = ws + (int64_t)(a_row0 + r) * wn;
+    const float* pb = ws + (int64_t)(b_row0 + r) * wn;
+    if (pp + 3 < p_end) {
+        ra = r < rows ? *reinterpret_cast<const float4*>(pa + pp) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        rb = *reinterpret_cast<const float4*>(pb + pp);
+    } else {
+        ra = make_float4(r < rows && pp < p_end ? pa[pp] : 0.0f, r < rows && pp + 1 < p_end ? pa[pp + 1] : 0.0f,
+                         r < rows && pp + 2 < p_end ? pa[pp + 2] : 0.0f, 0.0f);
+        rb = make_float4(pp < p_end ? pb[pp] : 0.0f, pp + 1 < p_end ? pb[pp + 1] : 0.0f,
+                         pp + 2 < p_end ? pb[pp + 2] : 0.0f, 0.0f);
+    }
+}
+__device__ __forceinline__ void wgrad_fetch(const float* __restrict__ ws, int64_t wn, int64_t p0,
+                                            int64_t p_end, int t, int rows, int a_row0, int b_row0,
+                                            float4& ra0, float4& rb0, float4& ra1, float4& rb1,
+                                            float4& ra2, float4& rb2, float4& ra3, float4& rb3) {
+    wgrad_piece(ws, wn, p0, p_end, t, rows, a_row0, b_row0, ra0, rb0);
+    wgrad_piece(ws, wn, p0, p_end, t + kBlock, rows, a_row0, b_row0, ra1, rb1);
+    wgrad_piece(ws, wn, p0, p_end, t + 2 * kBlock, rows, a_row0, b_row0, ra2, rb2);
+    wgrad_piece(ws, wn, p0, p_end, t + 3 * kBlock, rows, a_row0, b_row0, ra3, rb3);
+}
+__device__ __forceinline__ void wgrad_store(float (*A)[65], float (*B)[65], int t, int j,
+                                            const float4& ra, const float4& rb) {
+    const int idx = t + kBlock * j;
+    const int r = idx >> 4, c = (idx & 15) * 4;
+    A[r][c] = ra.x;
+    A[r][c + 1] = ra.y;
+    A[r][c + 2] = ra.z;
+    A[r][c + 3] = ra.w;
+    B[r][c] = rb.x;
+    B[r][c + 1] = rb.y;
+    B[r][c + 2] = rb.z;
+    B[r][c + 3] = rb.w;
+}
+
 // Weight-gradient partials on the matrix cores: blockIdx.y picks the product
 // (0: d1 x e -> W1, 1: d2 x h1 -> W2, 2: d3 x h2 -> W3), blockIdx.x a chunk
 // of kChunk points; the workgroup's four wavefronts form the 64 x 64
 // partial as four 32 x 32 tiles with v_mfma_f32_32x32x2f32, the points being
 // the reduction dimension, two per instruction.  Operands are staged
 // through LDS in tiles of 64 points by the whole workgroup (32-point tiles:
-// 7 % slower).  Lane layout of that instruction: lane l supplies
-// A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register r of lane l
-// holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-
+// 7 % slower); with VEC (rows 16-byte aligned: n a multiple of 4) each
+// thread reads its share of a tile as 16-byte loads, the next tile's loads
+// issued before the current tile's products.  Lane layout of that
+// instruction: lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32];
+// accumulator register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_hg_wgrad(const float* __restrict__ ws, int64_t wn,
                                                      int64_t n, float* __restrict__ part) {
     constexpr int kTile = 64;
@@ -603,27 +648,55 @@ __global__ __launch_bounds__(kBlock) void k_hg_wgrad(const float* __restrict__ w
     const int wave = t >> 6, lane = t & 63;
     const int ti = wave >> 1, tj = wave & 1;   // this wavefront's 32 x 32 tile
     const int li = lane % 32, lk = lane / 32;
+    // the rows of A beyond `rows` are zero: a tile of them adds nothing
+    const bool live_tile = 32 * ti < rows;
     v16f acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     const int64_t p_begin = (int64_t)blockIdx.x * kChunk;
     const int64_t p_end = std::min<int64_t>(n, p_begin + kChunk);
-    for (int64_t p0 = p_begin; p0 < p_end; p0 += kTile) {
-        // the workgroup stages 64 rows x 64 points of each operand
-        // (coalesced along points)
-        for (int idx = t; idx < 64 * kTile; idx += kBlock) {
-            const int r = idx / kTile, c = idx % kTile;
-            const int64_t pp = p0 + c;
-            const bool in = pp < p_end;
-            A[r][c] = (in && r < rows) ? ws[(int64_t)(a_row0 + r) * wn + pp] : 0.0f;
-            B[r][c] = in ? ws[(int64_t)(b_row0 + r) * wn + pp] : 0.0f;
-        }
-        __syncthreads();
+    if (VEC) {
+        // thread t stages four 4-point pieces of each operand per tile:
+        // piece j is row (t + 256 j) / 16, points 4 ((t + 256 j) % 16) .. + 3
+        float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+        wgrad_fetch(ws, wn, p_begin, p_end, t, rows, a_row0, b_row0, ra0, rb0, ra1, rb1, ra2, rb2, ra3, rb3);
+        for (int64_t p0 = p_begin; p0 < p_end; p0 += kTile) {
+            wgrad_store(A, B, t, 0, ra0, rb0);
+            wgrad_store(A, B, t, 1, ra1, rb1);
+            wgrad_store(A, B, t, 2, ra2, rb2);
+            wgrad_store(A, B, t, 3, ra3, rb3);
+            __syncthreads();
+            if (p0 + kTile < p_end)
+                wgrad_fetch(ws, wn, p0 + kTile, p_end, t, rows, a_row0, b_row0, ra0, rb0, ra1, rb1,
+                            ra2, rb2, ra3, rb3);
+            if (live_tile) {
 #pragma unroll
-        for (int k0 = 0; k0 < kTile; k0 += 2)
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[32 * ti + li][k0 + lk],
-                                                       B[32 * tj + li][k0 + lk], acc, 0, 0, 0);
-        __syncthreads();
+                for (int k0 = 0; k0 < kTile; k0 += 2)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[32 * ti + li][k0 + lk],
+                                                               B[32 * tj + li][k0 + lk], acc, 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int64_t p0 = p_begin; p0 < p_end; p0 += kTile) {
+            // the workgroup stages 64 rows x 64 points of each operand
+            // (coalesced along points)
+            for (int idx = t; idx < 64 * kTile; idx += kBlock) {
+                const int r = idx / kTile, c = idx % kTile;
+                const int64_t pp = p0 + c;
+                const bool in = pp < p_end;
+                A[r][c] = (in && r < rows) ? ws[(int64_t)(a_row0 + r) * wn + pp] : 0.0f;
+                B[r][c] = in ? ws[(int64_t)(b_row0 + r) * wn + pp] : 0.0f;
+            }
+            __syncthreads();
+            if (live_tile) {
+#pragma unroll
+                for (int k0 = 0; k0 < kTile; k0 += 2)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[32 * ti + li][k0 + lk],
+                                                               B[32 * tj + li][k0 + lk], acc, 0, 0, 0);
+            }
+            __syncthreads();
+        }
     }
     float* out = part + ((int64_t)mat * gridDim.x + blockIdx.x) * 4096;
 #pragma unroll
@@ -917,8 +990,14 @@ int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const f
     if (rc) return rc;
     const int64_t chunks = (n + kChunk - 1) / kChunk;
     float* part = workspace + (int64_t)(kWsRows + kFeatGradRows) * n;
-    hipLaunchKernelGGL(k_hg_wgrad, dim3((unsigned)chunks, 3), dim3(kBlock), 0, st, workspace, n, n,
-                       part);
+    // 16-byte staging when every workspace row starts 16-byte aligned
+    const bool vec = (n % 4 == 0) && (reinterpret_cast<uintptr_t>(workspace) % 16 == 0);
+    if (vec)
+        hipLaunchKernelGGL(k_hg_wgrad<true>, dim3((unsigned)chunks, 3), dim3(kBlock), 0, st, workspace, n,
+                           n, part);
+    else
+        hipLaunchKernelGGL(k_hg_wgrad<false>, dim3((unsigned)chunks, 3), dim3(kBlock), 0, st, workspace, n,
+                           n, part);
     rc = check_hg("hashgrid_wgrad");
     if (rc) return rc;
     hipLaunchKernelGGL(k_hg_wreduce, dim3((kWeights + kBlock - 1) / kBlock), dim3(kBlock), 0, st,

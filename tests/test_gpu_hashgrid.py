@@ -84,8 +84,10 @@ def _close(got, want, tol, what):
     assert not bad.any(), f"{what}: {bad.sum()} entries off, worst {np.max(np.abs(g - want) / scale):.3e}"
 
 
-def test_backward_parity_and_determinism():
-    n = 20000
+@pytest.mark.parametrize("n", [20000, 20003])
+def test_backward_parity_and_determinism(n):
+    """20000 points: the weight-gradient kernel stages 16-byte pieces (rows
+    16-byte aligned); 20003: 4-byte loads; both end in a partial chunk."""
     params = _params(5)
     x = _points(n, 6)
     gy = np.random.default_rng(7).standard_normal((5, n)).astype(np.float32)
