@@ -660,9 +660,10 @@ def run_refine(scene, sc, planes, tri, grid, out, t_bake_ms, reps=3):
 
 
 def run_hashgrid(sc, planes, shading, obs, reps=5):
-    """The paper's material network (Eq. 14) on the room's points: forward
-    (hash encoding + MLP), the factored loss with its material gradient,
-    and the backward pass into table and weight gradients."""
+    """The paper's material network (Eq. 14) on the room's points: a training
+    step (the forward pass keeping the encoding, the factored loss with its
+    material gradient, the backward pass into table and weight gradients
+    reading the kept encoding), and the plain forward pass alone."""
     N = planes.shape[1]
     dev = planes.device
     bmin, bmax = sc.bmin.tolist(), sc.bmax.tolist()
@@ -682,7 +683,7 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
     def once(tm=None):
         if tm:
             tm.mark("a")
-        fipt.fipt_hashgrid_forward(params, pos, bmin, bmax, out=mat)
+        fipt.fipt_hashgrid_forward_save(params, plan, ws, out=mat)
         if tm:
             tm.mark("b")
         fipt.fipt_render_loss(shading, mat, obs, sc.sigma, loss_buf=buf, grad=gmat)
@@ -691,7 +692,7 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
         gpar.zero_()
         if tm:
             tm.mark("d")
-        fipt.fipt_hashgrid_backward(plan, params, gmat, grad_params=gpar, workspace=ws)
+        fipt.fipt_hashgrid_backward(plan, params, gmat, grad_params=gpar, workspace=ws, saved=True)
         if tm:
             tm.mark("e")
 
@@ -704,6 +705,15 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
         once(tm)
     torch.cuda.synchronize()
     repeatable = bool(torch.equal(first, gpar))
+    # the plain forward pass (inference: nothing kept)
+    tf = Timer()
+    torch.cuda._sleep(5_000_000)
+    for _ in range(reps):
+        tf.mark("a")
+        fipt.fipt_hashgrid_forward(params, pos, bmin, bmax, out=mat)
+        tf.mark("b")
+    torch.cuda.synchronize()
+    t_fwd_plain = float(np.mean(tf.spans("a", "b")))
     del plan
     t_fwd = float(np.mean(tm.spans("a", "b")))
     t_loss = float(np.mean(tm.spans("b", "c")))
@@ -724,32 +734,36 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
     reads_pp = float(reads.mean().item())
     bytes_pp = 8.0 * reads_pp + 32.0
     # the backward call's algorithmic bytes per point: the per-point kernel
-    # (vertex gathers, position and output gradient in, 325 activations and
+    # (the kept encoding and the output gradient in, 261 activations and
     # layer gradients and 64 feature gradients out), the table gather (an
     # 8-byte entry and an 8-byte feature gradient per nonzero (point, corner),
     # as many as the forward's vertex reads), the weight-gradient products
     # (the 325 workspace floats read once); the tables' read-modify-write of
     # touched slots is not counted
-    bwd_pp = 8.0 * reads_pp + 32.0 + 4.0 * (325 + 64) + 16.0 * reads_pp + 4.0 * 325
-    bwd_note = ("8 B x vertex reads + 32 B + 4 B x (325 + 64) stores (per-point kernel); 16 B x vertex "
+    bwd_pp = 4.0 * 64 + 20.0 + 4.0 * (261 + 64) + 16.0 * reads_pp + 4.0 * 325
+    bwd_note = ("4 B x 64 encoding + 20 B in, 4 B x (261 + 64) out (per-point kernel); 16 B x vertex "
                 "reads (table gather); 4 B x 325 (weight-gradient products); table read-modify-write "
                 "not counted")
     del p, u, f, reads
-    return {"points": N, "params": int(params.numel()), "forward_ms": t_fwd,
+    fwd_gbs = bytes_pp * N / (t_fwd_plain * 1e-3) / 1e9
+    return {"points": N, "params": int(params.numel()), "forward_ms": t_fwd_plain,
+            "step": "fipt_hashgrid_forward_save (the encoding kept, 256 B per point more written) + "
+                    "loss + fipt_hashgrid_backward_saved",
+            "forward_save_ms": t_fwd,
             "loss_ms": t_loss, "zero_grad_ms": t_zero, "backward_ms": t_bwd,
             "backward_bitwise_repeatable": repeatable, "table_gradient": "gather over a per-level "
             "slot-sorted (point, corner) list (no atomics)", "plan_build_s": t_plan,
             "step_points_per_s": N / ((t_fwd + t_loss + t_zero + t_bwd) * 1e-3),
             "forward_vertex_reads_per_point": reads_pp,
             "forward_bytes_per_point": bytes_pp,
-            "forward_gbs": bytes_pp * N / (t_fwd * 1e-3) / 1e9,
+            "forward_gbs": fwd_gbs,
             "forward_flops_per_point": HG_FWD_FLOPS_PER_POINT,
-            "forward_tflops": HG_FWD_FLOPS_PER_POINT * N / (t_fwd * 1e-3) / 1e12,
+            "forward_tflops": HG_FWD_FLOPS_PER_POINT * N / (t_fwd_plain * 1e-3) / 1e12,
             "traffic_forward": measured_traffic().get("k_hg_forward"),
             "kernel": "k_hg_forward",
-            "roofline_forward": {"bound": "hbm", "achieved": bytes_pp * N / (t_fwd * 1e-3) / 1e9,
+            "roofline_forward": {"bound": "hbm", "achieved": fwd_gbs,
                                  "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                 "frac": bytes_pp * N / (t_fwd * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                 "frac": fwd_gbs / PEAK_HBM_GBS,
                                  "traffic": measured_traffic().get("k_hg_forward"),
                                  "kernel": "k_hg_forward"},
             "backward_bytes_per_point": bwd_pp,

@@ -579,6 +579,22 @@ int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const f
                            int64_t gm_stride, float* grad_params, float* workspace,
                            int64_t workspace_floats, void* stream);
 
+/* The forward pass of a training step (Eq. 14 as in fipt_hashgrid_forward)
+ * that also keeps the points' hash encoding (64 floats per point) in the
+ * first 64 n floats of `workspace` (at least fipt_hashgrid_workspace_floats(n)
+ * floats), and the backward pass that takes it from there instead of
+ * gathering it from the tables again: fipt_hashgrid_backward_saved, called
+ * with the plan of the same points, the same params and that workspace
+ * untouched in between, gives fipt_hashgrid_backward's result bit for bit.
+ * The material equals fipt_hashgrid_forward's bit for bit. */
+int fipt_hashgrid_forward_save(const float* params, const float* pos, int64_t pos_stride, int64_t n,
+                               const float* bmin_host, const float* bmax_host, float* material,
+                               int64_t mat_stride, float* workspace, int64_t workspace_floats,
+                               void* stream);
+int fipt_hashgrid_backward_saved(fipt_hashgrid_plan plan, const float* params,
+                                 const float* grad_material, int64_t gm_stride, float* grad_params,
+                                 float* workspace, int64_t workspace_floats, void* stream);
+
 /* ---- emission re-estimation (Sec. 4.4, Eq. 13) ------------------------- */
 
 /* Under the assumption that an emitter reflects no light (f = 0), the

@@ -133,6 +133,10 @@ __device__ __forceinline__ void swap_halves(float x, float y, float& lo_pair, fl
     hi_pair = __uint_as_float(r[1]);
 }
 
+// SAVED: the workspace already holds the encoding (rows 0-63, written by
+// the forward pass of the same parameters and points), which is read
+// instead of gathered from the tables again.
+template <bool SAVED>
 __global__ __launch_bounds__(kBlock) void k_hg_backward(HgArgs a, const float* __restrict__ gy,
                                                              int64_t gs, float* __restrict__ ws,
                                                              int64_t wn, float2* __restrict__ fgrad) {
@@ -162,26 +166,33 @@ __global__ __launch_bounds__(kBlock) void k_hg_backward(HgArgs a, const float* _
             for (int r = 0; r < 16; ++r) z[u][j][r] = 0.0f;
     {
         float p[3] = {0.0f, 0.0f, 0.0f};
-        if (live) unit_pos(a, i, p);
+        if (!SAVED && live) unit_pos(a, i, p);
         const float2* t2 = reinterpret_cast<const float2*>(a.params);
 #pragma unroll 1
         for (int l = 0; l < kLevels; ++l) {
-            uint32_t idx[8];
-            float wt[8];
-            corners(l, p, idx, wt);
-            const float2* t = t2 + (int64_t)l * kT;
             float e0 = 0.0f, e1 = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (wt[k] != 0.0f) {
-                    const float2 v = t[idx[k]];
-                    e0 = fmaf(wt[k], v.x, e0);
-                    e1 = fmaf(wt[k], v.y, e1);
+            if (SAVED) {
+                if (live) {
+                    e0 = ws[(int64_t)(2 * l) * wn + i];
+                    e1 = ws[(int64_t)(2 * l + 1) * wn + i];
                 }
-            }
-            if (live) {
-                ws[(int64_t)(2 * l) * wn + i] = e0;
-                ws[(int64_t)(2 * l + 1) * wn + i] = e1;
+            } else {
+                uint32_t idx[8];
+                float wt[8];
+                corners(l, p, idx, wt);
+                const float2* t = t2 + (int64_t)l * kT;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (wt[k] != 0.0f) {
+                        const float2 v = t[idx[k]];
+                        e0 = fmaf(wt[k], v.x, e0);
+                        e1 = fmaf(wt[k], v.y, e1);
+                    }
+                }
+                if (live) {
+                    ws[(int64_t)(2 * l) * wn + i] = e0;
+                    ws[(int64_t)(2 * l + 1) * wn + i] = e1;
+                }
             }
             float b0, b1;   // features 2l (lanes 0-31) and 2l + 1 (lanes 32-63) of point tiles 0 and 1
             swap_halves(e0, e1, b0, b1);
@@ -345,7 +356,11 @@ __global__ __launch_bounds__(kBlock) void k_hg_backward(HgArgs a, const float* _
 
 // The forward pass in the same layout: the two hidden layers on the matrix
 // cores, the five outputs summed per half-wave on the vector ALUs.
-__global__ __launch_bounds__(kBlock) void k_hg_forward(HgArgs a, float* __restrict__ out, int64_t os) {
+// SAVE: the encoding also goes to rows 0-63 of the backward pass's
+// workspace ws[.][wn], so that the backward pass need not gather it again.
+template <bool SAVE>
+__global__ __launch_bounds__(kBlock) void k_hg_forward(HgArgs a, float* __restrict__ out, int64_t os,
+                                                       float* __restrict__ ws, int64_t wn) {
     __shared__ float w[kLdsW];
     {
         const float* src = a.params + kTable;
@@ -387,6 +402,10 @@ __global__ __launch_bounds__(kBlock) void k_hg_forward(HgArgs a, float* __restri
                     e0 = fmaf(wt[k], v.x, e0);
                     e1 = fmaf(wt[k], v.y, e1);
                 }
+            }
+            if (SAVE && live) {
+                ws[(int64_t)(2 * l) * wn + i] = e0;
+                ws[(int64_t)(2 * l + 1) * wn + i] = e1;
             }
             float b0, b1;
             swap_halves(e0, e1, b0, b1);
@@ -949,15 +968,32 @@ int fipt_hashgrid_forward(const float* params, const float* pos, int64_t pos_str
     if (rc) return rc;
     if (!material) return fail(FIPT_EINVAL, "material is NULL");
     if (mat_stride < n) return fail(FIPT_EINVAL, "mat_stride < n");
-    hipLaunchKernelGGL(k_hg_forward, dim3(grid_points(n)), dim3(kBlock), 0, (hipStream_t)stream, a,
-                       material, mat_stride);
+    hipLaunchKernelGGL(k_hg_forward<false>, dim3(grid_points(n)), dim3(kBlock), 0, (hipStream_t)stream, a,
+                       material, mat_stride, nullptr, 0);
     return check_hg("hashgrid_forward");
 }
 
-int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const float* grad_material,
-                           int64_t gm_stride, float* grad_params, float* workspace,
-                           int64_t workspace_floats, void* stream) {
+int fipt_hashgrid_forward_save(const float* params, const float* pos, int64_t pos_stride, int64_t n,
+                               const float* bmin_host, const float* bmax_host, float* material,
+                               int64_t mat_stride, float* workspace, int64_t workspace_floats,
+                               void* stream) {
     clear_error();
+    HgArgs a;
+    int rc = make_args(params, pos, pos_stride, n, bmin_host, bmax_host, a);
+    if (rc) return rc;
+    if (!material || !workspace) return fail(FIPT_EINVAL, "NULL argument");
+    if (mat_stride < n) return fail(FIPT_EINVAL, "mat_stride < n");
+    if (workspace_floats < fipt_hashgrid_workspace_floats(n))
+        return fail(FIPT_EINVAL, "workspace holds %lld floats, %lld needed", (long long)workspace_floats,
+                    (long long)fipt_hashgrid_workspace_floats(n));
+    hipLaunchKernelGGL(k_hg_forward<true>, dim3(grid_points(n)), dim3(kBlock), 0, (hipStream_t)stream, a,
+                       material, mat_stride, workspace, n);
+    return check_hg("hashgrid_forward_save");
+}
+
+static int hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const float* grad_material,
+                             int64_t gm_stride, float* grad_params, float* workspace,
+                             int64_t workspace_floats, bool saved, void* stream) {
     if (!plan) return fail(FIPT_EINVAL, "plan is NULL");
     const int64_t n = plan->n;
     HgArgs a;
@@ -970,8 +1006,12 @@ int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const f
                     (long long)fipt_hashgrid_workspace_floats(n));
     hipStream_t st = (hipStream_t)stream;
     float2* fgrad = reinterpret_cast<float2*>(workspace + (int64_t)kWsRows * n);
-    hipLaunchKernelGGL(k_hg_backward, dim3(grid_points(n)), dim3(kBlock), 0, st, a, grad_material,
-                       gm_stride, workspace, n, fgrad);
+    if (saved)
+        hipLaunchKernelGGL(k_hg_backward<true>, dim3(grid_points(n)), dim3(kBlock), 0, st, a, grad_material,
+                           gm_stride, workspace, n, fgrad);
+    else
+        hipLaunchKernelGGL(k_hg_backward<false>, dim3(grid_points(n)), dim3(kBlock), 0, st, a, grad_material,
+                           gm_stride, workspace, n, fgrad);
     rc = check_hg("hashgrid_backward");
     if (rc) return rc;
     for (int l = 0; l < kLevels; ++l) {
@@ -1003,6 +1043,22 @@ int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const f
     hipLaunchKernelGGL(k_hg_wreduce, dim3((kWeights + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
                        part, chunks, grad_params);
     return check_hg("hashgrid_wreduce");
+}
+
+int fipt_hashgrid_backward(fipt_hashgrid_plan plan, const float* params, const float* grad_material,
+                           int64_t gm_stride, float* grad_params, float* workspace,
+                           int64_t workspace_floats, void* stream) {
+    clear_error();
+    return hashgrid_backward(plan, params, grad_material, gm_stride, grad_params, workspace,
+                             workspace_floats, false, stream);
+}
+
+int fipt_hashgrid_backward_saved(fipt_hashgrid_plan plan, const float* params,
+                                 const float* grad_material, int64_t gm_stride, float* grad_params,
+                                 float* workspace, int64_t workspace_floats, void* stream) {
+    clear_error();
+    return hashgrid_backward(plan, params, grad_material, gm_stride, grad_params, workspace,
+                             workspace_floats, true, stream);
 }
 
 }  // extern "C"

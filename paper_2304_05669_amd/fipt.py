@@ -37,6 +37,7 @@ EXPORTS = (
     "fipt_scene_set_voxel_radiance", "fipt_voxel_plan_create", "fipt_voxel_plan_destroy",
     "fipt_voxel_pool", "fipt_hashgrid_forward", "fipt_hashgrid_workspace_floats",
     "fipt_hashgrid_plan_create", "fipt_hashgrid_plan_destroy", "fipt_hashgrid_backward",
+    "fipt_hashgrid_forward_save", "fipt_hashgrid_backward_saved",
     "fipt_server_create", "fipt_server_submit", "fipt_server_poll", "fipt_server_wait",
     "fipt_server_result", "fipt_server_release", "fipt_server_cancel", "fipt_server_stats_get",
     "fipt_server_destroy",
@@ -117,6 +118,9 @@ def lib():
         "fipt_hashgrid_plan_create": (C.c_int, [_vp, _i64, _i64, _f32p, _f32p, _vp, C.POINTER(_vp)]),
         "fipt_hashgrid_plan_destroy": (C.c_int, [_vp]),
         "fipt_hashgrid_backward": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]),
+        "fipt_hashgrid_forward_save": (C.c_int, [_vp, _vp, _i64, _i64, _f32p, _f32p, _vp, _i64, _vp,
+                                                 _i64, _vp]),
+        "fipt_hashgrid_backward_saved": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp]),
         "fipt_scene_set_emission": (C.c_int, [_vp, _vp, _vp]),
         "fipt_scene_info_get": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
         "fipt_scene_destroy": (C.c_int, [_vp]),
@@ -837,11 +841,42 @@ class HashGridPlan:
             pass
 
 
-def fipt_hashgrid_backward(plan: HashGridPlan, params: torch.Tensor, grad_material: torch.Tensor,
-                           grad_params: torch.Tensor = None, workspace: torch.Tensor = None):
-    """Adds d(sum grad_material * material) / d params, for the plan's
-    points, into grad_params (zeros if None) and returns it."""
+def hashgrid_workspace(n: int, device) -> torch.Tensor:
+    """A workspace for the hash-grid backward pass of n points."""
+    return torch.empty((int(lib().fipt_hashgrid_workspace_floats(n)),), dtype=torch.float32,
+                       device=device)
+
+
+def fipt_hashgrid_forward_save(params: torch.Tensor, plan: "HashGridPlan", workspace: torch.Tensor,
+                               out: torch.Tensor = None):
+    """The forward pass for the plan's points that also keeps their hash
+    encoding in ``workspace`` for fipt_hashgrid_backward(..., saved=True)."""
     _need(params, (HG_PARAMS,), "params")
+    n = plan.n
+    need = int(lib().fipt_hashgrid_workspace_floats(n))
+    if workspace.dim() != 1 or workspace.shape[0] < need:
+        raise ValueError(f"workspace must hold at least {need} floats")
+    if out is None:
+        out = torch.empty((5, n), dtype=torch.float32, device=params.device)
+    _need(out, (5, n), "out")
+    _check(lib().fipt_hashgrid_forward_save(_dev(params, torch.float32, "params"),
+                                            _dev(plan.pos, torch.float32, "pos"), n, n,
+                                            _f32_array(plan.bmin, 3), _f32_array(plan.bmax, 3),
+                                            _dev(out, torch.float32, "out"), n,
+                                            _dev(workspace, torch.float32, "workspace"),
+                                            workspace.shape[0], _stream()))
+    return out
+
+
+def fipt_hashgrid_backward(plan: HashGridPlan, params: torch.Tensor, grad_material: torch.Tensor,
+                           grad_params: torch.Tensor = None, workspace: torch.Tensor = None,
+                           saved: bool = False):
+    """Adds d(sum grad_material * material) / d params, for the plan's
+    points, into grad_params (zeros if None) and returns it.  With ``saved``
+    the workspace holds the encoding fipt_hashgrid_forward_save left there."""
+    _need(params, (HG_PARAMS,), "params")
+    if saved and workspace is None:
+        raise ValueError("saved needs the workspace of fipt_hashgrid_forward_save")
     n = plan.n
     _need(grad_material, (5, n), "grad_material")
     if grad_params is None:
@@ -852,11 +887,11 @@ def fipt_hashgrid_backward(plan: HashGridPlan, params: torch.Tensor, grad_materi
         workspace = torch.empty((need,), dtype=torch.float32, device=params.device)
     if workspace.dim() != 1 or workspace.shape[0] < need:
         raise ValueError(f"workspace must hold at least {need} floats")
-    _check(lib().fipt_hashgrid_backward(plan.handle, _dev(params, torch.float32, "params"),
-                                        _dev(grad_material, torch.float32, "grad_material"), n,
-                                        _dev(grad_params, torch.float32, "grad_params"),
-                                        _dev(workspace, torch.float32, "workspace"),
-                                        workspace.shape[0], _stream()))
+    fn = lib().fipt_hashgrid_backward_saved if saved else lib().fipt_hashgrid_backward
+    _check(fn(plan.handle, _dev(params, torch.float32, "params"),
+              _dev(grad_material, torch.float32, "grad_material"), n,
+              _dev(grad_params, torch.float32, "grad_params"),
+              _dev(workspace, torch.float32, "workspace"), workspace.shape[0], _stream()))
     return grad_params
 
 
@@ -868,12 +903,16 @@ class HashGridMaterial(torch.autograd.Function):
     def forward(ctx, params, plan):
         ctx.save_for_backward(params)
         ctx.plan = plan
-        return fipt_hashgrid_forward(params.detach(), plan.pos, plan.bmin, plan.bmax)
+        # the encoding is kept for the backward pass (256 B per point)
+        ctx.ws = hashgrid_workspace(plan.n, params.device)
+        return fipt_hashgrid_forward_save(params.detach(), plan, ctx.ws)
 
     @staticmethod
     def backward(ctx, g):
         (params,) = ctx.saved_tensors
-        gp = fipt_hashgrid_backward(ctx.plan, params.detach(), g.contiguous())
+        gp = fipt_hashgrid_backward(ctx.plan, params.detach(), g.contiguous(), workspace=ctx.ws,
+                                    saved=True)
+        ctx.ws = None
         return gp, None
 
 

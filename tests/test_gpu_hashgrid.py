@@ -192,3 +192,25 @@ def test_backward_full_size_is_additive_over_point_sets():
     _close(a[:hg.N_TABLE], b[:hg.N_TABLE], 1e-3, "table grads, whole vs halves")
     assert np.abs(a[hg.N_TABLE:]).max() > 0 and np.abs(a[:hg.N_TABLE]).max() > 0
     scene.destroy()
+
+
+@pytest.mark.parametrize("n", [20000, 20003])
+def test_saved_encoding_gives_the_same_bits(n):
+    """fipt_hashgrid_forward_save returns fipt_hashgrid_forward's material
+    and leaves the encoding in the workspace; the backward pass that reads it
+    there equals the one that gathers it again, bit for bit."""
+    params = _params(8)
+    x = _points(n, 9)
+    gy = np.random.default_rng(10).standard_normal((5, n)).astype(np.float32)
+    P, X, G = _t(params), _t(x), _t(gy)
+    plan = fipt.HashGridPlan(X, LO, HI)
+    plain = fipt.fipt_hashgrid_forward(P, X, LO, HI)
+    ws = fipt.hashgrid_workspace(n, DEV)
+    saved = fipt.fipt_hashgrid_forward_save(P, plan, ws)
+    g_saved = fipt.fipt_hashgrid_backward(plan, P, G, workspace=ws, saved=True)
+    g_plain = fipt.fipt_hashgrid_backward(plan, P, G)
+    torch.cuda.synchronize()
+    assert torch.equal(saved, plain)
+    assert torch.equal(g_saved, g_plain)
+    with pytest.raises(ValueError):
+        fipt.fipt_hashgrid_backward(plan, P, G, saved=True)
