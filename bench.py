@@ -76,6 +76,7 @@ KERNEL_SOURCES = {
     "k_render_loss_masked": ("loss.hip", "fipt_internal.hpp"),
     "k_bake_voxel": ("bake.hip", "device.hpp", "fipt_internal.hpp", "bvh_build.cpp"),
     "k_hg_forward": ("hashgrid.hip", "fipt_internal.hpp"),
+    "k_hg_forward_save": ("hashgrid.hip", "fipt_internal.hpp"),
     "k_hg_backward": ("hashgrid.hip", "fipt_internal.hpp"),
     "k_hg_table_grad": ("hashgrid.hip", "fipt_internal.hpp"),
     "k_grid_adjoint": ("loss.hip", "grid.cpp", "fipt_internal.hpp"),
@@ -750,6 +751,7 @@ def run_hashgrid(sc, planes, shading, obs, reps=5):
             "step": "fipt_hashgrid_forward_save (the encoding kept, 256 B per point more written) + "
                     "loss + fipt_hashgrid_backward_saved",
             "forward_save_ms": t_fwd,
+            "traffic_forward_save": measured_traffic().get("k_hg_forward_save"),
             "loss_ms": t_loss, "zero_grad_ms": t_zero, "backward_ms": t_bwd,
             "backward_bitwise_repeatable": repeatable, "table_gradient": "gather over a per-level "
             "slot-sorted (point, corner) list (no atomics)", "plan_build_s": t_plan,
