@@ -116,6 +116,41 @@ def test_invalid_arguments_rejected_on_host():
     assert L.fipt_grid_plan_permute(None, 1, 1, 100, 2, 100, None) == fipt.EINVAL
 
 
+
+def test_empty_inputs_rejected_on_host():
+    """Zero points is an argument error (FIPT_EINVAL, "n ..." in the message)
+    for every entry point that takes a point count, checked before any
+    pointer is used; fipt_scale_by alone accepts n = 0 as a no-op."""
+    L = fipt.lib()
+    out = C.c_void_p()
+    box0 = (C.c_float * 3)(0, 0, 0)
+    box1 = (C.c_float * 3)(1, 1, 1)
+    buf = (C.c_float * 64)()
+    dbl = (C.c_double * 8)()
+    tri = (C.c_int32 * 4)()
+    sh = fipt.Shading(C.cast(buf, C.c_void_p), 1)
+    sig = (C.c_float * 6)(0.02, 0.1, 0.25, 0.5, 0.75, 1.0)
+    calls = {
+        "render_loss": lambda: L.fipt_render_loss(C.byref(sh), 0, 6, sig, buf, 1, buf, 1, 0, dbl, buf,
+                                                  1, None, 1, None),
+        "render_loss_noalloc": lambda: L.fipt_render_loss_noalloc(C.byref(sh), 0, 6, sig, buf, 1, buf, 1,
+                                                                  0, dbl, buf, 1, None, 1, None),
+        "grid_gather": lambda: L.fipt_grid_gather(buf, 5, 4, box0, box1, buf, 1, 0, buf, 1, None),
+        "grid_plan_create": lambda: L.fipt_grid_plan_create(buf, 0, 4, box0, box1, 0, C.byref(out)),
+        "emission_plan_create": lambda: L.fipt_emission_plan_create(tri, 0, 4, 0, C.byref(out)),
+        "voxel_plan_create": lambda: L.fipt_voxel_plan_create(buf, 0, 4, box0, box1, 0, C.byref(out)),
+        "hashgrid_forward": lambda: L.fipt_hashgrid_forward(buf, buf, 1, 0, box0, box1, buf, 1, None),
+        "hashgrid_plan_create": lambda: L.fipt_hashgrid_plan_create(buf, 1, 0, box0, box1, None,
+                                                                    C.byref(out)),
+        "hbm_stream": lambda: L.fipt_hbm_stream(0, buf, None, buf, 0, 1.0, None),
+    }
+    for name, call in calls.items():
+        assert call() == fipt.EINVAL, name
+        assert b"n must" in L.fipt_last_error(), (name, L.fipt_last_error())
+        assert out.value is None, name
+    assert L.fipt_scale_by(buf, 0, dbl, buf, None) == fipt.OK
+
+
 # (scale, offset) applied to the room: the 4-wide nodes store bounds as
 # half-precision offsets in units of one power of two for the whole tree, so
 # the validator's enclosure check runs at extreme scales and far from the origin
