@@ -372,8 +372,15 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
         // Lanes that are not tracing hold ref == kDone, so ref alone tells a
         // lane's position: >= 0 an inner node, other negative values a leaf.
         int32_t pend = kDone;
+        const uint64_t wave = dev::ballot(true);
         while (true) {
-            if (is_leaf(ref) && pend == kDone) {
+            const bool waits = pend == kDone;
+            const bool leaf = is_leaf(ref);
+            // lanes without a parked leaf after this step: those that had
+            // none and are not at a leaf now (taken before the branch, from
+            // the two compares, so the masks stay in scalar registers)
+            const uint64_t unparked = dev::ballot(waits) & ~dev::ballot(leaf);
+            if (waits && leaf) {
                 pend = ref;
                 dev::stack_pop(ref, top, stack, kBlock);
             }
@@ -381,11 +388,11 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
             // Stop descending once fewer than kSearchMin lanes are still
             // looking for a leaf and some lane has one to test: the rest would
             // otherwise idle while the last few rays search.
-            // (two ballots and a 32-bit count keep the test in scalar code)
-            const uint64_t searching = dev::ballot(inner) & dev::ballot(pend == kDone);
+            // (the masks and a 32-bit count keep the test in scalar code)
+            const uint64_t searching = dev::ballot(inner) & unparked;
             const int n_searching = __builtin_popcount((uint32_t)searching) +
                                     __builtin_popcount((uint32_t)(searching >> 32));
-            if (searching == 0 || (n_searching < kSearchMin && dev::ballot(pend != kDone) != 0))
+            if (searching == 0 || (n_searching < kSearchMin && (wave & ~unparked) != 0))
                 break;
             if (COUNT && lane == 0) ++n_node_steps;
             if (inner) {

@@ -780,16 +780,22 @@ __device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int3
         // ---- traversal: inner nodes until every lane has parked a leaf ----
         // (lanes not tracing hold ref == kDone)
         int32_t pend = kDone;
+        const uint64_t wave = dev::ballot(true);
         while (true) {
-            if (is_leaf(ref) && pend == kDone) {
+            // (the lanes left without a parked leaf are taken from the two
+            // compares before the branch, so the masks stay scalar)
+            const bool waits = pend == kDone;
+            const bool leaf = is_leaf(ref);
+            const uint64_t unparked = dev::ballot(waits) & ~dev::ballot(leaf);
+            if (waits && leaf) {
                 pend = ref;
                 dev::stack_pop(ref, top, stack, kBlock);
             }
             const bool inner = ref >= 0;
-            const uint64_t searching = dev::ballot(inner) & dev::ballot(pend == kDone);
+            const uint64_t searching = dev::ballot(inner) & unparked;
             const int n_searching = __builtin_popcount((uint32_t)searching) +
                                     __builtin_popcount((uint32_t)(searching >> 32));
-            if (searching == 0 || (n_searching < kSearchMin && dev::ballot(pend != kDone) != 0)) break;
+            if (searching == 0 || (n_searching < kSearchMin && (wave & ~unparked) != 0)) break;
             if (inner) dev::node4_step(sc.nodes, ref, top, stack, kBlock, rs, h.t);
         }
         if (pend != kDone) {
