@@ -269,7 +269,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
     int32_t* top = stack;
     dev::Hit h;
     h.leaf = -1;
-    h.t = INFINITY;
+    h.t = dev::kNoHit;
     h.u = h.v = 0.0f;
     int32_t best_orig = INT_MAX;
     int next_q = 0;                   // wave-uniform: next sample to hand out
@@ -356,7 +356,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                             }
                             ref = chain_end;
                             h.leaf = -1;
-                            h.t = INFINITY;
+                            h.t = dev::kNoHit;
                             h.u = h.v = 0.0f;
                             best_orig = INT_MAX;
                             state = kTracing;

@@ -30,6 +30,12 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 // mixes the high halves with words 1 / 3 and the round key; the key grows
 // by the Weyl constants 0x9E3779B9 / 0xBB67AE85 between rounds.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    // The key (wave-uniform in every caller) passes through an empty
+    // statement, so the twenty round keys are formed here with scalar adds:
+    // a loop-invariant seed otherwise has all of them hoisted out of the
+    // sampling loop, and the bake, short of scalar registers, spills them
+    // to vector lanes (a vector instruction per key on every refill).
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         // one 32 x 32 -> 64-bit multiply gives both halves of a product
@@ -117,6 +123,11 @@ struct Hit {
 // triangles).
 constexpr int32_t kDone = INT_MIN;
 
+// Hit distance of a ray that has hit nothing yet: the largest finite float,
+// so that the +inf key of a missed child box always lies beyond it (the
+// node step visits a child when its key is at most the hit distance).
+constexpr float kNoHit = 3.40282347e+38f;
+
 // Per-ray constants of the slab test against node bounds in units of
 // `scale`: the inverse direction times the unit (a power of two, so the
 // product is exact) and the origin times the inverse direction.
@@ -177,17 +188,20 @@ __device__ __forceinline__ float half_hi(uint32_t w) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
 }
 
-// Slab test of one child box against [0, tmax] from its near and far
+// Slab test of one child box against [0, inf) from its near and far
 // planes as half-precision offsets from the node origin: the distance to
 // plane (org + off) 2^E is fma(off, a, org a - o ix) with a = ix 2^E.
 // Returns the entry distance, or +inf when the box is missed.  An unused
 // slot (low offsets +inf, high -inf) has near distance +inf and far
-// distance -inf whatever the direction.
+// distance -inf whatever the direction.  The current hit distance is not
+// clipped in here: the caller compares the entry distance with it, once
+// per child after the sort (the same boxes are visited, in the same order,
+// as with the clipped interval, for one instruction less per child).
 __device__ __forceinline__ float box_entry(float nx, float fx, float ny, float fy, float nz,
                                            float fz, float ax, float bx, float ay, float by,
-                                           float az, float bz, float tmax) {
+                                           float az, float bz) {
     const float tn = fmaxf(fmaxf(fmaf(nx, ax, bx), fmaf(ny, ay, by)), fmaxf(fmaf(nz, az, bz), 0.0f));
-    const float tf = fminf(fminf(fmaf(fx, ax, bx), fmaf(fy, ay, by)), fminf(fmaf(fz, az, bz), tmax));
+    const float tf = fminf(fminf(fmaf(fx, ax, bx), fmaf(fy, ay, by)), fmaf(fz, az, bz));
     return tn <= tf ? tn : INFINITY;
 }
 
@@ -204,9 +218,10 @@ __device__ __forceinline__ void stack_pop(int32_t& ref, int32_t*& top, const int
     }
 }
 
-// One step of closest-hit traversal at 4-wide node `ref`: the hit children
-// are visited nearest first; the nearest becomes `ref`, the others are
-// pushed farthest first.  With no child hit, the next entry is popped
+// One step of closest-hit traversal at 4-wide node `ref`: the children the
+// ray enters no later than `tmax` (the current hit distance, finite) are
+// visited nearest first; the nearest becomes `ref`, the others are pushed
+// farthest first.  With no child hit, the next entry is popped
 // (kDone when the stack is empty).  Node byte offsets fit 32 bits (the
 // builder rejects trees of more than kMaxNodes4 nodes).
 __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, int32_t*& top,
@@ -237,33 +252,35 @@ __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, 
     const uint32_t nz01 = sz ? qz.z : qz.x, nz23 = sz ? qz.w : qz.y;
     const uint32_t fz01 = sz ? qz.x : qz.z, fz23 = sz ? qz.y : qz.w;
     float k0 = box_entry(half_lo(nx01), half_lo(fx01), half_lo(ny01), half_lo(fy01), half_lo(nz01),
-                         half_lo(fz01), ax, bx, ay, by, az, bz, tmax);
+                         half_lo(fz01), ax, bx, ay, by, az, bz);
     float k1 = box_entry(half_hi(nx01), half_hi(fx01), half_hi(ny01), half_hi(fy01), half_hi(nz01),
-                         half_hi(fz01), ax, bx, ay, by, az, bz, tmax);
+                         half_hi(fz01), ax, bx, ay, by, az, bz);
     float k2 = box_entry(half_lo(nx23), half_lo(fx23), half_lo(ny23), half_lo(fy23), half_lo(nz23),
-                         half_lo(fz23), ax, bx, ay, by, az, bz, tmax);
+                         half_lo(fz23), ax, bx, ay, by, az, bz);
     float k3 = box_entry(half_hi(nx23), half_hi(fx23), half_hi(ny23), half_hi(fy23), half_hi(nz23),
-                         half_hi(fz23), ax, bx, ay, by, az, bz, tmax);
-    // sorting network on four keys; a missed child keeps key +inf and sorts
-    // last, so the sorted keys say which children to visit
+                         half_hi(fz23), ax, bx, ay, by, az, bz);
+    // sorting network on four keys; a missed child keeps key +inf and one
+    // entered beyond the current hit a key above tmax (finite: kNoHit
+    // before the first hit), so both sort after every child to visit, and
+    // the sorted keys compared with tmax say which children to visit
     order2(k0, c0, k1, c1);
     order2(k2, c2, k3, c3);
     order2(k0, c0, k2, c2);
     order2(k1, c1, k3, c3);
     order2(k1, c1, k2, c2);
-    if (!(k0 < INFINITY)) {
+    if (!(k0 <= tmax)) {
         stack_pop(ref, top, bottom, stride);
         return;
     }
-    if (k3 < INFINITY) {
+    if (k3 <= tmax) {
         *top = c3;
         top += stride;
     }
-    if (k2 < INFINITY) {
+    if (k2 <= tmax) {
         *top = c2;
         top += stride;
     }
-    if (k1 < INFINITY) {
+    if (k1 <= tmax) {
         *top = c1;
         top += stride;
     }
@@ -458,7 +475,7 @@ __device__ __forceinline__ Hit trace(const DeviceScene& sc, V3 o, V3 d, int32_t*
     const RaySlab r = ray_slab(o, d, sc.box_scale);
     Hit h;
     h.leaf = -1;
-    h.t = INFINITY;
+    h.t = kNoHit;
     h.u = h.v = 0.0f;
     int32_t best_orig = INT_MAX;
     int32_t ref = 0;

@@ -549,7 +549,7 @@ __device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int3
     dev::RaySlab rs = dev::ray_slab(o, d, sc.box_scale);
     dev::Hit h;
     h.leaf = -1;
-    h.t = INFINITY;
+    h.t = dev::kNoHit;
     h.u = h.v = 0.0f;
     int32_t best_orig = INT_MAX;
     auto start_ray = [&]() {
@@ -557,7 +557,7 @@ __device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int3
         ref = 0;
         top = stack;
         h.leaf = -1;
-        h.t = INFINITY;
+        h.t = dev::kNoHit;
         h.u = h.v = 0.0f;
         best_orig = INT_MAX;
         state = kTracing;
