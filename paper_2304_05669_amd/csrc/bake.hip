@@ -94,7 +94,7 @@ __device__ __forceinline__ void bake_point(const BakeLaunch& b, const float* sig
                 const float alpha = sg * sg;
                 const float a2 = alpha * alpha;
                 const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
-                const float cos_m = rsqrtf(1.0f + tan2);
+                const float cos_m = dev::rsq_ge1(1.0f + tan2);
                 const float sin_m = dev::sqrt_hw(tan2) * cos_m;   // accurate for tiny tilts
                 const V3 m = dev::to_world(ft, fb, n, sin_m * cp_, sin_m * sp_, cos_m);
                 const float om = dev::dot(wo, m);
@@ -324,7 +324,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                             const float alpha = sg * sg;
                             const float a2 = alpha * alpha;
                             const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
-                            const float cos_m = rsqrtf(1.0f + tan2);
+                            const float cos_m = dev::rsq_ge1(1.0f + tan2);
                             const float sin_m = dev::sqrt_hw(tan2) * cos_m;
                             const V3 m = dev::to_world(ft, fb, n, sin_m * cp_, sin_m * sp_, cos_m);
                             const float om = dev::dot(wo, m);
@@ -352,7 +352,7 @@ __device__ __forceinline__ void bake_point_refill(const BakeLaunch& b, const flo
                             for (int i = 0; i < chain_len; ++i) {
                                 const int32_t cw = __builtin_amdgcn_readlane(chain, i);
                                 if (COUNT) ++n_chain;
-                                dev::chain_step(sc.nodes, cw >> 2, cw & 3, rs, top, kBlock);
+                                dev::chain_step(sc.nodes, cw & ~3, cw & 3, rs, top, kBlock);
                             }
                             ref = chain_end;
                             h.leaf = -1;

@@ -733,7 +733,7 @@ Bvh4Node encode4(const Wide4& w, int e) {
             n.q[k][4 + i] = half_bound_signed(std::ldexp((double)w.hi[k][i], -e) - org, true);
         }
     }
-    for (int i = 0; i < 4; ++i) n.child[i] = w.child[i];
+    for (int i = 0; i < 4; ++i) n.child[i] = node4_ref(w.child[i]);
     return n;
 }
 
@@ -774,7 +774,7 @@ int build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t 
         out->nodes4[i] = encode4(out->wide4[i], out->box_exp);
     if (out->max_push4 > kStackSize)
         return fail(FIPT_EINVAL, "4-wide BVH needs %d stack entries", out->max_push4);
-    // the traversal addresses nodes by 32-bit byte offsets
+    // the traversal addresses nodes by non-negative 32-bit byte offsets
     if ((int64_t)out->nodes4.size() > kMaxNodes4)
         return fail(FIPT_EINVAL, "4-wide BVH has %zu nodes (at most %lld)", out->nodes4.size(),
                     (long long)kMaxNodes4);
@@ -800,7 +800,8 @@ int validate4(const fipt::HostBvh& b, const float* verts, const int32_t* tris, i
     const Bvh4Node& en = b.nodes4[idx];
     int used = 0;
     for (int i = 0; i < 4; ++i) {
-        if (en.child[i] != nd.child[i]) return fail(FIPT_EINVAL, "4-wide node %d: child mismatch", idx);
+        if (en.child[i] != node4_ref(nd.child[i]))
+            return fail(FIPT_EINVAL, "4-wide node %d: child mismatch", idx);
         if (nd.child[i] != kEmptyChild) {
             ++used;
             continue;

@@ -106,6 +106,10 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // Square root by the hardware approximation (about 1 ulp), for the same
 // reason; inputs here are never denormal.
 __device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Reciprocal square root by the hardware instruction, for arguments known to
+// be at least 1 (where rsqrtf gives the same instruction's result after a
+// test for denormal inputs that cannot occur).
+__device__ __forceinline__ float rsq_ge1(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Smith G1 of GGX written as 2 c / (c + sqrt(alpha^2 + (1 - alpha^2) c^2)),
 // c = n.v > 0 (algebraically 2 / (1 + sqrt(1 + alpha^2 tan^2))).
@@ -222,12 +226,13 @@ __device__ __forceinline__ void stack_pop(int32_t& ref, int32_t*& top, const int
 // ray enters no later than `tmax` (the current hit distance, finite) are
 // visited nearest first; the nearest becomes `ref`, the others are pushed
 // farthest first.  With no child hit, the next entry is popped
-// (kDone when the stack is empty).  Node byte offsets fit 32 bits (the
-// builder rejects trees of more than kMaxNodes4 nodes).
+// (kDone when the stack is empty).  An inner reference is the node's byte
+// offset (below 2^31: the builder rejects trees of more than kMaxNodes4
+// nodes).
 __device__ __forceinline__ void node4_step(const Bvh4Node* nodes, int32_t& ref, int32_t*& top,
                                            const int32_t* bottom, int stride, const RaySlab& r,
                                            float tmax) {
-    const char* nb = reinterpret_cast<const char*>(nodes) + ((uint32_t)ref << 7);
+    const char* nb = reinterpret_cast<const char*>(nodes) + (uint32_t)ref;
     const int4 qx = load_global(reinterpret_cast<const int4*>(nb));
     const int4 qy = load_global(reinterpret_cast<const int4*>(nb + 16));
     const int4 qz = load_global(reinterpret_cast<const int4*>(nb + 32));
@@ -319,8 +324,9 @@ __device__ __forceinline__ float half_of(uint32_t w01, uint32_t w23) {
 }
 
 // The chain of point origin o (same value in every lane): lane i of `chain`
-// receives node << 2 | slot for level i (the node and which of its children
-// contains o); returns the number of levels; `end` is the reference the
+// receives node | slot for level i (the node's byte offset, whose low seven
+// bits are zero, and which of its children contains o); returns the number
+// of levels; `end` is the reference the
 // traversal continues from (the last chain child, or the node where no
 // child contains o, or the root).  Containment is tested on the decoded
 // half-precision bounds in units of the node scale.
@@ -332,7 +338,7 @@ __device__ __forceinline__ int point_chain(const Bvh4Node* nodes, float scale, V
     int32_t node = 0;
     chain = 0;
     while (L < kChainMax) {
-        const char* nb = reinterpret_cast<const char*>(nodes) + ((uint32_t)node << 7);
+        const char* nb = reinterpret_cast<const char*>(nodes) + (uint32_t)node;
         const int4 qx = load_uniform(nb), qy = load_uniform(nb + 16), qz = load_uniform(nb + 32);
         const float4 og = load_uniform_f(nb + 48);
         const int4 ch = load_uniform(nb + 64);
@@ -354,7 +360,7 @@ __device__ __forceinline__ int point_chain(const Bvh4Node* nodes, float scale, V
         }
         slot = __builtin_amdgcn_readfirstlane(slot);
         if (slot < 0) break;
-        if (lane == L) chain = (int32_t)((uint32_t)node << 2 | (uint32_t)slot);
+        if (lane == L) chain = (int32_t)((uint32_t)node | (uint32_t)slot);
         ++L;
         const int32_t child = __builtin_amdgcn_readfirstlane(
             slot == 0 ? ch.x : slot == 1 ? ch.y : slot == 2 ? ch.z : ch.w);
@@ -411,12 +417,12 @@ __device__ __forceinline__ void chain_siblings3(const int4& qx, const int4& qy, 
 }
 
 // One chain level for a ray: the three siblings of the chain's child at
-// node `node` (slot `skip`) are tested and the hit ones pushed, farthest
+// node `node` (a byte offset; slot `skip`) are tested and the hit ones pushed, farthest
 // first, as the plain step would push them (the chain's child, entered at
 // distance 0, is visited next without a push).
 __device__ __forceinline__ void chain_step(const Bvh4Node* nodes, int32_t node, int skip,
                                            const RaySlab& r, int32_t*& top, int stride) {
-    const char* nb = reinterpret_cast<const char*>(nodes) + ((uint32_t)node << 7);
+    const char* nb = reinterpret_cast<const char*>(nodes) + (uint32_t)node;
     const int4 qx = load_uniform(nb), qy = load_uniform(nb + 16), qz = load_uniform(nb + 32);
     const float4 og = load_uniform_f(nb + 48);
     const int4 ch = load_uniform(nb + 64);

@@ -87,11 +87,17 @@ struct alignas(16) Bvh4Node {
     uint16_t q[3][8];    // bytes 0..47: x, y, z; each lo[0..3], hi[0..3]
     float org[3];        // bytes 48..59
     int32_t spare;       // bytes 60..63
-    int32_t child[4];    // bytes 64..79
+    int32_t child[4];    // bytes 64..79: an inner child as the byte offset of its
+                         // node (index x 128), a leaf as in the binary tree
     int32_t pad[12];
 };
 static_assert(sizeof(Bvh4Node) == 128, "4-wide node is one 128-byte line");
-constexpr int64_t kMaxNodes4 = int64_t(1) << 25;   // node byte offsets stay below 2^32
+// node byte offsets stay below 2^31: an inner reference is a non-negative
+// int32 and its low seven bits are zero
+constexpr int64_t kMaxNodes4 = int64_t(1) << 24;
+inline int32_t node4_ref(int32_t child) {
+    return child >= 0 ? (int32_t)((uint32_t)child << 7) : child;
+}
 
 struct HostBvh {
     std::vector<BvhNode> nodes;

@@ -314,7 +314,7 @@ __device__ V3 refine_path(const RefineArgs& A, int64_t p, int lobe, int s, V3 o,
         V3 w2;
         if (unif24(u.w) < 0.5f) {
             const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
-            const float cos_m = rsqrtf(1.0f + tan2);
+            const float cos_m = dev::rsq_ge1(1.0f + tan2);
             const float sin_m = dev::sqrt_hw(tan2) * cos_m;
             const V3 m = dev::to_world(ft, fb, ny, sin_m * cp_, sin_m * sp_, cos_m);
             const float om = dev::dot(wo, m);
@@ -388,7 +388,7 @@ __device__ void refine_point(const RefineArgs& A, int64_t p, int lane, int32_t* 
                 const float alpha = sg * sg;
                 const float a2 = alpha * alpha;
                 const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
-                const float cos_m = rsqrtf(1.0f + tan2);
+                const float cos_m = dev::rsq_ge1(1.0f + tan2);
                 const float sin_m = dev::sqrt_hw(tan2) * cos_m;
                 const V3 m = dev::to_world(ft, fb, n, sin_m * cp_, sin_m * sp_, cos_m);
                 const float om = dev::dot(wo, m);
@@ -652,7 +652,7 @@ __device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int3
         cont = true;
         if (unif24(u.w) < 0.5f) {
             const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
-            const float cos_m = rsqrtf(1.0f + tan2);
+            const float cos_m = dev::rsq_ge1(1.0f + tan2);
             const float sin_m = dev::sqrt_hw(tan2) * cos_m;
             const V3 m = dev::to_world(ft, fb, ny, sin_m * cp_, sin_m * sp_, cos_m);
             const float om = dev::dot(wo, m);
@@ -744,7 +744,7 @@ __device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int3
                             const float alpha = sg * sg;
                             const float a2 = alpha * alpha;
                             const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
-                            const float cos_m = rsqrtf(1.0f + tan2);
+                            const float cos_m = dev::rsq_ge1(1.0f + tan2);
                             const float sin_m = dev::sqrt_hw(tan2) * cos_m;
                             const V3 m = dev::to_world(pft, pfb, n, sin_m * cp_, sin_m * sp_, cos_m);
                             const float om = dev::dot(wo0, m);
