@@ -310,7 +310,8 @@ __device__ V3 refine_path(const RefineArgs& A, int64_t p, int lobe, int s, V3 o,
         const V3 fb = dev::cross(ny, ft);
         const float xi1 = unif24(vv.x), xi2 = unif24(vv.y);
         float sp_, cp_;
-        sincospif(2.0f * xi2, &sp_, &cp_);
+        sp_ = __builtin_amdgcn_sinf(xi2);   // sin, cos of 2 pi xi2 (angle in turns)
+        cp_ = __builtin_amdgcn_cosf(xi2);
         V3 w2;
         if (unif24(u.w) < 0.5f) {
             const float tan2 = a2 * xi1 * dev::rcp(1.0f - xi1);
@@ -374,7 +375,8 @@ __device__ void refine_point(const RefineArgs& A, int64_t p, int lane, int32_t* 
             float xi1, xi2;
             dev::lobe_uniforms(b.seed, rng_p, lobe, s, lobe == 0 ? b.w_d : b.w_s, xi1, xi2);
             float sp_, cp_;
-            sincospif(2.0f * xi2, &sp_, &cp_);
+            sp_ = __builtin_amdgcn_sinf(xi2);   // sin, cos of 2 pi xi2 (angle in turns)
+            cp_ = __builtin_amdgcn_cosf(xi2);
             V3 wi = v3(0.0f, 0.0f, 1.0f);
             float w = 0.0f, F1 = 0.0f;
             bool shoot = false;
@@ -647,7 +649,8 @@ __device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int3
         const V3 fb = dev::cross(ny, ft);
         const float xi1 = unif24(vv.x), xi2 = unif24(vv.y);
         float sp_, cp_;
-        sincospif(2.0f * xi2, &sp_, &cp_);
+        sp_ = __builtin_amdgcn_sinf(xi2);   // sin, cos of 2 pi xi2 (angle in turns)
+        cp_ = __builtin_amdgcn_cosf(xi2);
         V3 w2 = v3(0.0f, 0.0f, 0.0f);
         cont = true;
         if (unif24(u.w) < 0.5f) {
@@ -731,7 +734,8 @@ __device__ void refine_point_spec(const RefineArgs& A, int64_t p, int lane, int3
                         float xi1, xi2;
                         dev::lobe_uniforms(b.seed, rng_p, lobe, s, lobe == 0 ? b.w_d : b.w_s, xi1, xi2);
                         float sp_, cp_;
-                        sincospif(2.0f * xi2, &sp_, &cp_);
+                        sp_ = __builtin_amdgcn_sinf(xi2);   // sin, cos of 2 pi xi2 (angle in turns)
+                        cp_ = __builtin_amdgcn_cosf(xi2);
                         bool shoot = false;
                         if (lobe == 0) {
                             const float r = dev::sqrt_hw(xi1);
