@@ -169,7 +169,9 @@ int32_t fipt_version(void);
  *   indices (each in [0, n_verts)); 1 <= n_tris < 2^28.
  * The scene owns its device memory until fipt_scene_destroy.  The radiance
  * starts at zero (no cache, no emission).  FIPT_EINVAL on bad sizes or
- * indices, FIPT_ENOMEM on allocation failure, FIPT_EHIP on HIP errors. */
+ * indices, and when the tree would exceed what the traversal addresses
+ * (2^24 4-wide nodes: tens of millions of triangles) or holds on its
+ * stack; FIPT_ENOMEM on allocation failure, FIPT_EHIP on HIP errors. */
 int fipt_scene_create(const float* verts, int64_t n_verts, const int32_t* tris,
                       int64_t n_tris, int32_t device, void* stream, fipt_scene* out);
 
